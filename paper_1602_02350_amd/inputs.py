@@ -1,0 +1,118 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only draws data. It holds none of the method's arithmetic: no
+objective, no sketch, no preconditioner, no sampler. Both the HIP path and the
+FP64 oracle consume what it returns, so neither has to import the other.
+
+Recipe (row-major, one instance per row, X is n x d):
+  * U  : Haar-random orthogonal d x d matrix (QR of a Gaussian matrix with the
+         signs of R's diagonal folded into Q, Mezzadri 2007).
+  * X  = G diag(sqrt(spec)) U^T with G ~ N(0,1)^{n x d}, so each row is
+         N(0, U diag(spec) U^T).
+  * w0 ~ N(0, I_d);  y = X w0 + e with e ~ N(0, noise_var).
+  * Omega ~ N(0,1)^{d x l} for the range finder.
+Spectra are power laws spec_j = j^{-alpha} (j = 1..d), optionally with a floor.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# Base seed of every workload; individual streams are offset from it.
+BASE_SEED = 20160207
+
+
+def power_spectrum(d: int, alpha: float, floor: float = 0.0) -> np.ndarray:
+    """Population covariance eigenvalues j^{-alpha} + floor, j = 1..d (descending)."""
+    j = np.arange(1, d + 1, dtype=np.float64)
+    return j ** (-float(alpha)) + float(floor)
+
+
+def haar_orthogonal(d: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed d x d orthogonal matrix."""
+    g = rng.standard_normal((d, d))
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+@dataclass
+class RidgeProblem:
+    X: np.ndarray        # n x d
+    y: np.ndarray        # n
+    w0: np.ndarray       # d, the planted weights
+    spec: np.ndarray     # d, population covariance eigenvalues
+    U: np.ndarray        # d x d, population covariance eigenvectors (columns)
+    lam: float           # ridge parameter
+    seed: int
+
+
+def make_ridge(n: int, d: int, alpha: float, lam: float, seed: int,
+               noise_var: float = 0.01, floor: float = 0.0,
+               dtype=np.float32, block: int = 65536) -> RidgeProblem:
+    """Draw one synthetic ridge problem; X and y are rounded to `dtype`."""
+    spec = power_spectrum(d, alpha, floor)
+    rng_u = np.random.default_rng([seed, 1])
+    rng_x = np.random.default_rng([seed, 2])
+    rng_w = np.random.default_rng([seed, 3])
+    rng_e = np.random.default_rng([seed, 4])
+    U = haar_orthogonal(d, rng_u)
+    M = (np.sqrt(spec)[:, None] * U.T)          # rows of X are g^T M
+    X = np.empty((n, d), dtype=dtype)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        X[r0:r1] = (rng_x.standard_normal((r1 - r0, d)) @ M).astype(dtype)
+    w0 = rng_w.standard_normal(d)
+    noise = rng_e.standard_normal(n) * np.sqrt(noise_var)
+    y = (X.astype(np.float64) @ w0 + noise).astype(dtype)
+    return RidgeProblem(X=X, y=y, w0=w0, spec=spec, U=U, lam=float(lam), seed=seed)
+
+
+def gaussian(shape, seed: int, dtype=np.float32) -> np.ndarray:
+    """i.i.d. N(0,1) array (e.g. the range finder's Omega)."""
+    return np.random.default_rng([seed, 5]).standard_normal(shape).astype(dtype)
+
+
+def random_orthonormal(d: int, k: int, seed: int) -> np.ndarray:
+    """d x k matrix with orthonormal columns (FP64)."""
+    g = np.random.default_rng([seed, 6]).standard_normal((d, k))
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def decreasing_values(k: int, seed: int, lo: float = 1e-3, hi: float = 1.0) -> np.ndarray:
+    """k positive values sorted descending, log-uniform in [lo, hi]."""
+    v = np.exp(np.random.default_rng([seed, 7]).uniform(np.log(lo), np.log(hi), k))
+    return np.sort(v)[::-1].copy()
+
+
+def index_stream(N: int, count: int, seed: int) -> np.ndarray:
+    """`count` indices drawn uniformly from [0, N) as int32 (an injected sample stream)."""
+    return np.random.default_rng([seed, 8]).integers(0, N, size=count, dtype=np.int64).astype(np.int32)
+
+
+def integer_weights(N: int, seed: int, max_weight: int = 1 << 20, zero_frac: float = 0.0) -> np.ndarray:
+    """N non-negative uint64 sampling weights (some zero if zero_frac > 0, never all)."""
+    rng = np.random.default_rng([seed, 9])
+    w = rng.integers(1, max_weight, size=N, dtype=np.int64).astype(np.uint64)
+    if zero_frac > 0:
+        z = rng.random(N) < zero_frac
+        z[rng.integers(0, N)] = False
+        w[z] = 0
+    return w
+
+
+def random_vector(d: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    return np.random.default_rng([seed, 10]).standard_normal(d) * scale
+
+
+# Workload recipes with their sizes. Each returns keyword arguments for make_ridge
+# plus the method parameters that go with the workload.
+WORKLOADS = {
+    # n=2000, d=100, spectrum j^-2, lambda=1e-4, k=10, p=5; solved to 1e-8.
+    "small_n2000_d100": dict(n=2000, d=100, alpha=2.0, lam=1e-4, k=10, b=8, eps=1e-8, floor=0.0),
+    # n=1e5, d=1000, spectrum j^-1.5, lambda=1e-5, k=50, minibatch 64; solved to 1e-6 in FP32.
+    "fp32_n100000_d1000": dict(n=100000, d=1000, alpha=1.5, lam=1e-5, k=50, b=64, eps=1e-6, floor=0.0),
+    # n=5e5, d=2048, spectrum j^-2 + 1e-6, lambda=1e-6, k=128; BF16 sketch and rows.
+    "mixed_n500000_d2048": dict(n=500000, d=2048, alpha=2.0, lam=1e-6, k=128, b=64, eps=1e-6, floor=1e-6),
+}

@@ -1,0 +1,104 @@
+"""Pins of the oracle's ridge-regression layer against values fixed by the paper and by mathematics."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from oracle import ridge
+from paper_1602_02350_amd import inputs
+
+
+def test_closed_form_hand_example():
+    """One-dimensional problem solved in rationals (Eq. (ridge) and its normal equations)."""
+    g = read_golden("ridge_scalar.txt")
+    x = np.array([float(v) for v in g["x"][0]])[:, None]
+    y = np.array([float(v) for v in g["y"][0]])
+    lam = float(g["lambda"][0][0])
+    w = ridge.closed_form(x, y, lam)
+    w_exact = Fraction(int(g["w_star_num"][0][0]), int(g["w_star_den"][0][0]))
+    L_exact = Fraction(int(g["L_star_num"][0][0]), int(g["L_star_den"][0][0]))
+    assert abs(w[0] - float(w_exact)) < 1e-15
+    assert abs(ridge.objective(x, y, lam, w) - float(L_exact)) < 1e-15
+
+
+def _loop_gradient(X, y, lam, w):
+    """grad L written term by term from Eq. (ridge), independent of the matrix form."""
+    n, d = X.shape
+    g = np.zeros(d)
+    for i in range(n):
+        r = sum(X[i, j] * w[j] for j in range(d)) - y[i]
+        g += r * X[i] / n
+    return g + lam * w
+
+
+def test_closed_form_is_stationary():
+    P = inputs.make_ridge(60, 7, 1.0, 1e-2, seed=11, dtype=np.float64)
+    w = ridge.closed_form(P.X, P.y, P.lam)
+    g = _loop_gradient(P.X, P.y, P.lam, w)
+    assert np.linalg.norm(g) < 1e-13
+    assert np.allclose(ridge.gradient(P.X, P.y, P.lam, w + 1.0), _loop_gradient(P.X, P.y, P.lam, w + 1.0))
+
+
+def test_closed_form_matches_augmented_least_squares():
+    """Ridge = least squares on [X/sqrt(n); sqrt(lam) I] (LAPACK gelsd, an SVD solver)."""
+    P = inputs.make_ridge(300, 20, 2.0, 1e-3, seed=12, dtype=np.float64)
+    n, d = P.X.shape
+    A = np.vstack([P.X / np.sqrt(n), np.sqrt(P.lam) * np.eye(d)])
+    t = np.concatenate([P.y / np.sqrt(n), np.zeros(d)])
+    w_ls = np.linalg.lstsq(A, t, rcond=None)[0]
+    w = ridge.closed_form(P.X, P.y, P.lam)
+    assert np.linalg.norm(w - w_ls) <= 1e-9 * np.linalg.norm(w_ls)
+
+
+def test_suboptimality_identity():
+    """L(w) - L(w*) equals 1/2 (w-w*)^T (C + lam I)(w-w*) for the quadratic L."""
+    P = inputs.make_ridge(200, 10, 1.0, 1e-2, seed=13, dtype=np.float64)
+    ws = ridge.closed_form(P.X, P.y, P.lam)
+    rng = np.random.default_rng(0)
+    for scale in [1e-1, 1.0, 10.0]:
+        w = ws + scale * rng.standard_normal(10)
+        direct = ridge.objective(P.X, P.y, P.lam, w) - ridge.objective(P.X, P.y, P.lam, ws)
+        assert abs(direct - ridge.suboptimality(P.X, P.lam, w, ws)) <= 1e-10 * direct
+        H = ridge.hessian(P.X, P.lam)
+        e = w - ws
+        assert abs(0.5 * e @ H @ e - ridge.suboptimality(P.X, P.lam, w, ws)) <= 1e-12 * direct
+
+
+def test_kappa_hat_on_diagonal_correlation():
+    """Eq. (initialCondition) on data with orthogonal columns: C = diag(s^2)."""
+    n, s = 8, np.array([2.0, 1.0, 0.5])
+    Q = np.linalg.qr(np.random.default_rng(1).standard_normal((n, 3)))[0]
+    X = Q * s * np.sqrt(n)                 # X^T X / n = diag(s^2)
+    lam = 0.25
+    ev = s ** 2
+    expect = np.sum(ev + lam) / (ev.min() + lam)
+    assert abs(ridge.kappa_hat(X, lam) - expect) < 1e-12 * expect
+
+
+def test_speedup_ratio_and_bound_on_hand_example():
+    g = read_golden("exact_precond_diag.txt")
+    ev = np.array([float(v) for v in g["diag"][0]])
+    k = int(g["k"][0][0])
+    lam = float(g["lambda"][0][0])
+    ratio = Fraction(int(g["ratio_num"][0][0]), int(g["ratio_den"][0][0]))
+    assert abs(ridge.speedup_ratio(ev, k) - float(ratio)) < 1e-15
+    assert abs(ridge.predicted_kappa(ev, lam, k) - float(g["bound"][0][0])) < 1e-12
+
+
+@pytest.mark.parametrize("lam", [1e-1, 1e-3])
+def test_planted_mistake_objective_without_half_is_caught(lam, monkeypatch):
+    """A dropped 1/2 in the regularizer moves the minimizer off the normal equations."""
+    P = inputs.make_ridge(50, 4, 1.0, lam, seed=14, dtype=np.float64)
+    ws = ridge.closed_form(P.X, P.y, P.lam)
+
+    def wrong(X, y, lam_, w):
+        r = X @ w - y
+        return 0.5 * float(r @ r) / X.shape[0] + lam_ * float(w @ w)
+
+    monkeypatch.setattr(ridge, "objective", wrong)
+    # the closed form is no longer the minimizer of the (wrong) objective:
+    h = 1e-4
+    e0 = np.eye(4)[0]
+    fd = (ridge.objective(P.X, P.y, lam, ws + h * e0) - ridge.objective(P.X, P.y, lam, ws - h * e0)) / (2 * h)
+    assert abs(fd) > 1e-3 * lam * abs(ws[0])
