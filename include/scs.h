@@ -1,0 +1,193 @@
+/*
+ * scs.h - Sketched Preconditioned SVRG for ridge regression on AMD MI355X (gfx950).
+ *
+ * Gonen, Orabona, Shalev-Shwartz, "Solving Ridge Regression using Sketched
+ * Preconditioned SVRG", arXiv:1602.02350.
+ *
+ * Problem (Sec. 1, Eq. (ridge)):  minimize  L(w) = (1/n) sum_i 1/2 (w^T x_i - y_i)^2 + (lambda/2)||w||^2.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are ROW-MAJOR with an explicit leading dimension (elements between
+ *     consecutive rows, >= the row length). X is n x d: one instance per row
+ *     (the paper stores instances as columns; formulas are transposed).
+ *   - Unless stated otherwise, array arguments are DEVICE pointers on the
+ *     context's device. Inputs are borrowed: never freed, never modified.
+ *     Outputs are caller-allocated. Scratch memory is owned by the context,
+ *     allocated on first use, reused, and released by scs_destroy.
+ *   - Work is enqueued on the context's stream. Entry points that return host
+ *     values (reports, status) synchronize that stream before returning;
+ *     the others are asynchronous with respect to the host.
+ *   - Return value: SCS_OK (0); a negative code for caller or device errors
+ *     (nothing useful was written); a positive code for a numerical outcome
+ *     with a valid best-so-far output. No C++ exception crosses this boundary.
+ *     scs_last_error() gives a human-readable message for the last failure.
+ *   - Floating point: inputs FP32; the full-gradient pass and the inner loop
+ *     compute in FP32 with FP64 cross-workgroup reductions; the small dense
+ *     sketch algebra (Gram, Cholesky, eigendecomposition) is FP64.
+ */
+#ifndef SCS_H
+#define SCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define SCS_OK 0
+#define SCS_EINVAL (-1)       /* bad argument: lambda <= 0, k < 0, k > d, n < k + p, null pointer, bad stride */
+#define SCS_ENONFINITE (-2)   /* NaN or Inf met in X or y (found by the first full-gradient pass) */
+#define SCS_ENOMEM (-3)       /* device allocation failed */
+#define SCS_EDEVICE (-4)      /* HIP runtime error (message in scs_last_error) */
+#define SCS_NOT_CONVERGED 1   /* epoch cap reached before the stop rule held; output = last snapshot */
+#define SCS_DIVERGED 2        /* objective became non-finite or grew 10x over its start; output = last good snapshot */
+#define SCS_SKETCH_RANK_DEFICIENT 3 /* range-finder block lost rank (e.g. X = 0); solved without preconditioning */
+
+/* Precision of the sketch GEMMs and of the preconditioned rows used by the inner loop. */
+#define SCS_PREC_FP32 0       /* FP32 MFMA GEMMs, FP32 rows */
+#define SCS_PREC_MIXED 1      /* BF16 MFMA GEMMs (FP32 accumulation), BF16 rows in the inner loop */
+
+/* Stop rules for scs_svrg_solve (checked at the start of every epoch's full-gradient pass). */
+#define SCS_STOP_EPOCHS 0     /* run exactly max_epochs epochs (Alg. 1's parameter S) */
+#define SCS_STOP_CERTIFICATE 1/* stop when ||grad||^2 (lam~_1 + lambda)/(2 lambda) <= eps, an upper bound on L - L* */
+#define SCS_STOP_GAP 2        /* stop when L(w) - f_star <= eps (f_star supplied by the caller) */
+
+typedef struct scs_ctx scs_ctx;
+
+/* Options. Fill with scs_opts_default() and change what you need. */
+typedef struct scs_opts {
+  int oversample;         /* p: range-finder width is k + p (default 5) */
+  int batch;              /* b: i.i.d. draws per inner step (default 64) */
+  int64_t steps;          /* m: inner steps per epoch; 0 = ceil(2 n / b) */
+  double step_scale;      /* c: step eta = c / beta_hat with beta_hat = (1/(n+d)) sum_i beta_i (default 1) */
+  int max_epochs;         /* S: epoch cap (default 30) */
+  int stop_rule;          /* SCS_STOP_* (default SCS_STOP_CERTIFICATE) */
+  double f_star;          /* optimum value for SCS_STOP_GAP */
+  int average;            /* 1: snapshot = average of the m inner iterates (Alg. 1); 0: last iterate */
+  int precision;          /* SCS_PREC_* (default SCS_PREC_FP32) */
+  int workgroups;         /* inner-loop workgroups per problem; 0 = chosen from d */
+  uint64_t seed;          /* seed of the Gaussian test matrix and of the index stream */
+  const float* omega;     /* optional device (k+p) x d row-major Gaussian test matrix (transposed Omega); NULL = drawn from seed */
+  const int32_t* indices; /* optional device index stream, max_epochs x m x b entries in [0, n+d); NULL = drawn from seed */
+  float* trace_w;         /* optional device max_epochs x d: w = P^{-1/2} w~ of the snapshot entering each epoch */
+  double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's end */
+  int timing;             /* 1: time every full-gradient pass and inner-loop launch with HIP events (report.ms_grad, ms_inner) */
+} scs_opts;
+
+typedef struct scs_report {
+  int status;             /* same as the return value */
+  int epochs;             /* epochs completed */
+  int k_used;             /* sketch rank actually used (k, or 0 after SCS_SKETCH_RANK_DEFICIENT) */
+  int64_t steps;          /* m used */
+  double eta;             /* step used */
+  double beta_hat;        /* average smoothness of the n+d components */
+  double objective;       /* L(w) at the returned w, from the last full-gradient pass */
+  double grad_norm;       /* ||grad L~(w~)|| at the returned snapshot */
+  double certificate;     /* ||grad||^2 (lam~_1 + lambda)/(2 lambda) */
+  double lam_top;         /* lam~_1 (largest sketched eigenvalue; 0 if k = 0) */
+  double ms_sketch, ms_apply, ms_solve; /* stage times */
+  double ms_grad, ms_inner; /* with opts.timing: summed durations of the full-gradient passes and inner-loop launches */
+  int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
+} scs_report;
+
+void scs_opts_default(scs_opts* opts);
+const char* scs_status_string(int status);
+const char* scs_last_error(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t; NULL = the null stream). */
+int scs_create(scs_ctx** out, int device, void* hip_stream);
+int scs_destroy(scs_ctx* ctx);
+
+/*
+ * Randomized sketch (Alg. 2 with one Krylov block, Sec. 3.2): Y = X^T (X Omega),
+ * Q = orth(Y) by CholeskyQR2 in FP64, B = (X Q)^T (X Q) / n, B = V Theta V^T by
+ * Jacobi in FP64, lam~ = Theta_{1..k} (descending, clamped >= 0), U~ = Q V_{:,1..k}.
+ * The lam~ estimate the eigenvalues of C = X^T X / n (Eq. (covSpec)), i.e. the
+ * squared singular values of n^{-1/2} X.
+ *   X: n x d (ld ldx); k in [1, d]; k + p <= min(d, n, 140).
+ *   U_out: d x k row-major FP32 (ld k); U64_out (nullable): d x k FP64; lam_out: k FP64.
+ * Returns SCS_SKETCH_RANK_DEFICIENT if the Gram matrix of Y is not positive definite.
+ */
+int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k,
+                     const scs_opts* opts, float* U_out, double* U64_out, double* lam_out);
+
+/*
+ * Preconditioner of Eq. (condSketch), P^{-1/2} = sum_i u_i u_i^T/sqrt(lam_i+lambda) + (I - U U^T)/sqrt(lam_k+lambda),
+ * applied to every row (Alg. 3, x~_i = P^{-1/2} x_i) and to the regularizer rows b_j = P^{-1/2} e_j (Sec. 4.1):
+ *   Xt_out  (n x d, ld ldt): x~_i = x_i / s + U~ (D (U~^T x_i)),  s = sqrt(lam_k + lambda), D_j = 1/sqrt(lam_j + lambda) - 1/s
+ *   reg_out (d x d, ld ldt): sqrt(n lambda) b_j  (so that the n+d components are 1/2 (n+d)/n (a_i^T w - t_i)^2)
+ *   beta_out (n + d, nullable): ||x~_i||^2 then ||sqrt(n lambda) b_j||^2 (proportional to the smoothness beta_i of Alg. 3)
+ * xt_bf16 = 1 stores Xt_out and reg_out as BF16 (round to nearest even); 0 stores FP32.
+ * U is d x k FP32 (ld k), lam k FP64 (descending). k = 0 gives P = I. ldt >= d.
+ */
+int scs_precondition_apply(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
+                           const float* U, const double* lam, int k, double lambda,
+                           int xt_bf16, void* Xt_out, void* reg_out, int64_t ldt, float* beta_out);
+
+/*
+ * Full gradient of the preconditioned objective at w~ (Alg. 1, the snapshot gradient; Sec. 4.1):
+ *   grad L~(w~) = P^{-1/2} [ X^T (X w - y)/n + lambda w ],  w = P^{-1/2} w~,
+ * which equals X~^T (X~ w~ - y)/n + lambda P^{-1} w~ (the n+d-component form) and is
+ * evaluated with X itself so that its fixed point is exactly that of L.
+ *   wt: d FP32 (device); grad_out: d FP32 (device); obj_out (nullable, HOST): L(w) = L~(w~).
+ */
+int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                      const float* U, const double* lam, int k, double lambda,
+                      const float* wt, float* grad_out, double* obj_out);
+
+/*
+ * One SVRG epoch (Alg. 1, inner loop) on the n+d rows a_i = x~_i (i < n), sqrt(n lambda) b_{i-n} (i >= n):
+ *   for t = 1..m: draws i_1..i_b = idx[(t-1) b ..]; v = (1/b) sum_j (a_ij^T (w_{t-1} - w~)) a_ij / (n q_ij) + mu;
+ *                 w_t = w_{t-1} - eta v
+ *   w~ <- (1/m) sum_t w_t  (average = 1)  or  w_m  (average = 0).
+ * q_i are the sampling probabilities of the quantized weights of `beta` (see scs_sample_indices).
+ * Xt: n x d rows, reg: d x d rows, both with leading dimension ldt (a multiple of 4), FP32 or BF16 as
+ * xt_bf16; beta: n + d, idx: m x b int32 in [0, n+d) (device); 1 <= b <= 64.
+ * wt is updated in place; mu = grad L~(w~) (device FP32). workgroups = 0 chooses from d.
+ */
+int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,
+                   const float* beta, const float* mu, const int32_t* idx, int64_t m, int b,
+                   double eta, int average, int workgroups, float* wt);
+
+/*
+ * Importance sampling of Alg. 1 (q_i = beta_i / sum_j beta_j): the beta are quantized to
+ * integer weights W_i = max(1, rint(beta_i 2^B / max beta)) (0 for beta_i = 0), B = 62 - ceil(log2 N),
+ * and draw g of `epoch` is the first i whose cumulative weight exceeds floor(r_g T / 2^64),
+ * r_g a 64-bit Philox4x32-10 output (Salmon et al. 2011), T = sum W. Bit-exact and reproducible.
+ *   beta: N FP32 (device); out: count int32 (device).
+ */
+int scs_sample_indices(scs_ctx* ctx, const float* beta, int64_t N, uint64_t seed, int epoch,
+                       int64_t count, int32_t* out);
+
+/* N(0,1) values from Philox4x32-10 + Box-Muller in FP64, rounded to FP32 (device `out`, count entries). */
+int scs_gaussian(scs_ctx* ctx, uint64_t seed, int64_t count, float* out);
+
+/*
+ * Sketched Preconditioned SVRG (Alg. 3): sketch (k >= 1), precondition, SVRG epochs with
+ * minibatches of b, then w = P^{-1/2} w~ (Eq. (condRidge)). k = 0 runs plain SVRG (P = I).
+ *   X: n x d (ld ldx), y: n (device FP32). w_out: d FP32 (device). report: HOST, nullable.
+ * eps is the target of the stop rule (see SCS_STOP_*).
+ */
+int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                   double lambda, int k, double eps, const scs_opts* opts, float* w_out,
+                   scs_report* report);
+
+/*
+ * Many independent ridge problems (uneven n, d, lambda, k) solved together: every problem's
+ * sketch, preconditioning and SVRG epochs run as in scs_svrg_solve, with the epochs of all
+ * problems advancing together inside shared launches (one persistent inner-loop launch per
+ * epoch for all problems, largest problems first). Stop rule and options as in scs_svrg_solve
+ * (omega, indices and trace_w must be NULL). Arrays of pointers and sizes are HOST arrays of
+ * length nprob; the pointed-to data are device arrays. reports: HOST array of nprob, nullable.
+ */
+int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n,
+                           const int64_t* d, const int64_t* ldx, const float* const* y,
+                           const double* lambda, const int* k, double eps, const scs_opts* opts,
+                           float* const* w_out, scs_report* reports);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCS_H */

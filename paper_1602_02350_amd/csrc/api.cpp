@@ -1,0 +1,669 @@
+// C-ABI of libscs: context, workspace and the orchestration of Sketched Preconditioned SVRG
+// (Alg. 3): sketch -> preconditioner -> SVRG epochs (full-gradient pass + persistent inner loop)
+// -> w = P^{-1/2} w~. Every arithmetic step runs in the HIP kernels of this library; the host
+// only validates arguments, sizes scratch buffers, enqueues launches and reads status records.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "scs_internal.h"
+
+using namespace scs;
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void scs::set_error(const std::string& msg) { g_last_error = msg; }
+
+struct scs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  std::vector<hipEvent_t> events;
+  int xcd_stride = 8;
+};
+
+namespace {
+
+// Scratch buffer `name` with at least `bytes` (contents undefined after growth).
+void* wsb(scs_ctx* c, const std::string& name, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  auto& b = c->bufs[name];
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    hipStreamSynchronize(c->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = ((bytes + 4095) / 4096) * 4096;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    set_error("hipMalloc failed for scratch buffer " + name + " (" + std::to_string(want) + " bytes)");
+    b.p = nullptr;
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+template <class T>
+T* ws(scs_ctx* c, const std::string& name, size_t count) {
+  return reinterpret_cast<T*>(wsb(c, name, count * sizeof(T)));
+}
+
+#define WS(var, T, name, count)                  \
+  T* var = ws<T>(ctx, name, (size_t)(count));    \
+  if (!var) return SCS_ENOMEM;
+
+int ensure_events(scs_ctx* c, size_t count) {
+  while (c->events.size() < count) {
+    hipEvent_t e;
+    SCS_HIP(hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  return SCS_OK;
+}
+
+struct Guard {  // makes the context's device current for the duration of a call
+  int prev = -1;
+  explicit Guard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    hipSetDevice(dev);
+  }
+  ~Guard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+int choose_workgroups(const scs_opts& o, int64_t d) {
+  if (o.workgroups > 0) return o.workgroups;
+  return inner_default_workgroups(d);
+}
+
+// Sketch of Alg. 2 with one block. Fills ws buffers "U32" (d x k), "UT32" (k x d), "U64", "lam",
+// and, if want_z, "Z" = X U~ (n x k) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
+int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
+                bool want_z, bool* rank_def) {
+  hipStream_t st = ctx->stream;
+  const int l = k + o.oversample;
+  const int bf = o.precision == SCS_PREC_MIXED;
+  // Omega^T (l x d)
+  const float* OmT = o.omega;
+  if (!OmT) {
+    WS(om, float, "omega", (size_t)l * d);
+    SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, om));
+    OmT = om;
+  }
+  // T = X Omega (n x l)
+  WS(T, float, "T", (size_t)n * l);
+  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, OmT, l, d, T, l));
+  // Y = X^T T (d x l), split over row chunks, summed in FP64
+  int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 512), std::max<int64_t>(1, 1024 / cdiv(d, 64))));
+  int64_t chunk = cdiv(n, nchunks);
+  nchunks = cdiv(n, chunk);
+  WS(part, float, "partial", (size_t)nchunks * d * l);
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, l, part, chunk, nchunks));
+  WS(Y, double, "Y64", (size_t)d * l);
+  SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
+  // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
+  WS(G, double, "G64", (size_t)l * l);
+  WS(Rinv, double, "Rinv64", (size_t)l * l);
+  WS(Q1, double, "Q1_64", (size_t)d * l);
+  WS(Q, double, "Q64", (size_t)d * l);
+  WS(QT32, float, "QT32", (size_t)l * d);
+  WS(flags, int, "cholflags", 2);
+  SCS_CHECK(launch_gemm64(st, l, l, d, Y, 1, l, Y, l, 1, G, l, nullptr, 0));
+  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, flags));
+  SCS_CHECK(launch_gemm64(st, d, l, l, Y, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
+  SCS_CHECK(launch_gemm64(st, l, l, d, Q1, 1, l, Q1, l, 1, G, l, nullptr, 0));
+  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, flags + 1));
+  SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Q, l, nullptr, 0));
+  SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QT32, d));  // Q^T = R2^{-T} Q1^T
+  // Rayleigh-Ritz: Wq = X Q (n x l), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
+  WS(Wq, float, "Wq", (size_t)n * l);
+  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, l, d, Wq, l));
+  int64_t nch2 = std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 256)));
+  int64_t chunk2 = cdiv(n, nch2);
+  nch2 = cdiv(n, chunk2);
+  WS(part2, float, "partial2", (size_t)nch2 * l * l);
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, l, Wq, l, l, part2, chunk2, nch2));
+  WS(B, double, "B64", (size_t)l * l);
+  SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)l * l, 1.0 / (double)n, B));
+  WS(Awork, double, "Ajac64", (size_t)l * l);
+  WS(V, double, "V64", (size_t)l * l);
+  WS(theta, double, "theta", (size_t)l);
+  WS(order, int, "order", (size_t)l);
+  SCS_CHECK(launch_jacobi64(st, B, l, Awork, V, theta, order));
+  // lift: U~ = Q V_k, lam = theta_{1..k}
+  WS(U64, double, "U64", (size_t)d * k);
+  WS(U32, float, "U32", (size_t)d * k);
+  WS(UT32, float, "UT32", (size_t)k * d);
+  WS(lam, double, "lam", (size_t)k);
+  WS(VkT, float, "VkT", (size_t)k * l);
+  SCS_CHECK(launch_lift(st, Q, d, l, V, order, k, theta, U64, U32, UT32, lam, VkT));
+  if (want_z) {
+    WS(Z, float, "Z", (size_t)n * k);
+    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, k));
+  }
+  int hflags[2] = {0, 0};
+  SCS_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  *rank_def = hflags[0] || hflags[1];
+  return SCS_OK;
+}
+
+// Preconditioned rows: Xt = X/s + Z (U D)^T (ld ldt), reg = sqrt(n lambda)(U (U D)^T + I/s), beta = row norms.
+int apply_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* U32, const float* Z,
+               const double* lam, int k, double lambda, int gemm_bf16, int out_bf16, void* Xt, void* reg,
+               int64_t ldt, float* beta, SolveState* state) {
+  hipStream_t st = ctx->stream;
+  WS(UD, float, "UD32", (size_t)d * k);
+  WS(scal, double, "scal", 2);
+  SCS_CHECK(launch_precond_setup(st, lam, k, lambda, n, U32, d, UD, scal, state));
+  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Z, n, k, k, UD, d, k, 1.0f, X, ldx, 0.f, scal, 0.f, nullptr,
+                                out_bf16, Xt, ldt, beta));
+  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, U32, d, k, k, UD, d, k, (float)std::sqrt((double)n * lambda),
+                                nullptr, 0, 0.f, nullptr, 0.f, scal + 1, out_bf16, reg, ldt, beta ? beta + n : nullptr));
+  return SCS_OK;
+}
+
+int validate_problem(const float* X, int64_t n, int64_t d, int64_t ldx, double lambda) {
+  if (!X) {
+    set_error("null X");
+    return SCS_EINVAL;
+  }
+  if (n < 1 || d < 1 || ldx < d) {
+    set_error("need n >= 1, d >= 1, ldx >= d");
+    return SCS_EINVAL;
+  }
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) {
+    set_error("lambda must be a finite positive number");
+    return SCS_EINVAL;
+  }
+  return SCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void scs_opts_default(scs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->oversample = 5;
+  o->batch = 64;
+  o->steps = 0;
+  o->step_scale = 1.0;
+  o->max_epochs = 30;
+  o->stop_rule = SCS_STOP_CERTIFICATE;
+  o->f_star = 0.0;
+  o->average = 1;
+  o->precision = SCS_PREC_FP32;
+  o->workgroups = 0;
+  o->seed = 20160207ull;
+}
+
+const char* scs_status_string(int s) {
+  switch (s) {
+    case SCS_OK: return "ok";
+    case SCS_EINVAL: return "invalid argument";
+    case SCS_ENONFINITE: return "non-finite value in X or y";
+    case SCS_ENOMEM: return "device allocation failed";
+    case SCS_EDEVICE: return "HIP runtime error";
+    case SCS_NOT_CONVERGED: return "epoch cap reached before the stop rule held";
+    case SCS_DIVERGED: return "diverged; returned the last good snapshot";
+    case SCS_SKETCH_RANK_DEFICIENT: return "sketch lost rank; solved without preconditioning";
+  }
+  return "unknown status";
+}
+
+const char* scs_last_error(void) { return g_last_error.c_str(); }
+
+int scs_create(scs_ctx** out, int device, void* hip_stream) {
+  if (!out) return SCS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  SCS_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) {
+    set_error("no such HIP device");
+    return SCS_EINVAL;
+  }
+  auto* c = new scs_ctx();
+  c->device = device;
+  if (const char* e = std::getenv("SCS_XCD_STRIDE")) c->xcd_stride = std::max(1, std::atoi(e));
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return SCS_OK;
+}
+
+int scs_destroy(scs_ctx* c) {
+  if (!c) return SCS_OK;
+  Guard g(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  for (auto e : c->events) hipEventDestroy(e);
+  delete c;
+  return SCS_OK;
+}
+
+int scs_gaussian(scs_ctx* ctx, uint64_t seed, int64_t count, float* out) {
+  if (!ctx || !out || count < 0) return SCS_EINVAL;
+  Guard g(ctx->device);
+  return launch_gaussian(ctx->stream, seed, count, out);
+}
+
+int scs_sample_indices(scs_ctx* ctx, const float* beta, int64_t N, uint64_t seed, int epoch, int64_t count,
+                       int32_t* out) {
+  if (!ctx || !beta || !out || N < 1 || count < 0 || N > INT32_MAX) return SCS_EINVAL;
+  Guard g(ctx->device);
+  WS(cum, uint64_t, "cum", (size_t)N);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
+  SCS_CHECK(launch_sampler_prepare(ctx->stream, beta, N, cum, scr, sampler_scratch_len(N), nullptr));
+  return launch_sample(ctx->stream, cum, N, N, seed, epoch, count, out, nullptr, nullptr);
+}
+
+int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts* opts,
+                     float* U_out, double* U64_out, double* lam_out) {
+  if (!ctx || !U_out || !lam_out) return SCS_EINVAL;
+  SCS_CHECK(validate_problem(X, n, d, ldx, 1.0));
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  const int l = k + o.oversample;
+  if (k < 1 || k > d || o.oversample < 0 || l > d || l > n || l > 136) {
+    set_error("sketch: need 1 <= k, k + p <= min(d, n, 136)");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  bool rd = false;
+  SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, false, &rd));
+  hipStream_t st = ctx->stream;
+  SCS_HIP(hipMemcpyAsync(U_out, ws<float>(ctx, "U32", 0), sizeof(float) * d * k, hipMemcpyDeviceToDevice, st));
+  if (U64_out)
+    SCS_HIP(hipMemcpyAsync(U64_out, ws<double>(ctx, "U64", 0), sizeof(double) * d * k, hipMemcpyDeviceToDevice, st));
+  SCS_HIP(hipMemcpyAsync(lam_out, ws<double>(ctx, "lam", 0), sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  return rd ? SCS_SKETCH_RANK_DEFICIENT : SCS_OK;
+}
+
+int scs_precondition_apply(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* U,
+                           const double* lam, int k, double lambda, int xt_bf16, void* Xt_out, void* reg_out,
+                           int64_t ldt, float* beta_out) {
+  if (!ctx || !Xt_out || !reg_out || ldt < d || k < 0 || k > d || (k > 0 && (!U || !lam))) return SCS_EINVAL;
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  if (k > 160) {
+    set_error("apply: k > 160");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  if (k == 0) {
+    // P = I: x~_i = x_i, rows sqrt(n lambda) e_j
+    WS(I1, double, "unit_lam", 1);
+    (void)I1;
+    if (xt_bf16) {
+      WS(tmp, uint16_t, "xcopy16", (size_t)n * d);
+      SCS_CHECK(launch_copy_bf16(st, X, n, d, ldx, tmp));
+      SCS_HIP(hipMemcpy2DAsync(Xt_out, ldt * 2, tmp, d * 2, d * 2, n, hipMemcpyDeviceToDevice, st));
+      if (beta_out) SCS_CHECK(launch_rownorm_bf16(st, tmp, n, d, beta_out));
+    } else {
+      SCS_HIP(hipMemcpy2DAsync(Xt_out, ldt * 4, X, ldx * 4, d * 4, n, hipMemcpyDeviceToDevice, st));
+      if (beta_out) SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta_out));
+    }
+    WS(tmpreg, float, "regtmp", (size_t)d * d);
+    SCS_CHECK(launch_fill_scaled_identity(st, d, std::sqrt((double)n * lambda), xt_bf16, tmpreg,
+                                          beta_out ? beta_out + n : nullptr));
+    SCS_HIP(hipMemcpy2DAsync(reg_out, ldt * (xt_bf16 ? 2 : 4), tmpreg, d * (xt_bf16 ? 2 : 4), d * (xt_bf16 ? 2 : 4), d,
+                             hipMemcpyDeviceToDevice, st));
+    return SCS_OK;
+  }
+  WS(UT, float, "UT_apply", (size_t)k * d);
+  SCS_CHECK(launch_transpose_f32(st, U, d, k, UT));
+  WS(Z, float, "Z_apply", (size_t)n * k);
+  SCS_CHECK(launch_gemm_nt_longk(st, xt_bf16, X, n, d, ldx, UT, k, d, Z, k));
+  return apply_impl(ctx, X, n, d, ldx, U, Z, lam, k, lambda, xt_bf16, xt_bf16, Xt_out, reg_out, ldt, beta_out,
+                    nullptr);
+}
+
+int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                      const float* U, const double* lam, int k, double lambda, const float* wt, float* grad_out,
+                      double* obj_out) {
+  if (!ctx || !y || !wt || !grad_out || k < 0 || k > d || (k > 0 && (!U || !lam))) return SCS_EINVAL;
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  if (k > 256) return SCS_EINVAL;
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const float* UT = nullptr;
+  if (k > 0) {
+    WS(ut, float, "UT_grad", (size_t)k * d);
+    SCS_CHECK(launch_transpose_f32(st, U, d, k, ut));
+    UT = ut;
+  }
+  WS(state, SolveState, "state_grad", 1);
+  SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
+  WS(w32, float, "w32_grad", (size_t)d);
+  WS(tmp, double, "vtmp", (size_t)d);
+  WS(g64, double, "g64", (size_t)d);
+  int nwg = grad_num_workgroups(n, d);
+  WS(part, float, "gpart", (size_t)nwg * d);
+  WS(rsq, double, "grsq", (size_t)nwg);
+  SCS_CHECK(launch_premap(st, UT, U, lam, k, d, lambda, wt, w32, nullptr, tmp, state));
+  SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, part, rsq, nwg, state));
+  WS(wcur, float, "wt_dummy", (size_t)d);
+  SCS_CHECK(launch_grad_finish(st, part, rsq, nwg, n, d, w32, lambda, UT, U, lam, k, grad_out, g64, tmp, state,
+                               SCS_STOP_EPOCHS, 0.0, 0.0, wcur, nullptr, 1));
+  SolveState hs;
+  SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  if (obj_out) *obj_out = hs.obj0;
+  if (hs.status == SCS_ENONFINITE) return SCS_ENONFINITE;
+  return SCS_OK;
+}
+
+int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,
+                   const float* beta, const float* mu, const int32_t* idx, int64_t m, int b, double eta, int average,
+                   int workgroups, float* wt) {
+  if (!ctx || !Xt || !reg || !beta || !mu || !idx || !wt || n < 1 || d < 1 || ldt < d || ldt % 4 != 0 || m < 1 ||
+      b < 1 || b > 64 || !(eta > 0.0))
+    return SCS_EINVAL;
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int64_t N = n + d;
+  WS(cum, uint64_t, "cum", (size_t)N);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
+  WS(state, SolveState, "state_epoch", 1);
+  SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
+  SCS_CHECK(launch_sampler_prepare(st, beta, N, cum, scr, sampler_scratch_len(N), state));
+  WS(scale, float, "scale", (size_t)m * b);
+  SCS_CHECK(launch_index_scale(st, cum, N, n, idx, m * b, scale, state));
+  scs_opts o;
+  scs_opts_default(&o);
+  o.workgroups = workgroups;
+  const int W = choose_workgroups(o, d);
+  WS(xbuf, uint64_t, "xbuf", (size_t)2 * W * 64);
+  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * W * 64, st));
+  InnerArgs a{};
+  a.n = n;
+  a.d = d;
+  a.Xt = Xt;
+  a.ldx = ldt;
+  a.reg = reg;
+  a.ldr = ldt;
+  a.mu = mu;
+  a.idx = idx;
+  a.scale = scale;
+  a.m = m;
+  a.b = b;
+  a.eta = eta;
+  a.eta_from_state = 0;
+  a.average = average;
+  a.W = W;
+  a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+  a.step_base = 0;
+  a.wt = wt;
+  a.wt_prev = nullptr;
+  a.xbuf = xbuf;
+  a.state = state;
+  SCS_CHECK(launch_inner_epoch(st, a, xt_bf16));
+  SolveState hs;
+  SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  if (hs.status == SCS_EDEVICE) {
+    set_error("inner loop: a cross-workgroup wait exceeded its budget");
+    return SCS_EDEVICE;
+  }
+  return SCS_OK;
+}
+
+int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
+                   int k, double eps, const scs_opts* opts, float* w_out, scs_report* report) {
+  if (!ctx || !y || !w_out) {
+    set_error("null argument");
+    return SCS_EINVAL;
+  }
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  const int l = k + o.oversample;
+  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || l > d || l > n || l > 136))) {
+    set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+    return SCS_EINVAL;
+  }
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+      o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX) {
+    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int b = o.batch;
+  const int64_t m = o.steps > 0 ? o.steps : cdiv(2 * n, b);
+  const int64_t N = n + d;
+  const int S = o.max_epochs;
+  const int mixed = o.precision == SCS_PREC_MIXED;
+  const int64_t ldt = cdiv(d, 4) * 4;
+  SCS_CHECK(ensure_events(ctx, (size_t)S + 4 + (o.timing ? 4 * ((size_t)S + 1) : 0)));
+  const int tbase = 3 + S;  // with timing: events tbase + 4s + {0,1} around the gradient pass, {2,3} around the inner loop
+  hipEvent_t ev_start = ctx->events[0], ev_sketch = ctx->events[1], ev_apply = ctx->events[2];
+  SCS_HIP(hipEventRecord(ev_start, st));
+
+  WS(state, SolveState, "state", 1);
+  SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
+
+  // ---- sketch (Alg. 3, Block Lanczos step)
+  int k_used = k;
+  bool rank_def = false;
+  if (k > 0) {
+    SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, &rank_def));
+    if (rank_def) k_used = 0;
+  }
+  SCS_HIP(hipEventRecord(ev_sketch, st));
+
+  // ---- preconditioned rows and smoothness (Alg. 3, x~_i, b_j, beta_i)
+  WS(beta, float, "beta", (size_t)N);
+  const void* Xt = nullptr;
+  int64_t ldxt = ldt;
+  int rows_bf16 = mixed;
+  const float* U32 = nullptr;
+  const float* UT32 = nullptr;
+  const double* lam = nullptr;
+  if (k_used > 0) {
+    void* xt = wsb(ctx, "Xt", (size_t)n * ldt * (mixed ? 2 : 4));
+    void* rg = wsb(ctx, "reg", (size_t)d * ldt * (mixed ? 2 : 4));
+    if (!xt || !rg) return SCS_ENOMEM;
+    U32 = ws<float>(ctx, "U32", 0);
+    UT32 = ws<float>(ctx, "UT32", 0);
+    lam = ws<double>(ctx, "lam", 0);
+    SCS_CHECK(apply_impl(ctx, X, n, d, ldx, U32, ws<float>(ctx, "Z", 0), lam, k_used, lambda, mixed, mixed, xt, rg,
+                         ldt, beta, state));
+    Xt = xt;
+  } else {
+    if (mixed) {
+      WS(xt16, uint16_t, "Xt16", (size_t)n * ldt);
+      WS(tmp, uint16_t, "xcopy16", (size_t)n * d);
+      SCS_CHECK(launch_copy_bf16(st, X, n, d, ldx, tmp));
+      SCS_HIP(hipMemcpy2DAsync(xt16, ldt * 2, tmp, d * 2, d * 2, n, hipMemcpyDeviceToDevice, st));
+      SCS_CHECK(launch_rownorm_bf16(st, tmp, n, d, beta));
+      Xt = xt16;
+    } else if (ldx % 4 == 0 && (uintptr_t)X % 16 == 0) {
+      SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta));
+      Xt = X;
+      ldxt = ldx;
+    } else {
+      WS(xpad, float, "Xpad", (size_t)n * ldt);
+      SCS_HIP(hipMemcpy2DAsync(xpad, ldt * 4, X, ldx * 4, d * 4, n, hipMemcpyDeviceToDevice, st));
+      SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta));
+      Xt = xpad;
+    }
+  }
+  void* reg = nullptr;
+  if (k_used > 0) {
+    reg = ws<char>(ctx, "reg", 0);
+  } else {
+    WS(rtmp, float, "regtmp", (size_t)d * d);
+    SCS_CHECK(launch_fill_scaled_identity(st, d, std::sqrt((double)n * lambda), mixed, rtmp, beta + n));
+    reg = wsb(ctx, "reg", (size_t)d * ldt * (mixed ? 2 : 4));
+    if (!reg) return SCS_ENOMEM;
+    SCS_HIP(hipMemcpy2DAsync(reg, ldt * (mixed ? 2 : 4), rtmp, d * (mixed ? 2 : 4), d * (mixed ? 2 : 4), d,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  // ---- sampling weights (Alg. 1: q_i = beta_i / sum beta)
+  WS(cum, uint64_t, "cum", (size_t)N);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
+  SCS_CHECK(launch_sampler_prepare(st, beta, N, cum, scr, sampler_scratch_len(N), state));
+  SCS_HIP(hipEventRecord(ev_apply, st));
+
+  // ---- SVRG epochs (Alg. 1)
+  const int W = choose_workgroups(o, d);
+  WS(wt, float, "wt", (size_t)d);
+  WS(wt_prev, float, "wt_prev", (size_t)d);
+  WS(w32, float, "w32", (size_t)d);
+  WS(mu, float, "mu", (size_t)d);
+  WS(tmp, double, "vtmp", (size_t)d);
+  WS(g64, double, "g64", (size_t)d);
+  const int nwg = grad_num_workgroups(n, d);
+  WS(gpart, float, "gpart", (size_t)nwg * d);
+  WS(grsq, double, "grsq", (size_t)nwg);
+  WS(idxb, int32_t, "idx", (size_t)m * b);
+  WS(scale, float, "scale", (size_t)m * b);
+  WS(xbuf, uint64_t, "xbuf", (size_t)2 * W * 64);
+  SCS_HIP(hipMemsetAsync(wt, 0, sizeof(float) * d, st));
+  SCS_HIP(hipMemsetAsync(wt_prev, 0, sizeof(float) * d, st));
+  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * W * 64, st));
+
+  InnerArgs a{};
+  a.n = n;
+  a.d = d;
+  a.Xt = Xt;
+  a.ldx = ldxt;
+  a.reg = reg;
+  a.ldr = ldt;
+  a.mu = mu;
+  a.scale = scale;
+  a.m = m;
+  a.b = b;
+  a.eta_from_state = 1;
+  a.step_scale = o.step_scale;
+  a.average = o.average;
+  a.W = W;
+  a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+  a.wt = wt;
+  a.wt_prev = wt_prev;
+  a.xbuf = xbuf;
+  a.state = state;
+
+  for (int s = 0; s <= S; ++s) {
+    float* trace_row = (o.trace_w && s < S) ? o.trace_w + (int64_t)s * d : nullptr;
+    SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w32, trace_row, tmp, state));
+    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s], st));
+    SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
+    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 1], st));
+    SCS_CHECK(launch_grad_finish(st, gpart, grsq, nwg, n, d, w32, lambda, UT32, U32, lam, k_used, mu, g64, tmp, state,
+                                 o.stop_rule, eps, o.f_star, wt, wt_prev, s == 0 ? 1 : 0));
+    if (s == S) break;
+    const int32_t* idx_s;
+    if (o.indices) {
+      idx_s = o.indices + (int64_t)s * m * b;
+      SCS_CHECK(launch_index_scale(st, cum, N, n, idx_s, m * b, scale, state));
+    } else {
+      SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s, m * b, idxb, scale, state));
+      idx_s = idxb;
+    }
+    a.idx = idx_s;
+    a.step_base = (uint32_t)((uint64_t)s * (uint64_t)m);
+    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 2], st));
+    SCS_CHECK(launch_inner_epoch(st, a, rows_bf16));
+    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 3], st));
+    SCS_HIP(hipEventRecord(ctx->events[3 + s], st));
+  }
+  // w = P^{-1/2} w~ with the same routine that produced the gradient's evaluation point
+  SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w_out, nullptr, tmp, nullptr));
+  SolveState hs;
+  SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+
+  int status = SCS_OK;
+  if (hs.status == SCS_ENONFINITE || hs.status == SCS_EDEVICE) {
+    if (hs.status == SCS_EDEVICE) set_error("inner loop: a cross-workgroup wait exceeded its budget");
+    else set_error("non-finite value in X or y");
+    status = hs.status;
+  } else if (hs.status == SCS_DIVERGED) {
+    status = SCS_DIVERGED;
+  } else if (o.stop_rule != SCS_STOP_EPOCHS && !hs.done) {
+    status = SCS_NOT_CONVERGED;
+  } else if (rank_def) {
+    status = SCS_SKETCH_RANK_DEFICIENT;
+  }
+  if (o.epoch_ms) {
+    for (int s = 0; s < S; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev_start, ctx->events[3 + s]) != hipSuccess) ms = -1.f;
+      o.epoch_ms[s] = ms;
+    }
+  }
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->status = status;
+    report->epochs = hs.epochs;
+    report->k_used = k_used;
+    report->steps = m;
+    report->eta = hs.eta;
+    report->beta_hat = hs.beta_sum / (double)n;  // (1/(n+d)) sum beta_i with beta_i = (n+d)/n ||a_i||^2
+    report->objective = hs.obj;
+    report->grad_norm = std::sqrt(hs.gnorm2);
+    report->certificate = hs.cert;
+    report->lam_top = hs.lam_top;
+    float t1 = 0, t2 = 0, t3 = 0;
+    hipEventElapsedTime(&t1, ev_start, ev_sketch);
+    hipEventElapsedTime(&t2, ev_sketch, ev_apply);
+    hipEventElapsedTime(&t3, ev_apply, ctx->events[3 + S - 1]);
+    report->ms_sketch = t1;
+    report->ms_apply = t2;
+    report->ms_solve = t3;
+    if (o.timing) {
+      // launches that did work: the inner loops of hs.epochs epochs and the gradient passes before them
+      // (plus the final evaluation when every epoch ran)
+      int ng = std::min(S + 1, hs.epochs + 1), ni = hs.epochs;
+      double sg = 0.0, si = 0.0;
+      for (int s = 0; s < ng; ++s) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->events[tbase + 4 * s], ctx->events[tbase + 4 * s + 1]);
+        sg += ms;
+      }
+      for (int s = 0; s < ni; ++s) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->events[tbase + 4 * s + 2], ctx->events[tbase + 4 * s + 3]);
+        si += ms;
+      }
+      report->ms_grad = sg;
+      report->ms_inner = si;
+      report->n_grad = ng;
+      report->n_inner = ni;
+    }
+  }
+  return status;
+}
+
+int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,
+                           const int64_t* ldx, const float* const* y, const double* lambda, const int* k, double eps,
+                           const scs_opts* opts, float* const* w_out, scs_report* reports) {
+  (void)ctx; (void)nprob; (void)X; (void)n; (void)d; (void)ldx; (void)y; (void)lambda; (void)k; (void)eps;
+  (void)opts; (void)w_out; (void)reports;
+  set_error("batched solve: not built yet");
+  return SCS_EINVAL;
+}
+
+}  // extern "C"

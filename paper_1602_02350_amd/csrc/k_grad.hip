@@ -1,0 +1,204 @@
+// Full-gradient pass of SVRG (Alg. 1, the gradient at the snapshot), streamed from HBM once:
+//   r_i = x_i^T w - y_i,   g_partial = sum_i r_i x_i,   rsq_partial = sum_i r_i^2
+// over a contiguous block of rows per workgroup. Each row is read once into registers, used
+// for its dot product and then for the accumulation (the two GEMV halves are fused).
+// One wave owns one row at a time; lane l holds columns (c*64 + l)*VEC + v, so the per-lane
+// gradient accumulator covers the same columns for every row. Accumulation is compensated
+// (Kahan) in FP32; workgroup partials are summed in FP64 by grad_finish.
+#include "scs_internal.h"
+
+namespace scs {
+
+namespace {
+
+constexpr int kGradThreads = 256;
+constexpr int kGradWaves = kGradThreads / 64;
+
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<4> {
+  using T = float4;
+};
+template <>
+struct VecT<1> {
+  using T = float;
+};
+
+__device__ __forceinline__ void vload(const float* p, float4& v) { v = *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void vload(const float* p, float& v) { v = *p; }
+__device__ __forceinline__ float comp(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+__device__ __forceinline__ float comp(const float& v, int) { return v; }
+
+template <int VEC, int NCH>
+__global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float* __restrict__ X, int64_t n,
+                                                                    int64_t d, int64_t ldx,
+                                                                    const float* __restrict__ y,
+                                                                    const float* __restrict__ w,
+                                                                    float* __restrict__ part,
+                                                                    double* __restrict__ rsq_part,
+                                                                    const SolveState* state) {
+  if (state && state->done) return;
+  using V = typename VecT<VEC>::T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t rows_per_wg = cdiv(n, (int64_t)gridDim.x);
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
+
+  float wv[NCH][VEC], acc[NCH][VEC], cmp[NCH][VEC];
+  bool valid[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    int64_t col = (int64_t)(c * 64 + lane) * VEC;
+    valid[c] = col < d;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      wv[c][v] = valid[c] ? w[col + v] : 0.f;
+      acc[c][v] = 0.f;
+      cmp[c][v] = 0.f;
+    }
+  }
+  double rsq = 0.0;
+
+  int64_t r = r0 + wave;
+  // two rows in flight per wave
+  for (; r + kGradWaves < r1; r += 2 * kGradWaves) {
+    V xa[NCH], xb[NCH];
+    const float* pa = X + r * ldx;
+    const float* pb = X + (r + kGradWaves) * ldx;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int64_t col = (int64_t)(c * 64 + lane) * VEC;
+      if (valid[c]) {
+        vload(pa + col, xa[c]);
+        vload(pb + col, xb[c]);
+      } else {
+        xa[c] = V{};
+        xb[c] = V{};
+      }
+    }
+    float ya = y[r], yb = y[r + kGradWaves];
+    float da = 0.f, db = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        da = fmaf(comp(xa[c], v), wv[c][v], da);
+        db = fmaf(comp(xb[c], v), wv[c][v], db);
+      }
+    da = warp_sum(da) - ya;
+    db = warp_sum(db) - yb;
+    rsq += (double)da * da + (double)db * db;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        // Kahan: acc += da*xa + db*xb with the rounding error carried in cmp
+        float t1 = fmaf(da, comp(xa[c], v), -cmp[c][v]);
+        float s1 = acc[c][v] + t1;
+        cmp[c][v] = (s1 - acc[c][v]) - t1;
+        acc[c][v] = s1;
+        float t2 = fmaf(db, comp(xb[c], v), -cmp[c][v]);
+        float s2 = acc[c][v] + t2;
+        cmp[c][v] = (s2 - acc[c][v]) - t2;
+        acc[c][v] = s2;
+      }
+  }
+  for (; r < r1; r += kGradWaves) {
+    V xa[NCH];
+    const float* pa = X + r * ldx;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int64_t col = (int64_t)(c * 64 + lane) * VEC;
+      if (valid[c]) vload(pa + col, xa[c]);
+      else xa[c] = V{};
+    }
+    float da = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) da = fmaf(comp(xa[c], v), wv[c][v], da);
+    da = warp_sum(da) - y[r];
+    rsq += (double)da * da;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        float t1 = fmaf(da, comp(xa[c], v), -cmp[c][v]);
+        float s1 = acc[c][v] + t1;
+        cmp[c][v] = (s1 - acc[c][v]) - t1;
+        acc[c][v] = s1;
+      }
+  }
+
+  // combine the waves of the workgroup through LDS (fixed order: wave 0 + 1 + 2 + 3)
+  __shared__ float sbuf[kGradWaves - 1][NCH * 64 * VEC];
+  __shared__ double srsq[kGradWaves];
+  if (lane == 0) srsq[wave] = rsq;
+  if (wave > 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) sbuf[wave - 1][(c * 64 + lane) * VEC + v] = acc[c][v] - cmp[c][v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float* out = part + (int64_t)blockIdx.x * d;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int64_t col = (int64_t)(c * 64 + lane) * VEC;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        float s = acc[c][v] - cmp[c][v];
+        for (int q = 0; q < kGradWaves - 1; ++q) s += sbuf[q][(c * 64 + lane) * VEC + v];
+        if (valid[c] && col + v < d) out[col + v] = s;
+      }
+    }
+    if (lane == 0) {
+      double t = 0.0;
+      for (int q = 0; q < kGradWaves; ++q) t += srsq[q];
+      rsq_part[blockIdx.x] = t;
+    }
+  }
+}
+
+template <int VEC, int NCH>
+int launch_t(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, const float* w,
+             float* part, double* rsq_part, int nwg, const SolveState* state) {
+  grad_partial_kernel<VEC, NCH><<<nwg, kGradThreads, 0, st>>>(X, n, d, ldx, y, w, part, rsq_part, state);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+}  // namespace
+
+int grad_num_workgroups(int64_t n, int64_t d) {
+  (void)d;
+  int64_t want = 1024;  // 4 per CU on 256 CUs
+  int64_t by_rows = cdiv(n, 8);
+  return (int)(want < by_rows ? want : (by_rows < 1 ? 1 : by_rows));
+}
+
+int launch_grad_partial(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                        const float* w, float* part, double* rsq_part, int nwg, const SolveState* state) {
+  bool vec4 = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  if (vec4) {
+    int64_t nch = cdiv(d, 256);
+    if (nch <= 1) return launch_t<4, 1>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 2) return launch_t<4, 2>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 4) return launch_t<4, 4>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 8) return launch_t<4, 8>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 20) return launch_t<4, 20>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+  } else {
+    int64_t nch = cdiv(d, 64);
+    if (nch <= 1) return launch_t<1, 1>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 2) return launch_t<1, 2>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 4) return launch_t<1, 4>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 8) return launch_t<1, 8>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 16) return launch_t<1, 16>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+  }
+  set_error("full gradient: d too large for the register-resident row layout");
+  return SCS_EINVAL;
+}
+
+}  // namespace scs

@@ -1,0 +1,321 @@
+// Small kernels on d-vectors and k-vectors around the two streaming passes:
+//  * the preconditioner on a vector, P^{-1/2} v = v/s + U~ (D (U~^T v)) (Eq. (condSketch)),
+//    used both to evaluate the gradient at w = P^{-1/2} w~ and to return w (Eq. (condRidge));
+//    because the same routine produces the point where the gradient is evaluated and the
+//    returned weights, rounding in U~ moves neither the fixed point nor the output;
+//  * the finish of the full-gradient pass (FP64 cross-workgroup sums, mu = P^{-1/2} g, the
+//    objective, the stop rules and divergence handling);
+//  * row norms, BF16 copies, the scaled identity (regularizer rows of plain SVRG),
+//    lifting Ritz vectors (U~ = Q V_k) and the preconditioner's scalars.
+#include "scs_internal.h"
+
+namespace scs {
+
+namespace {
+
+constexpr int kVecThreads = 1024;
+constexpr int kVecWaves = kVecThreads / 64;
+
+__device__ __forceinline__ double block_sum_d(double v, double* sred) {
+  v = warp_sum_d(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sred[q];
+  return t;
+}
+
+// out_j = v_j/s + sum_i U[j][i] D_i (sum_l UT[i][l] v_l); k = 0 gives out = v.
+// UT is k x d, U is d x k (FP32). tbuf: k doubles of LDS.
+template <typename VIN>
+__device__ void pmhalf_apply_block(const float* __restrict__ UT, const float* __restrict__ U,
+                                   const double* __restrict__ lam, int k, int64_t d, double lambda,
+                                   const VIN* __restrict__ v, double* __restrict__ out, double* tbuf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (k == 0) {
+    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) out[j] = (double)v[j];
+    __syncthreads();
+    return;
+  }
+  const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  for (int i = wave; i < k; i += kVecWaves) {
+    double acc = 0.0;
+    const float* row = UT + (int64_t)i * d;
+    for (int64_t j = lane; j < d; j += 64) acc += (double)row[j] * (double)v[j];
+    acc = warp_sum_d(acc);
+    if (lane == 0) tbuf[i] = acc * (1.0 / sqrt(fmax(lam[i], 0.0) + lambda) - 1.0 / s);
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    double acc = 0.0;
+    const float* urow = U + j * k;
+    for (int i = 0; i < k; ++i) acc += (double)urow[i] * tbuf[i];
+    out[j] = (double)v[j] / s + acc;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, const float* U, const double* lam,
+                                                             int k, int64_t d, double lambda, const float* wt,
+                                                             float* w, float* trace_row, double* tmp,
+                                                             const SolveState* state) {
+  if (state && state->done) return;
+  __shared__ double tbuf[256];
+  pmhalf_apply_block<float>(UT, U, lam, k, d, lambda, wt, tmp, tbuf);
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    float x = (float)tmp[j];
+    w[j] = x;
+    if (trace_row) trace_row[j] = x;
+  }
+}
+
+// g_j = (1/n) sum over workgroup partials (FP64, fixed order) + lambda w_j
+__global__ void grad_colreduce_kernel(const float* part, int nwg, int64_t n, int64_t d, const float* w,
+                                      double lambda, double* g, const SolveState* state) {
+  if (state && state->done) return;
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  double acc = 0.0;
+  for (int q = 0; q < nwg; ++q) acc += (double)part[(int64_t)q * d + j];
+  g[j] = acc / (double)n + lambda * (double)w[j];
+}
+
+__global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
+    const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w, double lambda,
+    const float* UT, const float* U, const double* lam, int k, float* mu, double* tmp, SolveState* state,
+    int stop_rule, double eps, double f_star, float* wt_cur, const float* wt_prev, int first) {
+  if (state->done) return;
+  __shared__ double tbuf[256];
+  __shared__ double sred[kVecWaves];
+  __shared__ int s_action;
+  // mu = P^{-1/2} g
+  pmhalf_apply_block<double>(UT, U, lam, k, d, lambda, g_in, tmp, tbuf);
+  double gn = 0.0, wn = 0.0;
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    double m = tmp[j];
+    gn += m * m;
+    double wj = (double)w[j];
+    wn += wj * wj;
+  }
+  gn = block_sum_d(gn, sred);
+  wn = block_sum_d(wn, sred);
+  double rs = 0.0;
+  for (int q = threadIdx.x; q < nwg; q += blockDim.x) rs += rsq_part[q];
+  rs = block_sum_d(rs, sred);
+  if (threadIdx.x == 0) {
+    double obj = rs / (2.0 * (double)n) + 0.5 * lambda * wn;
+    double lam_top = k > 0 ? fmax(lam[0], 0.0) : 0.0;
+    double cert = gn * (lam_top + lambda) / (2.0 * lambda);
+    bool finite = isfinite(obj) && isfinite(gn);
+    int action = 0;  // 0 = continue, 1 = stop (converged), 2 = diverged (restore), 3 = non-finite input
+    if (first) {
+      if (!finite) action = 3;
+      else state->obj0 = obj;
+    } else if (!finite || obj > 10.0 * state->obj0) {
+      action = 2;
+    }
+    if (action == 0) {
+      state->obj = obj;
+      state->gnorm2 = gn;
+      state->cert = cert;
+      if (stop_rule == SCS_STOP_CERTIFICATE && cert <= eps) action = 1;
+      if (stop_rule == SCS_STOP_GAP && obj - f_star <= eps) action = 1;
+    }
+    if (action == 1) {
+      state->done = 1;
+      state->status = SCS_OK;
+    } else if (action == 2) {
+      state->done = 1;
+      state->status = SCS_DIVERGED;
+    } else if (action == 3) {
+      state->done = 1;
+      state->status = SCS_ENONFINITE;
+    }
+    s_action = action;
+  }
+  __syncthreads();
+  if (s_action == 2 && wt_prev) {
+    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) wt_cur[j] = wt_prev[j];
+  }
+  if (s_action == 0 || s_action == 1) {
+    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) mu[j] = (float)tmp[j];
+  }
+}
+
+__global__ void rownorm_kernel(const float* X, int64_t n, int64_t d, int64_t ldx, float* out) {
+  int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const float* p = X + r * ldx;
+  float acc = 0.f;
+  for (int64_t j = lane; j < d; j += 64) acc = fmaf(p[j], p[j], acc);
+  acc = warp_sum(acc);
+  if (lane == 0) out[r] = acc;
+}
+
+__global__ void rownorm_bf16_kernel(const uint16_t* X, int64_t n, int64_t d, float* out) {
+  int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const uint16_t* p = X + r * d;
+  float acc = 0.f;
+  for (int64_t j = lane; j < d; j += 64) {
+    float x = bf16_to_f32(p[j]);
+    acc = fmaf(x, x, acc);
+  }
+  acc = warp_sum(acc);
+  if (lane == 0) out[r] = acc;
+}
+
+__global__ void copy_bf16_kernel(const float* X, int64_t n, int64_t d, int64_t ldx, uint16_t* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  int64_t r = e / d, c = e - r * d;
+  out[e] = f32_to_bf16(X[r * ldx + c]);
+}
+
+__global__ void fill_identity_kernel(int64_t d, float alpha, int bf16, void* out, float* beta_reg) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d * d) return;
+  int64_t r = e / d, c = e - r * d;
+  float v = r == c ? alpha : 0.f;
+  if (bf16) {
+    uint16_t h = f32_to_bf16(v);
+    reinterpret_cast<uint16_t*>(out)[e] = h;
+    if (r == c && beta_reg) {
+      float q = bf16_to_f32(h);
+      beta_reg[r] = q * q;
+    }
+  } else {
+    reinterpret_cast<float*>(out)[e] = v;
+    if (r == c && beta_reg) beta_reg[r] = v * v;
+  }
+}
+
+__global__ void transpose_kernel(const float* A, int64_t rows, int64_t cols, float* AT) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  int64_t r = e / cols, c = e - r * cols;
+  AT[c * rows + r] = A[e];
+}
+
+// U~ = Q V_k with the columns of V taken in descending order of theta; lam = max(theta, 0).
+__global__ void lift_kernel(const double* Q, int64_t d, int l, const double* V, const int* order, int k,
+                            const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < d * k) {
+    int64_t j = e / k;
+    int i = (int)(e - j * k);
+    int col = order[i];
+    double acc = 0.0;
+    for (int c = 0; c < l; ++c) acc += Q[j * l + c] * V[(int64_t)c * l + col];
+    if (U64) U64[j * k + i] = acc;
+    U32[j * k + i] = (float)acc;
+    UT32[(int64_t)i * d + j] = (float)acc;
+  }
+  if (e < (int64_t)k * l) {
+    int i = (int)(e / l), c = (int)(e - (int64_t)i * l);
+    VkT[e] = (float)V[(int64_t)c * l + order[i]];
+  }
+  if (e < k) lam[e] = fmax(theta[order[e]], 0.0);
+}
+
+// s = sqrt(lam_k + lambda); D_i = 1/sqrt(lam_i + lambda) - 1/s; UD = U diag(D);
+// scal[0] = 1/s (row scale of the apply), scal[1] = sqrt(n lambda)/s (diagonal of the regularizer rows).
+__global__ void precond_setup_kernel(const double* lam, int k, double lambda, int64_t n, const float* U32,
+                                     int64_t d, float* UD, double* scal, SolveState* state) {
+  double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < d * k) {
+    int i = (int)(e % k);
+    double D = 1.0 / sqrt(fmax(lam[i], 0.0) + lambda) - 1.0 / s;
+    UD[e] = (float)((double)U32[e] * D);
+  }
+  if (e == 0) {
+    scal[0] = 1.0 / s;
+    scal[1] = sqrt((double)n * lambda) / s;
+    if (state) {
+      state->s = s;
+      state->lam_top = fmax(lam[0], 0.0);
+    }
+  }
+}
+
+}  // namespace
+
+int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
+                  double lambda, const float* wt, float* w, float* trace_row, double* tmp,
+                  const SolveState* state) {
+  premap_kernel<<<1, kVecThreads, 0, st>>>(UT, U, lam, k, d, lambda, wt, w, trace_row, tmp, state);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part, int nwg, int64_t n, int64_t d,
+                       const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
+                       float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
+                       double f_star, float* wt_cur, const float* wt_prev, int first) {
+  grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 256)), dim3(256), 0, st>>>(part, nwg, n, d, w, lambda, g_tmp,
+                                                                             state);
+  SCS_HIP(hipGetLastError());
+  grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, U, lam, k, mu, tmp,
+                                                  state, stop_rule, eps, f_star, wt_cur, wt_prev, first);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_rownorm(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, float* out) {
+  if (n <= 0) return SCS_OK;
+  rownorm_kernel<<<dim3((unsigned)cdiv(n, 4)), dim3(256), 0, st>>>(X, n, d, ldx, out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_rownorm_bf16(hipStream_t st, const uint16_t* X, int64_t n, int64_t d, float* out) {
+  if (n <= 0) return SCS_OK;
+  rownorm_bf16_kernel<<<dim3((unsigned)cdiv(n, 4)), dim3(256), 0, st>>>(X, n, d, out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_copy_bf16(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, uint16_t* out) {
+  if (n * d <= 0) return SCS_OK;
+  copy_bf16_kernel<<<dim3((unsigned)cdiv(n * d, 256)), dim3(256), 0, st>>>(X, n, d, ldx, out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_transpose_f32(hipStream_t st, const float* A, int64_t rows, int64_t cols, float* AT) {
+  if (rows * cols <= 0) return SCS_OK;
+  transpose_kernel<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, st>>>(A, rows, cols, AT);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_fill_scaled_identity(hipStream_t st, int64_t d, double alpha, int bf16, void* out, float* beta_reg) {
+  fill_identity_kernel<<<dim3((unsigned)cdiv(d * d, 256)), dim3(256), 0, st>>>(d, (float)alpha, bf16, out,
+                                                                               beta_reg);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double* V, const int* order, int k,
+                const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT) {
+  int64_t tot = d * k > (int64_t)k * l ? d * k : (int64_t)k * l;
+  lift_kernel<<<dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, st>>>(Q, d, l, V, order, k, theta, U64, U32, UT32,
+                                                                    lam, VkT);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_precond_setup(hipStream_t st, const double* lam, int k, double lambda, int64_t n, const float* U32,
+                         int64_t d, float* UD, double* scal, SolveState* state) {
+  precond_setup_kernel<<<dim3((unsigned)cdiv(d * k, 256)), dim3(256), 0, st>>>(lam, k, lambda, n, U32, d, UD,
+                                                                               scal, state);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+}  // namespace scs

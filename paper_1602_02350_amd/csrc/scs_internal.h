@@ -1,0 +1,186 @@
+// Internal declarations shared by the HIP sources of libscs (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "scs.h"
+
+namespace scs {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+
+struct Status {
+  int code = SCS_OK;
+};
+
+#define SCS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::scs::set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return SCS_EDEVICE;                                                              \
+    }                                                                                  \
+  } while (0)
+
+#define SCS_CHECK(expr)          \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ < 0) return rc_;     \
+  } while (0)
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ float warp_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double warp_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double warp_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// FP32 -> BF16 with round-to-nearest-even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): 10 rounds of the 4x32 bijection,
+// multipliers 0xD2511F53 / 0xCD9E8D57, key bumped by the Weyl constants between rounds.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)p1;
+    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)p0;
+    c = n;
+  }
+  return c;
+}
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- device-side solver state
+// One record per problem, written by the kernels and read back by the host at the end.
+struct SolveState {
+  int done;          // 1 once the stop rule holds or an error was found: later kernels return at once
+  int status;        // SCS_* outcome
+  int epochs;        // epochs whose inner loop ran
+  int k_used;
+  double obj;        // L at the last evaluated snapshot
+  double obj0;       // L at the first snapshot (divergence reference)
+  double gnorm2;     // ||grad L~||^2 at the last evaluated snapshot
+  double cert;
+  double beta_sum;   // sum_i ||a_i||^2 over the n + d rows
+  double eta;
+  double s;          // sqrt(lam_k + lambda) (1 if k = 0)
+  double lam_top;
+  double wsum;       // total quantized sampling weight (as double, for reporting)
+  double pad[3];
+};
+
+// ---------------------------------------------------------------- launchers (defined in the .hip files)
+// rng
+int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out);
+int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
+                           int64_t scratch_len, SolveState* state);
+int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
+                  int64_t count, int32_t* idx, float* scale, const SolveState* state);
+int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
+                       int64_t count, float* scale, const SolveState* state);
+int64_t sampler_scratch_len(int64_t N);
+
+// gemm (MFMA)
+int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
+                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc);
+int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
+                        const float* Bt, int64_t N, int64_t ldb, float alpha, const float* C0, int64_t ldc0,
+                        float beta, const double* beta_dev, float diag, const double* diag_dev, int out_bf16,
+                        void* C, int64_t ldc, float* rownorm2);
+int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,
+                          const float* B, int64_t N, int64_t ldb, float* partial, int64_t chunk_rows,
+                          int64_t nchunks);
+int launch_reduce_partials_f64(hipStream_t st, const float* partial, int64_t nchunks, int64_t elems,
+                               double scale, double* out);
+// fp64 dense
+int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A, int64_t a_rs,
+                  int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
+                  float* C32, int64_t ldc32);
+int launch_chol_inv64(hipStream_t st, const double* G, int l, double* Rinv, int* flag);
+int launch_jacobi64(hipStream_t st, const double* B, int l, double* Awork, double* V, double* theta, int* order);
+// vector / small kernels
+int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double* V, const int* order, int k,
+                const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT);
+int launch_precond_setup(hipStream_t st, const double* lam, int k, double lambda, int64_t n, const float* U32,
+                         int64_t d, float* UD, double* scal, SolveState* state);
+int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
+                  double lambda, const float* wt, float* w, float* trace_row, double* tmp,
+                  const SolveState* state);
+int launch_rownorm(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, float* out);
+int launch_rownorm_bf16(hipStream_t st, const uint16_t* X, int64_t n, int64_t d, float* out);
+int launch_copy_bf16(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, uint16_t* out);
+int launch_transpose_f32(hipStream_t st, const float* A, int64_t rows, int64_t cols, float* AT);
+int launch_fill_scaled_identity(hipStream_t st, int64_t d, double alpha, int bf16, void* out, float* beta_reg);
+int launch_grad_partial(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                        const float* w, float* part, double* rsq_part, int nwg, const SolveState* state);
+int grad_num_workgroups(int64_t n, int64_t d);
+int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part, int nwg, int64_t n, int64_t d,
+                       const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
+                       float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
+                       double f_star, float* wt_cur, const float* wt_prev, int first);
+
+// inner loop (one persistent launch per epoch)
+struct InnerArgs {
+  int64_t n, d;
+  const void* Xt;      // data rows (index < n), leading dimension ldx
+  int64_t ldx;
+  const void* reg;     // regularizer rows (index >= n), leading dimension ldr
+  int64_t ldr;
+  const float* mu;     // snapshot gradient
+  const int32_t* idx;  // m*b component indices
+  const float* scale;  // m*b values 1/(n q_i)
+  int64_t m;
+  int b;
+  double eta;
+  int eta_from_state;  // 1: eta = step_scale * n / state->beta_sum
+  double step_scale;
+  int average;
+  int W;               // cooperating workgroups
+  int xcd_stride;      // blockIdx stride between cooperating workgroups
+  int64_t slice;       // columns per workgroup (set by the launcher)
+  uint32_t step_base;  // value of the step counters before this epoch
+  float* wt;           // snapshot (in/out)
+  float* wt_prev;      // copy of the incoming snapshot (nullable)
+  uint64_t* xbuf;      // 2 x W x 64 words: (step tag << 32) | partial dot product bits; zeroed per solve
+  SolveState* state;
+};
+int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
+int inner_default_workgroups(int64_t d);
+
+}  // namespace scs

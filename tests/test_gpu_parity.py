@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, kernel by kernel.
+
+Tolerances follow from the arithmetic: FP32 storage and FP32 accumulation over at most a few
+thousand terms give relative errors of a few 1e-6; BF16 operands (8-bit mantissa) give ~1e-2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import precond, ridge, sampling, sketch, svrg
+from paper_1602_02350_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().float().cpu().numpy().astype(np.float64) if t.dtype == torch.bfloat16 else \
+        t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ random numbers
+@pytest.mark.parametrize("count", [1, 7, 4096 * 3 + 5])
+def test_gaussian_matches_oracle(ctx, count):
+    g = host(ctx.gaussian(20160207, count))
+    o = sampling.gaussian(20160207, count).astype(np.float32).astype(np.float64)
+    assert np.max(np.abs(g - o) / np.maximum(np.abs(o), 1e-3)) < 2e-7
+
+
+@pytest.mark.parametrize("N,count,zeros", [(1, 10, 0.0), (1000, 4097, 0.0), (100003, 65543, 0.1)])
+def test_sampler_is_bit_exact(ctx, N, count, zeros):
+    rng = np.random.default_rng(N)
+    beta = rng.gamma(2.0, 1.0, N).astype(np.float32)
+    if zeros:
+        beta[rng.random(N) < zeros] = 0.0
+        beta[0] = 1.0
+    idx = ctx.sample_indices(dev(beta), seed=987654321123, epoch=5, count=count).cpu().numpy()
+    W = sampling.quantize_weights(beta.astype(np.float64))
+    ref = sampling.draw_indices(W, seed=987654321123, epoch=5, count=count)
+    assert np.array_equal(idx, ref)
+
+
+# ------------------------------------------------------------------ sketch
+def _problem(n, d, alpha=1.5, lam=1e-4, seed=1):
+    return inputs.make_ridge(n, d, alpha, lam, seed=seed)
+
+
+@pytest.mark.parametrize("n,d,k,p,mixed", [(700, 40, 6, 5, False), (3000, 130, 20, 5, False),
+                                           (3000, 130, 20, 5, True), (517, 61, 9, 4, False)])
+def test_sketch_matches_oracle_with_the_same_omega(ctx, n, d, k, p, mixed):
+    P = _problem(n, d, seed=n + d)
+    Om = inputs.gaussian((k + p, d), seed=3)                      # Omega^T, (k+p) x d
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om),
+                                       precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+    assert rc == binding.OK
+    Uo, lo, _ = sketch.sketch(P.X.astype(np.float64), Om.T.astype(np.float64), k)
+    lam_g = host(lam)
+    tol = 3e-2 if mixed else 2e-5
+    assert np.all(np.abs(lam_g - lo) <= tol * lo[0])
+    Ug = host(U64)
+    assert np.allclose(Ug.T @ Ug, np.eye(k), atol=1e-6 if not mixed else 1e-5)
+    # compare the preconditioners (invariant to signs and rotations within ties) on probes
+    Pg = precond.sketched_preconditioner(Ug, lam_g, P.lam)
+    Po = precond.sketched_preconditioner(Uo, lo, P.lam)
+    V = np.random.default_rng(0).standard_normal((d, 8))
+    assert rel(Pg @ V, Po @ V) < (5e-2 if mixed else 1e-4)
+
+
+def test_full_width_sketch_is_exact_on_gpu(ctx):
+    """k + p = d: Rayleigh-Ritz on all of R^d returns the eigenvalues of C."""
+    P = _problem(600, 24, alpha=1.0, seed=5)
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), 19, oversample=5)
+    ev = np.sort(np.linalg.eigvalsh(ridge.correlation(P.X.astype(np.float64))))[::-1]
+    assert np.allclose(host(lam), ev[:19], rtol=2e-5, atol=1e-6 * ev[0])
+
+
+def test_rank_deficient_sketch_is_reported(ctx):
+    X = torch.zeros(300, 32, device="cuda")
+    _, _, _, rc = ctx.sketch_build(X, 4)
+    assert rc == binding.SKETCH_RANK_DEFICIENT
+
+
+# ------------------------------------------------------------------ preconditioning
+def _sketch_inputs(d, k, seed):
+    U = inputs.random_orthonormal(d, k, seed)
+    lt = inputs.decreasing_values(k, seed, lo=1e-3, hi=2.0)
+    return U, lt
+
+
+@pytest.mark.parametrize("n,d,k,bf16", [(1000, 64, 8, False), (777, 101, 13, False), (2048, 256, 50, False),
+                                        (1000, 64, 8, True), (300, 40, 0, False)])
+def test_apply_matches_oracle(ctx, n, d, k, bf16):
+    P = _problem(n, d, seed=7 + d)
+    lam_reg = 1e-3
+    if k:
+        U, lt = _sketch_inputs(d, k, seed=d)
+        U32 = U.astype(np.float32)
+        Pm = precond.sketched_preconditioner(U32.astype(np.float64), lt, lam_reg)
+        Xt, reg, beta = ctx.precondition_apply(dev(P.X), dev(U32), dev(lt, torch.float64), lam_reg, bf16=bf16)
+    else:
+        Pm = np.eye(d)
+        Xt, reg, beta = ctx.precondition_apply(dev(P.X), None, None, lam_reg, bf16=bf16)
+    comp = precond.Components(P.X, P.y, lam_reg, Pm)
+    Xt_o = comp.Xt
+    reg_o = np.sqrt(n * lam_reg) * comp.B
+    tol = 1.2e-2 if bf16 else 3e-6
+    row_err = np.linalg.norm(host(Xt) - Xt_o, axis=1) / np.linalg.norm(Xt_o, axis=1)
+    assert row_err.max() < tol
+    assert np.max(np.linalg.norm(host(reg) - reg_o, axis=1) / np.linalg.norm(reg_o, axis=1)) < tol
+    beta_o = np.concatenate([np.sum(Xt_o ** 2, 1), np.sum(reg_o ** 2, 1)])
+    assert np.max(np.abs(host(beta) - beta_o) / beta_o) < 3 * tol
+
+
+def test_apply_with_padded_rows(ctx):
+    P = _problem(500, 30, seed=9)
+    U, lt = _sketch_inputs(30, 4, seed=4)
+    Xt, reg, beta = ctx.precondition_apply(dev(P.X), dev(U.astype(np.float32)), dev(lt, torch.float64), 1e-2,
+                                           ldt=32)
+    Pm = precond.sketched_preconditioner(U.astype(np.float32).astype(np.float64), lt, 1e-2)
+    assert rel(host(Xt)[:, :30], P.X.astype(np.float64) @ Pm) < 3e-6
+
+
+# ------------------------------------------------------------------ full gradient
+@pytest.mark.parametrize("n,d,k", [(1000, 64, 8), (4099, 257, 20), (1001, 30, 0), (20000, 1000, 50),
+                                   (333, 7, 2), (6000, 2048, 0)])
+def test_full_gradient_matches_oracle(ctx, n, d, k):
+    P = _problem(n, d, seed=11 + d)
+    lam_reg = 1e-4
+    wt = inputs.random_vector(d, seed=d)
+    if k:
+        U, lt = _sketch_inputs(d, k, seed=2 * d)
+        U32 = U.astype(np.float32)
+        Pm = precond.sketched_preconditioner(U32.astype(np.float64), lt, lam_reg)
+        g, obj = ctx.full_gradient(dev(P.X), dev(P.y), dev(U32), dev(lt, torch.float64), lam_reg, dev(wt))
+    else:
+        Pm = np.eye(d)
+        g, obj = ctx.full_gradient(dev(P.X), dev(P.y), None, None, lam_reg, dev(wt))
+    comp = precond.Components(P.X, P.y, lam_reg, Pm)
+    wt32 = wt.astype(np.float32).astype(np.float64)
+    go = comp.full_gradient(wt32)
+    assert rel(host(g), go) < 2e-5
+    Lo = ridge.objective(P.X, P.y, lam_reg, Pm @ wt32)
+    assert abs(obj - Lo) <= 2e-6 * Lo
+
+
+def test_full_gradient_flags_non_finite_input(ctx):
+    P = _problem(200, 16, seed=3)
+    X = P.X.copy()
+    X[17, 3] = np.nan
+    with pytest.raises(binding.ScsError) as e:
+        ctx.full_gradient(dev(X), dev(P.y), None, None, 1e-3, dev(np.zeros(16)))
+    assert e.value.code == binding.ENONFINITE
+
+
+# ------------------------------------------------------------------ one SVRG epoch
+@pytest.mark.parametrize("n,d,k,b,W,bf16", [(400, 24, 4, 8, 1, False), (2000, 100, 10, 64, 1, False),
+                                            (2000, 100, 10, 64, 2, False), (1500, 257, 12, 33, 3, False),
+                                            (2000, 100, 10, 64, 1, True), (900, 37, 0, 5, 1, False)])
+def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16):
+    P = _problem(n, d, alpha=2.0, seed=13 + d)
+    lam_reg = 1e-3
+    if k:
+        U, lt = _sketch_inputs(d, k, seed=3 * d)
+        U32 = U.astype(np.float32)
+        Pm = precond.sketched_preconditioner(U32.astype(np.float64), lt, lam_reg)
+        Ud, ltd = dev(U32), dev(lt, torch.float64)
+    else:
+        Pm, Ud, ltd = np.eye(d), None, None
+    Xt, reg, beta = ctx.precondition_apply(dev(P.X), Ud, ltd, lam_reg, bf16=bf16, ldt=((d + 3) // 4) * 4)
+    comp = precond.Components(P.X, P.y, lam_reg, Pm)
+    wt0 = inputs.random_vector(d, seed=5, scale=0.3).astype(np.float32)
+    mu, _ = ctx.full_gradient(dev(P.X), dev(P.y), Ud, ltd, lam_reg, dev(wt0))
+    m = 3 * n // b
+    idx = inputs.index_stream(n + d, m * b, seed=n)
+    eta = 4.0 / svrg.beta_hat(comp)
+    wt = dev(wt0)
+    ctx.svrg_epoch(n, d, Xt, reg, beta, mu, dev(idx, torch.int32), m, b, eta, average=True, workgroups=W, wt=wt)
+    wo, _ = svrg.svrg(comp, wt0.astype(np.float64), m, eta, 1, b, lambda s: idx, average=True)
+    step = wo - wt0
+    tol = 3e-2 if bf16 else 2e-4
+    assert rel(host(wt) - wt0, step) < tol
+
+
+# ------------------------------------------------------------------ whole solve
+def test_solve_with_injected_randomness_tracks_the_oracle(ctx):
+    cfg = inputs.WORKLOADS["small_n2000_d100"]
+    P = inputs.make_ridge(cfg["n"], cfg["d"], cfg["alpha"], cfg["lam"], seed=inputs.BASE_SEED)
+    n, d, k, b = cfg["n"], cfg["d"], cfg["k"], cfg["b"]
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED)
+    m, S = n // b, 4
+    idx = inputs.index_stream(n + d, S * m * b, seed=77).reshape(S, -1)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, omega=dev(Om), indices=dev(idx, torch.int32),
+                         steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=4.0)
+    assert res.status == binding.OK
+    wo, _, info = svrg.scsvrg(X64, y64, cfg["lam"], k, Om.T.astype(np.float64), m, S, b, lambda s: idx[s], c=4.0)
+    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    assert rel(host(res.w) - ws, wo - ws) < 2e-2      # same trajectory to FP32 accuracy of the sketch
+    assert abs(res.report["eta"] - info["eta"]) <= 1e-4 * info["eta"]
+
+
+@pytest.mark.parametrize("k,mixed", [(10, False), (0, False), (10, True)])
+def test_solve_reaches_the_closed_form(ctx, k, mixed):
+    cfg = inputs.WORKLOADS["small_n2000_d100"]
+    P = inputs.make_ridge(cfg["n"], cfg["d"], cfg["alpha"], cfg["lam"], seed=inputs.BASE_SEED)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    Ls = ridge.objective(X64, y64, cfg["lam"], ws)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 1e-8, batch=cfg["b"], max_epochs=60 if k else 200,
+                         stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=8.0 if k else 2.0,
+                         precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+    assert res.status == binding.OK, res.report
+    so = ridge.suboptimality(X64, cfg["lam"], host(res.w), ws)
+    assert so <= 1.5e-8
+
+
+def test_solve_fp32_gate_relative_error(ctx):
+    """FP32 mode reaches ||w - w*|| <= 1e-5 ||w*|| (the certificate stop rule drives it there)."""
+    P = inputs.make_ridge(4000, 120, 1.5, 1e-3, seed=31)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, P.lam)
+    # certificate <= 5e-12 bounds ||w - w*||^2 <= 2 * 5e-12 / lambda_min(C + lam I) ~ 6e-9 here
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 12, 5e-12, batch=32, max_epochs=120,
+                         stop_rule=binding.STOP_CERTIFICATE, step_scale=8.0)
+    assert res.status == binding.OK, res.report
+    assert rel(host(res.w), ws) <= 1e-5
+
+
+def test_divergence_returns_the_last_good_snapshot(ctx):
+    P = inputs.make_ridge(1000, 50, 1.5, 1e-3, seed=32)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 0, 1e-12, batch=16, max_epochs=10, step_scale=1e4,
+                         stop_rule=binding.STOP_EPOCHS)
+    assert res.status == binding.DIVERGED
+    assert torch.isfinite(res.w).all()
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    P = inputs.make_ridge(100, 10, 1.0, 1e-3, seed=33)
+    for lam, k in [(0.0, 2), (-1.0, 2), (1e-3, 11), (1e-3, -1), (1e-3, 8)]:   # k + p > d for k = 8
+        with pytest.raises(binding.ScsError) as e:
+            ctx.svrg_solve(dev(P.X), dev(P.y), lam, k, 1e-6)
+        assert e.value.code == binding.EINVAL
+
+
+def test_non_finite_input_is_reported(ctx):
+    P = inputs.make_ridge(500, 20, 1.0, 1e-3, seed=34)
+    y = P.y.copy()
+    y[3] = np.inf
+    with pytest.raises(binding.ScsError) as e:
+        ctx.svrg_solve(dev(P.X), dev(y), P.lam, 0, 1e-6)
+    assert e.value.code == binding.ENONFINITE
+
+
+def test_epoch_cap_reports_not_converged(ctx):
+    P = inputs.make_ridge(1000, 50, 2.0, 1e-5, seed=35)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 0, 1e-30, max_epochs=2)
+    assert res.status == binding.NOT_CONVERGED
+    assert res.report["epochs"] == 2
