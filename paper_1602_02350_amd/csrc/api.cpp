@@ -509,15 +509,16 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
       Xt = xpad;
     }
   }
+  // regularizer rows share the data rows' leading dimension (the inner loop addresses both from one stride)
   void* reg = nullptr;
   if (k_used > 0) {
     reg = ws<char>(ctx, "reg", 0);
   } else {
     WS(rtmp, float, "regtmp", (size_t)d * d);
     SCS_CHECK(launch_fill_scaled_identity(st, d, std::sqrt((double)n * lambda), mixed, rtmp, beta + n));
-    reg = wsb(ctx, "reg", (size_t)d * ldt * (mixed ? 2 : 4));
+    reg = wsb(ctx, "reg", (size_t)d * ldxt * (mixed ? 2 : 4));
     if (!reg) return SCS_ENOMEM;
-    SCS_HIP(hipMemcpy2DAsync(reg, ldt * (mixed ? 2 : 4), rtmp, d * (mixed ? 2 : 4), d * (mixed ? 2 : 4), d,
+    SCS_HIP(hipMemcpy2DAsync(reg, ldxt * (mixed ? 2 : 4), rtmp, d * (mixed ? 2 : 4), d * (mixed ? 2 : 4), d,
                              hipMemcpyDeviceToDevice, st));
   }
   // ---- sampling weights (Alg. 1: q_i = beta_i / sum beta)
@@ -550,7 +551,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   a.Xt = Xt;
   a.ldx = ldxt;
   a.reg = reg;
-  a.ldr = ldt;
+  a.ldr = ldxt;
   a.mu = mu;
   a.scale = scale;
   a.m = m;

@@ -16,6 +16,8 @@
 // that exceeds its poll budget raises an abort flag that ends every workgroup's loop.
 // Rows of the next step are loaded while the current step's reductions run (the index stream
 // does not depend on the iterate).
+#include <type_traits>
+
 #include "scs_internal.h"
 
 namespace scs {
@@ -26,39 +28,34 @@ namespace {
 
 constexpr int kInnerThreads = 256;
 constexpr uint32_t kPollBudget = 1u << 22;
-constexpr int kMaxPairs = 4;  // exchange words gathered per thread: W * b <= 4 * 256
 
 // Barrier for LDS traffic only: waits for this wave's LDS operations but not for its
 // outstanding global loads (the prefetched rows of the next step stay in flight).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <bool BF16>
-__device__ __forceinline__ float4 row_load(const void* base, int64_t ld, int64_t row, int64_t col, int64_t d) {
-  if constexpr (BF16) {
-    const uint16_t* p = reinterpret_cast<const uint16_t*>(base) + row * ld + col;
-    if (col + 3 < d) {
-      uint2 u = *reinterpret_cast<const uint2*>(p);
-      return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                         __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
-    }
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (col + 0 < d) v.x = bf16_to_f32(p[0]);
-    if (col + 1 < d) v.y = bf16_to_f32(p[1]);
-    if (col + 2 < d) v.z = bf16_to_f32(p[2]);
-    return v;
-  } else {
-    const float* p = reinterpret_cast<const float*>(base) + row * ld + col;
-    if (col + 3 < d) return *reinterpret_cast<const float4*>(p);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (col + 0 < d) v.x = p[0];
-    if (col + 1 < d) v.y = p[1];
-    if (col + 2 < d) v.z = p[2];
-    return v;
-  }
-}
 
 __device__ __forceinline__ float f4get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 
+// Sum of v over the lanes l, l^8, l^16, ..., l^56 (the 8 row groups sharing a column), left in
+// every one of them: DPP row rotation by 8 (xor 8 inside a 16-lane row), then the gfx950 row
+// swaps, which exchange 16-lane rows 0<->1, 2<->3 and 32-lane halves respectively.
+__device__ __forceinline__ float rowgroup_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+  auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
+  auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
+}
+
+// Lane layout: lane = 8 * rg + cl and column thread cgt = 8 * wave + cl, so the 8 row groups that
+// share a column are in one wave and the update's sum over rows is a lane butterfly. Wave 0 also
+// owns the per-step communication: it sums the partial dot products, exchanges them with the
+// other workgroups, publishes the step coefficients and stages the index stream into LDS two
+// steps ahead. Every global load a wave issues is consumed at least one step later, except the
+// exchange polls, so no wait for one load also waits for a load issued after it (loads complete
+// in order per wave). Rows live in a two-slot ring whose roles alternate at compile time.
+// Data rows and regularizer rows share one leading dimension, so a row address is one
+// multiply-add from a base selected by the index range.
 template <int RPT, int CPT, bool BF16>
 __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a) {
   const int bid = blockIdx.x;
@@ -67,32 +64,44 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   if (w >= a.W) return;
   if (a.state->done) return;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cgt = lane & 31;
-  const int rg = wave * 2 + (lane >> 5);
+  constexpr int ES = BF16 ? 2 : 4;          // bytes per element
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index made provably uniform so that wave-0-only work compiles to scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rg = lane >> 3;                 // row group: rows j = rg + 8 q
+  const int cgt = wave * 8 + (lane & 7);    // column thread 0..31
   const int b = a.b, W = a.W;
-  const int64_t NR = a.n + a.d;
+  const uint32_t NR = (uint32_t)(a.n + a.d), n32 = (uint32_t)a.n;
   const int64_t c_begin = (int64_t)w * a.slice;
   const int64_t c_end = c_begin + a.slice < a.d ? c_begin + a.slice : a.d;
+  const int64_t mlast = a.m - 1;
   uint64_t* xb = a.xbuf;
+  const char* xt_base = reinterpret_cast<const char*>(a.Xt);
+  // base for regularizer rows, offset so that row i >= n is at reg_base + i * ld (pointer arithmetic
+  // done on integers; only ever dereferenced for i >= n)
+  const char* reg_base =
+      reinterpret_cast<const char*>((uintptr_t)a.reg - (uintptr_t)a.n * (uintptr_t)a.ldx * (uintptr_t)ES);
+  const uint64_t ldb = (uint64_t)a.ldx * ES;
 
-  __shared__ float pd[64][33];
+  __shared__ float pd[64][36];
   __shared__ float gam[64];
-  __shared__ float xs[16][64];
-  __shared__ float4 red[8][32 * CPT];
+  __shared__ int32_t s_idx[4][8][8];  // [step slot][row group][q]: index of row rg + 8q, staged by wave 0
   __shared__ int s_abort;
 
   float dl[CPT][4], sm[CPT][4], smc[CPT][4], muv[CPT][4], w0[CPT][4];
   int64_t col[CPT];
+  uint64_t colb[CPT];   // byte offset of the 4 columns loaded (inside the slice, a multiple of 4)
+  bool cok[CPT][4];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     col[q] = c_begin + 4 * (cgt + 32 * q);
+    colb[q] = (uint64_t)(col[q] < c_end ? col[q] : c_begin) * ES;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int64_t c = col[q] + v;
-      bool ok = c < c_end;
-      muv[q][v] = ok ? a.mu[c] : 0.f;
-      w0[q][v] = ok ? a.wt[c] : 0.f;
+      cok[q][v] = c < c_end;
+      muv[q][v] = cok[q][v] ? a.mu[c] : 0.f;
+      w0[q][v] = cok[q][v] ? a.wt[c] : 0.f;
       dl[q][v] = 0.f;
       sm[q][v] = 0.f;
       smc[q][v] = 0.f;
@@ -101,46 +110,51 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   const float eta = a.eta_from_state ? (float)(a.step_scale * (double)a.n / a.state->beta_sum) : (float)a.eta;
   if (tid == 0) s_abort = 0;
 
-  // component indices of this thread's rows for a step (0 for rows j >= b)
-  auto load_idx = [&](int64_t t, int32_t (&ix)[RPT]) {
+  // Row loads are unconditional from in-bounds addresses: rows j >= b get coefficient 0 and
+  // columns outside the slice are excluded from the update, so their values never matter.
+  auto load_rows = [&](int slot, float4 (&buf)[RPT][CPT]) {
+    const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][0]);
+    const int4 i1 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][4]);
+    const int32_t ix[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      int j = rg + 8 * q;
-      int32_t i = (j < b && t < a.m) ? a.idx[t * b + j] : 0;
-      ix[q] = ((uint64_t)(int64_t)i >= (uint64_t)NR) ? 0 : i;  // out-of-range injected index: stay in bounds
-    }
-  };
-  auto load_rows = [&](const int32_t (&ix)[RPT], float4 (&buf)[RPT][CPT]) {
+      const uint32_t i = (uint32_t)ix[q] < NR ? (uint32_t)ix[q] : 0u;
+      const char* rowp = (i < n32 ? xt_base : reg_base) + (uint64_t)i * ldb;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      int j = rg + 8 * q;
-      int64_t i = ix[q];
-      const void* base = i < a.n ? a.Xt : a.reg;
-      int64_t ld = i < a.n ? a.ldx : a.ldr;
-      int64_t row = i < a.n ? i : i - a.n;
-#pragma unroll
-      for (int c = 0; c < CPT; ++c)
-        buf[q][c] = (j < b && col[c] < c_end) ? row_load<BF16>(base, ld, row, col[c], c_end)
-                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int c = 0; c < CPT; ++c) {
+        if constexpr (BF16) {
+          uint2 u = *reinterpret_cast<const uint2*>(rowp + colb[c]);
+          buf[q][c] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                                  __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+        } else {
+          buf[q][c] = *reinterpret_cast<const float4*>(rowp + colb[c]);
+        }
+      }
     }
   };
 
-  float4 cur[RPT][CPT], nxt[RPT][CPT];
-  int32_t ix_next[RPT];
-  {
-    int32_t ix0[RPT];
-    load_idx(0, ix0);
-    load_rows(ix0, cur);
-    load_idx(1, ix_next);
+  const int jj = lane < b ? lane : b - 1;
+  const int srg = lane & 7, sq = lane >> 3;  // where wave 0 lane j stages index j (j = srg + 8 sq)
+  // wave 0, two-slot rings alternating like the row buffers: a step consumes idxX (index of step
+  // t+2) and scX (scale of step t), both loaded one step earlier, and loads the other slot
+  int32_t idxA = 0, idxB = 0;
+  float scA = 0.f, scB = 0.f;
+  if (wave == 0) {
+    s_idx[0][srg][sq] = lane < b ? a.idx[lane] : 0;
+    s_idx[1][srg][sq] = lane < b ? a.idx[(1 < mlast ? 1 : mlast) * b + lane] : 0;
+    idxA = a.idx[(2 < mlast ? 2 : mlast) * b + jj];
+    scA = a.scale[jj];
   }
-  float sc_cur = (tid < b) ? a.scale[tid] : 0.f;
   lds_barrier();
-  for (int64_t t = 0; t < a.m; ++t) {
-    // prefetch: rows of step t+1 (indices loaded one step ago), indices of step t+2
-    if (t + 1 < a.m) load_rows(ix_next, nxt);
-    load_idx(t + 2, ix_next);
-    const float sc_next = (tid < b && t + 1 < a.m) ? a.scale[(t + 1) * b + tid] : 0.f;
-    // partial dot products over this workgroup's columns
+  float4 bufA[RPT][CPT], bufB[RPT][CPT];
+  load_rows(0, bufA);
+
+  // One inner step t on rows `cur`, prefetching the rows of step t+1 into `nxt`.
+  // Returns false when the epoch must stop (abort).
+  auto step = [&](int64_t t, float4 (&cur)[RPT][CPT], float4 (&nxt)[RPT][CPT], int32_t& idx_use, int32_t& idx_next,
+                  float& sc_use, float& sc_next) -> bool {
+    load_rows((int)((t + 1) & 3), nxt);
+    // partial dot products over this workgroup's columns (delta is 0 outside the slice)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       float p = 0.f;
@@ -148,121 +162,96 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
       for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) p = fmaf(f4get(cur[q][c], v), dl[c][v], p);
-      int j = rg + 8 * q;
-      if (j < b) pd[j][cgt] = p;
+      pd[rg + 8 * q][cgt] = p;
     }
     lds_barrier();
-    float cl = 0.f;
-    if (tid < b) {
-#pragma unroll 8
-      for (int g = 0; g < 32; ++g) cl += pd[tid][g];
-    }
-    if (W > 1) {
-      // post (value, step tag) as one 64-bit word, then gather all W x b words in parallel;
-      // a word is valid once its tag equals this step's, so no fence is needed
-      const int par = (int)(t & 1);
-      const uint32_t target = a.step_base + (uint32_t)t + 1u;
-      uint64_t* slot = xb + (int64_t)par * W * 64;
-      if (tid < b)
-        __hip_atomic_store(&slot[(int64_t)w * 64 + tid], ((uint64_t)target << 32) | __float_as_uint(cl),
+    if (wave == 0) {
+      const int j = lane;
+      float cl = 0.f;
+#pragma unroll
+      for (int g = 0; g < 32; g += 4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(&pd[j][g]);
+        cl += (v4.x + v4.y) + (v4.z + v4.w);
+      }
+      if (W > 1) {
+        // post (step tag, value) as one 64-bit word; gather the W words of row j; a word is
+        // valid once its tag is this step's, so no fence is needed
+        const int par = (int)(t & 1);
+        const uint32_t target = a.step_base + (uint32_t)t + 1u;
+        uint64_t* slot = xb + (int64_t)par * W * 64;
+        __hip_atomic_store(&slot[(int64_t)w * 64 + j], ((uint64_t)target << 32) | __float_as_uint(cl),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint64_t xv[kMaxPairs];
-      bool need[kMaxPairs];
+        uint64_t xv[16];
 #pragma unroll
-      for (int q = 0; q < kMaxPairs; ++q) {
-        int pidx = tid + kInnerThreads * q;
-        need[q] = pidx < W * b;
-        xv[q] = 0;
-        if (need[q]) {
-          int v = pidx / b, j = pidx - v * b;
-          xv[q] = __hip_atomic_load(&slot[(int64_t)v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      uint32_t polls = 0;
-      bool bad = false;
-      for (;;) {
-        bool pending = false;
+        for (int v = 0; v < 16; ++v)
+          xv[v] = v < W ? __hip_atomic_load(&slot[v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : ((uint64_t)target << 32);
+        uint32_t polls = 0;
+        bool bad = false;
+        for (;;) {
+          bool pending = false;
 #pragma unroll
-        for (int q = 0; q < kMaxPairs; ++q) pending |= need[q] && (uint32_t)(xv[q] >> 32) != target;
-        if (!pending) break;
-        if (++polls > kPollBudget ||
-            __hip_atomic_load(&a.state->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SCS_EDEVICE) {
-          bad = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int q = 0; q < kMaxPairs; ++q) {
-          if (need[q] && (uint32_t)(xv[q] >> 32) != target) {
-            int pidx = tid + kInnerThreads * q;
-            int v = pidx / b, j = pidx - v * b;
-            xv[q] = __hip_atomic_load(&slot[(int64_t)v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int v = 0; v < 16; ++v) pending |= (uint32_t)(xv[v] >> 32) != target;
+          if (!pending) break;
+          if ((++polls & 1023u) == 0 &&
+              (polls > kPollBudget ||
+               __hip_atomic_load(&a.state->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SCS_EDEVICE)) {
+            bad = true;
+            break;
           }
-        }
-      }
-      if (bad) {
-        s_abort = 1;
-        __hip_atomic_store(&a.state->status, SCS_EDEVICE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.state->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
 #pragma unroll
-      for (int q = 0; q < kMaxPairs; ++q) {
-        if (need[q]) {
-          int pidx = tid + kInnerThreads * q;
-          int v = pidx / b, j = pidx - v * b;
-          xs[v][j] = __uint_as_float((uint32_t)xv[q]);
+          for (int v = 0; v < 16; ++v)
+            if ((uint32_t)(xv[v] >> 32) != target)
+              xv[v] = __hip_atomic_load(&slot[v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        if (__any(bad) && lane == 0) {
+          s_abort = 1;
+          __hip_atomic_store(&a.state->status, SCS_EDEVICE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.state->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        float sum = 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          if (v < W) sum += __uint_as_float((uint32_t)xv[v]);  // same order in every workgroup
+        cl = sum;
       }
-      lds_barrier();
-      if (tid < b) {
-        float s = 0.f;
-        for (int v = 0; v < W; ++v) s += xs[v][tid];  // same order in every workgroup
-        cl = s;
-      }
+      gam[j] = j < b ? sc_use * cl / (float)b : 0.f;
+      s_idx[(t + 2) & 3][srg][sq] = j < b ? idx_use : 0;
+      // loads consumed at the next step, issued after the polls so the polls never wait for them
+      idx_next = a.idx[(t + 3 < mlast ? t + 3 : mlast) * b + jj];
+      sc_next = a.scale[(t + 1 < mlast ? t + 1 : mlast) * b + jj];
     }
-    if (tid < b) gam[tid] = sc_cur * cl / (float)b;
     lds_barrier();
-    if (s_abort) break;
-    // (1/b) sum_j c_j a_j / (n q_j) over this thread's rows, then across the 8 row groups
+    if (s_abort) return false;
+    // (1/b) sum_j c_j a_j / (n q_j): this thread's rows, then the 8 row groups of the wave
+    float g8[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) g8[q] = gam[rg + 8 * q];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       float u[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        int j = rg + 8 * q;
-        float gj = j < b ? gam[j] : 0.f;
+      for (int q = 0; q < RPT; ++q)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) u[v] = fmaf(gj, f4get(cur[q][c], v), u[v]);
-      }
-      red[rg][cgt + 32 * c] = make_float4(u[0], u[1], u[2], u[3]);
-    }
-    lds_barrier();
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      float tot[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        float4 r = red[g][cgt + 32 * c];
-        tot[0] += r.x;
-        tot[1] += r.y;
-        tot[2] += r.z;
-        tot[3] += r.w;
-      }
+        for (int v = 0; v < 4; ++v) u[v] = fmaf(g8[q], f4get(cur[q][c], v), u[v]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        dl[c][v] -= eta * (tot[v] + muv[c][v]);
+        const float uu = cok[c][v] ? rowgroup_sum(u[v]) : 0.f;
+        dl[c][v] -= eta * (uu + muv[c][v]);
         float y = dl[c][v] - smc[c][v];
         float s2 = sm[c][v] + y;
         smc[c][v] = (s2 - sm[c][v]) - y;
         sm[c][v] = s2;
       }
     }
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) cur[q][c] = nxt[q][c];
-    sc_cur = sc_next;
-  }
+    return true;
+  };
+
+  int64_t t = 0;
+  bool go = true;
+  for (; go && t + 1 < a.m; t += 2)
+    go = step(t, bufA, bufB, idxA, idxB, scA, scB) && step(t + 1, bufB, bufA, idxB, idxA, scB, scA);
+  if (go && t < a.m) go = step(t, bufA, bufB, idxA, idxB, scA, scB);
 
   if (!s_abort && rg == 0) {
     const float inv_m = 1.0f / (float)a.m;
@@ -323,8 +312,8 @@ int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
     set_error("inner loop: need 1 <= b <= 64, m >= 1, 1 <= workgroups <= 16");
     return SCS_EINVAL;
   }
-  if (a.ldx % 4 != 0 || a.ldr % 4 != 0) {
-    set_error("inner loop: row strides must be multiples of 4 elements");
+  if (a.ldx % 4 != 0 || a.ldr != a.ldx) {
+    set_error("inner loop: data and regularizer rows need one leading dimension, a multiple of 4");
     return SCS_EINVAL;
   }
   a.slice = cdiv(cdiv(a.d, a.W), 4) * 4;
