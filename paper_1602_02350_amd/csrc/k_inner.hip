@@ -26,7 +26,7 @@ namespace scs {
 
 namespace {
 
-constexpr int kInnerThreads = 256;
+constexpr int kInnerThreads = 512;  // 8 waves: 16 row groups x 32 column threads
 constexpr uint32_t kPollBudget = 1u << 22;
 
 // Barrier for LDS traffic only: waits for this wave's LDS operations but not for its
@@ -36,18 +36,19 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 
 __device__ __forceinline__ float f4get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 
-// Sum of v over the lanes l, l^8, l^16, ..., l^56 (the 8 row groups sharing a column), left in
-// every one of them: DPP row rotation by 8 (xor 8 inside a 16-lane row), then the gfx950 row
-// swaps, which exchange 16-lane rows 0<->1, 2<->3 and 32-lane halves respectively.
+// Sum of v over the 16 lanes of the wave with the same lane % 4 (the 16 row groups sharing a
+// column), left in every one of them: DPP rotations by 8 and 4 inside each 16-lane row, then the
+// gfx950 row swaps, which exchange 16-lane rows 0<->1, 2<->3 and 32-lane halves respectively.
 __device__ __forceinline__ float rowgroup_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
   auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   v = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
   auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   return __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
 }
 
-// Lane layout: lane = 8 * rg + cl and column thread cgt = 8 * wave + cl, so the 8 row groups that
+// Lane layout: lane = 4 * rg + cl and column thread cgt = 4 * wave + cl, so the 16 row groups that
 // share a column are in one wave and the update's sum over rows is a lane butterfly. Wave 0 also
 // owns the per-step communication: it sums the partial dot products, exchanges them with the
 // other workgroups, publishes the step coefficients and stages the index stream into LDS two
@@ -68,8 +69,8 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index made provably uniform so that wave-0-only work compiles to scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int rg = lane >> 3;                 // row group: rows j = rg + 8 q
-  const int cgt = wave * 8 + (lane & 7);    // column thread 0..31
+  const int rg = lane >> 2;                 // row group: rows j = rg + 16 q
+  const int cgt = wave * 4 + (lane & 3);    // column thread 0..31
   const int b = a.b, W = a.W;
   const uint32_t NR = (uint32_t)(a.n + a.d), n32 = (uint32_t)a.n;
   const int64_t c_begin = (int64_t)w * a.slice;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
 
   __shared__ float pd[64][36];
   __shared__ float gam[64];
-  __shared__ int32_t s_idx[4][8][8];  // [step slot][row group][q]: index of row rg + 8q, staged by wave 0
+  __shared__ int32_t s_idx[4][16][4];  // [step slot][row group][q]: index of row rg + 16q, staged by wave 0
   __shared__ int s_abort;
 
   float dl[CPT][4], sm[CPT][4], smc[CPT][4], muv[CPT][4], w0[CPT][4];
@@ -114,8 +115,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   // columns outside the slice are excluded from the update, so their values never matter.
   auto load_rows = [&](int slot, float4 (&buf)[RPT][CPT]) {
     const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][0]);
-    const int4 i1 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][4]);
-    const int32_t ix[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+    const int32_t ix[4] = {i0.x, i0.y, i0.z, i0.w};
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const uint32_t i = (uint32_t)ix[q] < NR ? (uint32_t)ix[q] : 0u;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   };
 
   const int jj = lane < b ? lane : b - 1;
-  const int srg = lane & 7, sq = lane >> 3;  // where wave 0 lane j stages index j (j = srg + 8 sq)
+  const int srg = lane & 15, sq = lane >> 4;  // where wave 0 lane j stages index j (j = srg + 16 sq)
   // wave 0, two-slot rings alternating like the row buffers: a step consumes idxX (index of step
   // t+2) and scX (scale of step t), both loaded one step earlier, and loads the other slot
   int32_t idxA = 0, idxB = 0;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
       for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) p = fmaf(f4get(cur[q][c], v), dl[c][v], p);
-      pd[rg + 8 * q][cgt] = p;
+      pd[rg + 16 * q][cgt] = p;
     }
     lds_barrier();
     if (wave == 0) {
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
     // (1/b) sum_j c_j a_j / (n q_j): this thread's rows, then the 8 row groups of the wave
     float g8[RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) g8[q] = gam[rg + 8 * q];
+    for (int q = 0; q < RPT; ++q) g8[q] = gam[rg + 16 * q];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       float u[4] = {0.f, 0.f, 0.f, 0.f};
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
     go = step(t, bufA, bufB, idxA, idxB, scA, scB) && step(t + 1, bufB, bufA, idxB, idxA, scB, scA);
   if (go && t < a.m) go = step(t, bufA, bufB, idxA, idxB, scA, scB);
 
-  if (!s_abort && rg == 0) {
+  if (!s_abort && rg == 0) {  // lanes 0..3 of every wave: one writer per column thread
     const float inv_m = 1.0f / (float)a.m;
 #pragma unroll
     for (int q = 0; q < CPT; ++q)
@@ -301,7 +301,9 @@ int launch_c(hipStream_t st, InnerArgs& a, int cpt) {
 }  // namespace
 
 int inner_default_workgroups(int64_t d) {
-  int64_t W = cdiv(d, 128);
+  // measured on MI355X at d = 1000: 64 columns per workgroup beats 128 (the per-step chain is
+  // dominated by latency, so less work per workgroup wins until the exchange cost takes over)
+  int64_t W = cdiv(d, 64);
   if (W < 1) W = 1;
   if (W > 16) W = 16;
   return (int)W;
@@ -318,11 +320,10 @@ int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
   }
   a.slice = cdiv(cdiv(a.d, a.W), 4) * 4;
   int cpt = (int)cdiv(a.slice, 128);
-  int rpt = (int)cdiv(a.b, 8);
+  int rpt = (int)cdiv(a.b, 16);
   if (rpt <= 1) return bf16 ? launch_c<1, true>(st, a, cpt) : launch_c<1, false>(st, a, cpt);
   if (rpt <= 2) return bf16 ? launch_c<2, true>(st, a, cpt) : launch_c<2, false>(st, a, cpt);
-  if (rpt <= 4) return bf16 ? launch_c<4, true>(st, a, cpt) : launch_c<4, false>(st, a, cpt);
-  return bf16 ? launch_c<8, true>(st, a, cpt) : launch_c<8, false>(st, a, cpt);
+  return bf16 ? launch_c<4, true>(st, a, cpt) : launch_c<4, false>(st, a, cpt);
 }
 
 }  // namespace scs
