@@ -37,6 +37,11 @@ def parse():
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-epochs", type=int, default=2)
+    ap.add_argument("--fixed", default=None,
+                    help="skip tuning: 'c,mf;c,mf' = step scale and epoch-length factor (m = mf n / b) "
+                         "for the preconditioned and the plain solve")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of a known size (reference for HBM traffic counters)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -87,7 +92,7 @@ def subopt(H, w, ws):
     return 0.5 * float(e @ (H @ e))
 
 
-def cpu_baseline(args, X, y, cfg, k, c, epochs_needed, seed):
+def cpu_baseline(args, X, y, cfg, k, c, m, epochs_needed, seed):
     """The FP64 oracle on the host: preprocessing plus `cpu_epochs` SVRG epochs, scaled to the epochs needed."""
     import numpy as np
     from oracle import precond, sampling, svrg
@@ -101,7 +106,6 @@ def cpu_baseline(args, X, y, cfg, k, c, epochs_needed, seed):
     yh = y.cpu().numpy().astype(np.float64)
     n, d = Xh.shape
     b = cfg["b"]
-    m = -(-2 * n // b)
     t0 = time.perf_counter()
     Om = inputs.gaussian((d, k + 5), seed=seed).astype(np.float64)
     Pm, _, _ = svrg.preconditioner_from_sketch(Xh, cfg["lam"], k, Om)
@@ -143,27 +147,43 @@ def main():
 
     ctx = binding.Context(0)
 
-    def solve(kk, c, s, timing=False, max_epochs=60):
-        return ctx.svrg_solve(X, y, lam, kk, eps, batch=b, max_epochs=max_epochs, stop_rule=binding.STOP_GAP,
-                              f_star=Ls, step_scale=c, seed=s, precision=prec, workgroups=args.workgroups,
-                              timing=int(timing))
+    def solve(kk, c, mf, s, timing=False, max_epochs=60):
+        return ctx.svrg_solve(X, y, lam, kk, eps, batch=b, steps=max(1, int(round(mf * n / b))),
+                              max_epochs=max_epochs, stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=c, seed=s,
+                              precision=prec, workgroups=args.workgroups, timing=int(timing))
 
-    # ---- tune the step per method on a separate seed (untimed)
-    grid = [1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0]
+    if args.copy_calibration:
+        src = torch.empty(256 * 2 ** 20 // 4, device="cuda", dtype=torch.float32).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, "calibration copy: 256 MiB read + 256 MiB written")
+
+    # ---- tune the step scale c and the epoch length m = mf n / b per method on a separate seed
+    # (untimed; the paper tunes eta per method and takes m proportional to n)
     tuned = {}
-    for name, kk in (("precond", k), ("plain", 0)):
-        best = None
-        for c in grid:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = solve(kk, c, seed + 1000)
-            t = time.perf_counter() - t0
-            log(args, f"tune {name} c={c}: status={r.status} epochs={r.report['epochs']} {t * 1e3:.1f} ms")
-            if r.status == binding.OK and (best is None or t < best[1]):
-                best = (c, t, r.report["epochs"])
-        if best is None:
-            raise SystemExit(f"no step size in {grid} reached eps={eps} for {name}")
-        tuned[name] = best
+    if args.fixed:
+        for name, part in zip(("precond", "plain"), args.fixed.split(";")):
+            c, mf = (float(v) for v in part.split(","))
+            tuned[name] = (c, mf, None, None)
+    else:
+        for name, kk in (("precond", k), ("plain", 0)):
+            best = None
+            for mf in (0.25, 0.5, 1.0, 2.0):
+                for c in (1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = solve(kk, c, mf, seed + 1000)
+                    t = time.perf_counter() - t0
+                    log(args, f"tune {name} c={c} mf={mf}: status={r.status} epochs={r.report['epochs']} "
+                              f"{t * 1e3:.1f} ms")
+                    if r.status == binding.DIVERGED:
+                        break
+                    if r.status == binding.OK and (best is None or t < best[2]):
+                        best = (c, mf, t, r.report["epochs"])
+            if best is None:
+                raise SystemExit(f"no step size reached eps={eps} for {name}")
+            tuned[name] = best
     log(args, "tuned", tuned)
 
     # ---- warmup + timed steps
@@ -174,7 +194,7 @@ def main():
         for name, kk in (("precond", k), ("plain", 0)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = solve(kk, tuned[name][0], seed, timing=True)
+            r = solve(kk, tuned[name][0], tuned[name][1], seed, timing=True)
             torch.cuda.synchronize()
             step[name] = (time.perf_counter() - t0, r)
         if it >= args.warmup:
@@ -204,7 +224,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(args, "timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(args, X, y, cfg, k, tuned["precond"][0], rp["epochs"], seed)
+        cpu = cpu_baseline(args, X, y, cfg, k, tuned["precond"][0], rp["steps"], rp["epochs"], seed)
 
     out = {
         "metric": "seconds to L(w)-L(w*)<=1e-6 (precond vs plain SVRG, 1 GPU); grad-pass HBM GB/s",
@@ -226,6 +246,7 @@ def main():
         "speedup_vs_plain": t_plain / t_pre,
         "epochs": {"precond": rp["epochs"], "plain": reps["plain"].report["epochs"]},
         "step_scale": {"precond": tuned["precond"][0], "plain": tuned["plain"][0]},
+        "steps_per_epoch": {"precond": rp["steps"], "plain": reps["plain"].report["steps"]},
         "suboptimality": so,
         "w_rel_err": relerr,
         "stage_ms": {"sketch": rp["ms_sketch"], "apply": rp["ms_apply"], "solve": rp["ms_solve"]},

@@ -355,7 +355,7 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
   SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
   WS(w32, float, "w32_grad", (size_t)d);
   WS(tmp, double, "vtmp", (size_t)d);
-  WS(g64, double, "g64", (size_t)d);
+  WS(g64, double, "g64", (size_t)16 * d);  // kColSplit x d first-level gradient sums
   int nwg = grad_num_workgroups(n, d);
   WS(part, float, "gpart", (size_t)nwg * d);
   WS(rsq, double, "grsq", (size_t)nwg);
@@ -454,7 +454,9 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   const int64_t N = n + d;
   const int S = o.max_epochs;
   const int mixed = o.precision == SCS_PREC_MIXED;
-  const int64_t ldt = cdiv(d, 4) * 4;
+  // rows used by the inner loop start on 256-byte boundaries, so a workgroup's column slice of a
+  // gathered row covers whole cache lines
+  const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
   SCS_CHECK(ensure_events(ctx, (size_t)S + 4 + (o.timing ? 4 * ((size_t)S + 1) : 0)));
   const int tbase = 3 + S;  // with timing: events tbase + 4s + {0,1} around the gradient pass, {2,3} around the inner loop
   hipEvent_t ev_start = ctx->events[0], ev_sketch = ctx->events[1], ev_apply = ctx->events[2];
@@ -498,11 +500,8 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
       SCS_HIP(hipMemcpy2DAsync(xt16, ldt * 2, tmp, d * 2, d * 2, n, hipMemcpyDeviceToDevice, st));
       SCS_CHECK(launch_rownorm_bf16(st, tmp, n, d, beta));
       Xt = xt16;
-    } else if (ldx % 4 == 0 && (uintptr_t)X % 16 == 0) {
-      SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta));
-      Xt = X;
-      ldxt = ldx;
     } else {
+      // P = I: the rows are x_i themselves, copied into the padded layout of the inner loop
       WS(xpad, float, "Xpad", (size_t)n * ldt);
       SCS_HIP(hipMemcpy2DAsync(xpad, ldt * 4, X, ldx * 4, d * 4, n, hipMemcpyDeviceToDevice, st));
       SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta));
@@ -534,7 +533,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   WS(w32, float, "w32", (size_t)d);
   WS(mu, float, "mu", (size_t)d);
   WS(tmp, double, "vtmp", (size_t)d);
-  WS(g64, double, "g64", (size_t)d);
+  WS(g64, double, "g64", (size_t)16 * d);  // kColSplit x d first-level gradient sums
   const int nwg = grad_num_workgroups(n, d);
   WS(gpart, float, "gpart", (size_t)nwg * d);
   WS(grsq, double, "grsq", (size_t)nwg);

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   if (tid == 0) s_abort = 0;
 
   // Row loads are unconditional from in-bounds addresses: rows j >= b get coefficient 0 and
-  // columns outside the slice are excluded from the update, so their values never matter.
+  // columns outside the slice are zeroed before use.
   auto load_rows = [&](int slot, float4 (&buf)[RPT][CPT]) {
     const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][0]);
     const int32_t ix[4] = {i0.x, i0.y, i0.z, i0.w};
@@ -154,9 +154,17 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
   auto step = [&](int64_t t, float4 (&cur)[RPT][CPT], float4 (&nxt)[RPT][CPT], int32_t& idx_use, int32_t& idx_next,
                   float& sc_use, float& sc_next) -> bool {
     load_rows((int)((t + 1) & 3), nxt);
-    // partial dot products over this workgroup's columns (delta is 0 outside the slice)
+    // columns outside the slice (and padding past d) may hold anything: zero them, then partial
+    // dot products over this workgroup's columns
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        cur[q][c].x = cok[c][0] ? cur[q][c].x : 0.f;
+        cur[q][c].y = cok[c][1] ? cur[q][c].y : 0.f;
+        cur[q][c].z = cok[c][2] ? cur[q][c].z : 0.f;
+        cur[q][c].w = cok[c][3] ? cur[q][c].w : 0.f;
+      }
       float p = 0.f;
 #pragma unroll
       for (int c = 0; c < CPT; ++c)

@@ -71,15 +71,27 @@ __global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, co
   }
 }
 
-// g_j = (1/n) sum over workgroup partials (FP64, fixed order) + lambda w_j
-__global__ void grad_colreduce_kernel(const float* part, int nwg, int64_t n, int64_t d, const float* w,
-                                      double lambda, double* g, const SolveState* state) {
+// First level of the cross-workgroup sum of the gradient partials, in FP64 and a fixed order:
+// workgroup (bx, by) sums partial rows [by R, (by+1) R) of columns [64 bx, 64 bx + 64) into
+// g2[by][j]; grad_finalize adds the kColSplit rows of g2 in order.
+constexpr int kColSplit = 16;
+
+__global__ __launch_bounds__(256) void grad_colreduce_kernel(const float* part, int nwg, int64_t d, double* g2,
+                                                             const SolveState* state) {
   if (state && state->done) return;
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= d) return;
+  __shared__ double sacc[4][64];
+  const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  const int R = (nwg + kColSplit - 1) / kColSplit;
+  const int r0 = blockIdx.y * R, r1 = r0 + R < nwg ? r0 + R : nwg;
   double acc = 0.0;
-  for (int q = 0; q < nwg; ++q) acc += (double)part[(int64_t)q * d + j];
-  g[j] = acc / (double)n + lambda * (double)w[j];
+  if (j < d) {
+#pragma unroll 4
+    for (int q = r0 + rs; q < r1; q += 4) acc += (double)part[(int64_t)q * d + j];
+  }
+  sacc[rs][c] = acc;
+  __syncthreads();
+  if (rs == 0 && j < d) g2[(int64_t)blockIdx.y * d + j] = ((sacc[0][c] + sacc[1][c]) + sacc[2][c]) + sacc[3][c];
 }
 
 __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
@@ -90,8 +102,16 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   __shared__ double tbuf[256];
   __shared__ double sred[kVecWaves];
   __shared__ int s_action;
+  // g = (1/n) sum of the partial rows (fixed order) + lambda w, written over the first row of g2
+  double* g = const_cast<double*>(g_in);
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    double acc = 0.0;
+    for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
+    g[j] = acc / (double)n + lambda * (double)w[j];
+  }
+  __syncthreads();
   // mu = P^{-1/2} g
-  pmhalf_apply_block<double>(UT, U, lam, k, d, lambda, g_in, tmp, tbuf);
+  pmhalf_apply_block<double>(UT, U, lam, k, d, lambda, g, tmp, tbuf);
   double gn = 0.0, wn = 0.0;
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double m = tmp[j];
@@ -257,8 +277,7 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
                        const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
                        float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
                        double f_star, float* wt_cur, const float* wt_prev, int first) {
-  grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 256)), dim3(256), 0, st>>>(part, nwg, n, d, w, lambda, g_tmp,
-                                                                             state);
+  grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
   SCS_HIP(hipGetLastError());
   grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, U, lam, k, mu, tmp,
                                                   state, stop_rule, eps, f_star, wt_cur, wt_prev, first);
