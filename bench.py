@@ -169,7 +169,7 @@ def main():
     else:
         for name, kk in (("precond", k), ("plain", 0)):
             best = None
-            for mf in (0.25, 0.5, 1.0, 2.0):
+            for mf in (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0):
                 for c in (1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()

@@ -71,8 +71,10 @@ typedef struct scs_opts {
   uint64_t seed;          /* seed of the Gaussian test matrix and of the index stream */
   const float* omega;     /* optional device (k+p) x d row-major Gaussian test matrix (transposed Omega); NULL = drawn from seed */
   const int32_t* indices; /* optional device index stream, max_epochs x m x b entries in [0, n+d); NULL = drawn from seed */
-  float* trace_w;         /* optional device max_epochs x d: w = P^{-1/2} w~ of the snapshot entering each epoch */
-  double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's end */
+  float* trace_w;         /* optional device max_epochs x d: w = P^{-1/2} w~ of the snapshot entering each epoch
+                             (rows of epochs after the stop rule held are left untouched) */
+  double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's
+                             end; -1 for epochs never enqueued because the stop rule had held */
   int timing;             /* 1: time every full-gradient pass and inner-loop launch with HIP events (report.ms_grad, ms_inner) */
 } scs_opts;
 

@@ -30,7 +30,10 @@ struct scs_ctx {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
-  std::vector<hipEvent_t> events;
+  std::vector<hipEvent_t> events;   // synchronizing events (host waits on them)
+  std::vector<hipEvent_t> tevents;  // timing-only events (no system-scope fence when recorded)
+  int* stop_flags = nullptr;  // host-pinned, one per epoch: set by the device when the solve is finished
+  size_t stop_cap = 0;
   int xcd_stride = 8;
 };
 
@@ -66,12 +69,31 @@ T* ws(scs_ctx* c, const std::string& name, size_t count) {
   T* var = ws<T>(ctx, name, (size_t)(count));    \
   if (!var) return SCS_ENOMEM;
 
-int ensure_events(scs_ctx* c, size_t count) {
+int ensure_events(scs_ctx* c, size_t count, size_t tcount = 0) {
   while (c->events.size() < count) {
     hipEvent_t e;
     SCS_HIP(hipEventCreate(&e));
     c->events.push_back(e);
   }
+  while (c->tevents.size() < tcount) {
+    hipEvent_t e;
+    SCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    c->tevents.push_back(e);
+  }
+  return SCS_OK;
+}
+
+// Host-pinned (coherent) flags the gradient finalizer writes; the host reads them to stop enqueuing.
+int ensure_stop_flags(scs_ctx* c, size_t count) {
+  if (c->stop_cap >= count) return SCS_OK;
+  if (c->stop_flags) {
+    hipStreamSynchronize(c->stream);
+    hipHostFree(c->stop_flags);
+    c->stop_flags = nullptr;
+    c->stop_cap = 0;
+  }
+  SCS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stop_flags), count * sizeof(int), hipHostMallocCoherent));
+  c->stop_cap = count;
   return SCS_OK;
 }
 
@@ -254,6 +276,8 @@ int scs_destroy(scs_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) hipFree(kv.second.p);
   for (auto e : c->events) hipEventDestroy(e);
+  for (auto e : c->tevents) hipEventDestroy(e);
+  if (c->stop_flags) hipHostFree(c->stop_flags);
   delete c;
   return SCS_OK;
 }
@@ -271,7 +295,7 @@ int scs_sample_indices(scs_ctx* ctx, const float* beta, int64_t N, uint64_t seed
   WS(cum, uint64_t, "cum", (size_t)N);
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
   SCS_CHECK(launch_sampler_prepare(ctx->stream, beta, N, cum, scr, sampler_scratch_len(N), nullptr));
-  return launch_sample(ctx->stream, cum, N, N, seed, epoch, count, out, nullptr, nullptr);
+  return launch_sample(ctx->stream, cum, N, N, seed, epoch, count, count, out, nullptr, nullptr);
 }
 
 int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts* opts,
@@ -363,7 +387,7 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
   SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, part, rsq, nwg, state));
   WS(wcur, float, "wt_dummy", (size_t)d);
   SCS_CHECK(launch_grad_finish(st, part, rsq, nwg, n, d, w32, lambda, UT, U, lam, k, grad_out, g64, tmp, state,
-                               SCS_STOP_EPOCHS, 0.0, 0.0, wcur, nullptr, 1));
+                               SCS_STOP_EPOCHS, 0.0, 0.0, wcur, nullptr, 1, nullptr));
   SolveState hs;
   SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
   SCS_HIP(hipStreamSynchronize(st));
@@ -457,9 +481,18 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   // rows used by the inner loop start on 256-byte boundaries, so a workgroup's column slice of a
   // gathered row covers whole cache lines
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
-  SCS_CHECK(ensure_events(ctx, (size_t)S + 4 + (o.timing ? 4 * ((size_t)S + 1) : 0)));
-  const int tbase = 3 + S;  // with timing: events tbase + 4s + {0,1} around the gradient pass, {2,3} around the inner loop
-  hipEvent_t ev_start = ctx->events[0], ev_sketch = ctx->events[1], ev_apply = ctx->events[2];
+  // Synchronizing events: dec[s] after the stop decision of snapshot s (just before the inner loop of
+  // epoch s). Timing-only events: 0 start, 1 sketch done, 2 preconditioner done, 3 end of solve,
+  // 4 + s end of epoch s; with timing, 4 + S + s and 5 + 2S + s bracket the gradient pass of s.
+  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)(o.timing ? 6 + 3 * S : 4 + S)));
+  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
+  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
+  hipEvent_t* dec = ctx->events.data();
+  hipEvent_t* tev = ctx->tevents.data();
+  hipEvent_t ev_start = tev[0], ev_sketch = tev[1], ev_apply = tev[2], ev_end = tev[3];
+  auto ev_epoch = [&](int s) { return tev[4 + s]; };
+  auto ev_g0 = [&](int s) { return tev[4 + S + s]; };
+  auto ev_g1 = [&](int s) { return tev[5 + 2 * S + s]; };
   SCS_HIP(hipEventRecord(ev_start, st));
 
   WS(state, SolveState, "state", 1);
@@ -537,8 +570,10 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   const int nwg = grad_num_workgroups(n, d);
   WS(gpart, float, "gpart", (size_t)nwg * d);
   WS(grsq, double, "grsq", (size_t)nwg);
-  WS(idxb, int32_t, "idx", (size_t)m * b);
-  WS(scale, float, "scale", (size_t)m * b);
+  // index streams are drawn kSampleGroup epochs per launch
+  constexpr int kSampleGroup = 8;
+  WS(idxb, int32_t, "idx", (size_t)kSampleGroup * m * b);
+  WS(scale, float, "scale", (size_t)kSampleGroup * m * b);
   WS(xbuf, uint64_t, "xbuf", (size_t)2 * W * 64);
   SCS_HIP(hipMemsetAsync(wt, 0, sizeof(float) * d, st));
   SCS_HIP(hipMemsetAsync(wt_prev, 0, sizeof(float) * d, st));
@@ -565,32 +600,45 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   a.xbuf = xbuf;
   a.state = state;
 
+  constexpr int kLookahead = 3;
+  int last_epoch = -1;
   for (int s = 0; s <= S; ++s) {
     float* trace_row = (o.trace_w && s < S) ? o.trace_w + (int64_t)s * d : nullptr;
     SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w32, trace_row, tmp, state));
-    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s], st));
+    if (o.timing) SCS_HIP(hipEventRecord(ev_g0(s), st));
     SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
-    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 1], st));
+    if (o.timing) SCS_HIP(hipEventRecord(ev_g1(s), st));
     SCS_CHECK(launch_grad_finish(st, gpart, grsq, nwg, n, d, w32, lambda, UT32, U32, lam, k_used, mu, g64, tmp, state,
-                                 o.stop_rule, eps, o.f_star, wt, wt_prev, s == 0 ? 1 : 0));
-    if (s == S) break;
-    const int32_t* idx_s;
-    if (o.indices) {
-      idx_s = o.indices + (int64_t)s * m * b;
-      SCS_CHECK(launch_index_scale(st, cum, N, n, idx_s, m * b, scale, state));
-    } else {
-      SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s, m * b, idxb, scale, state));
-      idx_s = idxb;
+                                 o.stop_rule, eps, o.f_star, wt, wt_prev, s == 0 ? 1 : 0, ctx->stop_flags + s));
+    if (s == S) {
+      SCS_HIP(hipEventRecord(dec[s], st));
+      break;
     }
-    a.idx = idx_s;
+    const int64_t mb = m * b, slot = s % kSampleGroup;
+    if (slot == 0) {
+      const int64_t cnt = (int64_t)std::min(kSampleGroup, S - s) * mb;
+      if (o.indices) SCS_CHECK(launch_index_scale(st, cum, N, n, o.indices + (int64_t)s * mb, cnt, scale, state));
+      else SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s, mb, cnt, idxb, scale, state));
+    }
+    a.idx = o.indices ? o.indices + (int64_t)s * mb : idxb + slot * mb;
+    a.scale = scale + slot * mb;
     a.step_base = (uint32_t)((uint64_t)s * (uint64_t)m);
-    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 2], st));
+    SCS_HIP(hipEventRecord(dec[s], st));
     SCS_CHECK(launch_inner_epoch(st, a, rows_bf16));
-    if (o.timing) SCS_HIP(hipEventRecord(ctx->events[tbase + 4 * s + 3], st));
-    SCS_HIP(hipEventRecord(ctx->events[3 + s], st));
+    SCS_HIP(hipEventRecord(ev_epoch(s), st));
+    last_epoch = s;
+    // Keep kLookahead epochs queued ahead of the host's view: once the decision taken at snapshot
+    // s - kLookahead + 1 says the solve is finished, the epochs already queued after it are no-ops
+    // (every kernel returns on the device's done flag) and nothing more is enqueued.
+    if (s + 1 >= kLookahead) {
+      const int q = s + 1 - kLookahead;
+      SCS_HIP(hipEventSynchronize(dec[q]));
+      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+    }
   }
   // w = P^{-1/2} w~ with the same routine that produced the gradient's evaluation point
   SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w_out, nullptr, tmp, nullptr));
+  SCS_HIP(hipEventRecord(ev_end, st));
   SolveState hs;
   SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
   SCS_HIP(hipStreamSynchronize(st));
@@ -609,8 +657,8 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   }
   if (o.epoch_ms) {
     for (int s = 0; s < S; ++s) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev_start, ctx->events[3 + s]) != hipSuccess) ms = -1.f;
+      float ms = -1.f;
+      if (s > last_epoch || hipEventElapsedTime(&ms, ev_start, ev_epoch(s)) != hipSuccess) ms = -1.f;
       o.epoch_ms[s] = ms;
     }
   }
@@ -629,7 +677,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     float t1 = 0, t2 = 0, t3 = 0;
     hipEventElapsedTime(&t1, ev_start, ev_sketch);
     hipEventElapsedTime(&t2, ev_sketch, ev_apply);
-    hipEventElapsedTime(&t3, ev_apply, ctx->events[3 + S - 1]);
+    hipEventElapsedTime(&t3, ev_apply, ev_end);
     report->ms_sketch = t1;
     report->ms_apply = t2;
     report->ms_solve = t3;
@@ -640,12 +688,12 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
       double sg = 0.0, si = 0.0;
       for (int s = 0; s < ng; ++s) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->events[tbase + 4 * s], ctx->events[tbase + 4 * s + 1]);
+        hipEventElapsedTime(&ms, ev_g0(s), ev_g1(s));
         sg += ms;
       }
       for (int s = 0; s < ni; ++s) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->events[tbase + 4 * s + 2], ctx->events[tbase + 4 * s + 3]);
+        hipEventElapsedTime(&ms, dec[s], ev_epoch(s));
         si += ms;
       }
       report->ms_grad = sg;

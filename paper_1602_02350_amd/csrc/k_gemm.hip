@@ -137,11 +137,13 @@ __global__ __launch_bounds__(256) void gemm_nt_wide_kernel(const float* __restri
                                                            int64_t ldc0, float beta, const double* beta_dev,
                                                            float diag, const double* diag_dev, void* Cout,
                                                            int64_t ldc, float* __restrict__ rownorm2, int KP,
-                                                           bool a_al, bool b_al) {
+                                                           bool a_al, bool b_al, bool c0_al, bool out_al) {
   extern __shared__ float S[];
   const int LW = KP + 4;
+  constexpr int CW = kWdBN + 4;
   float* As = S;                  // kWdBM x LW
   float* Bs = S + kWdBM * LW;     // kWdBN x LW
+  float* Cs = Bs + kWdBN * LW;    // kWdBM x CW: the MFMA tile, re-read by rows for the epilogue
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * kWdBM;
   if (beta_dev) beta = (float)beta_dev[0];
@@ -151,6 +153,9 @@ __global__ __launch_bounds__(256) void gemm_nt_wide_kernel(const float* __restri
     int r = e / kv, c4 = e % kv;
     *reinterpret_cast<float4*>(&As[r * LW + 4 * c4]) = load4(A, lda, M, K, m0 + r, 4 * c4, a_al);
   }
+  // epilogue mapping: lane owns columns cc..cc+3 of rows 4p + lane/16 (p = 0..3) of its wave's 16 rows,
+  // so 16 lanes move one contiguous 256-byte row segment
+  const int cc = 4 * (lane & 15);
   float rn[4] = {0.f, 0.f, 0.f, 0.f};
   for (int64_t n0 = 0; n0 < N; n0 += kWdBN) {
     __syncthreads();
@@ -174,33 +179,71 @@ __global__ __launch_bounds__(256) void gemm_nt_wide_kernel(const float* __restri
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int64_t row = m0 + wave * 16 + 4 * (lane >> 4) + r;
-        int64_t col = n0 + cb * 16 + (lane & 15);
-        if (row < M && col < N) {
-          float v = alpha * acc[cb][r];
-          if (C0) v = fmaf(beta, C0[row * ldc0 + col], v);
-          if (row == col) v += diag;
-          if constexpr (OUT_BF16) {
-            uint16_t h = f32_to_bf16(v);
-            reinterpret_cast<uint16_t*>(Cout)[row * ldc + col] = h;
-            v = bf16_to_f32(h);
-          } else {
-            reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
-          }
-          rn[r] = fmaf(v, v, rn[r]);
+      for (int r = 0; r < 4; ++r) Cs[(wave * 16 + 4 * (lane >> 4) + r) * CW + cb * 16 + (lane & 15)] = acc[cb][r];
+    __syncthreads();
+    const int64_t col = n0 + cc;
+    if (col < N) {
+      const bool full = col + 3 < N;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int rl = wave * 16 + 4 * p + (lane >> 4);
+        const int64_t row = m0 + rl;
+        if (row >= M) continue;
+        float4 t = *reinterpret_cast<const float4*>(&Cs[rl * CW + cc]);
+        float v[4] = {alpha * t.x, alpha * t.y, alpha * t.z, alpha * t.w};
+        if (C0) {
+          float4 c = load4(C0, ldc0, M, N, row, col, c0_al);
+          v[0] = fmaf(beta, c.x, v[0]);
+          v[1] = fmaf(beta, c.y, v[1]);
+          v[2] = fmaf(beta, c.z, v[2]);
+          v[3] = fmaf(beta, c.w, v[3]);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (row == col + q) v[q] += diag;
+        if constexpr (OUT_BF16) {
+          uint16_t h[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            h[q] = f32_to_bf16(v[q]);
+            v[q] = bf16_to_f32(h[q]);
+          }
+          uint16_t* o = reinterpret_cast<uint16_t*>(Cout) + row * ldc + col;
+          if (full && out_al) {
+            uint2 w;
+            w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+            *reinterpret_cast<uint2*>(o) = w;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (col + q < N) o[q] = h[q];
+          }
+        } else {
+          float* o = reinterpret_cast<float*>(Cout) + row * ldc + col;
+          if (full && out_al) {
+            *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (col + q < N) o[q] = v[q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (col + q < N) rn[p] = fmaf(v[q], v[q], rn[p]);
       }
+    }
   }
   if (rownorm2) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float t = rn[r];
+    for (int p = 0; p < 4; ++p) {
+      float t = rn[p];
       t += __shfl_xor(t, 1);
       t += __shfl_xor(t, 2);
       t += __shfl_xor(t, 4);
       t += __shfl_xor(t, 8);
-      int64_t row = m0 + wave * 16 + 4 * (lane >> 4) + r;
+      int64_t row = m0 + wave * 16 + 4 * p + (lane >> 4);
       if ((lane & 15) == 0 && row < M) rownorm2[row] = t;
     }
   }
@@ -287,6 +330,7 @@ __global__ void reduce_partials_kernel(const float* partial, int64_t nchunks, in
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= elems) return;
   double acc = 0.0;
+#pragma unroll 8
   for (int64_t c = 0; c < nchunks; ++c) acc += (double)partial[c * elems + e];
   out[e] = acc * scale;
 }
@@ -353,16 +397,18 @@ int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int
     return SCS_EINVAL;
   }
   int KP = (int)cdiv(K < 1 ? 1 : K, 16) * 16;
-  size_t bytes = (size_t)(kWdBM + kWdBN) * (KP + 4) * sizeof(float);
+  size_t bytes = ((size_t)(kWdBM + kWdBN) * (KP + 4) + (size_t)kWdBM * (kWdBN + 4)) * sizeof(float);
   dim3 grid((unsigned)cdiv(M, kWdBM));
   bool aa = aligned16(A, lda), ba = aligned16(Bt, ldb);
+  bool ca = C0 ? aligned16(C0, ldc0) : false;
+  bool oa = out_bf16 ? ((uintptr_t)C % 8 == 0 && ldc % 4 == 0) : aligned16(C, ldc);
   const void* fn;
   if (bf16) fn = out_bf16 ? (const void*)gemm_nt_wide_kernel<true, true> : (const void*)gemm_nt_wide_kernel<true, false>;
   else fn = out_bf16 ? (const void*)gemm_nt_wide_kernel<false, true> : (const void*)gemm_nt_wide_kernel<false, false>;
   if (bytes > 65536) SCS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 #define SCS_WD(B1, B2)                                                                                          \
   gemm_nt_wide_kernel<B1, B2><<<grid, 256, bytes, st>>>(A, M, K, lda, Bt, N, ldb, alpha, C0, ldc0, beta,     \
-                                                         beta_dev, diag, diag_dev, C, ldc, rownorm2, KP, aa, ba)
+                                                         beta_dev, diag, diag_dev, C, ldc, rownorm2, KP, aa, ba, ca, oa)
   if (bf16) {
     if (out_bf16) SCS_WD(true, true);
     else SCS_WD(true, false);

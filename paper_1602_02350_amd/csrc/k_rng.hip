@@ -169,14 +169,20 @@ __device__ __forceinline__ float inv_nq(const uint64_t* cum, int64_t i, int64_t 
   return (float)((double)T / ((double)n_rows * (double)wi));
 }
 
-__global__ void sample_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, uint32_t epoch,
-                              int64_t count, int32_t* idx, float* scale, const SolveState* state) {
+// Draws `count` indices for consecutive epochs epoch0, epoch0 + 1, ... (per_epoch draws each); draw
+// g of epoch e uses Philox call g/2 with counter (call_lo, call_hi, e, 0), words (x0, x1) for even g
+// and (x2, x3) for odd g, so a multi-epoch launch draws exactly what per-epoch launches would.
+__global__ void sample_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, uint32_t epoch0,
+                              int64_t per_epoch, int64_t count, int32_t* idx, float* scale,
+                              const SolveState* state) {
   if (state && state->done) return;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= count) return;
-  uint64_t c = (uint64_t)g >> 1;
+  const uint32_t epoch = epoch0 + (uint32_t)(g / per_epoch);
+  const int64_t gl = g % per_epoch;
+  uint64_t c = (uint64_t)gl >> 1;
   U4 x = philox4x32_10(U4{(uint32_t)c, (uint32_t)(c >> 32), epoch, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
-  uint64_t r = (g & 1) ? (((uint64_t)x.z << 32) | x.w) : (((uint64_t)x.x << 32) | x.y);
+  uint64_t r = (gl & 1) ? (((uint64_t)x.z << 32) | x.w) : (((uint64_t)x.x << 32) | x.y);
   uint64_t T = cum[N - 1];
   uint64_t u = __umul64hi(r, T);
   int64_t i = upper_bound_u64(cum, N, u);
@@ -231,10 +237,11 @@ int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_
 }
 
 int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
-                  int64_t count, int32_t* idx, float* scale, const SolveState* state) {
+                  int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state) {
   if (count <= 0) return SCS_OK;
+  if (per_epoch <= 0) per_epoch = count;
   sample_kernel<<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, seed, (uint32_t)epoch,
-                                                                        count, idx, scale, state);
+                                                                        per_epoch, count, idx, scale, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -27,31 +27,43 @@ __device__ __forceinline__ double block_sum_d(double v, double* sred) {
   return t;
 }
 
-// out_j = v_j/s + sum_i U[j][i] D_i (sum_l UT[i][l] v_l); k = 0 gives out = v.
-// UT is k x d, U is d x k (FP32). tbuf: k doubles of LDS.
+// out_j = v_j/s + sum_i UT[i][j] D_i (sum_l UT[i][l] v_l); k = 0 gives out = v.
+// UT is k x d (FP32). tbuf: k doubles of LDS. Both phases read UT along rows (coalesced) and keep
+// several independent loads in flight per lane; one workgroup, so the result is deterministic.
 template <typename VIN>
-__device__ void pmhalf_apply_block(const float* __restrict__ UT, const float* __restrict__ U,
-                                   const double* __restrict__ lam, int k, int64_t d, double lambda,
-                                   const VIN* __restrict__ v, double* __restrict__ out, double* tbuf) {
+__device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* __restrict__ lam, int k, int64_t d,
+                                   double lambda, const VIN* __restrict__ v, double* __restrict__ out,
+                                   double* tbuf) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int dd = (int)d;
   if (k == 0) {
-    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) out[j] = (double)v[j];
+    for (int j = threadIdx.x; j < dd; j += blockDim.x) out[j] = (double)v[j];
     __syncthreads();
     return;
   }
   const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
-  for (int i = wave; i < k; i += kVecWaves) {
-    double acc = 0.0;
-    const float* row = UT + (int64_t)i * d;
-    for (int64_t j = lane; j < d; j += 64) acc += (double)row[j] * (double)v[j];
-    acc = warp_sum_d(acc);
-    if (lane == 0) tbuf[i] = acc * (1.0 / sqrt(fmax(lam[i], 0.0) + lambda) - 1.0 / s);
+  constexpr int R = 4;  // rows of UT per wave and pass
+  for (int i0 = wave * R; i0 < k; i0 += kVecWaves * R) {
+    double acc[R] = {0.0, 0.0, 0.0, 0.0};
+    const float* r0 = UT + (int64_t)i0 * d;
+#pragma unroll 4
+    for (int j = lane; j < dd; j += 64) {
+      const double vj = (double)v[j];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (i0 + r < k) acc[r] += (double)r0[(int64_t)r * d + j] * vj;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double t = warp_sum_d(acc[r]);
+      if (lane == 0 && i0 + r < k) tbuf[i0 + r] = t * (1.0 / sqrt(fmax(lam[i0 + r], 0.0) + lambda) - 1.0 / s);
+    }
   }
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+  for (int j = threadIdx.x; j < dd; j += blockDim.x) {
     double acc = 0.0;
-    const float* urow = U + j * k;
-    for (int i = 0; i < k; ++i) acc += (double)urow[i] * tbuf[i];
+#pragma unroll 16
+    for (int i = 0; i < k; ++i) acc += (double)UT[(int64_t)i * d + j] * tbuf[i];
     out[j] = (double)v[j] / s + acc;
   }
   __syncthreads();
@@ -63,7 +75,7 @@ __global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, co
                                                              const SolveState* state) {
   if (state && state->done) return;
   __shared__ double tbuf[256];
-  pmhalf_apply_block<float>(UT, U, lam, k, d, lambda, wt, tmp, tbuf);
+  pmhalf_apply_block<float>(UT, lam, k, d, lambda, wt, tmp, tbuf);
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     float x = (float)tmp[j];
     w[j] = x;
@@ -97,8 +109,13 @@ __global__ __launch_bounds__(256) void grad_colreduce_kernel(const float* part, 
 __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
     const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w, double lambda,
     const float* UT, const float* U, const double* lam, int k, float* mu, double* tmp, SolveState* state,
-    int stop_rule, double eps, double f_star, float* wt_cur, const float* wt_prev, int first) {
-  if (state->done) return;
+    int stop_rule, double eps, double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
+  // host_stop (host-pinned, may be null) receives 1 once no further epoch will change anything, so the
+  // host can stop enqueuing epochs; it is a plain system-scope store from one lane
+  if (state->done) {
+    if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
   __shared__ double tbuf[256];
   __shared__ double sred[kVecWaves];
   __shared__ int s_action;
@@ -106,12 +123,13 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   double* g = const_cast<double*>(g_in);
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double acc = 0.0;
+#pragma unroll
     for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
     g[j] = acc / (double)n + lambda * (double)w[j];
   }
   __syncthreads();
   // mu = P^{-1/2} g
-  pmhalf_apply_block<double>(UT, U, lam, k, d, lambda, g, tmp, tbuf);
+  pmhalf_apply_block<double>(UT, lam, k, d, lambda, g, tmp, tbuf);
   double gn = 0.0, wn = 0.0;
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double m = tmp[j];
@@ -154,6 +172,7 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
       state->status = SCS_ENONFINITE;
     }
     s_action = action;
+    if (host_stop) __hip_atomic_store(host_stop, action != 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   __syncthreads();
   if (s_action == 2 && wt_prev) {
@@ -276,11 +295,11 @@ int launch_premap(hipStream_t st, const float* UT, const float* U, const double*
 int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part, int nwg, int64_t n, int64_t d,
                        const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
                        float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
-                       double f_star, float* wt_cur, const float* wt_prev, int first) {
+                       double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
   grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
   SCS_HIP(hipGetLastError());
   grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, U, lam, k, mu, tmp,
-                                                  state, stop_rule, eps, f_star, wt_cur, wt_prev, first);
+                                                  state, stop_rule, eps, f_star, wt_cur, wt_prev, first, host_stop);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

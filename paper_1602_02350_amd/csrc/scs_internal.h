@@ -111,7 +111,7 @@ int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out);
 int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
                            int64_t scratch_len, SolveState* state);
 int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
-                  int64_t count, int32_t* idx, float* scale, const SolveState* state);
+                  int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state);
 int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
                        int64_t count, float* scale, const SolveState* state);
 int64_t sampler_scratch_len(int64_t N);
@@ -153,7 +153,7 @@ int grad_num_workgroups(int64_t n, int64_t d);
 int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part, int nwg, int64_t n, int64_t d,
                        const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
                        float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
-                       double f_star, float* wt_cur, const float* wt_prev, int first);
+                       double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop);
 
 // inner loop (one persistent launch per epoch)
 struct InnerArgs {
