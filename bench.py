@@ -17,6 +17,7 @@ Prints one JSON line. Reported beside the headline number:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -25,6 +26,9 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
 
 
 def parse():
@@ -124,6 +128,31 @@ def cpu_baseline(args, X, y, cfg, k, c, m, epochs_needed, seed):
                        f"the GPU")}
 
 
+KERNEL_SOURCES = {"inner_epoch": "k_inner.hip", "grad_partial": "k_grad.hip"}
+
+
+def pmc_traffic(kernel, workload, **shape):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a copy of known size), or None when the
+    summary has no line for this workload and launch shape or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.txt")
+    src = os.path.join(ROOT, "paper_1602_02350_amd", "csrc", KERNEL_SOURCES[kernel])
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        f = line.split()
+        if len(f) < 3 or line.startswith("#") or f[0] != kernel or f[1] != workload:
+            continue
+        kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
+        if kv.get("src") != digest:
+            continue
+        if any(kv.get(key) != str(val) for key, val in shape.items()):
+            continue
+        return float(kv["bytes"])
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -221,6 +250,9 @@ def main():
     inner_gbs = inner_bytes / (inner_ms * 1e-3) / 1e9
     grad_gbs = grad_bytes / (grad_ms * 1e-3) / 1e9
 
+    inner_traffic = pmc_traffic("inner_epoch", args.workload, m=m, b=b)
+    grad_traffic = pmc_traffic("grad_partial", args.workload)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(args, "timing the FP64 oracle on the host ...")
@@ -251,11 +283,13 @@ def main():
         "w_rel_err": relerr,
         "stage_ms": {"sketch": rp["ms_sketch"], "apply": rp["ms_apply"], "solve": rp["ms_solve"]},
         "roofline": {"kernel": "inner_epoch", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms},
+                     "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": inner_traffic,
+                     "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms,
+                     "us_per_step": 1e3 * inner_ms / m,
+                     "note": "sequential chain of m dependent steps; bound by the per-step latency, not by HBM"},
         "grad_pass": {"kernel": "grad_partial", "bound": "hbm", "achieved": grad_gbs, "peak": HBM_PEAK_GBS,
-                      "unit": "GB/s", "frac": grad_gbs / HBM_PEAK_GBS, "bytes_per_launch": grad_bytes,
-                      "avg_launch_ms": grad_ms},
+                      "unit": "GB/s", "frac": grad_gbs / HBM_PEAK_GBS, "traffic": grad_traffic,
+                      "bytes_per_launch": grad_bytes, "avg_launch_ms": grad_ms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

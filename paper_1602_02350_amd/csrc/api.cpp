@@ -483,8 +483,9 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
   // Synchronizing events: dec[s] after the stop decision of snapshot s (just before the inner loop of
   // epoch s). Timing-only events: 0 start, 1 sketch done, 2 preconditioner done, 3 end of solve,
-  // 4 + s end of epoch s; with timing, 4 + S + s and 5 + 2S + s bracket the gradient pass of s.
-  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)(o.timing ? 6 + 3 * S : 4 + S)));
+  // 4 + s end of epoch s; with timing, 4 + S + s and 5 + 2S + s bracket the gradient pass of s and
+  // 6 + 3S + s opens the inner loop of s.
+  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)(o.timing ? 6 + 4 * S : 4 + S)));
   SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
   std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
   hipEvent_t* dec = ctx->events.data();
@@ -493,6 +494,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   auto ev_epoch = [&](int s) { return tev[4 + s]; };
   auto ev_g0 = [&](int s) { return tev[4 + S + s]; };
   auto ev_g1 = [&](int s) { return tev[5 + 2 * S + s]; };
+  auto ev_i0 = [&](int s) { return tev[6 + 3 * S + s]; };
   SCS_HIP(hipEventRecord(ev_start, st));
 
   WS(state, SolveState, "state", 1);
@@ -624,6 +626,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     a.scale = scale + slot * mb;
     a.step_base = (uint32_t)((uint64_t)s * (uint64_t)m);
     SCS_HIP(hipEventRecord(dec[s], st));
+    if (o.timing) SCS_HIP(hipEventRecord(ev_i0(s), st));
     SCS_CHECK(launch_inner_epoch(st, a, rows_bf16));
     SCS_HIP(hipEventRecord(ev_epoch(s), st));
     last_epoch = s;
@@ -693,7 +696,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
       }
       for (int s = 0; s < ni; ++s) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, dec[s], ev_epoch(s));
+        hipEventElapsedTime(&ms, ev_i0(s), ev_epoch(s));
         si += ms;
       }
       report->ms_grad = sg;
