@@ -51,7 +51,8 @@ extern "C" {
 
 /* Stop rules for scs_svrg_solve (checked at the start of every epoch's full-gradient pass). */
 #define SCS_STOP_EPOCHS 0     /* run exactly max_epochs epochs (Alg. 1's parameter S) */
-#define SCS_STOP_CERTIFICATE 1/* stop when ||grad||^2 (lam~_1 + lambda)/(2 lambda) <= eps, an upper bound on L - L* */
+#define SCS_STOP_CERTIFICATE 1/* stop when ||grad||^2 (lam~_1 + lambda)/(2 lambda) <= eps (||grad||^2/(2 lambda) for k = 0),
+                                 an upper bound on L - L* */
 #define SCS_STOP_GAP 2        /* stop when L(w) - f_star <= eps (f_star supplied by the caller) */
 
 typedef struct scs_ctx scs_ctx;
@@ -87,7 +88,7 @@ typedef struct scs_report {
   double beta_hat;        /* average smoothness of the n+d components */
   double objective;       /* L(w) at the returned w, from the last full-gradient pass */
   double grad_norm;       /* ||grad L~(w~)|| at the returned snapshot */
-  double certificate;     /* ||grad||^2 (lam~_1 + lambda)/(2 lambda) */
+  double certificate;     /* ||grad||^2 (lam~_1 + lambda)/(2 lambda); ||grad||^2/(2 lambda) for k = 0 */
   double lam_top;         /* lam~_1 (largest sketched eigenvalue; 0 if k = 0) */
   double ms_sketch, ms_apply, ms_solve; /* stage times */
   double ms_grad, ms_inner; /* with opts.timing: summed durations of the full-gradient passes and inner-loop launches */

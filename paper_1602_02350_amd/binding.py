@@ -241,6 +241,29 @@ class Context:
                "scs_svrg_epoch", False)
         return wt
 
+    def svrg_solve_batched(self, Xs, ys, lams, ks, eps: float, **opts):
+        """Independent problems solved together; returns (status, [w], [report dict])."""
+        P = len(Xs)
+        assert len(ys) == P and len(lams) == P and len(ks) == P and P > 0
+        for X, y in zip(Xs, ys):
+            _dev(X, torch.float32)
+            _dev(y, torch.float32)
+        ws_ = [torch.empty(X.shape[1], dtype=torch.float32, device=X.device) for X in Xs]
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        Xa = (vp * P)(*[X.data_ptr() for X in Xs])
+        ya = (vp * P)(*[y.data_ptr() for y in ys])
+        wa = (vp * P)(*[w.data_ptr() for w in ws_])
+        na = (i64 * P)(*[X.shape[0] for X in Xs])
+        da = (i64 * P)(*[X.shape[1] for X in Xs])
+        la = (i64 * P)(*[X.stride(0) for X in Xs])
+        lama = (ctypes.c_double * P)(*[float(v) for v in lams])
+        ka = (ctypes.c_int * P)(*[int(v) for v in ks])
+        reps = (ScsReport * P)()
+        o = self.opts(**opts)
+        rc = _check(self._L.scs_svrg_solve_batched(self._h, P, Xa, na, da, la, ya, lama, ka, float(eps),
+                                                   ctypes.byref(o), wa, reps), "scs_svrg_solve_batched")
+        return rc, ws_, [r.as_dict() for r in reps]
+
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
         _dev(X, torch.float32)
         n, d = X.shape

@@ -115,8 +115,10 @@ int choose_workgroups(const scs_opts& o, int64_t d) {
 
 // Sketch of Alg. 2 with one block. Fills ws buffers "U32" (d x k), "UT32" (k x d), "U64", "lam",
 // and, if want_z, "Z" = X U~ (n x k) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
+// flags_out (device, 2 ints, nullable): where CholeskyQR's breakdown flags go; when given, the call
+// does not wait for them and *rank_def is left unchanged (the caller reads the flags later).
 int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
-                bool want_z, bool* rank_def) {
+                bool want_z, bool* rank_def, int* flags_out = nullptr) {
   hipStream_t st = ctx->stream;
   const int l = k + o.oversample;
   const int bf = o.precision == SCS_PREC_MIXED;
@@ -144,7 +146,11 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   WS(Q1, double, "Q1_64", (size_t)d * l);
   WS(Q, double, "Q64", (size_t)d * l);
   WS(QT32, float, "QT32", (size_t)l * d);
-  WS(flags, int, "cholflags", 2);
+  int* flags = flags_out;
+  if (!flags) {
+    flags = ws<int>(ctx, "cholflags", 2);
+    if (!flags) return SCS_ENOMEM;
+  }
   SCS_CHECK(launch_gemm64(st, l, l, d, Y, 1, l, Y, l, 1, G, l, nullptr, 0));
   SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, flags));
   SCS_CHECK(launch_gemm64(st, d, l, l, Y, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
@@ -178,6 +184,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     WS(Z, float, "Z", (size_t)n * k);
     SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, k));
   }
+  if (flags_out) return SCS_OK;
   int hflags[2] = {0, 0};
   SCS_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   SCS_HIP(hipStreamSynchronize(st));
@@ -711,10 +718,324 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,
                            const int64_t* ldx, const float* const* y, const double* lambda, const int* k, double eps,
                            const scs_opts* opts, float* const* w_out, scs_report* reports) {
-  (void)ctx; (void)nprob; (void)X; (void)n; (void)d; (void)ldx; (void)y; (void)lambda; (void)k; (void)eps;
-  (void)opts; (void)w_out; (void)reports;
-  set_error("batched solve: not built yet");
-  return SCS_EINVAL;
+  if (!ctx || nprob < 1 || !X || !n || !d || !ldx || !y || !lambda || !k || !w_out) {
+    set_error("null argument or nprob < 1");
+    return SCS_EINVAL;
+  }
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.omega || o.indices || o.trace_w) {
+    set_error("batched solve: omega, indices and trace_w must be NULL");
+    return SCS_EINVAL;
+  }
+  if (o.stop_rule == SCS_STOP_GAP) {
+    set_error("batched solve: the gap rule needs one optimum per problem; use the certificate or an epoch count");
+    return SCS_EINVAL;
+  }
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
+      o.stop_rule > 2) {
+    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
+    return SCS_EINVAL;
+  }
+  int64_t max_d = 0;
+  std::vector<int> vec4(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    SCS_CHECK(validate_problem(X[p], n[p], d[p], ldx[p], lambda[p]));
+    const int l = k[p] + o.oversample;
+    if (!y[p] || !w_out[p] || k[p] < 0 || k[p] > d[p] ||
+        (k[p] > 0 && (o.oversample < 0 || l > d[p] || l > n[p] || l > 136)) || n[p] + d[p] > INT32_MAX) {
+      set_error("batched solve: problem " + std::to_string(p) +
+                ": need y, w_out, 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+      return SCS_EINVAL;
+    }
+    max_d = std::max(max_d, d[p]);
+    vec4[p] = d[p] % 4 == 0 && ldx[p] % 4 == 0 && (uintptr_t)X[p] % 16 == 0;
+  }
+  // kernel order: problems whose rows allow float4 loads first, so each row layout of the gradient
+  // pass gets one launch over a contiguous range (the layout a single solve would use)
+  std::vector<int> kord;
+  for (int p = 0; p < nprob; ++p)
+    if (vec4[p]) kord.push_back(p);
+  const int nv = (int)kord.size();
+  for (int p = 0; p < nprob; ++p)
+    if (!vec4[p]) kord.push_back(p);
+  std::vector<int> sidx(nprob);
+  for (int i = 0; i < nprob; ++i) sidx[kord[i]] = i;
+  if (max_d > 16 * 512) {
+    set_error("batched solve: d > 8192");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
+  const int es = mixed ? 2 : 4;
+  constexpr int G = 8;  // epochs of index streams drawn per sampling launch
+  // one workgroup per problem while its row fits 512 columns; wider problems get W cooperating ones
+  const int W = (int)cdiv(max_d, 512);
+
+  // ---- per-problem sizes and arena offsets (elements)
+  std::vector<int64_t> ldt(nprob), m(nprob), nwg(nprob), o_xt(nprob), o_reg(nprob), o_beta(nprob), o_vec(nprob),
+      o_g64(nprob), o_gp(nprob), o_gr(nprob), o_idx(nprob), o_ut(nprob), o_lam(nprob);
+  int64_t t_xt = 0, t_reg = 0, t_beta = 0, t_vec = 0, t_g64 = 0, t_gp = 0, t_gr = 0, t_idx = 0, t_ut = 0, t_lam = 0;
+  int64_t max_N = 0;
+  for (int p = 0; p < nprob; ++p) {
+    ldt[p] = cdiv(d[p], mixed ? 128 : 64) * (mixed ? 128 : 64);
+    m[p] = o.steps > 0 ? o.steps : cdiv(2 * n[p], b);
+    nwg[p] = grad_num_workgroups(n[p], d[p]);  // as in a single solve, so the sums agree bit for bit
+    o_xt[p] = t_xt;
+    t_xt += n[p] * ldt[p];
+    o_reg[p] = t_reg;
+    t_reg += d[p] * ldt[p];
+    o_beta[p] = t_beta;
+    t_beta += n[p] + d[p];
+    o_vec[p] = t_vec;
+    t_vec += d[p];
+    o_g64[p] = t_g64;
+    t_g64 += 16 * d[p];
+    o_gp[p] = t_gp;
+    t_gp += nwg[p] * d[p];
+    o_gr[p] = t_gr;
+    t_gr += nwg[p];
+    o_idx[p] = t_idx;
+    t_idx += (int64_t)G * m[p] * b;
+    o_ut[p] = t_ut;
+    t_ut += (int64_t)k[p] * d[p];
+    o_lam[p] = t_lam;
+    t_lam += k[p];
+    max_N = std::max(max_N, n[p] + d[p]);
+  }
+  void* xt_all = wsb(ctx, "b_xt", (size_t)t_xt * es);
+  void* reg_all = wsb(ctx, "b_reg", (size_t)t_reg * es);
+  if (!xt_all || !reg_all) return SCS_ENOMEM;
+  WS(beta_all, float, "b_beta", t_beta);
+  WS(cum_all, uint64_t, "b_cum", t_beta);
+  WS(vec_all, float, "b_vec", 4 * t_vec);  // wt | wt_prev | w32 | mu
+  WS(tmp_all, double, "b_tmp", t_vec);
+  WS(g64_all, double, "b_g64", t_g64);
+  WS(gp_all, float, "b_gpart", t_gp);
+  WS(gr_all, double, "b_grsq", t_gr);
+  WS(idx_all, int32_t, "b_idx", t_idx);
+  WS(sc_all, float, "b_scale", t_idx);
+  WS(ut_all, float, "b_UT", std::max<int64_t>(t_ut, 1));
+  WS(lam_all, double, "b_lam", std::max<int64_t>(t_lam, 1));
+  WS(xbuf_all, uint64_t, "b_xbuf", (int64_t)nprob * 2 * W * 64);
+  WS(states, SolveState, "b_state", nprob);
+  WS(flags_all, int, "b_cholflags", 2 * nprob);
+  WS(done_count, int, "b_done", 1);
+  WS(desc, BatchProb, "b_desc", nprob);
+  WS(prefix, int64_t, "b_prefix", 3 * ((int64_t)nprob + 1));
+  WS(wout_dev, float*, "b_wout", nprob);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(max_N));
+  SCS_HIP(hipMemsetAsync(states, 0, sizeof(SolveState) * nprob, st));
+  SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * t_vec, st));  // wt and wt_prev start at 0
+  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * nprob * 2 * W * 64, st));
+  SCS_HIP(hipMemsetAsync(flags_all, 0, sizeof(int) * 2 * nprob, st));
+  SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
+
+  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)4 + S));
+  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
+  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
+  hipEvent_t* dec = ctx->events.data();
+  hipEvent_t* tev = ctx->tevents.data();
+  SCS_HIP(hipEventRecord(tev[0], st));
+
+  // ---- per-problem setup (largest first, so shared sketch temporaries are sized once)
+  std::vector<int> ord(nprob);
+  for (int p = 0; p < nprob; ++p) ord[p] = p;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a_, int b_) { return n[a_] * d[a_] > n[b_] * d[b_]; });
+  auto setup_identity = [&](int p) -> int {
+    char* xt = (char*)xt_all + o_xt[p] * es;
+    char* rg = (char*)reg_all + o_reg[p] * es;
+    float* beta = beta_all + o_beta[p];
+    if (mixed) {
+      WS(tmp16, uint16_t, "xcopy16", n[p] * d[p]);
+      SCS_CHECK(launch_copy_bf16(st, X[p], n[p], d[p], ldx[p], tmp16));
+      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 2, tmp16, d[p] * 2, d[p] * 2, n[p], hipMemcpyDeviceToDevice, st));
+      SCS_CHECK(launch_rownorm_bf16(st, tmp16, n[p], d[p], beta));
+    } else {
+      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 4, X[p], ldx[p] * 4, d[p] * 4, n[p], hipMemcpyDeviceToDevice, st));
+      SCS_CHECK(launch_rownorm(st, X[p], n[p], d[p], ldx[p], beta));
+    }
+    WS(rtmp, float, "regtmp", d[p] * d[p]);
+    SCS_CHECK(launch_fill_scaled_identity(st, d[p], std::sqrt((double)n[p] * lambda[p]), mixed, rtmp, beta + n[p]));
+    SCS_HIP(hipMemcpy2DAsync(rg, ldt[p] * es, rtmp, d[p] * es, d[p] * es, d[p], hipMemcpyDeviceToDevice, st));
+    return SCS_OK;
+  };
+  for (int p : ord) {
+    if (k[p] > 0) {
+      bool unused = false;
+      SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p));
+      const float* U32 = ws<float>(ctx, "U32", 0);
+      SCS_HIP(hipMemcpyAsync(ut_all + o_ut[p], ws<float>(ctx, "UT32", 0), sizeof(float) * k[p] * d[p],
+                             hipMemcpyDeviceToDevice, st));
+      SCS_HIP(hipMemcpyAsync(lam_all + o_lam[p], ws<double>(ctx, "lam", 0), sizeof(double) * k[p],
+                             hipMemcpyDeviceToDevice, st));
+      SCS_CHECK(apply_impl(ctx, X[p], n[p], d[p], ldx[p], U32, ws<float>(ctx, "Z", 0), lam_all + o_lam[p], k[p],
+                           lambda[p], mixed, mixed, (char*)xt_all + o_xt[p] * es, (char*)reg_all + o_reg[p] * es,
+                           ldt[p], beta_all + o_beta[p], states + sidx[p]));
+    } else {
+      SCS_CHECK(setup_identity(p));
+    }
+  }
+  // CholeskyQR breakdown: those problems fall back to P = I (status SKETCH_RANK_DEFICIENT)
+  std::vector<int> hflags(2 * nprob, 0);
+  SCS_HIP(hipMemcpyAsync(hflags.data(), flags_all, sizeof(int) * 2 * nprob, hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  std::vector<int> k_used(nprob), rank_def(nprob, 0);
+  for (int p = 0; p < nprob; ++p) {
+    k_used[p] = k[p];
+    if (k[p] > 0 && (hflags[2 * p] || hflags[2 * p + 1])) {
+      rank_def[p] = 1;
+      k_used[p] = 0;
+      SCS_CHECK(setup_identity(p));
+    }
+  }
+  for (int p = 0; p < nprob; ++p)
+    SCS_CHECK(launch_sampler_prepare(st, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], scr,
+                                     sampler_scratch_len(max_N), states + sidx[p]));
+  SCS_HIP(hipEventRecord(tev[1], st));
+
+  // ---- descriptors and flattened-grid prefixes
+  std::vector<BatchProb> hp(nprob);
+  std::vector<int64_t> pre(3 * ((size_t)nprob + 1), 0);
+  int64_t* wg_pre = pre.data();
+  int64_t* cb_pre = wg_pre + nprob + 1;
+  int64_t* dr_pre = cb_pre + nprob + 1;
+  int64_t max_slice = 0, max_d_v = 0, max_d_s = 0;
+  std::vector<float*> wout_k(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const int p = kord[i];
+    BatchProb& q = hp[i];
+    wout_k[i] = w_out[p];
+    (i < nv ? max_d_v : max_d_s) = std::max(i < nv ? max_d_v : max_d_s, d[p]);
+    std::memset(&q, 0, sizeof(q));
+    q.X = X[p];
+    q.n = n[p];
+    q.d = d[p];
+    q.ldx = ldx[p];
+    q.y = y[p];
+    q.lambda = lambda[p];
+    q.k = k_used[p];
+    q.UT = k_used[p] > 0 ? ut_all + o_ut[p] : nullptr;
+    q.lam = k_used[p] > 0 ? lam_all + o_lam[p] : nullptr;
+    q.wt = vec_all + o_vec[p];
+    q.wt_prev = vec_all + t_vec + o_vec[p];
+    q.w32 = vec_all + 2 * t_vec + o_vec[p];
+    q.mu = vec_all + 3 * t_vec + o_vec[p];
+    q.tmp = tmp_all + o_vec[p];
+    q.state = states + i;
+    q.gpart = gp_all + o_gp[p];
+    q.grsq = gr_all + o_gr[p];
+    q.g64 = g64_all + o_g64[p];
+    q.nwg = (int)nwg[p];
+    q.stop_rule = o.stop_rule;
+    q.eps = eps;
+    q.f_star = 0.0;
+    q.cum = cum_all + o_beta[p];
+    q.N = n[p] + d[p];
+    q.draws = m[p] * b;
+    q.idx = idx_all + o_idx[p];
+    q.scale = sc_all + o_idx[p];
+    InnerArgs& a = q.inner;
+    a.n = n[p];
+    a.d = d[p];
+    a.Xt = (char*)xt_all + o_xt[p] * es;
+    a.ldx = ldt[p];
+    a.reg = (char*)reg_all + o_reg[p] * es;
+    a.ldr = ldt[p];
+    a.mu = q.mu;
+    a.m = m[p];
+    a.b = b;
+    a.eta_from_state = 1;
+    a.step_scale = o.step_scale;
+    a.average = o.average;
+    a.W = W;
+    a.xcd_stride = 1;
+    a.slice = cdiv(cdiv(d[p], W), 4) * 4;
+    a.wt = q.wt;
+    a.wt_prev = q.wt_prev;
+    a.xbuf = xbuf_all + (int64_t)p * 2 * W * 64;
+    a.state = q.state;
+    max_slice = std::max(max_slice, a.slice);
+    wg_pre[i + 1] = wg_pre[i] + nwg[p];
+    cb_pre[i + 1] = cb_pre[i] + cdiv(d[p], 64);
+    dr_pre[i + 1] = dr_pre[i] + (int64_t)G * m[p] * b;
+  }
+  if (max_slice > 512) {
+    set_error("batched solve: column slice too wide");
+    return SCS_EINVAL;
+  }
+  SCS_HIP(hipMemcpyAsync(desc, hp.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice, st));
+  SCS_HIP(hipMemcpyAsync(prefix, pre.data(), sizeof(int64_t) * pre.size(), hipMemcpyHostToDevice, st));
+  SCS_HIP(hipMemcpyAsync(wout_dev, wout_k.data(), sizeof(float*) * nprob, hipMemcpyHostToDevice, st));
+  const int64_t* d_wg = prefix;
+  const int64_t* d_cb = prefix + nprob + 1;
+  const int64_t* d_dr = prefix + 2 * (nprob + 1);
+
+  // ---- epochs of all problems in shared launches (Alg. 1 per problem)
+  constexpr int kLookahead = 3;
+  for (int s = 0; s <= S; ++s) {
+    SCS_CHECK(launch_premap_batched(st, desc, nprob, 0, nullptr));
+    SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, 0, wg_pre[nv], max_d_v, 1));
+    SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, wg_pre[nv], wg_pre[nprob] - wg_pre[nv], max_d_s, 0));
+    SCS_CHECK(launch_grad_finish_batched(st, desc, nprob, d_cb, cb_pre[nprob], s == 0 ? 1 : 0, done_count,
+                                         ctx->stop_flags + s));
+    if (s == S) {
+      SCS_HIP(hipEventRecord(dec[s], st));
+      break;
+    }
+    const int slot = s % G;
+    if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, nprob, d_dr, dr_pre[nprob], o.seed, s, G));
+    SCS_HIP(hipEventRecord(dec[s], st));
+    SCS_CHECK(launch_inner_epoch_batched(st, desc, nprob, W, max_slice, b, mixed, slot, s));
+    SCS_HIP(hipEventRecord(tev[4 + s], st));
+    if (s + 1 >= kLookahead) {
+      const int q = s + 1 - kLookahead;
+      SCS_HIP(hipEventSynchronize(dec[q]));
+      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+    }
+  }
+  SCS_CHECK(launch_premap_batched(st, desc, nprob, 1, wout_dev));
+  SCS_HIP(hipEventRecord(tev[3], st));
+  std::vector<SolveState> hs(nprob);
+  SCS_HIP(hipMemcpyAsync(hs.data(), states, sizeof(SolveState) * nprob, hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+
+  int worst = SCS_OK;
+  float t_setup = 0.f, t_solve = 0.f;
+  hipEventElapsedTime(&t_setup, tev[0], tev[1]);
+  hipEventElapsedTime(&t_solve, tev[1], tev[3]);
+  for (int p = 0; p < nprob; ++p) {
+    const SolveState& h = hs[sidx[p]];
+    int status = SCS_OK;
+    if (h.status == SCS_ENONFINITE || h.status == SCS_EDEVICE) status = h.status;
+    else if (h.status == SCS_DIVERGED) status = SCS_DIVERGED;
+    else if (o.stop_rule != SCS_STOP_EPOCHS && !h.done) status = SCS_NOT_CONVERGED;
+    else if (rank_def[p]) status = SCS_SKETCH_RANK_DEFICIENT;
+    if (status < 0) worst = std::min(worst, status);
+    else if (worst >= 0) worst = std::max(worst, status);
+    if (reports) {
+      scs_report& r = reports[p];
+      std::memset(&r, 0, sizeof(r));
+      r.status = status;
+      r.epochs = h.epochs;
+      r.k_used = k_used[p];
+      r.steps = m[p];
+      r.eta = h.eta;
+      r.beta_hat = h.beta_sum / (double)n[p];
+      r.objective = h.obj;
+      r.grad_norm = std::sqrt(h.gnorm2);
+      r.certificate = h.cert;
+      r.lam_top = h.lam_top;
+      r.ms_sketch = t_setup;
+      r.ms_apply = 0.0;
+      r.ms_solve = t_solve;
+    }
+  }
+  if (worst == SCS_ENONFINITE) set_error("non-finite value in X or y of at least one problem");
+  if (worst == SCS_EDEVICE) set_error("inner loop: a cross-workgroup wait exceeded its budget");
+  return worst;
 }
 
 }  // extern "C"

@@ -30,19 +30,16 @@ __device__ __forceinline__ void vload(const float* p, float& v) { v = *p; }
 __device__ __forceinline__ float comp(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 __device__ __forceinline__ float comp(const float& v, int) { return v; }
 
+// Workgroup wg of nwg covering rows [wg ceil(n/nwg), (wg+1) ceil(n/nwg)) of one problem.
 template <int VEC, int NCH>
-__global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float* __restrict__ X, int64_t n,
-                                                                    int64_t d, int64_t ldx,
-                                                                    const float* __restrict__ y,
-                                                                    const float* __restrict__ w,
-                                                                    float* __restrict__ part,
-                                                                    double* __restrict__ rsq_part,
-                                                                    const SolveState* state) {
-  if (state && state->done) return;
+__device__ __forceinline__ void grad_partial_body(const float* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
+                                                  const float* __restrict__ y, const float* __restrict__ w,
+                                                  float* __restrict__ part, double* __restrict__ rsq_part,
+                                                  int64_t wg, int64_t nwg) {
   using V = typename VecT<VEC>::T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t rows_per_wg = cdiv(n, (int64_t)gridDim.x);
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t rows_per_wg = cdiv(n, nwg);
+  const int64_t r0 = wg * rows_per_wg;
   const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
 
   float wv[NCH][VEC], acc[NCH][VEC], cmp[NCH][VEC];
@@ -143,7 +140,7 @@ __global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float*
   }
   __syncthreads();
   if (wave == 0) {
-    float* out = part + (int64_t)blockIdx.x * d;
+    float* out = part + wg * d;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       int64_t col = (int64_t)(c * 64 + lane) * VEC;
@@ -157,9 +154,34 @@ __global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float*
     if (lane == 0) {
       double t = 0.0;
       for (int q = 0; q < kGradWaves; ++q) t += srsq[q];
-      rsq_part[blockIdx.x] = t;
+      rsq_part[wg] = t;
     }
   }
+}
+
+template <int VEC, int NCH>
+__global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float* __restrict__ X, int64_t n,
+                                                                    int64_t d, int64_t ldx,
+                                                                    const float* __restrict__ y,
+                                                                    const float* __restrict__ w,
+                                                                    float* __restrict__ part,
+                                                                    double* __restrict__ rsq_part,
+                                                                    const SolveState* state) {
+  if (state && state->done) return;
+  grad_partial_body<VEC, NCH>(X, n, d, ldx, y, w, part, rsq_part, blockIdx.x, gridDim.x);
+}
+
+// All problems of a batch in one launch: problem p owns workgroups [wg_prefix[p], wg_prefix[p+1]).
+// Workgroups [base, base + gridDim.x) of the batch's flattened grid (problems sharing one row layout
+// are launched together).
+template <int VEC, int NCH>
+__global__ __launch_bounds__(kGradThreads) void grad_partial_batched_kernel(const BatchProb* P, int nprob,
+                                                                            const int64_t* wg_prefix, int64_t base) {
+  const int64_t x = base + blockIdx.x;
+  const int p = find_prob(wg_prefix, nprob, x);
+  const BatchProb& q = P[p];
+  if (q.state->done) return;
+  grad_partial_body<VEC, NCH>(q.X, q.n, q.d, q.ldx, q.y, q.w32, q.gpart, q.grsq, x - wg_prefix[p], q.nwg);
 }
 
 template <int VEC, int NCH>
@@ -170,7 +192,35 @@ int launch_t(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, 
   return SCS_OK;
 }
 
+template <int VEC, int NCH>
+int launch_bt(hipStream_t st, const BatchProb* P, int nprob, const int64_t* wg_prefix, int64_t base, int64_t count) {
+  grad_partial_batched_kernel<VEC, NCH><<<(unsigned)count, kGradThreads, 0, st>>>(P, nprob, wg_prefix, base);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
 }  // namespace
+
+int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* wg_prefix,
+                                int64_t base, int64_t count, int64_t max_d, int vec4) {
+  if (nprob < 1 || count < 1) return SCS_OK;
+  if (vec4) {
+    int64_t nch = cdiv(max_d, 256);
+    if (nch <= 1) return launch_bt<4, 1>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 2) return launch_bt<4, 2>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 4) return launch_bt<4, 4>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 8) return launch_bt<4, 8>(st, P, nprob, wg_prefix, base, count);
+  } else {
+    int64_t nch = cdiv(max_d, 64);
+    if (nch <= 1) return launch_bt<1, 1>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 2) return launch_bt<1, 2>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 4) return launch_bt<1, 4>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 8) return launch_bt<1, 8>(st, P, nprob, wg_prefix, base, count);
+    if (nch <= 16) return launch_bt<1, 16>(st, P, nprob, wg_prefix, base, count);
+  }
+  set_error("batched full gradient: d too large for the register-resident row layout");
+  return SCS_EINVAL;
+}
 
 int grad_num_workgroups(int64_t n, int64_t d) {
   (void)d;

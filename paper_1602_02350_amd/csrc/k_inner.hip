@@ -57,14 +57,9 @@ __device__ __forceinline__ float rowgroup_sum(float v) {
 // in order per wave). Rows live in a two-slot ring whose roles alternate at compile time.
 // Data rows and regularizer rows share one leading dimension, so a row address is one
 // multiply-add from a base selected by the index range.
+// Workgroup w (0 <= w < a.W) of one problem's inner loop.
 template <int RPT, int CPT, bool BF16>
-__global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a) {
-  const int bid = blockIdx.x;
-  if (bid % a.xcd_stride != 0) return;
-  const int w = bid / a.xcd_stride;
-  if (w >= a.W) return;
-  if (a.state->done) return;
-
+__device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w) {
   constexpr int ES = BF16 ? 2 : 4;          // bytes per element
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index made provably uniform so that wave-0-only work compiles to scalar branches
@@ -282,6 +277,58 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
 }
 
 template <int RPT, int CPT, bool BF16>
+__global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a) {
+  const int bid = blockIdx.x;
+  if (bid % a.xcd_stride != 0) return;
+  const int w = bid / a.xcd_stride;
+  if (w >= a.W) return;
+  if (a.state->done) return;
+  inner_epoch_body<RPT, CPT, BF16>(a, w);
+}
+
+// All problems of a batch: block w * nprob + p is workgroup w of problem p (with nprob a multiple
+// of 8 the W workgroups of a problem share an XCD). The epoch's index stream is slot `slot` of the
+// problem's sampled group.
+template <int RPT, int CPT, bool BF16>
+__global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(const BatchProb* P, int nprob, int slot,
+                                                                            int64_t epoch) {
+  const int p = blockIdx.x % nprob, w = blockIdx.x / nprob;
+  InnerArgs a = P[p].inner;
+  if (w >= a.W || a.state->done) return;
+  a.idx = P[p].idx + slot * P[p].draws;
+  a.scale = P[p].scale + slot * P[p].draws;
+  a.step_base = (uint32_t)((uint64_t)epoch * (uint64_t)a.m);
+  inner_epoch_body<RPT, CPT, BF16>(a, w);
+}
+
+template <int RPT, int CPT, bool BF16>
+int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, int64_t epoch) {
+  dim3 grid((unsigned)(nprob * W)), block(kInnerThreads);
+  if (W > 1) {
+    // the workgroups of a problem wait on each other: they must all be resident
+    void* args[] = {&P, &nprob, &slot, &epoch};
+    SCS_HIP(hipLaunchCooperativeKernel((const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>, grid, block, args, 0,
+                                       st));
+  } else {
+    inner_epoch_batched_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch);
+    SCS_HIP(hipGetLastError());
+  }
+  return SCS_OK;
+}
+
+template <int RPT, bool BF16>
+int launch_bc(hipStream_t st, const BatchProb* P, int nprob, int W, int cpt, int slot, int64_t epoch) {
+  switch (cpt) {
+    case 1: return launch_bt<RPT, 1, BF16>(st, P, nprob, W, slot, epoch);
+    case 2: return launch_bt<RPT, 2, BF16>(st, P, nprob, W, slot, epoch);
+    case 3: return launch_bt<RPT, 3, BF16>(st, P, nprob, W, slot, epoch);
+    case 4: return launch_bt<RPT, 4, BF16>(st, P, nprob, W, slot, epoch);
+  }
+  set_error("batched inner loop: column slice too wide (more than 512 columns per workgroup)");
+  return SCS_EINVAL;
+}
+
+template <int RPT, int CPT, bool BF16>
 int launch_t(hipStream_t st, InnerArgs& a) {
   dim3 grid((unsigned)(a.W * a.xcd_stride)), block(kInnerThreads);
   if (a.W > 1) {
@@ -332,6 +379,22 @@ int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
   if (rpt <= 1) return bf16 ? launch_c<1, true>(st, a, cpt) : launch_c<1, false>(st, a, cpt);
   if (rpt <= 2) return bf16 ? launch_c<2, true>(st, a, cpt) : launch_c<2, false>(st, a, cpt);
   return bf16 ? launch_c<4, true>(st, a, cpt) : launch_c<4, false>(st, a, cpt);
+}
+
+int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
+                               int bf16, int epoch_slot, int64_t epoch) {
+  if (nprob < 1) return SCS_OK;
+  if (max_b < 1 || max_b > 64 || W < 1 || W > 16) {
+    set_error("batched inner loop: need 1 <= b <= 64 and 1 <= workgroups <= 16");
+    return SCS_EINVAL;
+  }
+  const int cpt = (int)cdiv(max_slice, 128), rpt = (int)cdiv(max_b, 16);
+  if (rpt <= 1) return bf16 ? launch_bc<1, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
+                            : launch_bc<1, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
+  if (rpt <= 2) return bf16 ? launch_bc<2, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
+                            : launch_bc<2, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
+  return bf16 ? launch_bc<4, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
+              : launch_bc<4, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
 }
 
 }  // namespace scs

@@ -172,12 +172,35 @@ __device__ __forceinline__ float inv_nq(const uint64_t* cum, int64_t i, int64_t 
 // Draws `count` indices for consecutive epochs epoch0, epoch0 + 1, ... (per_epoch draws each); draw
 // g of epoch e uses Philox call g/2 with counter (call_lo, call_hi, e, 0), words (x0, x1) for even g
 // and (x2, x3) for odd g, so a multi-epoch launch draws exactly what per-epoch launches would.
+__device__ __forceinline__ void sample_one(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed,
+                                           uint32_t epoch0, int64_t per_epoch, int64_t g, int32_t* idx,
+                                           float* scale);
+
 __global__ void sample_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, uint32_t epoch0,
                               int64_t per_epoch, int64_t count, int32_t* idx, float* scale,
                               const SolveState* state) {
   if (state && state->done) return;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= count) return;
+  sample_one(cum, N, n_rows, seed, epoch0, per_epoch, g, idx, scale);
+}
+
+// Batched: draw g of the launch belongs to problem p with draw_prefix[p] <= g < draw_prefix[p+1];
+// each problem draws `groups` epochs of its own m b draws from its own weights (same stream as a
+// single solve with the same seed).
+__global__ void sample_batched_kernel(const BatchProb* P, int nprob, const int64_t* draw_prefix, int64_t total,
+                                      uint64_t seed, uint32_t epoch0) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int p = find_prob(draw_prefix, nprob, g);
+  const BatchProb& q = P[p];
+  if (q.state->done) return;
+  sample_one(q.cum, q.N, q.n, seed, epoch0, q.draws, g - draw_prefix[p], q.idx, q.scale);
+}
+
+__device__ __forceinline__ void sample_one(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed,
+                                           uint32_t epoch0, int64_t per_epoch, int64_t g, int32_t* idx,
+                                           float* scale) {
   const uint32_t epoch = epoch0 + (uint32_t)(g / per_epoch);
   const int64_t gl = g % per_epoch;
   uint64_t c = (uint64_t)gl >> 1;
@@ -242,6 +265,17 @@ int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows
   if (per_epoch <= 0) per_epoch = count;
   sample_kernel<<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, seed, (uint32_t)epoch,
                                                                         per_epoch, count, idx, scale, state);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
+                          int64_t total_draws, uint64_t seed, int epoch, int groups) {
+  (void)groups;
+  if (total_draws <= 0) return SCS_OK;
+  sample_batched_kernel<<<dim3((unsigned)cdiv(total_draws, 256)), dim3(256), 0, st>>>(P, nprob, draw_prefix,
+                                                                                       total_draws, seed,
+                                                                                       (uint32_t)epoch);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

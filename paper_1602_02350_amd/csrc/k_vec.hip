@@ -69,11 +69,8 @@ __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* _
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, const float* U, const double* lam,
-                                                             int k, int64_t d, double lambda, const float* wt,
-                                                             float* w, float* trace_row, double* tmp,
-                                                             const SolveState* state) {
-  if (state && state->done) return;
+__device__ __forceinline__ void premap_body(const float* UT, const double* lam, int k, int64_t d, double lambda,
+                                            const float* wt, float* w, float* trace_row, double* tmp) {
   __shared__ double tbuf[256];
   pmhalf_apply_block<float>(UT, lam, k, d, lambda, wt, tmp, tbuf);
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
@@ -83,19 +80,38 @@ __global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, co
   }
 }
 
+__global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, const double* lam, int k, int64_t d,
+                                                             double lambda, const float* wt, float* w,
+                                                             float* trace_row, double* tmp,
+                                                             const SolveState* state) {
+  if (state && state->done) return;
+  premap_body(UT, lam, k, d, lambda, wt, w, trace_row, tmp);
+}
+
+// One workgroup per problem: w = P^{-1/2} w~ at the snapshot (skipped once a problem is done), or,
+// with final_out, the returned weights of every problem.
+__global__ __launch_bounds__(kVecThreads) void premap_batched_kernel(const BatchProb* P, int final_out,
+                                                                     float* const* w_out) {
+  const BatchProb& q = P[blockIdx.x];
+  if (final_out) {
+    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, w_out[blockIdx.x], nullptr, q.tmp);
+  } else {
+    if (q.state->done) return;
+    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, q.w32, nullptr, q.tmp);
+  }
+}
+
 // First level of the cross-workgroup sum of the gradient partials, in FP64 and a fixed order:
 // workgroup (bx, by) sums partial rows [by R, (by+1) R) of columns [64 bx, 64 bx + 64) into
 // g2[by][j]; grad_finalize adds the kColSplit rows of g2 in order.
 constexpr int kColSplit = 16;
 
-__global__ __launch_bounds__(256) void grad_colreduce_kernel(const float* part, int nwg, int64_t d, double* g2,
-                                                             const SolveState* state) {
-  if (state && state->done) return;
+__device__ __forceinline__ void colreduce_body(const float* part, int nwg, int64_t d, double* g2, int64_t bx, int by) {
   __shared__ double sacc[4][64];
   const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  const int64_t j = bx * 64 + c;
   const int R = (nwg + kColSplit - 1) / kColSplit;
-  const int r0 = blockIdx.y * R, r1 = r0 + R < nwg ? r0 + R : nwg;
+  const int r0 = by * R, r1 = r0 + R < nwg ? r0 + R : nwg;
   double acc = 0.0;
   if (j < d) {
 #pragma unroll 4
@@ -103,19 +119,30 @@ __global__ __launch_bounds__(256) void grad_colreduce_kernel(const float* part, 
   }
   sacc[rs][c] = acc;
   __syncthreads();
-  if (rs == 0 && j < d) g2[(int64_t)blockIdx.y * d + j] = ((sacc[0][c] + sacc[1][c]) + sacc[2][c]) + sacc[3][c];
+  if (rs == 0 && j < d) g2[(int64_t)by * d + j] = ((sacc[0][c] + sacc[1][c]) + sacc[2][c]) + sacc[3][c];
 }
 
-__global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
-    const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w, double lambda,
-    const float* UT, const float* U, const double* lam, int k, float* mu, double* tmp, SolveState* state,
-    int stop_rule, double eps, double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
-  // host_stop (host-pinned, may be null) receives 1 once no further epoch will change anything, so the
-  // host can stop enqueuing epochs; it is a plain system-scope store from one lane
-  if (state->done) {
-    if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    return;
-  }
+__global__ __launch_bounds__(256) void grad_colreduce_kernel(const float* part, int nwg, int64_t d, double* g2,
+                                                             const SolveState* state) {
+  if (state && state->done) return;
+  colreduce_body(part, nwg, d, g2, blockIdx.x, blockIdx.y);
+}
+
+// problem p owns column blocks [cb_prefix[p], cb_prefix[p+1]) of grid dimension x
+__global__ __launch_bounds__(256) void grad_colreduce_batched_kernel(const BatchProb* P, int nprob,
+                                                                     const int64_t* cb_prefix) {
+  const int p = find_prob(cb_prefix, nprob, blockIdx.x);
+  const BatchProb& q = P[p];
+  if (q.state->done) return;
+  colreduce_body(q.gpart, q.nwg, q.d, q.g64, blockIdx.x - cb_prefix[p], blockIdx.y);
+}
+
+// Finish of the gradient at the snapshot for one problem (one workgroup); returns the action taken
+// (0 continue, 1 converged, 2 diverged and restored, 3 non-finite input), the same in every thread.
+__device__ int finalize_body(const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d,
+                             const float* w, double lambda, const float* UT, const double* lam, int k, float* mu,
+                             double* tmp, SolveState* state, int stop_rule, double eps, double f_star, float* wt_cur,
+                             const float* wt_prev, int first) {
   __shared__ double tbuf[256];
   __shared__ double sred[kVecWaves];
   __shared__ int s_action;
@@ -144,8 +171,11 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   rs = block_sum_d(rs, sred);
   if (threadIdx.x == 0) {
     double obj = rs / (2.0 * (double)n) + 0.5 * lambda * wn;
+    // H~ = P^{-1/2} H P^{-1/2} >= lambda P^{-1} >= lambda / (lam_1 + lambda) I, so
+    // L - L* <= ||mu||^2 / (2 lambda_min(H~)) <= ||mu||^2 (lam_1 + lambda) / (2 lambda); with P = I the
+    // factor lam_1 + lambda is 1
     double lam_top = k > 0 ? fmax(lam[0], 0.0) : 0.0;
-    double cert = gn * (lam_top + lambda) / (2.0 * lambda);
+    double cert = gn * (k > 0 ? lam_top + lambda : 1.0) / (2.0 * lambda);
     bool finite = isfinite(obj) && isfinite(gn);
     int action = 0;  // 0 = continue, 1 = stop (converged), 2 = diverged (restore), 3 = non-finite input
     if (first) {
@@ -172,7 +202,6 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
       state->status = SCS_ENONFINITE;
     }
     s_action = action;
-    if (host_stop) __hip_atomic_store(host_stop, action != 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   __syncthreads();
   if (s_action == 2 && wt_prev) {
@@ -180,6 +209,37 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   }
   if (s_action == 0 || s_action == 1) {
     for (int64_t j = threadIdx.x; j < d; j += blockDim.x) mu[j] = (float)tmp[j];
+  }
+  return s_action;
+}
+
+__global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
+    const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w, double lambda,
+    const float* UT, const double* lam, int k, float* mu, double* tmp, SolveState* state, int stop_rule, double eps,
+    double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
+  // host_stop (host-pinned, may be null) receives 1 once no further epoch will change anything, so the
+  // host can stop enqueuing epochs; it is a plain system-scope store from one lane
+  if (state->done) {
+    if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
+  const int action = finalize_body(g_in, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp, state, stop_rule, eps,
+                                   f_star, wt_cur, wt_prev, first);
+  if (host_stop && threadIdx.x == 0)
+    __hip_atomic_store(host_stop, action != 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One workgroup per problem. A problem that finishes in this launch adds one to done_count; the
+// workgroup that brings it to nprob sets the host-pinned flag (the host then stops enqueuing).
+__global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(const BatchProb* P, int nprob, int first,
+                                                                            int* done_count, int* host_stop) {
+  const BatchProb& q = P[blockIdx.x];
+  if (q.state->done) return;
+  const int action = finalize_body(q.g64, q.grsq, q.nwg, q.n, q.d, q.w32, q.lambda, q.UT, q.lam, q.k, q.mu, q.tmp,
+                                   q.state, q.stop_rule, q.eps, q.f_star, q.wt, q.wt_prev, first);
+  if (action != 0 && threadIdx.x == 0) {
+    const int before = atomicAdd(done_count, 1);
+    if (before + 1 == nprob && host_stop) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -287,7 +347,8 @@ __global__ void precond_setup_kernel(const double* lam, int k, double lambda, in
 int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,
                   const SolveState* state) {
-  premap_kernel<<<1, kVecThreads, 0, st>>>(UT, U, lam, k, d, lambda, wt, w, trace_row, tmp, state);
+  (void)U;
+  premap_kernel<<<1, kVecThreads, 0, st>>>(UT, lam, k, d, lambda, wt, w, trace_row, tmp, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
@@ -298,8 +359,26 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
                        double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
   grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
   SCS_HIP(hipGetLastError());
-  grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, U, lam, k, mu, tmp,
+  (void)U;
+  grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp,
                                                   state, stop_rule, eps, f_star, wt_cur, wt_prev, first, host_stop);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_premap_batched(hipStream_t st, const BatchProb* P, int nprob, int final_out, float* const* w_out) {
+  if (nprob < 1) return SCS_OK;
+  premap_batched_kernel<<<nprob, kVecThreads, 0, st>>>(P, final_out, w_out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
+                               int64_t total_cb, int first, int* done_count, int* host_stop) {
+  if (nprob < 1) return SCS_OK;
+  grad_colreduce_batched_kernel<<<dim3((unsigned)total_cb, kColSplit), dim3(256), 0, st>>>(P, nprob, cb_prefix);
+  SCS_HIP(hipGetLastError());
+  grad_finalize_batched_kernel<<<nprob, kVecThreads, 0, st>>>(P, nprob, first, done_count, host_stop);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

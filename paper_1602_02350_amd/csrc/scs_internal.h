@@ -86,6 +86,17 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Problem owning unit x of a flattened batched grid: the largest p with prefix[p] <= x.
+__device__ __forceinline__ int find_prob(const int64_t* prefix, int nprob, int64_t x) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------- device-side solver state
 // One record per problem, written by the kernels and read back by the host at the end.
 struct SolveState {
@@ -182,5 +193,46 @@ struct InnerArgs {
 };
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
 int inner_default_workgroups(int64_t d);
+
+// ---------------------------------------------------------------- batched solves
+// One problem of a batched solve; an array of these lives in device memory and every batched
+// kernel finds its problem from its block index (flattened grids use the prefix arrays below).
+struct BatchProb {
+  const float* X;        // n x d, leading dimension ldx (the gradient pass streams X itself)
+  int64_t n, d, ldx;
+  const float* y;
+  double lambda;
+  const float* UT;       // k x d (FP32) and the Ritz values; k = 0: P = I
+  const double* lam;
+  int k;
+  float* wt;             // snapshot w~ (in/out)
+  float* wt_prev;
+  float* w32;            // w = P^{-1/2} w~ at the snapshot
+  float* mu;             // P^{-1/2}-mapped gradient (inner loop input)
+  double* tmp;           // d doubles
+  SolveState* state;
+  float* gpart;          // nwg x d gradient partials
+  double* grsq;          // nwg residual partials
+  double* g64;           // 16 x d first-level column sums
+  int nwg;
+  int stop_rule;
+  double eps, f_star;
+  const uint64_t* cum;   // cumulative integer sampling weights over N = n + d components
+  int64_t N;
+  int64_t draws;         // m b draws per epoch
+  int32_t* idx;          // kSampleGroup epochs of draws
+  float* scale;
+  InnerArgs inner;       // idx / scale / step_base are set per epoch by the batched launchers
+};
+// flattened grids: prefix[p] = first unit of problem p, prefix[nprob] = total
+int launch_premap_batched(hipStream_t st, const BatchProb* P, int nprob, int final_out, float* const* w_out);
+int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* wg_prefix,
+                                int64_t base, int64_t count, int64_t max_d, int vec4);
+int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
+                               int64_t total_cb, int first, int* done_count, int* host_stop);
+int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
+                          int64_t total_draws, uint64_t seed, int epoch, int groups);
+int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
+                               int bf16, int epoch_slot, int64_t epoch);
 
 }  // namespace scs

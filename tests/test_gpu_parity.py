@@ -272,3 +272,92 @@ def test_epoch_cap_reports_not_converged(ctx):
     res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 0, 1e-30, max_epochs=2)
     assert res.status == binding.NOT_CONVERGED
     assert res.report["epochs"] == 2
+
+
+# ------------------------------------------------------------------ batched solves
+def _uneven_batch(shapes, seed0=40):
+    probs = []
+    for i, (n, d, alpha, lam, k) in enumerate(shapes):
+        P = inputs.make_ridge(n, d, alpha, lam, seed=seed0 + i)
+        probs.append((P, k))
+    return probs
+
+
+UNEVEN = [(1500, 100, 2.0, 1e-4, 6), (700, 37, 1.2, 1e-3, 2), (3000, 257, 1.5, 1e-5, 16),
+          (400, 64, 2.5, 1e-6, 4), (2200, 130, 1.8, 1e-4, 0), (900, 24, 1.0, 3e-4, 1)]
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_equals_single_solves(ctx, mixed):
+    """The batched launches run the same kernels in the same order per problem: bit-identical to
+    single solves with one workgroup per inner loop."""
+    probs = _uneven_batch(UNEVEN)
+    common = dict(batch=16, steps=50, max_epochs=3, stop_rule=binding.STOP_EPOCHS, step_scale=1.0, seed=99,
+                  precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    rc, wb, reps = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 0.0, **common)
+    for i, (P, k) in enumerate(probs):
+        r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, workgroups=1, **common)
+        assert reps[i]["status"] == r.status, (i, reps[i]["status"], r.status)
+        assert torch.equal(wb[i], r.w), (i, rel(host(wb[i]), host(r.w)))
+        assert reps[i]["epochs"] == r.report["epochs"] and reps[i]["k_used"] == k
+    assert rc == binding.OK, [r["status"] for r in reps]
+
+
+def test_batched_wide_problem_uses_cooperating_workgroups(ctx):
+    probs = _uneven_batch([(2000, 600, 1.5, 1e-4, 8), (800, 90, 2.0, 1e-3, 3), (1200, 513, 1.2, 1e-4, 0)], seed0=60)
+    common = dict(batch=32, steps=40, max_epochs=2, stop_rule=binding.STOP_EPOCHS, step_scale=1.0, seed=5)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    rc, wb, _ = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 0.0, **common)
+    assert rc == binding.OK
+    for i, (P, k) in enumerate(probs):
+        r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, workgroups=2, **common)   # W = ceil(600 / 512)
+        assert torch.equal(wb[i], r.w), i
+
+
+WELL_POSED = [(1500, 100, 2.0, 1e-4, 10), (700, 37, 1.2, 1e-3, 2), (3000, 257, 1.5, 1e-4, 16),
+              (400, 64, 2.5, 1e-4, 8), (2200, 130, 1.8, 1e-3, 0), (900, 24, 1.0, 3e-4, 1)]
+
+
+def test_batched_solves_reach_their_closed_forms(ctx):
+    probs = _uneven_batch(WELL_POSED, seed0=70)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    rc, wb, reps = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 1e-10,
+                                          batch=16, max_epochs=150, stop_rule=binding.STOP_CERTIFICATE,
+                                          step_scale=2.0)
+    assert rc == binding.OK, [r["status"] for r in reps]
+    for i, (P, k) in enumerate(probs):
+        X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+        ws = ridge.closed_form(X64, y64, P.lam)
+        # the certificate bounds the gap: L(w) - L* <= 1e-10 (plus FP32 evaluation error)
+        assert ridge.suboptimality(X64, P.lam, host(wb[i]), ws) <= 2e-10, i
+        assert reps[i]["certificate"] <= 1e-10
+
+
+def test_batched_rejects_what_it_cannot_do(ctx):
+    probs = _uneven_batch(UNEVEN[:2])
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    with pytest.raises(binding.ScsError) as e:
+        ctx.svrg_solve_batched(Xs, ys, [1e-3, 1e-3], [2, 2], 1e-6, stop_rule=binding.STOP_GAP)
+    assert e.value.code == binding.EINVAL
+    with pytest.raises(binding.ScsError) as e:
+        ctx.svrg_solve_batched(Xs, ys, [1e-3, 1e-3], [2, 40], 1e-6)   # k + p > d for the second problem
+    assert e.value.code == binding.EINVAL
+
+
+@pytest.mark.parametrize("k", [0, 6])
+def test_certificate_bounds_the_gap(ctx, k):
+    """Stopping on the certificate guarantees L(w) - L* <= eps, with and without the preconditioner."""
+    P = inputs.make_ridge(3000, 80, 1.5, 1e-3, seed=36)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, P.lam)
+    eps = 1e-9
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, k, eps, batch=16, max_epochs=200,
+                         stop_rule=binding.STOP_CERTIFICATE, step_scale=2.0)
+    assert res.status == binding.OK, res.report
+    assert res.report["certificate"] <= eps
+    assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= eps * 1.01
