@@ -190,6 +190,23 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
                            const double* lambda, const int* k, double eps, const scs_opts* opts,
                            float* const* w_out, scs_report* reports);
 
+/*
+ * Regularization path with one shared sketch: one X, ny right-hand sides and nl values of lambda,
+ * nl * ny solves. The sketch of X (Alg. 2; it does not involve lambda) is built once; every lambda
+ * gets its own preconditioner from the same U~ and lam~ (Eq. (condSketch) with that lambda) and its
+ * own preconditioned rows, sampling weights and step size; the ny solves of one lambda share them.
+ * All solves advance together: each epoch's full gradients are two FP32 MFMA GEMMs over X
+ * (R = X W^T - Y, G = X^T R, FP64 sums of the row-chunk partials), and one batched launch runs every
+ * inner loop.
+ *   X: n x d (ld ldx), Y: ny x n row-major (right-hand side r is row r), both device FP32.
+ *   lambdas: HOST array of nl. W_out: device (nl * ny) x d row-major; solve (j, r) is row j * ny + r.
+ *   reports: HOST array of nl * ny, nullable (same order). Stop rule: certificate or epoch count;
+ *   omega, indices and trace_w must be NULL. Workspace grows with nl (one set of rows per lambda).
+ */
+int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y,
+                        int ny, const double* lambdas, int nl, int k, double eps, const scs_opts* opts,
+                        float* W_out, scs_report* reports);
+
 #ifdef __cplusplus
 }
 #endif

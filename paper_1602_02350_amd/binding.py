@@ -22,7 +22,7 @@ STOP_EPOCHS, STOP_CERTIFICATE, STOP_GAP = 0, 1, 2
 EXPORTED = [
     "scs_opts_default", "scs_status_string", "scs_last_error", "scs_create", "scs_destroy",
     "scs_sketch_build", "scs_precondition_apply", "scs_full_gradient", "scs_svrg_epoch",
-    "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched",
+    "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched", "scs_svrg_solve_path",
 ]
 
 
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_svrg_solve.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), vp, P(ScsReport)]
     L.scs_svrg_solve_batched.argtypes = [vp, i32, P(vp), P(i64), P(i64), P(i64), P(vp), P(dbl), P(i32), dbl,
                                          P(ScsOpts), P(vp), P(ScsReport)]
+    L.scs_svrg_solve_path.argtypes = [vp, vp, i64, i64, i64, vp, i32, P(dbl), i32, i32, dbl, P(ScsOpts), vp,
+                                      P(ScsReport)]
     for name in EXPORTED:
         if name not in ("scs_opts_default", "scs_status_string", "scs_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -263,6 +265,22 @@ class Context:
         rc = _check(self._L.scs_svrg_solve_batched(self._h, P, Xa, na, da, la, ya, lama, ka, float(eps),
                                                    ctypes.byref(o), wa, reps), "scs_svrg_solve_batched")
         return rc, ws_, [r.as_dict() for r in reps]
+
+    def svrg_solve_path(self, X, Y, lams, k: int, eps: float, **opts):
+        """All (lambda, y) solves with one shared sketch; returns (status, W (nl*ny x d), [report])."""
+        _dev(X, torch.float32)
+        _dev(Y, torch.float32)
+        n, d = X.shape
+        ny = Y.shape[0]
+        assert Y.shape[1] == n and Y.is_contiguous()
+        nl = len(lams)
+        W = torch.empty(nl * ny, d, dtype=torch.float32, device=X.device)
+        la = (ctypes.c_double * nl)(*[float(v) for v in lams])
+        reps = (ScsReport * (nl * ny))()
+        o = self.opts(**opts)
+        rc = _check(self._L.scs_svrg_solve_path(self._h, _ptr(X), n, d, X.stride(0), _ptr(Y), ny, la, nl, int(k),
+                                                float(eps), ctypes.byref(o), _ptr(W), reps), "scs_svrg_solve_path")
+        return rc, W, [r.as_dict() for r in reps]
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
         _dev(X, torch.float32)

@@ -928,6 +928,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     q.gpart = gp_all + o_gp[p];
     q.grsq = gr_all + o_gr[p];
     q.g64 = g64_all + o_g64[p];
+    q.grows = 16;
     q.nwg = (int)nwg[p];
     q.stop_rule = o.stop_rule;
     q.eps = eps;
@@ -1034,6 +1035,261 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     }
   }
   if (worst == SCS_ENONFINITE) set_error("non-finite value in X or y of at least one problem");
+  if (worst == SCS_EDEVICE) set_error("inner loop: a cross-workgroup wait exceeded its budget");
+  return worst;
+}
+
+int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y, int ny,
+                        const double* lambdas, int nl, int k, double eps, const scs_opts* opts, float* W_out,
+                        scs_report* reports) {
+  if (!ctx || !Y || !lambdas || !W_out || ny < 1 || nl < 1) {
+    set_error("null argument, ny < 1 or nl < 1");
+    return SCS_EINVAL;
+  }
+  SCS_CHECK(validate_problem(X, n, d, ldx, 1.0));
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  const int l = k + o.oversample;
+  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || l > d || l > n || l > 136)) || n + d > INT32_MAX) {
+    set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+    return SCS_EINVAL;
+  }
+  for (int j = 0; j < nl; ++j)
+    if (!(lambdas[j] > 0.0) || !std::isfinite(lambdas[j])) {
+      set_error("every lambda must be a finite positive number");
+      return SCS_EINVAL;
+    }
+  if (o.omega || o.indices || o.trace_w || o.stop_rule == SCS_STOP_GAP) {
+    set_error("path solve: omega, indices, trace_w must be NULL and the stop rule certificate or epochs");
+    return SCS_EINVAL;
+  }
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
+      o.stop_rule > 2 || d > 16 * 512) {
+    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0, d <= 8192");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int P = nl * ny, b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
+  const int es = mixed ? 2 : 4;
+  constexpr int G = 8;
+  const int W = (int)cdiv(d, 512);
+  const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
+  const int64_t m = o.steps > 0 ? o.steps : cdiv(2 * n, b);
+  const int64_t N = n + d;
+  const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 64)));  // residual row blocks
+
+  // ---- workspace
+  void* xt_all = wsb(ctx, "p_xt", (size_t)nl * n * ldt * es);
+  void* reg_all = wsb(ctx, "p_reg", (size_t)nl * d * ldt * es);
+  if (!xt_all || !reg_all) return SCS_ENOMEM;
+  WS(beta_all, float, "p_beta", (int64_t)nl * N);
+  WS(cum_all, uint64_t, "p_cum", (int64_t)nl * N);
+  WS(vec_all, float, "p_vec", (int64_t)4 * P * d);  // wt | wt_prev | w32 | mu, each P x d
+  WS(tmp_all, double, "p_tmp", (int64_t)P * d);
+  WS(gsum, double, "p_g", (int64_t)P * d);
+  WS(rsq, double, "p_rsq", (int64_t)P * nblk);
+  WS(R, float, "p_R", n * P);
+  WS(idx_all, int32_t, "p_idx", (int64_t)P * G * m * b);
+  WS(sc_all, float, "p_scale", (int64_t)P * G * m * b);
+  WS(ut, float, "p_UT", std::max<int64_t>((int64_t)k * d, 1));
+  WS(lam64, double, "p_lam", std::max(k, 1));
+  WS(xbuf_all, uint64_t, "p_xbuf", (int64_t)P * 2 * W * 64);
+  WS(states, SolveState, "p_state", P);
+  WS(done_count, int, "p_done", 1);
+  WS(desc, BatchProb, "p_desc", P);
+  WS(draw_pre, int64_t, "p_prefix", (int64_t)P + 1);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 512), std::max<int64_t>(1, 1024 / cdiv(d, 64))));
+  const int64_t chunk = cdiv(n, nch), nchunks = cdiv(n, chunk);
+  constexpr int kPc = 128;  // problems per GEMM call (the MFMA kernels take up to 144 columns)
+  WS(part, float, "p_partial", nchunks * d * kPc);
+  SCS_HIP(hipMemsetAsync(states, 0, sizeof(SolveState) * P, st));
+  SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * P * d, st));
+  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * P * 2 * W * 64, st));
+  SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
+  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)4 + S));
+  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
+  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
+  hipEvent_t* dec = ctx->events.data();
+  hipEvent_t* tev = ctx->tevents.data();
+  SCS_HIP(hipEventRecord(tev[0], st));
+
+  // ---- one sketch for every lambda (Alg. 2 does not involve lambda)
+  int k_used = k;
+  bool rank_def = false;
+  if (k > 0) {
+    SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, &rank_def));
+    if (rank_def) k_used = 0;
+  }
+  if (k_used > 0) {
+    SCS_HIP(hipMemcpyAsync(ut, ws<float>(ctx, "UT32", 0), sizeof(float) * k * d, hipMemcpyDeviceToDevice, st));
+    SCS_HIP(hipMemcpyAsync(lam64, ws<double>(ctx, "lam", 0), sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  }
+  SCS_HIP(hipEventRecord(tev[1], st));
+  // ---- per lambda: P_lambda^{-1/2} rows, smoothness and sampling tables (shared by its ny solves)
+  for (int j = 0; j < nl; ++j) {
+    char* xt = (char*)xt_all + (size_t)j * n * ldt * es;
+    char* rg = (char*)reg_all + (size_t)j * d * ldt * es;
+    float* beta = beta_all + (int64_t)j * N;
+    SolveState* st0 = states + (int64_t)j * ny;
+    if (k_used > 0) {
+      SCS_CHECK(apply_impl(ctx, X, n, d, ldx, ws<float>(ctx, "U32", 0), ws<float>(ctx, "Z", 0), lam64, k_used,
+                           lambdas[j], mixed, mixed, xt, rg, ldt, beta, st0));
+    } else {
+      if (mixed) {
+        WS(tmp16, uint16_t, "xcopy16", n * d);
+        SCS_CHECK(launch_copy_bf16(st, X, n, d, ldx, tmp16));
+        SCS_HIP(hipMemcpy2DAsync(xt, ldt * 2, tmp16, d * 2, d * 2, n, hipMemcpyDeviceToDevice, st));
+        SCS_CHECK(launch_rownorm_bf16(st, tmp16, n, d, beta));
+      } else {
+        SCS_HIP(hipMemcpy2DAsync(xt, ldt * 4, X, ldx * 4, d * 4, n, hipMemcpyDeviceToDevice, st));
+        SCS_CHECK(launch_rownorm(st, X, n, d, ldx, beta));
+      }
+      WS(rtmp, float, "regtmp", d * d);
+      SCS_CHECK(launch_fill_scaled_identity(st, d, std::sqrt((double)n * lambdas[j]), mixed, rtmp, beta + n));
+      SCS_HIP(hipMemcpy2DAsync(rg, ldt * es, rtmp, d * es, d * es, d, hipMemcpyDeviceToDevice, st));
+    }
+    SCS_CHECK(launch_sampler_prepare(st, beta, N, cum_all + (int64_t)j * N, scr, sampler_scratch_len(N), st0));
+    for (int r = 1; r < ny; ++r)
+      SCS_HIP(hipMemcpyAsync(st0 + r, st0, sizeof(SolveState), hipMemcpyDeviceToDevice, st));
+  }
+  SCS_HIP(hipEventRecord(tev[2], st));
+
+  // ---- descriptors: solve p = j ny + r
+  std::vector<BatchProb> hp(P);
+  std::vector<int64_t> dpre((size_t)P + 1, 0);
+  const int64_t slice = cdiv(cdiv(d, W), 4) * 4;
+  for (int p = 0; p < P; ++p) {
+    const int j = p / ny, r = p % ny;
+    BatchProb& q = hp[p];
+    std::memset(&q, 0, sizeof(q));
+    q.X = X;
+    q.n = n;
+    q.d = d;
+    q.ldx = ldx;
+    q.y = Y + (int64_t)r * n;
+    q.lambda = lambdas[j];
+    q.k = k_used;
+    q.UT = k_used > 0 ? ut : nullptr;
+    q.lam = k_used > 0 ? lam64 : nullptr;
+    q.wt = vec_all + (int64_t)p * d;
+    q.wt_prev = vec_all + (int64_t)(P + p) * d;
+    q.w32 = vec_all + (int64_t)(2 * P + p) * d;
+    q.mu = vec_all + (int64_t)(3 * P + p) * d;
+    q.tmp = tmp_all + (int64_t)p * d;
+    q.state = states + p;
+    q.g64 = gsum + (int64_t)p * d;
+    q.grows = 1;
+    q.grsq = rsq + (int64_t)p * nblk;
+    q.nwg = nblk;
+    q.stop_rule = o.stop_rule;
+    q.eps = eps;
+    q.cum = cum_all + (int64_t)j * N;
+    q.N = N;
+    q.draws = m * b;
+    q.idx = idx_all + (int64_t)p * G * m * b;
+    q.scale = sc_all + (int64_t)p * G * m * b;
+    InnerArgs& a = q.inner;
+    a.n = n;
+    a.d = d;
+    a.Xt = (char*)xt_all + (size_t)j * n * ldt * es;
+    a.ldx = ldt;
+    a.reg = (char*)reg_all + (size_t)j * d * ldt * es;
+    a.ldr = ldt;
+    a.mu = q.mu;
+    a.m = m;
+    a.b = b;
+    a.eta_from_state = 1;
+    a.step_scale = o.step_scale;
+    a.average = o.average;
+    a.W = W;
+    a.xcd_stride = 1;
+    a.slice = slice;
+    a.wt = q.wt;
+    a.wt_prev = q.wt_prev;
+    a.xbuf = xbuf_all + (int64_t)p * 2 * W * 64;
+    a.state = q.state;
+    dpre[p + 1] = dpre[p] + (int64_t)G * m * b;
+  }
+  SCS_HIP(hipMemcpyAsync(desc, hp.data(), sizeof(BatchProb) * P, hipMemcpyHostToDevice, st));
+  SCS_HIP(hipMemcpyAsync(draw_pre, dpre.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, st));
+  const float* W32 = vec_all + (int64_t)2 * P * d;
+
+  // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X
+  constexpr int kLookahead = 3;
+  for (int s = 0; s <= S; ++s) {
+    SCS_CHECK(launch_premap_batched(st, desc, P, 0, nullptr));
+    for (int c0 = 0; c0 < P; c0 += kPc) {
+      const int pc = std::min(kPc, P - c0);
+      SCS_CHECK(launch_gemm_nt_longk(st, 0, X, n, d, ldx, W32 + (int64_t)c0 * d, pc, d, R + c0, P));
+    }
+    SCS_CHECK(launch_residual_batched(st, R, n, P, Y, ny, nblk, rsq));
+    for (int c0 = 0; c0 < P; c0 += kPc) {
+      const int pc = std::min(kPc, P - c0);
+      SCS_CHECK(launch_gemm_tn_splitk(st, 0, X, n, d, ldx, R + c0, pc, P, part, chunk, nchunks));
+      SCS_CHECK(launch_reduce_partials_t(st, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d));
+    }
+    SCS_CHECK(launch_grad_finalize_batched(st, desc, P, s == 0 ? 1 : 0, done_count, ctx->stop_flags + s));
+    if (s == S) {
+      SCS_HIP(hipEventRecord(dec[s], st));
+      break;
+    }
+    const int slot = s % G;
+    if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, P, draw_pre, dpre[P], o.seed, s, G));
+    SCS_HIP(hipEventRecord(dec[s], st));
+    SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
+    SCS_HIP(hipEventRecord(tev[4 + s], st));
+    if (s + 1 >= kLookahead) {
+      const int q = s + 1 - kLookahead;
+      SCS_HIP(hipEventSynchronize(dec[q]));
+      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+    }
+  }
+  std::vector<float*> wo(P);
+  for (int p = 0; p < P; ++p) wo[p] = W_out + (int64_t)p * d;
+  WS(wout_dev, float*, "p_wout", P);
+  SCS_HIP(hipMemcpyAsync(wout_dev, wo.data(), sizeof(float*) * P, hipMemcpyHostToDevice, st));
+  SCS_CHECK(launch_premap_batched(st, desc, P, 1, wout_dev));
+  SCS_HIP(hipEventRecord(tev[3], st));
+  std::vector<SolveState> hs(P);
+  SCS_HIP(hipMemcpyAsync(hs.data(), states, sizeof(SolveState) * P, hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+
+  float t_sk = 0.f, t_ap = 0.f, t_so = 0.f;
+  hipEventElapsedTime(&t_sk, tev[0], tev[1]);
+  hipEventElapsedTime(&t_ap, tev[1], tev[2]);
+  hipEventElapsedTime(&t_so, tev[2], tev[3]);
+  int worst = SCS_OK;
+  for (int p = 0; p < P; ++p) {
+    const SolveState& h = hs[p];
+    int status = SCS_OK;
+    if (h.status == SCS_ENONFINITE || h.status == SCS_EDEVICE) status = h.status;
+    else if (h.status == SCS_DIVERGED) status = SCS_DIVERGED;
+    else if (o.stop_rule != SCS_STOP_EPOCHS && !h.done) status = SCS_NOT_CONVERGED;
+    else if (rank_def) status = SCS_SKETCH_RANK_DEFICIENT;
+    if (status < 0) worst = std::min(worst, status);
+    else if (worst >= 0) worst = std::max(worst, status);
+    if (reports) {
+      scs_report& rp = reports[p];
+      std::memset(&rp, 0, sizeof(rp));
+      rp.status = status;
+      rp.epochs = h.epochs;
+      rp.k_used = k_used;
+      rp.steps = m;
+      rp.eta = h.eta;
+      rp.beta_hat = h.beta_sum / (double)n;
+      rp.objective = h.obj;
+      rp.grad_norm = std::sqrt(h.gnorm2);
+      rp.certificate = h.cert;
+      rp.lam_top = h.lam_top;
+      rp.ms_sketch = t_sk;
+      rp.ms_apply = t_ap;
+      rp.ms_solve = t_so;
+    }
+  }
+  if (worst == SCS_ENONFINITE) set_error("non-finite value in X or Y");
   if (worst == SCS_EDEVICE) set_error("inner loop: a cross-workgroup wait exceeded its budget");
   return worst;
 }

@@ -335,6 +335,39 @@ __global__ void reduce_partials_kernel(const float* partial, int64_t nchunks, in
   out[e] = acc * scale;
 }
 
+// Column sums of the split-K partials, transposed: G[c ldg + j] = sum_chunk partial[chunk][j][c] (FP64, in
+// chunk order), so that column c (one problem) becomes a contiguous row of G.
+__global__ void reduce_partials_t_kernel(const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
+                                         int64_t ldg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t elems = d * Pc;
+  if (e >= elems) return;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int64_t c = 0; c < nchunks; ++c) acc += (double)partial[c * elems + e];
+  const int64_t j = e / Pc, col = e % Pc;
+  G[col * ldg + j] = acc;
+}
+
+// R[i][p] -= Y[p mod ny][i] for the n x P residual matrix of a shared-X batch, and the FP64 residual
+// sums of squares per (problem, row block): rsq[p nblk + blk].
+__global__ __launch_bounds__(256) void residual_batched_kernel(float* R, int64_t n, int P, const float* Y, int ny,
+                                                               int nblk, double* rsq) {
+  const int64_t rows = (n + nblk - 1) / nblk;
+  const int64_t i0 = (int64_t)blockIdx.x * rows;
+  const int64_t i1 = i0 + rows < n ? i0 + rows : n;
+  for (int c = threadIdx.x; c < P; c += blockDim.x) {
+    const float* y = Y + (int64_t)(c % ny) * n;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+      const float r = R[i * P + c] - y[i];
+      R[i * P + c] = r;
+      acc += (double)r * r;
+    }
+    rsq[(int64_t)c * nblk + blockIdx.x] = acc;
+  }
+}
+
 bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 template <bool BF16>
@@ -428,6 +461,22 @@ int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, i
   int nb = (int)cdiv(N, 16);
   return bf16 ? tn_dispatch<true>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks)
               : tn_dispatch<false>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks);
+}
+
+int launch_reduce_partials_t(hipStream_t st, const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
+                             int64_t ldg) {
+  if (d * Pc <= 0) return SCS_OK;
+  reduce_partials_t_kernel<<<dim3((unsigned)cdiv(d * Pc, 256)), dim3(256), 0, st>>>(partial, nchunks, d, Pc, G, ldg);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const float* Y, int ny, int nblk,
+                            double* rsq) {
+  if (n <= 0 || P <= 0) return SCS_OK;
+  residual_batched_kernel<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(R, n, P, Y, ny, nblk, rsq);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
 }
 
 int launch_reduce_partials_f64(hipStream_t st, const float* partial, int64_t nchunks, int64_t elems, double scale,

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void grad_colreduce_batched_kernel(const Batch
 
 // Finish of the gradient at the snapshot for one problem (one workgroup); returns the action taken
 // (0 continue, 1 converged, 2 diverged and restored, 3 non-finite input), the same in every thread.
-__device__ int finalize_body(const double* g_in, const double* rsq_part, int nwg, int64_t n, int64_t d,
+__device__ int finalize_body(const double* g_in, int grows, const double* rsq_part, int nwg, int64_t n, int64_t d,
                              const float* w, double lambda, const float* UT, const double* lam, int k, float* mu,
                              double* tmp, SolveState* state, int stop_rule, double eps, double f_star, float* wt_cur,
                              const float* wt_prev, int first) {
@@ -150,8 +150,12 @@ __device__ int finalize_body(const double* g_in, const double* rsq_part, int nwg
   double* g = const_cast<double*>(g_in);
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double acc = 0.0;
+    if (grows == kColSplit) {
 #pragma unroll
-    for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
+      for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
+    } else {
+      for (int q = 0; q < grows; ++q) acc += g_in[(int64_t)q * d + j];
+    }
     g[j] = acc / (double)n + lambda * (double)w[j];
   }
   __syncthreads();
@@ -223,8 +227,8 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
     if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return;
   }
-  const int action = finalize_body(g_in, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp, state, stop_rule, eps,
-                                   f_star, wt_cur, wt_prev, first);
+  const int action = finalize_body(g_in, kColSplit, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp, state,
+                                   stop_rule, eps, f_star, wt_cur, wt_prev, first);
   if (host_stop && threadIdx.x == 0)
     __hip_atomic_store(host_stop, action != 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -235,8 +239,8 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(cons
                                                                             int* done_count, int* host_stop) {
   const BatchProb& q = P[blockIdx.x];
   if (q.state->done) return;
-  const int action = finalize_body(q.g64, q.grsq, q.nwg, q.n, q.d, q.w32, q.lambda, q.UT, q.lam, q.k, q.mu, q.tmp,
-                                   q.state, q.stop_rule, q.eps, q.f_star, q.wt, q.wt_prev, first);
+  const int action = finalize_body(q.g64, q.grows, q.grsq, q.nwg, q.n, q.d, q.w32, q.lambda, q.UT, q.lam, q.k, q.mu,
+                                   q.tmp, q.state, q.stop_rule, q.eps, q.f_star, q.wt, q.wt_prev, first);
   if (action != 0 && threadIdx.x == 0) {
     const int before = atomicAdd(done_count, 1);
     if (before + 1 == nprob && host_stop) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -378,6 +382,12 @@ int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, co
   if (nprob < 1) return SCS_OK;
   grad_colreduce_batched_kernel<<<dim3((unsigned)total_cb, kColSplit), dim3(256), 0, st>>>(P, nprob, cb_prefix);
   SCS_HIP(hipGetLastError());
+  return launch_grad_finalize_batched(st, P, nprob, first, done_count, host_stop);
+}
+
+int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
+                                 int* host_stop) {
+  if (nprob < 1) return SCS_OK;
   grad_finalize_batched_kernel<<<nprob, kVecThreads, 0, st>>>(P, nprob, first, done_count, host_stop);
   SCS_HIP(hipGetLastError());
   return SCS_OK;

@@ -213,8 +213,9 @@ struct BatchProb {
   SolveState* state;
   float* gpart;          // nwg x d gradient partials
   double* grsq;          // nwg residual partials
-  double* g64;           // 16 x d first-level column sums
-  int nwg;
+  double* g64;           // grows x d first-level column sums (summed by the finalizer)
+  int grows;             // 16 for the streaming pass, 1 when the sums come from the batched GEMMs
+  int nwg;               // residual partials in grsq
   int stop_rule;
   double eps, f_star;
   const uint64_t* cum;   // cumulative integer sampling weights over N = n + d components
@@ -230,6 +231,14 @@ int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, c
                                 int64_t base, int64_t count, int64_t max_d, int vec4);
 int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
                                int64_t total_cb, int first, int* done_count, int* host_stop);
+int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
+                                 int* host_stop);
+// Shared-X gradient of many problems: R = X W^T (gemm), then R[i][p] -= Y[p % ny][i] with per-block
+// residual sums rsq[p][blk]; then G (P x d, FP64) = sum over row chunks of the X^T R partials.
+int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const float* Y, int ny, int nblk,
+                            double* rsq);
+int launch_reduce_partials_t(hipStream_t st, const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
+                             int64_t ldg);
 int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
                           int64_t total_draws, uint64_t seed, int epoch, int groups);
 int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,

@@ -361,3 +361,26 @@ def test_certificate_bounds_the_gap(ctx, k):
     assert res.status == binding.OK, res.report
     assert res.report["certificate"] <= eps
     assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= eps * 1.01
+
+
+# ------------------------------------------------------------------ regularization path (shared sketch)
+@pytest.mark.parametrize("n,d,k,ny,lams", [(3000, 200, 10, 3, [1e-4, 1e-3, 1e-2]),
+                                            (2500, 600, 12, 2, [3e-4, 3e-3])])
+def test_path_solves_reach_their_closed_forms(ctx, n, d, k, ny, lams):
+    P = inputs.make_ridge(n, d, 1.5, lams[0], seed=80)
+    X64 = P.X.astype(np.float64)
+    # right-hand side 0 is the problem's own y; the others come from other planted weights
+    extra = [P.X.astype(np.float64) @ inputs.random_vector(d, seed=90 + r) + 0.1 * inputs.random_vector(n, seed=95 + r)
+             for r in range(1, ny)]
+    Ys = np.stack([P.y.astype(np.float64)] + extra).astype(np.float32)
+    eps = 1e-9
+    rc, W, reps = ctx.svrg_solve_path(dev(P.X), dev(Ys), lams, k, eps, batch=16, max_epochs=200,
+                                      stop_rule=binding.STOP_CERTIFICATE, step_scale=2.0)
+    assert rc == binding.OK, [r["status"] for r in reps]
+    Wh = host(W)
+    for j, lam in enumerate(lams):
+        for r in range(ny):
+            ws = ridge.closed_form(X64, Ys[r].astype(np.float64), lam)
+            so = ridge.suboptimality(X64, lam, Wh[j * ny + r], ws)
+            assert so <= eps * 1.01, (j, r, so)
+            assert reps[j * ny + r]["k_used"] == k
