@@ -181,14 +181,16 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
  * Many independent ridge problems (uneven n, d, lambda, k) solved together: every problem's
  * sketch, preconditioning and SVRG epochs run as in scs_svrg_solve, with the epochs of all
  * problems advancing together inside shared launches (one persistent inner-loop launch per
- * epoch for all problems, largest problems first). Stop rule and options as in scs_svrg_solve
- * (omega, indices and trace_w must be NULL). Arrays of pointers and sizes are HOST arrays of
- * length nprob; the pointed-to data are device arrays. reports: HOST array of nprob, nullable.
+ * epoch for all problems). Stop rule and options as in scs_svrg_solve (omega, indices and trace_w
+ * must be NULL; opts.f_star is ignored: the gap rule takes f_star, a HOST array of nprob optima,
+ * NULL otherwise). Arrays of pointers and sizes are HOST arrays of length nprob; the pointed-to
+ * data are device arrays. reports: HOST array of nprob, nullable. The sketch and preconditioner
+ * time of all problems is reported as ms_sketch (ms_apply = 0).
  */
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n,
                            const int64_t* d, const int64_t* ldx, const float* const* y,
-                           const double* lambda, const int* k, double eps, const scs_opts* opts,
-                           float* const* w_out, scs_report* reports);
+                           const double* lambda, const int* k, double eps, const double* f_star,
+                           const scs_opts* opts, float* const* w_out, scs_report* reports);
 
 /*
  * Regularization path with one shared sketch: one X, ny right-hand sides and nl values of lambda,
@@ -200,12 +202,13 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
  * inner loop.
  *   X: n x d (ld ldx), Y: ny x n row-major (right-hand side r is row r), both device FP32.
  *   lambdas: HOST array of nl. W_out: device (nl * ny) x d row-major; solve (j, r) is row j * ny + r.
- *   reports: HOST array of nl * ny, nullable (same order). Stop rule: certificate or epoch count;
- *   omega, indices and trace_w must be NULL. Workspace grows with nl (one set of rows per lambda).
+ *   reports: HOST array of nl * ny, nullable (same order). f_star: HOST array of nl * ny optima for
+ *   the gap rule (same order), NULL otherwise. omega, indices and trace_w must be NULL. Workspace
+ *   grows with nl (one set of preconditioned rows per lambda).
  */
 int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y,
-                        int ny, const double* lambdas, int nl, int k, double eps, const scs_opts* opts,
-                        float* W_out, scs_report* reports);
+                        int ny, const double* lambdas, int nl, int k, double eps, const double* f_star,
+                        const scs_opts* opts, float* W_out, scs_report* reports);
 
 #ifdef __cplusplus
 }

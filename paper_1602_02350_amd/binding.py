@@ -101,9 +101,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
     L.scs_svrg_solve.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), vp, P(ScsReport)]
     L.scs_svrg_solve_batched.argtypes = [vp, i32, P(vp), P(i64), P(i64), P(i64), P(vp), P(dbl), P(i32), dbl,
-                                         P(ScsOpts), P(vp), P(ScsReport)]
-    L.scs_svrg_solve_path.argtypes = [vp, vp, i64, i64, i64, vp, i32, P(dbl), i32, i32, dbl, P(ScsOpts), vp,
-                                      P(ScsReport)]
+                                         P(dbl), P(ScsOpts), P(vp), P(ScsReport)]
+    L.scs_svrg_solve_path.argtypes = [vp, vp, i64, i64, i64, vp, i32, P(dbl), i32, i32, dbl, P(dbl), P(ScsOpts),
+                                      vp, P(ScsReport)]
     for name in EXPORTED:
         if name not in ("scs_opts_default", "scs_status_string", "scs_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -243,7 +243,7 @@ class Context:
                "scs_svrg_epoch", False)
         return wt
 
-    def svrg_solve_batched(self, Xs, ys, lams, ks, eps: float, **opts):
+    def svrg_solve_batched(self, Xs, ys, lams, ks, eps: float, f_star=None, **opts):
         """Independent problems solved together; returns (status, [w], [report dict])."""
         P = len(Xs)
         assert len(ys) == P and len(lams) == P and len(ks) == P and P > 0
@@ -262,11 +262,12 @@ class Context:
         ka = (ctypes.c_int * P)(*[int(v) for v in ks])
         reps = (ScsReport * P)()
         o = self.opts(**opts)
-        rc = _check(self._L.scs_svrg_solve_batched(self._h, P, Xa, na, da, la, ya, lama, ka, float(eps),
+        fs = None if f_star is None else (ctypes.c_double * P)(*[float(v) for v in f_star])
+        rc = _check(self._L.scs_svrg_solve_batched(self._h, P, Xa, na, da, la, ya, lama, ka, float(eps), fs,
                                                    ctypes.byref(o), wa, reps), "scs_svrg_solve_batched")
         return rc, ws_, [r.as_dict() for r in reps]
 
-    def svrg_solve_path(self, X, Y, lams, k: int, eps: float, **opts):
+    def svrg_solve_path(self, X, Y, lams, k: int, eps: float, f_star=None, **opts):
         """All (lambda, y) solves with one shared sketch; returns (status, W (nl*ny x d), [report])."""
         _dev(X, torch.float32)
         _dev(Y, torch.float32)
@@ -278,8 +279,10 @@ class Context:
         la = (ctypes.c_double * nl)(*[float(v) for v in lams])
         reps = (ScsReport * (nl * ny))()
         o = self.opts(**opts)
+        fs = None if f_star is None else (ctypes.c_double * (nl * ny))(*[float(v) for v in f_star])
         rc = _check(self._L.scs_svrg_solve_path(self._h, _ptr(X), n, d, X.stride(0), _ptr(Y), ny, la, nl, int(k),
-                                                float(eps), ctypes.byref(o), _ptr(W), reps), "scs_svrg_solve_path")
+                                                float(eps), fs, ctypes.byref(o), _ptr(W), reps),
+                    "scs_svrg_solve_path")
         return rc, W, [r.as_dict() for r in reps]
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:

@@ -717,7 +717,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
 
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,
                            const int64_t* ldx, const float* const* y, const double* lambda, const int* k, double eps,
-                           const scs_opts* opts, float* const* w_out, scs_report* reports) {
+                           const double* f_star, const scs_opts* opts, float* const* w_out, scs_report* reports) {
   if (!ctx || nprob < 1 || !X || !n || !d || !ldx || !y || !lambda || !k || !w_out) {
     set_error("null argument or nprob < 1");
     return SCS_EINVAL;
@@ -729,8 +729,8 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     set_error("batched solve: omega, indices and trace_w must be NULL");
     return SCS_EINVAL;
   }
-  if (o.stop_rule == SCS_STOP_GAP) {
-    set_error("batched solve: the gap rule needs one optimum per problem; use the certificate or an epoch count");
+  if (o.stop_rule == SCS_STOP_GAP && !f_star) {
+    set_error("batched solve: the gap rule needs f_star, one optimum per problem");
     return SCS_EINVAL;
   }
   if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
@@ -932,7 +932,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     q.nwg = (int)nwg[p];
     q.stop_rule = o.stop_rule;
     q.eps = eps;
-    q.f_star = 0.0;
+    q.f_star = f_star ? f_star[p] : 0.0;
     q.cum = cum_all + o_beta[p];
     q.N = n[p] + d[p];
     q.draws = m[p] * b;
@@ -1040,8 +1040,8 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
 }
 
 int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y, int ny,
-                        const double* lambdas, int nl, int k, double eps, const scs_opts* opts, float* W_out,
-                        scs_report* reports) {
+                        const double* lambdas, int nl, int k, double eps, const double* f_star, const scs_opts* opts,
+                        float* W_out, scs_report* reports) {
   if (!ctx || !Y || !lambdas || !W_out || ny < 1 || nl < 1) {
     set_error("null argument, ny < 1 or nl < 1");
     return SCS_EINVAL;
@@ -1060,8 +1060,8 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       set_error("every lambda must be a finite positive number");
       return SCS_EINVAL;
     }
-  if (o.omega || o.indices || o.trace_w || o.stop_rule == SCS_STOP_GAP) {
-    set_error("path solve: omega, indices, trace_w must be NULL and the stop rule certificate or epochs");
+  if (o.omega || o.indices || o.trace_w || (o.stop_rule == SCS_STOP_GAP && !f_star)) {
+    set_error("path solve: omega, indices, trace_w must be NULL; the gap rule needs f_star for every solve");
     return SCS_EINVAL;
   }
   if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
@@ -1186,6 +1186,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     q.nwg = nblk;
     q.stop_rule = o.stop_rule;
     q.eps = eps;
+    q.f_star = f_star ? f_star[p] : 0.0;
     q.cum = cum_all + (int64_t)j * N;
     q.N = N;
     q.draws = m * b;

@@ -341,7 +341,7 @@ def test_batched_rejects_what_it_cannot_do(ctx):
     probs = _uneven_batch(UNEVEN[:2])
     Xs = [dev(P.X) for P, _ in probs]
     ys = [dev(P.y) for P, _ in probs]
-    with pytest.raises(binding.ScsError) as e:
+    with pytest.raises(binding.ScsError) as e:   # the gap rule needs one optimum per problem
         ctx.svrg_solve_batched(Xs, ys, [1e-3, 1e-3], [2, 2], 1e-6, stop_rule=binding.STOP_GAP)
     assert e.value.code == binding.EINVAL
     with pytest.raises(binding.ScsError) as e:
@@ -384,3 +384,21 @@ def test_path_solves_reach_their_closed_forms(ctx, n, d, k, ny, lams):
             so = ridge.suboptimality(X64, lam, Wh[j * ny + r], ws)
             assert so <= eps * 1.01, (j, r, so)
             assert reps[j * ny + r]["k_used"] == k
+
+
+def test_batched_gap_rule_with_per_problem_optima(ctx):
+    probs = _uneven_batch(WELL_POSED[:4], seed0=75)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    fs, wss = [], []
+    for P, _ in probs:
+        X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+        ws = ridge.closed_form(X64, y64, P.lam)
+        wss.append(ws)
+        fs.append(ridge.objective(X64, y64, P.lam, ws))
+    eps = 1e-8
+    rc, wb, reps = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], eps, f_star=fs,
+                                          batch=16, max_epochs=150, stop_rule=binding.STOP_GAP, step_scale=2.0)
+    assert rc == binding.OK, [r["status"] for r in reps]
+    for i, (P, _) in enumerate(probs):
+        assert ridge.suboptimality(P.X.astype(np.float64), P.lam, host(wb[i]), wss[i]) <= 1.5 * eps
