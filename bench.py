@@ -153,6 +153,127 @@ def pmc_traffic(kernel, workload, **shape):
     return None
 
 
+def _multi_line(args, metric, value, cfg_out, extra):
+    out = {"metric": metric, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic", "config": cfg_out}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_path(args, cfg):
+    """All 8 x 32 solves of a regularization path with one shared sketch, timed to L - L* <= eps each."""
+    import numpy as np
+    import torch
+    from paper_1602_02350_amd import binding
+    n, d, k, b, eps, ny, nl = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["eps"], cfg["ny"], cfg["nl"]
+    mixed = args.precision == "mixed"
+    seed = 20160207 + 3
+    X, y0 = make_problem_gpu(cfg, seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed + 1)
+    Y = torch.empty(ny, n, device="cuda", dtype=torch.float32)
+    Y[0] = y0
+    for r in range(1, ny):
+        w0 = torch.randn(d, generator=g, device="cuda", dtype=torch.float64)
+        Y[r] = (X.double() @ w0 + 0.1 * torch.randn(n, generator=g, device="cuda", dtype=torch.float64)).float()
+    lams = np.logspace(np.log10(cfg["lam_lo"]), np.log10(cfg["lam_hi"]), nl)
+    # FP64 optima (measurement only): one Gram matrix, one Cholesky per lambda
+    Xd = X.double()
+    C = Xd.T @ Xd / n
+    B = Xd.T @ Y.double().T / n
+    Wst, fs, Hs = [], [], []
+    for lam in lams:
+        H = C + lam * torch.eye(d, device="cuda", dtype=torch.float64)
+        Ws = torch.cholesky_solve(B, torch.linalg.cholesky(H))           # d x ny
+        Rr = Xd @ Ws - Y.double().T
+        for r in range(ny):
+            fs.append(0.5 * float(Rr[:, r] @ Rr[:, r]) / n + 0.5 * lam * float(Ws[:, r] @ Ws[:, r]))
+            Wst.append(Ws[:, r])
+        Hs.append(H)
+    del Xd
+    torch.cuda.synchronize()
+    c, mf = (float(v) for v in (args.fixed or "16,0.25").split(";")[0].split(","))
+    ctx = binding.Context(0)
+    times, res = [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.svrg_solve_path(X, Y, list(lams), k, eps, f_star=fs, batch=b, epoch_factor=mf, max_epochs=150,
+                                  stop_rule=binding.STOP_GAP, step_scale=c,
+                                  precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            times.append(time.perf_counter() - t0)
+    rc, W, reps = res
+    so = []
+    for p in range(nl * ny):
+        e = W[p].double() - Wst[p]
+        so.append(0.5 * float(e @ (Hs[p // ny] @ e)))
+    ep = [r["epochs"] for r in reps]
+    st = {}
+    for r in reps:
+        st[r["status"]] = st.get(r["status"], 0) + 1
+    _multi_line(args, f"seconds to L(w)-L(w*)<={eps} for all {nl * ny} solves of a regularization path "
+                      f"(shared sketch, 1 GPU)", statistics.median(times),
+                {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "ny": ny, "nl": nl,
+                 "lambda": [float(lams[0]), float(lams[-1])], "eps": eps, "parallelism": "1 GPU"},
+                {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
+                 "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
+                 "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
+                 "stage_ms": {"sketch": reps[0]["ms_sketch"], "apply": reps[0]["ms_apply"],
+                              "solve": reps[0]["ms_solve"]}})
+    ctx.close()
+
+
+def bench_batch(args, cfg):
+    """256 independent uneven problems solved together, timed to L - L* <= eps for every problem."""
+    import torch
+    from paper_1602_02350_amd import binding, inputs
+    shapes = inputs.uneven_batch_shapes(cfg, seed=20160207 + 4)
+    mixed = args.precision != "fp32"
+    Xs, ys, fs, wss, Hs = [], [], [], [], []
+    for p, (n, d, a, lam, k) in enumerate(shapes):
+        X, y = make_problem_gpu({"n": n, "d": d, "alpha": a, "floor": cfg["floor"]}, 20160207 + 1000 + p)
+        ws, Ls, H = reference_optimum(X, y, lam)
+        Xs.append(X)
+        ys.append(y)
+        fs.append(Ls)
+        wss.append(ws)
+        Hs.append(H)
+    torch.cuda.synchronize()
+    c, mf = (float(v) for v in (args.fixed or "16,0.25").split(";")[0].split(","))
+    ctx = binding.Context(0)
+    times, res = [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.svrg_solve_batched(Xs, ys, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
+                                     f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=150,
+                                     stop_rule=binding.STOP_GAP, step_scale=c,
+                                     precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            times.append(time.perf_counter() - t0)
+    rc, W, reps = res
+    so = [subopt(Hs[p], W[p], wss[p]) for p in range(len(shapes))]
+    ep = [r["epochs"] for r in reps]
+    st = {}
+    for r in reps:
+        st[r["status"]] = st.get(r["status"], 0) + 1
+    nd = sum(n * d for n, d, _, _, _ in shapes)
+    _multi_line(args, f"seconds to L(w)-L(w*)<={cfg['eps']} for all {len(shapes)} uneven problems (1 GPU)",
+                statistics.median(times),
+                {"workload": args.workload, "nprob": len(shapes), "n": [cfg["n_lo"], cfg["n_hi"]],
+                 "d": [cfg["d_lo"], cfg["d_hi"]], "b": cfg["b"], "eps": cfg["eps"], "total_nd": nd,
+                 "parallelism": "1 GPU"},
+                {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
+                 "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
+                 "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
+                 "stage_ms": {"setup": reps[0]["ms_sketch"], "solve": reps[0]["ms_solve"]}})
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +285,10 @@ def main():
     from paper_1602_02350_amd import binding, inputs
 
     cfg = dict(inputs.WORKLOADS[args.workload])
+    if "nl" in cfg:
+        return bench_path(args, cfg)
+    if "nprob" in cfg:
+        return bench_batch(args, cfg)
     mixed = (args.precision == "mixed") if args.precision else args.workload.startswith("mixed")
     prec = binding.PREC_MIXED if mixed else binding.PREC_FP32
     n, d, k, b, lam, eps = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["lam"], cfg["eps"]

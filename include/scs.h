@@ -42,7 +42,8 @@ extern "C" {
 #define SCS_ENOMEM (-3)       /* device allocation failed */
 #define SCS_EDEVICE (-4)      /* HIP runtime error (message in scs_last_error) */
 #define SCS_NOT_CONVERGED 1   /* epoch cap reached before the stop rule held; output = last snapshot */
-#define SCS_DIVERGED 2        /* objective became non-finite or grew 10x over its start; output = last good snapshot */
+#define SCS_DIVERGED 2        /* objective became non-finite or grew 10x over its start even after 6 step halvings;
+                                 output = last good snapshot */
 #define SCS_SKETCH_RANK_DEFICIENT 3 /* range-finder block lost rank (e.g. X = 0); solved without preconditioning */
 
 /* Precision of the sketch GEMMs and of the preconditioned rows used by the inner loop. */
@@ -61,7 +62,7 @@ typedef struct scs_ctx scs_ctx;
 typedef struct scs_opts {
   int oversample;         /* p: range-finder width is k + p (default 5) */
   int batch;              /* b: i.i.d. draws per inner step (default 64) */
-  int64_t steps;          /* m: inner steps per epoch; 0 = ceil(2 n / b) */
+  int64_t steps;          /* m: inner steps per epoch; 0 = ceil(epoch_factor n / b), or ceil(2 n / b) */
   double step_scale;      /* c: step eta = c / beta_hat with beta_hat = (1/(n+d)) sum_i beta_i (default 1) */
   int max_epochs;         /* S: epoch cap (default 30) */
   int stop_rule;          /* SCS_STOP_* (default SCS_STOP_CERTIFICATE) */
@@ -77,6 +78,7 @@ typedef struct scs_opts {
   double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's
                              end; -1 for epochs never enqueued because the stop rule had held */
   int timing;             /* 1: time every full-gradient pass and inner-loop launch with HIP events (report.ms_grad, ms_inner) */
+  double epoch_factor;    /* with steps = 0 and epoch_factor > 0: m = ceil(epoch_factor n / b) per problem (default 0) */
 } scs_opts;
 
 typedef struct scs_report {
@@ -93,6 +95,7 @@ typedef struct scs_report {
   double ms_sketch, ms_apply, ms_solve; /* stage times */
   double ms_grad, ms_inner; /* with opts.timing: summed durations of the full-gradient passes and inner-loop launches */
   int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
+  int backoffs;             /* rejected snapshots: each restored the previous one and halved the step */
 } scs_report;
 
 void scs_opts_default(scs_opts* opts);

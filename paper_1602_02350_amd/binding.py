@@ -44,6 +44,7 @@ class ScsOpts(ctypes.Structure):
         ("trace_w", ctypes.c_void_p),
         ("epoch_ms", ctypes.c_void_p),
         ("timing", ctypes.c_int),
+        ("epoch_factor", ctypes.c_double),
     ]
 
 
@@ -66,6 +67,7 @@ class ScsReport(ctypes.Structure):
         ("ms_inner", ctypes.c_double),
         ("n_grad", ctypes.c_int),
         ("n_inner", ctypes.c_int),
+        ("backoffs", ctypes.c_int),
     ]
 
     def as_dict(self):

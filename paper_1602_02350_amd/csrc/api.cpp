@@ -108,6 +108,13 @@ struct Guard {  // makes the context's device current for the duration of a call
   }
 };
 
+// m of Alg. 1: the literal step count, else epoch_factor n / b, else 2 n / b
+int64_t epoch_steps(const scs_opts& o, int64_t n, int b) {
+  if (o.steps > 0) return o.steps;
+  if (o.epoch_factor > 0.0) return std::max<int64_t>(1, (int64_t)std::ceil(o.epoch_factor * (double)n / b));
+  return cdiv(2 * n, b);
+}
+
 int choose_workgroups(const scs_opts& o, int64_t d) {
   if (o.workgroups > 0) return o.workgroups;
   return inner_default_workgroups(d);
@@ -473,7 +480,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) ||
       o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX) {
     set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
     return SCS_EINVAL;
@@ -481,7 +488,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   Guard g(ctx->device);
   hipStream_t st = ctx->stream;
   const int b = o.batch;
-  const int64_t m = o.steps > 0 ? o.steps : cdiv(2 * n, b);
+  const int64_t m = epoch_steps(o, n, b);
   const int64_t N = n + d;
   const int S = o.max_epochs;
   const int mixed = o.precision == SCS_PREC_MIXED;
@@ -684,6 +691,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     report->grad_norm = std::sqrt(hs.gnorm2);
     report->certificate = hs.cert;
     report->lam_top = hs.lam_top;
+    report->backoffs = hs.backoffs;
     float t1 = 0, t2 = 0, t3 = 0;
     hipEventElapsedTime(&t1, ev_start, ev_sketch);
     hipEventElapsedTime(&t2, ev_sketch, ev_apply);
@@ -733,7 +741,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     set_error("batched solve: the gap rule needs f_star, one optimum per problem");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) || o.stop_rule < 0 ||
       o.stop_rule > 2) {
     set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
     return SCS_EINVAL;
@@ -781,7 +789,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   int64_t max_N = 0;
   for (int p = 0; p < nprob; ++p) {
     ldt[p] = cdiv(d[p], mixed ? 128 : 64) * (mixed ? 128 : 64);
-    m[p] = o.steps > 0 ? o.steps : cdiv(2 * n[p], b);
+    m[p] = epoch_steps(o, n[p], b);
     nwg[p] = grad_num_workgroups(n[p], d[p]);  // as in a single solve, so the sums agree bit for bit
     o_xt[p] = t_xt;
     t_xt += n[p] * ldt[p];
@@ -1029,6 +1037,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
       r.grad_norm = std::sqrt(h.gnorm2);
       r.certificate = h.cert;
       r.lam_top = h.lam_top;
+      r.backoffs = h.backoffs;
       r.ms_sketch = t_setup;
       r.ms_apply = 0.0;
       r.ms_solve = t_solve;
@@ -1064,7 +1073,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     set_error("path solve: omega, indices, trace_w must be NULL; the gap rule needs f_star for every solve");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || o.stop_rule < 0 ||
+  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) || o.stop_rule < 0 ||
       o.stop_rule > 2 || d > 16 * 512) {
     set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0, d <= 8192");
     return SCS_EINVAL;
@@ -1076,7 +1085,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   constexpr int G = 8;
   const int W = (int)cdiv(d, 512);
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
-  const int64_t m = o.steps > 0 ? o.steps : cdiv(2 * n, b);
+  const int64_t m = epoch_steps(o, n, b);
   const int64_t N = n + d;
   const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 64)));  // residual row blocks
 
@@ -1285,6 +1294,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       rp.grad_norm = std::sqrt(h.gnorm2);
       rp.certificate = h.cert;
       rp.lam_top = h.lam_top;
+      rp.backoffs = h.backoffs;
       rp.ms_sketch = t_sk;
       rp.ms_apply = t_ap;
       rp.ms_solve = t_so;

@@ -103,7 +103,9 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
       smc[q][v] = 0.f;
     }
   }
-  const float eta = a.eta_from_state ? (float)(a.step_scale * (double)a.n / a.state->beta_sum) : (float)a.eta;
+  const float eta = a.eta_from_state
+                        ? (float)ldexp(a.step_scale * (double)a.n / a.state->beta_sum, -a.state->backoffs)
+                        : (float)a.eta;
   if (tid == 0) s_abort = 0;
 
   // Row loads are unconditional from in-bounds addresses: rows j >= b get coefficient 0 and
@@ -303,13 +305,35 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(cons
 
 template <int RPT, int CPT, bool BF16>
 int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, int64_t epoch) {
-  dim3 grid((unsigned)(nprob * W)), block(kInnerThreads);
+  dim3 block(kInnerThreads);
   if (W > 1) {
-    // the workgroups of a problem wait on each other: they must all be resident
-    void* args[] = {&P, &nprob, &slot, &epoch};
-    SCS_HIP(hipLaunchCooperativeKernel((const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>, grid, block, args, 0,
-                                       st));
+    // The workgroups of a problem wait on each other, so they must all be resident: problems go in
+    // groups that fit the device at once, one cooperative launch per group.
+    static int resident = 0;  // co-resident workgroups of this instantiation on the device
+    if (resident == 0) {
+      int per_cu = 0, dev = 0, cus = 0;
+      SCS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>,
+                                                           kInnerThreads, 0));
+      SCS_HIP(hipGetDevice(&dev));
+      SCS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      resident = per_cu * cus;
+    }
+    int group = resident / W;
+    if (group >= 8) group -= group % 8;  // keeps the W workgroups of a problem on one XCD
+    if (group < 1) {
+      set_error("batched inner loop: not enough resident workgroups for one problem");
+      return SCS_EINVAL;
+    }
+    for (int p0 = 0; p0 < nprob; p0 += group) {
+      const BatchProb* Pg = P + p0;
+      int cnt = nprob - p0 < group ? nprob - p0 : group;
+      dim3 grid((unsigned)(cnt * W));
+      void* args[] = {&Pg, &cnt, &slot, &epoch};
+      SCS_HIP(hipLaunchCooperativeKernel((const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>, grid, block, args, 0,
+                                         st));
+    }
   } else {
+    dim3 grid((unsigned)nprob);
     inner_epoch_batched_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch);
     SCS_HIP(hipGetLastError());
   }

@@ -181,12 +181,19 @@ __device__ int finalize_body(const double* g_in, int grows, const double* rsq_pa
     double lam_top = k > 0 ? fmax(lam[0], 0.0) : 0.0;
     double cert = gn * (k > 0 ? lam_top + lambda : 1.0) / (2.0 * lambda);
     bool finite = isfinite(obj) && isfinite(gn);
-    int action = 0;  // 0 = continue, 1 = stop (converged), 2 = diverged (restore), 3 = non-finite input
+    // 0 = continue, 1 = stop (converged), 2 = diverged (restore, stop), 3 = non-finite input,
+    // 4 = rejected snapshot: restore the previous one, halve the step size and continue
+    int action = 0;
     if (first) {
       if (!finite) action = 3;
       else state->obj0 = obj;
     } else if (!finite || obj > 10.0 * state->obj0) {
-      action = 2;
+      if (state->backoffs < kMaxBackoffs) {
+        state->backoffs += 1;
+        action = 4;
+      } else {
+        action = 2;
+      }
     }
     if (action == 0) {
       state->obj = obj;
@@ -208,7 +215,7 @@ __device__ int finalize_body(const double* g_in, int grows, const double* rsq_pa
     s_action = action;
   }
   __syncthreads();
-  if (s_action == 2 && wt_prev) {
+  if ((s_action == 2 || s_action == 4) && wt_prev) {
     for (int64_t j = threadIdx.x; j < d; j += blockDim.x) wt_cur[j] = wt_prev[j];
   }
   if (s_action == 0 || s_action == 1) {
@@ -230,7 +237,8 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   const int action = finalize_body(g_in, kColSplit, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp, state,
                                    stop_rule, eps, f_star, wt_cur, wt_prev, first);
   if (host_stop && threadIdx.x == 0)
-    __hip_atomic_store(host_stop, action != 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 0, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // One workgroup per problem. A problem that finishes in this launch adds one to done_count; the
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(cons
   if (q.state->done) return;
   const int action = finalize_body(q.g64, q.grows, q.grsq, q.nwg, q.n, q.d, q.w32, q.lambda, q.UT, q.lam, q.k, q.mu,
                                    q.tmp, q.state, q.stop_rule, q.eps, q.f_star, q.wt, q.wt_prev, first);
-  if (action != 0 && threadIdx.x == 0) {
+  if ((action == 1 || action == 2 || action == 3) && threadIdx.x == 0) {
     const int before = atomicAdd(done_count, 1);
     if (before + 1 == nprob && host_stop) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }

@@ -113,8 +113,11 @@ struct SolveState {
   double s;          // sqrt(lam_k + lambda) (1 if k = 0)
   double lam_top;
   double wsum;       // total quantized sampling weight (as double, for reporting)
-  double pad[3];
+  int backoffs;      // step-size halvings after rejected snapshots (eta is scaled by 2^-backoffs)
+  int pad_i;
+  double pad[2];
 };
+constexpr int kMaxBackoffs = 6;  // a further rejected snapshot ends the solve with SCS_DIVERGED
 
 // ---------------------------------------------------------------- launchers (defined in the .hip files)
 // rng

@@ -115,4 +115,25 @@ WORKLOADS = {
     "fp32_n100000_d1000": dict(n=100000, d=1000, alpha=1.5, lam=1e-5, k=50, b=64, eps=1e-6, floor=0.0),
     # n=5e5, d=2048, spectrum j^-2 + 1e-6, lambda=1e-6, k=128; BF16 sketch and rows.
     "mixed_n500000_d2048": dict(n=500000, d=2048, alpha=2.0, lam=1e-6, k=128, b=64, eps=1e-6, floor=1e-6),
+    # regularization path: one X (n=2e5, d=1024, j^-1.5), 8 right-hand sides, 32 lambda log-spaced
+    # from 1e-7 to 1e-2, one shared sketch with k=64: 256 solves.
+    "path_n200000_d1024": dict(n=200000, d=1024, alpha=1.5, k=64, b=64, eps=1e-6, floor=0.0, ny=8, nl=32,
+                               lam_lo=1e-7, lam_hi=1e-2),
+    # 256 independent problems: n ~ U[1000, 50000], d ~ U{64..512}, spectrum j^-a with a ~ U[1, 2.5],
+    # lambda ~ logU[1e-6, 1e-3], k = floor(d / 16); BF16 rows in the inner loop.
+    "batch256_uneven": dict(nprob=256, n_lo=1000, n_hi=50000, d_lo=64, d_hi=512, a_lo=1.0, a_hi=2.5,
+                            lam_lo=1e-6, lam_hi=1e-3, b=64, eps=1e-6, floor=0.0),
 }
+
+
+def uneven_batch_shapes(cfg, seed):
+    """Per-problem (n, d, alpha, lambda, k) of an uneven batch, drawn from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(cfg["nprob"]):
+        n = int(rng.integers(cfg["n_lo"], cfg["n_hi"] + 1))
+        d = int(rng.integers(cfg["d_lo"], cfg["d_hi"] + 1))
+        a = float(rng.uniform(cfg["a_lo"], cfg["a_hi"]))
+        lam = float(np.exp(rng.uniform(np.log(cfg["lam_lo"]), np.log(cfg["lam_hi"]))))
+        out.append((n, d, a, lam, d // 16))
+    return out

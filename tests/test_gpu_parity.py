@@ -402,3 +402,16 @@ def test_batched_gap_rule_with_per_problem_optima(ctx):
     assert rc == binding.OK, [r["status"] for r in reps]
     for i, (P, _) in enumerate(probs):
         assert ridge.suboptimality(P.X.astype(np.float64), P.lam, host(wb[i]), wss[i]) <= 1.5 * eps
+
+
+def test_step_backoff_recovers_from_a_too_large_step(ctx):
+    """A snapshot whose objective blows up is rejected, the step halved and the solve goes on."""
+    P = inputs.make_ridge(2000, 50, 1.5, 1e-3, seed=37)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, P.lam)
+    Ls = ridge.objective(X64, y64, P.lam, ws)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 0, 1e-9, batch=8, max_epochs=200, step_scale=40.0,
+                         stop_rule=binding.STOP_GAP, f_star=Ls)
+    assert res.status == binding.OK, res.report
+    assert 1 <= res.report["backoffs"] <= 6
+    assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= 1.5e-9
