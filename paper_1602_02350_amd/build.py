@@ -25,7 +25,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wno-unused-command-line-argument"]
 
-SOURCES = ["k_rng.hip", "k_gemm.hip", "k_dense64.hip", "k_vec.hip", "k_grad.hip", "k_inner.hip", "api.cpp"]
+SOURCES = ["k_rng.hip", "k_gemm.hip", "k_dense64.hip", "k_eig64.hip", "k_vec.hip", "k_grad.hip", "k_inner.hip",
+           "api.cpp"]
 
 
 def _compile(src: str) -> str:

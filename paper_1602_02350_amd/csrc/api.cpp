@@ -175,11 +175,11 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, l, Wq, l, l, part2, chunk2, nch2));
   WS(B, double, "B64", (size_t)l * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)l * l, 1.0 / (double)n, B));
-  WS(Awork, double, "Ajac64", (size_t)l * l);
   WS(V, double, "V64", (size_t)l * l);
   WS(theta, double, "theta", (size_t)l);
   WS(order, int, "order", (size_t)l);
-  SCS_CHECK(launch_jacobi64(st, B, l, Awork, V, theta, order));
+  WS(eigw, double, "eig_work", eig64_work_len(l));
+  SCS_CHECK(launch_eig64(st, B, l, eigw, V, theta, order));
   // lift: U~ = Q V_k, lam = theta_{1..k}
   WS(U64, double, "U64", (size_t)d * k);
   WS(U32, float, "U32", (size_t)d * k);

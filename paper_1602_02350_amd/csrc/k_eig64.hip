@@ -1,0 +1,373 @@
+// Symmetric eigendecomposition of the l x l Rayleigh-Ritz matrix of the sketch (Alg. 2: the SVD of
+// the projected block, here B = (XQ)^T (XQ) / n), in FP64, l = k + p <= 136:
+//  1. Householder reduction to tridiagonal form, T = Qh^T B Qh, Qh = H_0 H_1 ... H_{l-3}
+//     (one workgroup, B in LDS; reflector j is stored with its scale tau_j);
+//  2. every eigenvalue of T by bisection on Sturm counts (one thread per eigenvalue, so the
+//     eigenvalues come out sorted);
+//  3. the eigenvectors of T by inverse iteration with a partially pivoted LU of T - theta I (one
+//     thread per eigenvector); members of groups of eigenvalues closer than 1e-10 ||T|| are redone
+//     in sequence with the earlier members projected out at every iteration;
+//  4. V = Qh Z by applying the reflectors to Z in reverse order (one workgroup, Z in LDS).
+// The outputs follow the library's convention: theta[i] and column i of V (row-major l x l) form
+// an eigenpair, order[r] is the index of the r-th largest eigenvalue.
+#include "scs_internal.h"
+
+namespace scs {
+
+namespace {
+
+constexpr int kEigThreads = 1024;
+constexpr int kEigMaxL = 144;  // >= the largest sketch width
+
+__device__ __forceinline__ double eig_block_sum(double v, double* sred) {
+  v = wave_sum_d_fast(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sred[q];
+  return t;
+}
+
+// Reduction of B to tridiagonal form (lower variant): for j = 0 .. l-3 the reflector
+// H_j = I - tau_j v v^T, v = (1, v_1, ..., v_{m-1}) acting on rows j+1 .. l-1, maps column j below
+// the diagonal onto beta_j e_1; the trailing block is updated as A - v w^T - w v^T with
+// w = tau A v - (tau^2 / 2)(v^T A v) v.
+__global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B, int l, double* dd, double* ee,
+                                                                double* Vh, double* tau_out) {
+  extern __shared__ double A[];  // l x l
+  __shared__ double vv[kEigMaxL], ww[kEigMaxL];
+  __shared__ double sred[kEigThreads / 64];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  for (int e = tid; e < l * l; e += nt) A[e] = B[e];
+  __syncthreads();
+  for (int j = 0; j + 2 < l; ++j) {
+    const int m = l - j - 1, r0 = j + 1;
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += nt) {
+      const double x = A[(r0 + i) * l + j];
+      part += x * x;
+    }
+    const double sig = eig_block_sum(part, sred);
+    const double x0 = A[r0 * l + j];
+    double beta = x0, tau = 0.0, scal = 0.0;
+    if (sig > 0.0) {
+      const double mu = sqrt(x0 * x0 + sig);
+      beta = x0 <= 0.0 ? mu : -mu;
+      tau = (beta - x0) / beta;
+      scal = 1.0 / (x0 - beta);
+    }
+    for (int i = tid; i < m; i += nt) {
+      const double v = i == 0 ? 1.0 : A[(r0 + i) * l + j] * scal;
+      vv[i] = v;
+      Vh[(int64_t)j * l + i] = v;
+    }
+    if (tid == 0) {
+      dd[j] = A[j * l + j];
+      ee[j] = beta;
+      tau_out[j] = tau;
+    }
+    __syncthreads();
+    if (tau == 0.0) continue;  // uniform: every thread holds the same tau
+    for (int i = wave; i < m; i += nwave) {
+      double acc = 0.0;
+      for (int c = lane; c < m; c += 64) acc += A[(r0 + i) * l + r0 + c] * vv[c];
+      acc = wave_sum_d_fast(acc);
+      if (lane == 0) ww[i] = tau * acc;
+    }
+    __syncthreads();
+    double pp = 0.0;
+    for (int i = tid; i < m; i += nt) pp += ww[i] * vv[i];
+    const double al = -0.5 * tau * eig_block_sum(pp, sred);
+    for (int i = tid; i < m; i += nt) ww[i] += al * vv[i];
+    __syncthreads();
+    for (int i = wave; i < m; i += nwave) {
+      const double vi = vv[i], wi = ww[i];
+      double* row = A + (r0 + i) * l + r0;
+      for (int c = lane; c < m; c += 64) row[c] -= vi * ww[c] + wi * vv[c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (l >= 2) {
+      dd[l - 2] = A[(l - 2) * l + l - 2];
+      ee[l - 2] = A[(l - 1) * l + l - 2];
+      tau_out[l - 2] = 0.0;
+    }
+    dd[l - 1] = A[(l - 1) * l + l - 1];
+  }
+}
+
+// Number of eigenvalues of T below x: negative pivots of the LDL^T factorization of T - x I.
+__device__ __forceinline__ int sturm_count(const double* sd, const double* se2, int l, double x, double pivmin) {
+  double q = sd[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < l; ++i) {
+    q = (sd[i] - x) - se2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// One solve (T - theta_t I) z_new = z on column t of zz with the stored LU factors of thread t,
+// rescaled to unit max norm. Arrays are laid out [i * l + t].
+__device__ void inv_solve(const double* u0, const double* u1, const double* u2, const double* mlt,
+                          const double* swp, double* zz, int l, int t) {
+  for (int i = 0; i + 1 < l; ++i) {
+    const int64_t o = (int64_t)i * l + t, o1 = o + l;
+    double ri = zz[o], ri1 = zz[o1];
+    if (swp[o] != 0.0) {
+      const double tmp = ri;
+      ri = ri1;
+      ri1 = tmp;
+    }
+    zz[o] = ri;
+    zz[o1] = ri1 - mlt[o] * ri;
+  }
+  double z1 = 0.0, z2 = 0.0, nz = 0.0;
+  for (int i = l - 1; i >= 0; --i) {
+    const int64_t o = (int64_t)i * l + t;
+    const double zi = (zz[o] - u1[o] * z1 - u2[o] * z2) / u0[o];
+    zz[o] = zi;
+    z2 = z1;
+    z1 = zi;
+    nz = fmax(nz, fabs(zi));
+  }
+  const double inv = nz > 0.0 ? 1.0 / nz : 1.0;
+  for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] *= inv;
+}
+
+__device__ void start_vector(double* zz, int l, int t) {
+  for (int i = 0; i < l; ++i)
+    zz[(int64_t)i * l + t] = 1.0 + 0.25 * (double)(((uint32_t)(i + 1) * 2654435761u + (uint32_t)t * 40503u) % 997u) / 997.0;
+}
+
+__device__ void normalize2(double* zz, int l, int t) {
+  double n2 = 0.0;
+  for (int i = 0; i < l; ++i) n2 += zz[(int64_t)i * l + t] * zz[(int64_t)i * l + t];
+  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] *= inv;
+}
+
+// Eigenpairs of the symmetric tridiagonal T (diagonal dd, off-diagonal ee). work: 5 l^2 doubles (the LU
+// factors of T - theta_t I); the vectors live in LDS.
+__global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* dd, const double* ee, int l,
+                                                                  double* theta, double* Z, double* work) {
+  extern __shared__ double zz[];  // l x l: the inverse-iteration vectors, element i of vector t at [i * l + t]
+  __shared__ double sd[kEigMaxL], se[kEigMaxL], se2[kEigMaxL], sth[kEigMaxL];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < l; i += nt) {
+    sd[i] = dd[i];
+    const double e = i + 1 < l ? ee[i] : 0.0;
+    se[i] = e;
+    se2[i] = e * e;
+  }
+  __syncthreads();
+  // Gershgorin interval and the scale of T (every thread, identical results)
+  double lo = 0.0, hi = 0.0, nrm = 0.0, maxe2 = 0.0;
+  for (int i = 0; i < l; ++i) {
+    const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i + 1 < l ? fabs(se[i]) : 0.0);
+    lo = i == 0 ? sd[i] - r : fmin(lo, sd[i] - r);
+    hi = i == 0 ? sd[i] + r : fmax(hi, sd[i] + r);
+    nrm = fmax(nrm, fabs(sd[i]) + r);
+    if (i + 1 < l) maxe2 = fmax(maxe2, se2[i]);
+  }
+  if (nrm == 0.0) nrm = 1.0;
+  const double pivmin = 1e-290 * fmax(1.0, maxe2);
+  const double abstol = 1e-16 * nrm;
+  // per-thread work arrays, element i of thread t at [i * l + t] (coalesced across threads)
+  const int64_t L2 = (int64_t)l * l;
+  double* u0 = work;
+  double* u1 = work + L2;
+  double* u2 = work + 2 * L2;
+  double* mlt = work + 3 * L2;
+  double* swp = work + 4 * L2;
+  // The t-th smallest eigenvalue by multisection: G lanes of one wave (G a power of two) evaluate
+  // the Sturm count at G interior points of [a, b] together and keep the subinterval where the
+  // count passes t, so count(a) <= t < count(b) holds throughout and [a, b] shrinks (G+1)-fold
+  // per round.
+  const int G = l <= 128 ? 8 : (l <= 256 ? 4 : 1);
+  const int lane = tid & 63;
+  if (tid < G * l) {
+    const int t = tid / G, s = tid % G;
+    double a = lo - abstol, b = hi + abstol;
+    for (int it = 0; it < 200; ++it) {
+      const double h = (b - a) / (double)(G + 1);
+      if (b - a <= fmax(abstol, 4.4e-16 * fmax(fabs(a), fabs(b))) || h <= 0.0 || a + h <= a) break;
+      const double x = a + (double)(s + 1) * h;
+      const bool above = sturm_count(sd, se2, l, x, pivmin) > t;
+      // lanes of this eigenvalue: [base, base + G) of the wave
+      const int base = lane - s;
+      const uint64_t mask = (uint64_t)__ballot(above) >> base;
+      const uint64_t mine = G == 64 ? mask : (mask & ((1ull << G) - 1ull));
+      const int first = mine ? __builtin_ctzll(mine) : G;  // first point with count > t
+      const double na = first == 0 ? a : a + (double)first * h;
+      const double nb = first == G ? b : a + (double)(first + 1) * h;
+      a = na;
+      b = nb;
+    }
+    if (s == 0) {
+      sth[t] = 0.5 * (a + b);
+      theta[t] = 0.5 * (a + b);
+    }
+  }
+  __syncthreads();
+  if (tid < l) {
+    const int t = tid;
+    const double th = sth[t];
+    // LU of T - th I with row interchanges: row i of U holds up to two super-diagonals; a zero
+    // pivot (th is an eigenvalue) is replaced by a tiny multiple of ||T||, as inverse iteration wants
+    const double tiny = 1e-15 * nrm;
+    double ca = sd[0] - th, cb = l > 1 ? se[0] : 0.0;
+    for (int i = 0; i + 1 < l; ++i) {
+      const double na = sd[i + 1] - th, nb = i + 2 < l ? se[i + 1] : 0.0, nc = se[i];
+      const int64_t o = (int64_t)i * l + t;
+      if (fabs(ca) >= fabs(nc)) {
+        const double piv = ca != 0.0 ? ca : tiny;
+        const double m = nc / piv;
+        u0[o] = piv;
+        u1[o] = cb;
+        u2[o] = 0.0;
+        mlt[o] = m;
+        swp[o] = 0.0;
+        ca = na - m * cb;
+        cb = nb;
+      } else {
+        const double m = ca / nc;
+        u0[o] = nc;
+        u1[o] = na;
+        u2[o] = nb;
+        mlt[o] = m;
+        swp[o] = 1.0;
+        ca = cb - m * na;
+        cb = -m * nb;
+      }
+    }
+    u0[(int64_t)(l - 1) * l + t] = ca != 0.0 ? ca : tiny;
+    u1[(int64_t)(l - 1) * l + t] = 0.0;
+    u2[(int64_t)(l - 1) * l + t] = 0.0;
+    // three solves from a fixed start vector (different per thread)
+    start_vector(zz, l, t);
+    for (int rep = 0; rep < 3; ++rep) inv_solve(u0, u1, u2, mlt, swp, zz, l, t);
+    normalize2(zz, l, t);
+  }
+  __syncthreads();
+  // Eigenvalues within 1e-10 ||T|| of their predecessor do not determine their inverse-iteration
+  // vectors individually: those are recomputed one after another (thread 0), projecting out the
+  // earlier members of the group at every iteration, so the group's vectors come out orthonormal.
+  const double ortol = 1e-10 * nrm;
+  for (int t = 1; t < l; ++t) {
+    if (sth[t] - sth[t - 1] > ortol) continue;  // uniform
+    if (tid == 0) {
+      int g0 = t - 1;
+      while (g0 > 0 && sth[g0] - sth[g0 - 1] <= ortol) --g0;
+      start_vector(zz, l, t);
+      for (int rep = 0; rep < 3; ++rep) {
+        inv_solve(u0, u1, u2, mlt, swp, zz, l, t);
+        for (int j = g0; j < t; ++j) {
+          double dot = 0.0;
+          for (int i = 0; i < l; ++i) dot += zz[(int64_t)i * l + j] * zz[(int64_t)i * l + t];
+          for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] -= dot * zz[(int64_t)i * l + j];
+        }
+        normalize2(zz, l, t);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < l * l; e += nt) Z[e] = zz[e];
+}
+
+// V = Qh Z = H_0 (H_1 (... (H_{l-3} Z))): reflector j acts on rows j+1 .. l-1. Z in LDS; each
+// column dot is split over `parts` threads.
+__global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const double* Zin, const double* Vh,
+                                                                      const double* tau, int l, double* V,
+                                                                      const double* theta, int* order) {
+  extern __shared__ double Zs[];  // l x l
+  __shared__ double vv[kEigMaxL], wcol[kEigMaxL];
+  __shared__ double red[8][kEigMaxL];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int parts = nt / l < 8 ? nt / l : 8;
+  for (int e = tid; e < l * l; e += nt) Zs[e] = Zin[e];
+  __syncthreads();
+  for (int j = l - 3; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;  // uniform
+    const int m = l - j - 1, r0 = j + 1;
+    for (int i = tid; i < m; i += nt) vv[i] = Vh[(int64_t)j * l + i];
+    __syncthreads();
+    if (tid < parts * l) {
+      const int c = tid % l, pt = tid / l;
+      double acc = 0.0;
+      for (int i = pt; i < m; i += parts) acc += vv[i] * Zs[(r0 + i) * l + c];
+      red[pt][c] = acc;
+    }
+    __syncthreads();
+    for (int c = tid; c < l; c += nt) {
+      double s = 0.0;
+      for (int pt = 0; pt < parts; ++pt) s += red[pt][c];
+      wcol[c] = tj * s;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    for (int i = wave; i < m; i += nwave) {
+      const double vi = vv[i];
+      double* row = Zs + (r0 + i) * l;
+      for (int c = lane; c < l; c += 64) row[c] -= vi * wcol[c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < l * l; e += nt) V[e] = Zs[e];
+  // theta ascending: the r-th largest is index l - 1 - r
+  for (int r = tid; r < l; r += nt) order[r] = l - 1 - r;
+  (void)theta;
+}
+
+int g_max_lds_eig = -1;
+
+int max_lds_eig() {
+  if (g_max_lds_eig < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 65536;
+    g_max_lds_eig = (int)prop.sharedMemPerBlock;
+  }
+  return g_max_lds_eig;
+}
+
+}  // namespace
+
+int eig64_work_len(int l) { return 8 * l * l + 4 * l; }
+
+int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V, double* theta, int* order) {
+  const size_t bytes = (size_t)l * l * sizeof(double);
+  if (l < 1 || l > kEigMaxL || (int64_t)bytes + 16384 > max_lds_eig()) {
+    set_error("eigendecomposition: the sketch width k + p must be in [1, 136]");
+    return SCS_EINVAL;
+  }
+  double* Vh = work;                         // l x l reflectors
+  double* dd = work + (int64_t)l * l;        // l
+  double* ee = dd + l;                       // l
+  double* tau = ee + l;                      // l
+  double* Zt = tau + l;                      // l x l
+  double* tw = Zt + (int64_t)l * l;          // 6 l^2: the tridiagonal solver's per-thread arrays
+  if (bytes > 65536) {
+    SCS_HIP(hipFuncSetAttribute((const void*)tridiag64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    SCS_HIP(hipFuncSetAttribute((const void*)backtransform64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+  }
+  tridiag64_kernel<<<1, 512, bytes, st>>>(B, l, dd, ee, Vh, tau);  // 512 threads: fewer waves at each barrier
+  SCS_HIP(hipGetLastError());
+  if (bytes > 65536)
+    SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  tridiag_eig_kernel<<<1, kEigThreads, bytes, st>>>(dd, ee, l, theta, Zt, tw);
+  SCS_HIP(hipGetLastError());
+  backtransform64_kernel<<<1, kEigThreads, bytes, st>>>(Zt, Vh, tau, l, V, theta, order);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+}  // namespace scs

@@ -17,7 +17,7 @@ constexpr int kVecThreads = 1024;
 constexpr int kVecWaves = kVecThreads / 64;
 
 __device__ __forceinline__ double block_sum_d(double v, double* sred) {
-  v = warp_sum_d(v);
+  v = wave_sum_d_fast(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sred[wave] = v;
@@ -55,7 +55,7 @@ __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* _
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      double t = warp_sum_d(acc[r]);
+      double t = wave_sum_d_fast(acc[r]);
       if (lane == 0 && i0 + r < k) tbuf[i0 + r] = t * (1.0 / sqrt(fmax(lam[i0 + r], 0.0) + lambda) - 1.0 / s);
     }
   }

@@ -45,6 +45,38 @@ __device__ __forceinline__ double warp_sum_d(double v) {
   return v;
 }
 
+// Sum over the 64 lanes with DPP row rotations (by 8, 4, 2, 1 inside each 16-lane row) and the
+// gfx950 row swaps (16-lane rows 0<->1, 2<->3, then the 32-lane halves): a few cycles per step
+// instead of an LDS round trip per step. Every lane ends with a sum of all 64 values; lanes may
+// differ in the last bit (their summation orders differ), so use one lane's value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double swap_add_d(double v, bool halves) {
+  const long long b = __double_as_longlong(v);
+  const unsigned int lo = (unsigned int)b, hi = (unsigned int)(b >> 32);
+  if (halves) {
+    auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __longlong_as_double(((long long)ph[0] << 32) | pl[0]) + __longlong_as_double(((long long)ph[1] << 32) | pl[1]);
+  }
+  auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __longlong_as_double(((long long)ph[0] << 32) | pl[0]) + __longlong_as_double(((long long)ph[1] << 32) | pl[1]);
+}
+__device__ __forceinline__ double wave_sum_d_fast(double v) {
+  v += dpp_d<0x128>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x121>(v);
+  v = swap_add_d(v, false);
+  return swap_add_d(v, true);
+}
+
 __device__ __forceinline__ double warp_max_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -147,7 +179,9 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
                   int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
                   float* C32, int64_t ldc32);
 int launch_chol_inv64(hipStream_t st, const double* G, int l, double* Rinv, int* flag);
-int launch_jacobi64(hipStream_t st, const double* B, int l, double* Awork, double* V, double* theta, int* order);
+// symmetric eigendecomposition B = V diag(theta) V^T (k_eig64.hip); work: eig64_work_len(l) doubles
+int eig64_work_len(int l);
+int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V, double* theta, int* order);
 // vector / small kernels
 int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double* V, const int* order, int k,
                 const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT);
