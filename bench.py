@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of a known size (reference for HBM traffic counters)")
     ap.add_argument("--plain-epochs", type=int, default=60, help="epoch cap of the plain-SVRG solves")
+    ap.add_argument("--implicit-apply", action="store_true",
+                    help="path workload: inner loop on x_i and z_i instead of formed preconditioned rows")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -201,7 +203,7 @@ def bench_path(args, cfg):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = ctx.svrg_solve_path(X, Y, list(lams), k, eps, f_star=fs, batch=b, epoch_factor=mf, max_epochs=150,
-                                  stop_rule=binding.STOP_GAP, step_scale=c,
+                                  stop_rule=binding.STOP_GAP, step_scale=c, implicit_apply=int(args.implicit_apply),
                                   precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
         if it >= args.warmup:
@@ -222,6 +224,7 @@ def bench_path(args, cfg):
                 {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
                  "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
                  "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
+                 "implicit_apply": bool(args.implicit_apply),
                  "stage_ms": {"sketch": reps[0]["ms_sketch"], "apply": reps[0]["ms_apply"],
                               "solve": reps[0]["ms_solve"]}})
     ctx.close()

@@ -79,6 +79,8 @@ typedef struct scs_opts {
                              end; -1 for epochs never enqueued because the stop rule had held */
   int timing;             /* 1: time every full-gradient pass and inner-loop launch with HIP events (report.ms_grad, ms_inner) */
   double epoch_factor;    /* with steps = 0 and epoch_factor > 0: m = ceil(epoch_factor n / b) per problem (default 0) */
+  int implicit_apply;     /* scs_svrg_solve_path only: 1 = never form the preconditioned rows; the inner loop uses
+                             x_i and z_i = U~^T x_i, O(d + k) per row (FP32 rows; needs d <= 2048, k <= 128) */
 } scs_opts;
 
 typedef struct scs_report {

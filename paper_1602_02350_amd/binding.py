@@ -45,6 +45,7 @@ class ScsOpts(ctypes.Structure):
         ("epoch_ms", ctypes.c_void_p),
         ("timing", ctypes.c_int),
         ("epoch_factor", ctypes.c_double),
+        ("implicit_apply", ctypes.c_int),
     ]
 
 

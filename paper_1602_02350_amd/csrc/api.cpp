@@ -1088,10 +1088,16 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   const int64_t m = epoch_steps(o, n, b);
   const int64_t N = n + d;
   const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 64)));  // residual row blocks
+  if (o.implicit_apply && (mixed || d > 2048 || k > 128 || k < 1)) {
+    set_error("implicit apply: needs FP32 precision, 1 <= k <= 128 and d <= 2048");
+    return SCS_EINVAL;
+  }
 
   // ---- workspace
-  void* xt_all = wsb(ctx, "p_xt", (size_t)nl * n * ldt * es);
-  void* reg_all = wsb(ctx, "p_reg", (size_t)nl * d * ldt * es);
+  // materialized rows: one set per lambda; implicit: one padded copy of X shared by every lambda
+  const int nsets = o.implicit_apply ? 1 : nl;
+  void* xt_all = wsb(ctx, "p_xt", (size_t)nsets * n * ldt * es);
+  void* reg_all = wsb(ctx, "p_reg", (size_t)nsets * d * ldt * es);
   if (!xt_all || !reg_all) return SCS_ENOMEM;
   WS(beta_all, float, "p_beta", (int64_t)nl * N);
   WS(cum_all, uint64_t, "p_cum", (int64_t)nl * N);
@@ -1132,18 +1138,28 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, &rank_def));
     if (rank_def) k_used = 0;
   }
+  const bool implicit = o.implicit_apply && k_used > 0;
   if (k_used > 0) {
     SCS_HIP(hipMemcpyAsync(ut, ws<float>(ctx, "UT32", 0), sizeof(float) * k * d, hipMemcpyDeviceToDevice, st));
     SCS_HIP(hipMemcpyAsync(lam64, ws<double>(ctx, "lam", 0), sizeof(double) * k, hipMemcpyDeviceToDevice, st));
   }
   SCS_HIP(hipEventRecord(tev[1], st));
   // ---- per lambda: P_lambda^{-1/2} rows, smoothness and sampling tables (shared by its ny solves)
+  float* xn2 = nullptr;
+  if (implicit) {
+    SCS_HIP(hipMemcpy2DAsync(xt_all, ldt * 4, X, ldx * 4, d * 4, n, hipMemcpyDeviceToDevice, st));
+    xn2 = ws<float>(ctx, "p_xnorm2", n);
+    if (!xn2) return SCS_ENOMEM;
+    SCS_CHECK(launch_rownorm(st, X, n, d, ldx, xn2));
+  }
   for (int j = 0; j < nl; ++j) {
-    char* xt = (char*)xt_all + (size_t)j * n * ldt * es;
-    char* rg = (char*)reg_all + (size_t)j * d * ldt * es;
+    char* xt = (char*)xt_all + (size_t)(implicit ? 0 : j) * n * ldt * es;
+    char* rg = (char*)reg_all + (size_t)(implicit ? 0 : j) * d * ldt * es;
     float* beta = beta_all + (int64_t)j * N;
     SolveState* st0 = states + (int64_t)j * ny;
-    if (k_used > 0) {
+    if (implicit) {
+      SCS_CHECK(launch_implicit_beta(st, xn2, ws<float>(ctx, "Z", 0), ut, lam64, k_used, n, d, lambdas[j], beta));
+    } else if (k_used > 0) {
       SCS_CHECK(apply_impl(ctx, X, n, d, ldx, ws<float>(ctx, "U32", 0), ws<float>(ctx, "Z", 0), lam64, k_used,
                            lambdas[j], mixed, mixed, xt, rg, ldt, beta, st0));
     } else {
@@ -1204,9 +1220,10 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     InnerArgs& a = q.inner;
     a.n = n;
     a.d = d;
-    a.Xt = (char*)xt_all + (size_t)j * n * ldt * es;
+    q.Z = implicit ? ws<float>(ctx, "Z", 0) : nullptr;
+    a.Xt = (char*)xt_all + (size_t)(implicit ? 0 : j) * n * ldt * es;
     a.ldx = ldt;
-    a.reg = (char*)reg_all + (size_t)j * d * ldt * es;
+    a.reg = (char*)reg_all + (size_t)(implicit ? 0 : j) * d * ldt * es;
     a.ldr = ldt;
     a.mu = q.mu;
     a.m = m;
@@ -1249,7 +1266,8 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     const int slot = s % G;
     if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, P, draw_pre, dpre[P], o.seed, s, G));
     SCS_HIP(hipEventRecord(dec[s], st));
-    SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
+    if (implicit) SCS_CHECK(launch_inner_implicit_batched(st, desc, P, d, k_used, b, slot, s));
+    else SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
     SCS_HIP(hipEventRecord(tev[4 + s], st));
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;

@@ -257,6 +257,7 @@ struct BatchProb {
   double eps, f_star;
   const uint64_t* cum;   // cumulative integer sampling weights over N = n + d components
   int64_t N;
+  const float* Z;        // n x k (X U~) for the implicit inner loop, else unused
   int64_t draws;         // m b draws per epoch
   int32_t* idx;          // kSampleGroup epochs of draws
   float* scale;
@@ -268,6 +269,11 @@ int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, c
                                 int64_t base, int64_t count, int64_t max_d, int vec4);
 int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
                                int64_t total_cb, int first, int* done_count, int* host_stop);
+// implicit preconditioned rows (k_implicit.hip): one workgroup per problem; inner.Xt holds X itself
+int launch_inner_implicit_batched(hipStream_t st, const BatchProb* P, int nprob, int64_t max_d, int max_k, int max_b,
+                                  int epoch_slot, int64_t epoch);
+int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, const float* UT, const double* lam, int k,
+                         int64_t n, int64_t d, double lambda, float* beta);
 int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
                                  int* host_stop);
 // Shared-X gradient of many problems: R = X W^T (gemm), then R[i][p] -= Y[p % ny][i] with per-block

@@ -364,9 +364,12 @@ def test_certificate_bounds_the_gap(ctx, k):
 
 
 # ------------------------------------------------------------------ regularization path (shared sketch)
+@pytest.mark.parametrize("implicit", [False, True])
 @pytest.mark.parametrize("n,d,k,ny,lams", [(3000, 200, 10, 3, [1e-4, 1e-3, 1e-2]),
-                                            (2500, 600, 12, 2, [3e-4, 3e-3])])
-def test_path_solves_reach_their_closed_forms(ctx, n, d, k, ny, lams):
+                                            (2500, 601, 12, 2, [3e-4, 3e-3])])
+def test_path_solves_reach_their_closed_forms(ctx, n, d, k, ny, lams, implicit):
+    """Every (lambda, y) solve of a path reaches its own closed form; with implicit_apply the rows
+    x~_i are never formed (the inner loop works from x_i and z_i = U~^T x_i)."""
     P = inputs.make_ridge(n, d, 1.5, lams[0], seed=80)
     X64 = P.X.astype(np.float64)
     # right-hand side 0 is the problem's own y; the others come from other planted weights
@@ -375,7 +378,8 @@ def test_path_solves_reach_their_closed_forms(ctx, n, d, k, ny, lams):
     Ys = np.stack([P.y.astype(np.float64)] + extra).astype(np.float32)
     eps = 1e-9
     rc, W, reps = ctx.svrg_solve_path(dev(P.X), dev(Ys), lams, k, eps, batch=16, max_epochs=200,
-                                      stop_rule=binding.STOP_CERTIFICATE, step_scale=2.0)
+                                      stop_rule=binding.STOP_CERTIFICATE, step_scale=2.0,
+                                      implicit_apply=int(implicit))
     assert rc == binding.OK, [r["status"] for r in reps]
     Wh = host(W)
     for j, lam in enumerate(lams):
