@@ -25,8 +25,13 @@ struct VecT<1> {
   using T = float;
 };
 
-__device__ __forceinline__ void vload(const float* p, float4& v) { v = *reinterpret_cast<const float4*>(p); }
-__device__ __forceinline__ void vload(const float* p, float& v) { v = *p; }
+// X is streamed once per pass: non-temporal loads keep it from displacing reused data in the caches
+typedef float f4v_nt __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void vload(const float* p, float4& v) {
+  const f4v_nt t = __builtin_nontemporal_load(reinterpret_cast<const f4v_nt*>(p));
+  v = make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ void vload(const float* p, float& v) { v = __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float comp(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 __device__ __forceinline__ float comp(const float& v, int) { return v; }
 
@@ -57,24 +62,31 @@ __device__ __forceinline__ void grad_partial_body(const float* __restrict__ X, i
   }
   double rsq = 0.0;
 
+  // Rows are taken in pairs (r, r + 4) per wave, and the next pair's loads are issued before the
+  // current pair is reduced (two pairs in flight per wave). Prefetch addresses past the block are
+  // clamped to row n - 1 and never used.
   int64_t r = r0 + wave;
-  // two rows in flight per wave
-  for (; r + kGradWaves < r1; r += 2 * kGradWaves) {
-    V xa[NCH], xb[NCH];
-    const float* pa = X + r * ldx;
-    const float* pb = X + (r + kGradWaves) * ldx;
+  constexpr int64_t kStep = 2 * kGradWaves;
+  auto load_pair = [&](int64_t rr, V (&A)[NCH], V (&Bv)[NCH], float& ya_, float& yb_) {
+    const int64_t ra = rr < n ? rr : n - 1;
+    const int64_t rb = rr + kGradWaves < n ? rr + kGradWaves : n - 1;
+    const float* pa = X + ra * ldx;
+    const float* pb = X + rb * ldx;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       int64_t col = (int64_t)(c * 64 + lane) * VEC;
       if (valid[c]) {
-        vload(pa + col, xa[c]);
-        vload(pb + col, xb[c]);
+        vload(pa + col, A[c]);
+        vload(pb + col, Bv[c]);
       } else {
-        xa[c] = V{};
-        xb[c] = V{};
+        A[c] = V{};
+        Bv[c] = V{};
       }
     }
-    float ya = y[r], yb = y[r + kGradWaves];
+    ya_ = y[ra];
+    yb_ = y[rb];
+  };
+  auto reduce_pair = [&](const V (&xa)[NCH], const V (&xb)[NCH], float ya, float yb) {
     float da = 0.f, db = 0.f;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -100,6 +112,21 @@ __device__ __forceinline__ void grad_partial_body(const float* __restrict__ X, i
         cmp[c][v] = (s2 - acc[c][v]) - t2;
         acc[c][v] = s2;
       }
+  };
+  if (r + kGradWaves < r1) {
+    V xa[NCH], xb[NCH], na[NCH], nb[NCH];
+    float ya, yb, nya, nyb;
+    load_pair(r, xa, xb, ya, yb);
+    for (;;) {
+      load_pair(r + kStep, na, nb, nya, nyb);
+      reduce_pair(xa, xb, ya, yb);
+      r += kStep;
+      if (!(r + kGradWaves < r1)) break;
+      load_pair(r + kStep, xa, xb, ya, yb);
+      reduce_pair(na, nb, nya, nyb);
+      r += kStep;
+      if (!(r + kGradWaves < r1)) break;
+    }
   }
   for (; r < r1; r += kGradWaves) {
     V xa[NCH];
@@ -224,7 +251,7 @@ int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, c
 
 int grad_num_workgroups(int64_t n, int64_t d) {
   (void)d;
-  int64_t want = 1024;  // 4 per CU on 256 CUs
+  int64_t want = 512;  // 2 per CU on 256 CUs (measured: 1024 and 2048 are slower, more rows per wave pipeline better)
   int64_t by_rows = cdiv(n, 8);
   return (int)(want < by_rows ? want : (by_rows < 1 ? 1 : by_rows));
 }
