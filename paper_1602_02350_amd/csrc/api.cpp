@@ -32,6 +32,8 @@ struct scs_ctx {
   std::map<std::string, Buf> bufs;
   std::vector<hipEvent_t> events;   // synchronizing events (host waits on them)
   std::vector<hipEvent_t> tevents;  // timing-only events (no system-scope fence when recorded)
+  std::vector<hipStream_t> side;       // extra streams for independent per-problem setup work
+  std::vector<hipEvent_t> side_events;
   int* stop_flags = nullptr;  // host-pinned, one per epoch: set by the device when the solve is finished
   size_t stop_cap = 0;
   int xcd_stride = 8;
@@ -45,7 +47,7 @@ void* wsb(scs_ctx* c, const std::string& name, size_t bytes) {
   auto& b = c->bufs[name];
   if (b.bytes >= bytes) return b.p;
   if (b.p) {
-    hipStreamSynchronize(c->stream);
+    hipDeviceSynchronize();  // the old buffer may be in use on any of the context's streams
     hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
@@ -79,6 +81,19 @@ int ensure_events(scs_ctx* c, size_t count, size_t tcount = 0) {
     hipEvent_t e;
     SCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     c->tevents.push_back(e);
+  }
+  return SCS_OK;
+}
+
+// count streams besides the context's own (default priority, non-blocking), each with an event
+int ensure_side_streams(scs_ctx* c, int count) {
+  while ((int)c->side.size() < count) {
+    hipStream_t q;
+    hipEvent_t e;
+    SCS_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    SCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->side.push_back(q);
+    c->side_events.push_back(e);
   }
   return SCS_OK;
 }
@@ -124,38 +139,41 @@ int choose_workgroups(const scs_opts& o, int64_t d) {
 // and, if want_z, "Z" = X U~ (n x k) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
 // flags_out (device, 2 ints, nullable): where CholeskyQR's breakdown flags go; when given, the call
 // does not wait for them and *rank_def is left unchanged (the caller reads the flags later).
+// st_in / sfx: the stream to use and a suffix for the names of its workspace buffers (so that
+// sketches of different problems can run on different streams at once).
 int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
-                bool want_z, bool* rank_def, int* flags_out = nullptr) {
-  hipStream_t st = ctx->stream;
+                bool want_z, bool* rank_def, int* flags_out = nullptr, hipStream_t st_in = nullptr,
+                const std::string& sfx = "") {
+  hipStream_t st = st_in ? st_in : ctx->stream;
   const int l = k + o.oversample;
   const int bf = o.precision == SCS_PREC_MIXED;
   // Omega^T (l x d)
   const float* OmT = o.omega;
   if (!OmT) {
-    WS(om, float, "omega", (size_t)l * d);
+    WS(om, float, std::string("omega") + sfx, (size_t)l * d);
     SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, om));
     OmT = om;
   }
   // T = X Omega (n x l)
-  WS(T, float, "T", (size_t)n * l);
+  WS(T, float, std::string("T") + sfx, (size_t)n * l);
   SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, OmT, l, d, T, l));
   // Y = X^T T (d x l), split over row chunks, summed in FP64
   int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 512), std::max<int64_t>(1, 1024 / cdiv(d, 64))));
   int64_t chunk = cdiv(n, nchunks);
   nchunks = cdiv(n, chunk);
-  WS(part, float, "partial", (size_t)nchunks * d * l);
+  WS(part, float, std::string("partial") + sfx, (size_t)nchunks * d * l);
   SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, l, part, chunk, nchunks));
-  WS(Y, double, "Y64", (size_t)d * l);
+  WS(Y, double, std::string("Y64") + sfx, (size_t)d * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
   // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
-  WS(G, double, "G64", (size_t)l * l);
-  WS(Rinv, double, "Rinv64", (size_t)l * l);
-  WS(Q1, double, "Q1_64", (size_t)d * l);
-  WS(Q, double, "Q64", (size_t)d * l);
-  WS(QT32, float, "QT32", (size_t)l * d);
+  WS(G, double, std::string("G64") + sfx, (size_t)l * l);
+  WS(Rinv, double, std::string("Rinv64") + sfx, (size_t)l * l);
+  WS(Q1, double, std::string("Q1_64") + sfx, (size_t)d * l);
+  WS(Q, double, std::string("Q64") + sfx, (size_t)d * l);
+  WS(QT32, float, std::string("QT32") + sfx, (size_t)l * d);
   int* flags = flags_out;
   if (!flags) {
-    flags = ws<int>(ctx, "cholflags", 2);
+    flags = ws<int>(ctx, "cholflags" + sfx, 2);
     if (!flags) return SCS_ENOMEM;
   }
   SCS_CHECK(launch_gemm64(st, l, l, d, Y, 1, l, Y, l, 1, G, l, nullptr, 0));
@@ -166,29 +184,29 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Q, l, nullptr, 0));
   SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QT32, d));  // Q^T = R2^{-T} Q1^T
   // Rayleigh-Ritz: Wq = X Q (n x l), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
-  WS(Wq, float, "Wq", (size_t)n * l);
+  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * l);
   SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, l, d, Wq, l));
   int64_t nch2 = std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 256)));
   int64_t chunk2 = cdiv(n, nch2);
   nch2 = cdiv(n, chunk2);
-  WS(part2, float, "partial2", (size_t)nch2 * l * l);
+  WS(part2, float, std::string("partial2") + sfx, (size_t)nch2 * l * l);
   SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, l, Wq, l, l, part2, chunk2, nch2));
-  WS(B, double, "B64", (size_t)l * l);
+  WS(B, double, std::string("B64") + sfx, (size_t)l * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)l * l, 1.0 / (double)n, B));
-  WS(V, double, "V64", (size_t)l * l);
-  WS(theta, double, "theta", (size_t)l);
-  WS(order, int, "order", (size_t)l);
-  WS(eigw, double, "eig_work", eig64_work_len(l));
+  WS(V, double, std::string("V64") + sfx, (size_t)l * l);
+  WS(theta, double, std::string("theta") + sfx, (size_t)l);
+  WS(order, int, std::string("order") + sfx, (size_t)l);
+  WS(eigw, double, std::string("eig_work") + sfx, eig64_work_len(l));
   SCS_CHECK(launch_eig64(st, B, l, eigw, V, theta, order));
   // lift: U~ = Q V_k, lam = theta_{1..k}
-  WS(U64, double, "U64", (size_t)d * k);
-  WS(U32, float, "U32", (size_t)d * k);
-  WS(UT32, float, "UT32", (size_t)k * d);
-  WS(lam, double, "lam", (size_t)k);
-  WS(VkT, float, "VkT", (size_t)k * l);
+  WS(U64, double, std::string("U64") + sfx, (size_t)d * k);
+  WS(U32, float, std::string("U32") + sfx, (size_t)d * k);
+  WS(UT32, float, std::string("UT32") + sfx, (size_t)k * d);
+  WS(lam, double, std::string("lam") + sfx, (size_t)k);
+  WS(VkT, float, std::string("VkT") + sfx, (size_t)k * l);
   SCS_CHECK(launch_lift(st, Q, d, l, V, order, k, theta, U64, U32, UT32, lam, VkT));
   if (want_z) {
-    WS(Z, float, "Z", (size_t)n * k);
+    WS(Z, float, std::string("Z") + sfx, (size_t)n * k);
     SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, k));
   }
   if (flags_out) return SCS_OK;
@@ -202,10 +220,10 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
 // Preconditioned rows: Xt = X/s + Z (U D)^T (ld ldt), reg = sqrt(n lambda)(U (U D)^T + I/s), beta = row norms.
 int apply_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* U32, const float* Z,
                const double* lam, int k, double lambda, int gemm_bf16, int out_bf16, void* Xt, void* reg,
-               int64_t ldt, float* beta, SolveState* state) {
-  hipStream_t st = ctx->stream;
-  WS(UD, float, "UD32", (size_t)d * k);
-  WS(scal, double, "scal", 2);
+               int64_t ldt, float* beta, SolveState* state, hipStream_t st_in = nullptr, const std::string& sfx = "") {
+  hipStream_t st = st_in ? st_in : ctx->stream;
+  WS(UD, float, "UD32" + sfx, (size_t)d * k);
+  WS(scal, double, "scal" + sfx, 2);
   SCS_CHECK(launch_precond_setup(st, lam, k, lambda, n, U32, d, UD, scal, state));
   SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Z, n, k, k, UD, d, k, 1.0f, X, ldx, 0.f, scal, 0.f, nullptr,
                                 out_bf16, Xt, ldt, beta));
@@ -291,6 +309,8 @@ int scs_destroy(scs_ctx* c) {
     if (kv.second.p) hipFree(kv.second.p);
   for (auto e : c->events) hipEventDestroy(e);
   for (auto e : c->tevents) hipEventDestroy(e);
+  for (auto e : c->side_events) hipEventDestroy(e);
+  for (auto q : c->side) hipStreamDestroy(q);
   if (c->stop_flags) hipHostFree(c->stop_flags);
   delete c;
   return SCS_OK;
@@ -852,39 +872,55 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   std::vector<int> ord(nprob);
   for (int p = 0; p < nprob; ++p) ord[p] = p;
   std::stable_sort(ord.begin(), ord.end(), [&](int a_, int b_) { return n[a_] * d[a_] > n[b_] * d[b_]; });
-  auto setup_identity = [&](int p) -> int {
+  auto setup_identity = [&](int p, hipStream_t sq, const std::string& sfx) -> int {
     char* xt = (char*)xt_all + o_xt[p] * es;
     char* rg = (char*)reg_all + o_reg[p] * es;
     float* beta = beta_all + o_beta[p];
     if (mixed) {
-      WS(tmp16, uint16_t, "xcopy16", n[p] * d[p]);
-      SCS_CHECK(launch_copy_bf16(st, X[p], n[p], d[p], ldx[p], tmp16));
-      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 2, tmp16, d[p] * 2, d[p] * 2, n[p], hipMemcpyDeviceToDevice, st));
-      SCS_CHECK(launch_rownorm_bf16(st, tmp16, n[p], d[p], beta));
+      WS(tmp16, uint16_t, "xcopy16" + sfx, n[p] * d[p]);
+      SCS_CHECK(launch_copy_bf16(sq, X[p], n[p], d[p], ldx[p], tmp16));
+      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 2, tmp16, d[p] * 2, d[p] * 2, n[p], hipMemcpyDeviceToDevice, sq));
+      SCS_CHECK(launch_rownorm_bf16(sq, tmp16, n[p], d[p], beta));
     } else {
-      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 4, X[p], ldx[p] * 4, d[p] * 4, n[p], hipMemcpyDeviceToDevice, st));
-      SCS_CHECK(launch_rownorm(st, X[p], n[p], d[p], ldx[p], beta));
+      SCS_HIP(hipMemcpy2DAsync(xt, ldt[p] * 4, X[p], ldx[p] * 4, d[p] * 4, n[p], hipMemcpyDeviceToDevice, sq));
+      SCS_CHECK(launch_rownorm(sq, X[p], n[p], d[p], ldx[p], beta));
     }
-    WS(rtmp, float, "regtmp", d[p] * d[p]);
-    SCS_CHECK(launch_fill_scaled_identity(st, d[p], std::sqrt((double)n[p] * lambda[p]), mixed, rtmp, beta + n[p]));
-    SCS_HIP(hipMemcpy2DAsync(rg, ldt[p] * es, rtmp, d[p] * es, d[p] * es, d[p], hipMemcpyDeviceToDevice, st));
+    WS(rtmp, float, "regtmp" + sfx, d[p] * d[p]);
+    SCS_CHECK(launch_fill_scaled_identity(sq, d[p], std::sqrt((double)n[p] * lambda[p]), mixed, rtmp, beta + n[p]));
+    SCS_HIP(hipMemcpy2DAsync(rg, ldt[p] * es, rtmp, d[p] * es, d[p] * es, d[p], hipMemcpyDeviceToDevice, sq));
     return SCS_OK;
   };
-  for (int p : ord) {
+  // Problems are independent until their epochs: their sketches and preconditioned rows are built
+  // on up to kLanes streams at once (each with its own workspace buffers), largest problems first,
+  // so the latency-bound small kernels of different problems overlap on different CUs.
+  constexpr int kLanes = 8;
+  const int lanes = std::min(nprob, kLanes);
+  SCS_CHECK(ensure_side_streams(ctx, lanes));
+  SCS_HIP(hipEventRecord(tev[1], st));
+  for (int q = 0; q < lanes; ++q) SCS_HIP(hipStreamWaitEvent(ctx->side[q], tev[1], 0));
+  for (int i = 0; i < nprob; ++i) {
+    const int p = ord[i], lane = i % lanes;
+    hipStream_t sq = ctx->side[lane];
+    const std::string sfx = "#" + std::to_string(lane);
     if (k[p] > 0) {
       bool unused = false;
-      SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p));
-      const float* U32 = ws<float>(ctx, "U32", 0);
-      SCS_HIP(hipMemcpyAsync(ut_all + o_ut[p], ws<float>(ctx, "UT32", 0), sizeof(float) * k[p] * d[p],
-                             hipMemcpyDeviceToDevice, st));
-      SCS_HIP(hipMemcpyAsync(lam_all + o_lam[p], ws<double>(ctx, "lam", 0), sizeof(double) * k[p],
-                             hipMemcpyDeviceToDevice, st));
-      SCS_CHECK(apply_impl(ctx, X[p], n[p], d[p], ldx[p], U32, ws<float>(ctx, "Z", 0), lam_all + o_lam[p], k[p],
-                           lambda[p], mixed, mixed, (char*)xt_all + o_xt[p] * es, (char*)reg_all + o_reg[p] * es,
-                           ldt[p], beta_all + o_beta[p], states + sidx[p]));
+      SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p, sq, sfx));
+      const float* U32 = ws<float>(ctx, "U32" + sfx, 0);
+      SCS_HIP(hipMemcpyAsync(ut_all + o_ut[p], ws<float>(ctx, "UT32" + sfx, 0), sizeof(float) * k[p] * d[p],
+                             hipMemcpyDeviceToDevice, sq));
+      SCS_HIP(hipMemcpyAsync(lam_all + o_lam[p], ws<double>(ctx, "lam" + sfx, 0), sizeof(double) * k[p],
+                             hipMemcpyDeviceToDevice, sq));
+      SCS_CHECK(apply_impl(ctx, X[p], n[p], d[p], ldx[p], U32, ws<float>(ctx, "Z" + sfx, 0), lam_all + o_lam[p],
+                           k[p], lambda[p], mixed, mixed, (char*)xt_all + o_xt[p] * es,
+                           (char*)reg_all + o_reg[p] * es, ldt[p], beta_all + o_beta[p], states + sidx[p], sq,
+                           sfx));
     } else {
-      SCS_CHECK(setup_identity(p));
+      SCS_CHECK(setup_identity(p, sq, sfx));
     }
+  }
+  for (int q = 0; q < lanes; ++q) {
+    SCS_HIP(hipEventRecord(ctx->side_events[q], ctx->side[q]));
+    SCS_HIP(hipStreamWaitEvent(st, ctx->side_events[q], 0));
   }
   // CholeskyQR breakdown: those problems fall back to P = I (status SKETCH_RANK_DEFICIENT)
   std::vector<int> hflags(2 * nprob, 0);
@@ -896,7 +932,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     if (k[p] > 0 && (hflags[2 * p] || hflags[2 * p + 1])) {
       rank_def[p] = 1;
       k_used[p] = 0;
-      SCS_CHECK(setup_identity(p));
+      SCS_CHECK(setup_identity(p, st, ""));
     }
   }
   for (int p = 0; p < nprob; ++p)
