@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fp32_n100000_d1000")
     ap.add_argument("--precision", choices=["fp32", "mixed"], default=None)
-    ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--workgroups", type=int, default=-1, help="inner-loop workgroups; -1 = autotuned by the library")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-epochs", type=int, default=2)
     ap.add_argument("--fixed", default=None,
@@ -419,6 +419,7 @@ def main():
         "epochs": {"precond": rp["epochs"], "plain": reps["plain"].report["epochs"]},
         "step_scale": {"precond": tuned["precond"][0], "plain": tuned["plain"][0]},
         "steps_per_epoch": {"precond": rp["steps"], "plain": reps["plain"].report["steps"]},
+        "workgroups": {"precond": rp["workgroups"], "plain": reps["plain"].report["workgroups"]},
         "suboptimality": so,
         "w_rel_err": relerr,
         "stage_ms": {"sketch": rp["ms_sketch"], "apply": rp["ms_apply"], "solve": rp["ms_solve"]},

@@ -69,7 +69,8 @@ typedef struct scs_opts {
   double f_star;          /* optimum value for SCS_STOP_GAP */
   int average;            /* 1: snapshot = average of the m inner iterates (Alg. 1); 0: last iterate */
   int precision;          /* SCS_PREC_* (default SCS_PREC_FP32) */
-  int workgroups;         /* inner-loop workgroups per problem; 0 = chosen from d */
+  int workgroups;         /* inner-loop workgroups per problem; 0 = chosen from d; -1 = autotuned: timed on the
+                             problem's own rows on first use per (d, b, precision), cached in the context */
   uint64_t seed;          /* seed of the Gaussian test matrix and of the index stream */
   const float* omega;     /* optional device (k+p) x d row-major Gaussian test matrix (transposed Omega); NULL = drawn from seed */
   const int32_t* indices; /* optional device index stream, max_epochs x m x b entries in [0, n+d); NULL = drawn from seed */
@@ -98,6 +99,7 @@ typedef struct scs_report {
   double ms_grad, ms_inner; /* with opts.timing: summed durations of the full-gradient passes and inner-loop launches */
   int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
   int backoffs;             /* rejected snapshots: each restored the previous one and halved the step */
+  int workgroups;           /* inner-loop workgroups used per problem */
 } scs_report;
 
 void scs_opts_default(scs_opts* opts);

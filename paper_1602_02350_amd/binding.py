@@ -69,6 +69,7 @@ class ScsReport(ctypes.Structure):
         ("n_grad", ctypes.c_int),
         ("n_inner", ctypes.c_int),
         ("backoffs", ctypes.c_int),
+        ("workgroups", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -32,6 +32,8 @@ struct scs_ctx {
   std::map<std::string, Buf> bufs;
   std::vector<hipEvent_t> events;   // synchronizing events (host waits on them)
   std::vector<hipEvent_t> tevents;  // timing-only events (no system-scope fence when recorded)
+  std::map<std::string, int> tuned_w;  // autotuned inner-loop workgroup counts per (d, b, precision)
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   std::vector<hipStream_t> side;       // extra streams for independent per-problem setup work
   std::vector<hipEvent_t> side_events;
   int* stop_flags = nullptr;  // host-pinned, one per epoch: set by the device when the solve is finished
@@ -133,6 +135,78 @@ int64_t epoch_steps(const scs_opts& o, int64_t n, int b) {
 int choose_workgroups(const scs_opts& o, int64_t d) {
   if (o.workgroups > 0) return o.workgroups;
   return inner_default_workgroups(d);
+}
+
+// Measured choice of the inner loop's workgroup count (the width of each workgroup's column slice):
+// a few dozen steps of the epoch kernel on the problem's own rows, with a scratch snapshot, state and
+// exchange buffer, for each candidate; the fastest is kept in the context per (d, b, precision).
+int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int bf16, const uint64_t* cum,
+                        int64_t N, uint64_t seed, int* W_out) {
+  const std::string key = std::to_string(base.d) + "/" + std::to_string(base.b) + "/" + std::to_string(bf16);
+  auto it = ctx->tuned_w.find(key);
+  if (it != ctx->tuned_w.end()) {
+    *W_out = it->second;
+    return SCS_OK;
+  }
+  std::vector<int> cand;
+  for (int cols : {128, 64, 32}) {
+    const int W = (int)std::max<int64_t>(1, std::min<int64_t>(16, cdiv(base.d, cols)));
+    if (cdiv(cdiv(base.d, W), 4) * 4 > 512) continue;
+    if (std::find(cand.begin(), cand.end(), W) == cand.end()) cand.push_back(W);
+  }
+  if (cand.size() <= 1) {
+    *W_out = cand.empty() ? inner_default_workgroups(base.d) : cand[0];
+    ctx->tuned_w[key] = *W_out;
+    return SCS_OK;
+  }
+  for (auto& e : ctx->tune_ev)
+    if (!e) SCS_HIP(hipEventCreate(&e));
+  // every timed run gathers its own rows (a fresh index stream), as a real epoch does: rows already
+  // in the caches would favour fewer, wider workgroups
+  const int64_t mp = std::min<int64_t>(base.m, 48);
+  const int reps = 2, runs = (int)cand.size() * reps;
+  WS(twt, float, "at_wt", base.d);
+  WS(tmu, float, "at_mu", base.d);
+  WS(tidx, int32_t, "at_idx", runs * mp * base.b);
+  WS(tsc, float, "at_scale", runs * mp * base.b);
+  WS(tstate, SolveState, "at_state", 1);
+  WS(txb, uint64_t, "at_xbuf", 2 * 16 * 64);
+  SCS_HIP(hipMemsetAsync(tmu, 0, sizeof(float) * base.d, st));
+  SCS_CHECK(launch_sample(st, cum, N, base.n, seed, 0x7fff0000, mp * base.b, runs * mp * base.b, tidx, tsc, nullptr));
+  int best = cand[0], run = 0;
+  float best_ms = 1e30f;
+  for (int W : cand) {
+    for (int rep = 0; rep < reps; ++rep, ++run) {
+      SCS_HIP(hipMemsetAsync(twt, 0, sizeof(float) * base.d, st));
+      SCS_HIP(hipMemsetAsync(txb, 0, sizeof(uint64_t) * 2 * 16 * 64, st));
+      SCS_HIP(hipMemcpyAsync(tstate, base.state, sizeof(SolveState), hipMemcpyDeviceToDevice, st));
+      InnerArgs a = base;
+      a.W = W;
+      a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+      a.m = mp;
+      a.idx = tidx + (int64_t)run * mp * base.b;
+      a.scale = tsc + (int64_t)run * mp * base.b;
+      a.mu = tmu;
+      a.wt = twt;
+      a.wt_prev = nullptr;
+      a.xbuf = txb;
+      a.state = tstate;
+      a.step_base = 0;
+      SCS_HIP(hipEventRecord(ctx->tune_ev[0], st));
+      SCS_CHECK(launch_inner_epoch(st, a, bf16));
+      SCS_HIP(hipEventRecord(ctx->tune_ev[1], st));
+      SCS_HIP(hipEventSynchronize(ctx->tune_ev[1]));
+      float ms = 0.f;
+      SCS_HIP(hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = W;
+      }
+    }
+  }
+  ctx->tuned_w[key] = best;
+  *W_out = best;
+  return SCS_OK;
 }
 
 // Sketch of Alg. 2 with one block. Fills ws buffers "U32" (d x k), "UT32" (k x d), "U64", "lam",
@@ -311,6 +385,8 @@ int scs_destroy(scs_ctx* c) {
   for (auto e : c->tevents) hipEventDestroy(e);
   for (auto e : c->side_events) hipEventDestroy(e);
   for (auto q : c->side) hipStreamDestroy(q);
+  for (auto e : c->tune_ev)
+    if (e) hipEventDestroy(e);
   if (c->stop_flags) hipHostFree(c->stop_flags);
   delete c;
   return SCS_OK;
@@ -596,7 +672,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   SCS_HIP(hipEventRecord(ev_apply, st));
 
   // ---- SVRG epochs (Alg. 1)
-  const int W = choose_workgroups(o, d);
+  int W = choose_workgroups(o, d);
   WS(wt, float, "wt", (size_t)d);
   WS(wt_prev, float, "wt_prev", (size_t)d);
   WS(w32, float, "w32", (size_t)d);
@@ -610,10 +686,10 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   constexpr int kSampleGroup = 8;
   WS(idxb, int32_t, "idx", (size_t)kSampleGroup * m * b);
   WS(scale, float, "scale", (size_t)kSampleGroup * m * b);
-  WS(xbuf, uint64_t, "xbuf", (size_t)2 * W * 64);
+  WS(xbuf, uint64_t, "xbuf", (size_t)2 * 16 * 64);
   SCS_HIP(hipMemsetAsync(wt, 0, sizeof(float) * d, st));
   SCS_HIP(hipMemsetAsync(wt_prev, 0, sizeof(float) * d, st));
-  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * W * 64, st));
+  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * 16 * 64, st));
 
   InnerArgs a{};
   a.n = n;
@@ -635,6 +711,11 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   a.wt_prev = wt_prev;
   a.xbuf = xbuf;
   a.state = state;
+  if (o.workgroups < 0) {
+    SCS_CHECK(autotune_workgroups(ctx, st, a, rows_bf16, cum, N, o.seed, &W));
+    a.W = W;
+    a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+  }
 
   constexpr int kLookahead = 3;
   int last_epoch = -1;
@@ -712,6 +793,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     report->certificate = hs.cert;
     report->lam_top = hs.lam_top;
     report->backoffs = hs.backoffs;
+    report->workgroups = W;
     float t1 = 0, t2 = 0, t3 = 0;
     hipEventElapsedTime(&t1, ev_start, ev_sketch);
     hipEventElapsedTime(&t2, ev_sketch, ev_apply);
@@ -788,6 +870,11 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   const int nv = (int)kord.size();
   for (int p = 0; p < nprob; ++p)
     if (!vec4[p]) kord.push_back(p);
+  // largest first inside each group (when the inner loop needs several launches, the longest
+  // problems start first)
+  auto bigger = [&](int a_, int b_) { return n[a_] * d[a_] > n[b_] * d[b_]; };
+  std::stable_sort(kord.begin(), kord.begin() + nv, bigger);
+  std::stable_sort(kord.begin() + nv, kord.end(), bigger);
   std::vector<int> sidx(nprob);
   for (int i = 0; i < nprob; ++i) sidx[kord[i]] = i;
   if (max_d > 16 * 512) {
@@ -1074,6 +1161,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
       r.certificate = h.cert;
       r.lam_top = h.lam_top;
       r.backoffs = h.backoffs;
+      r.workgroups = W;
       r.ms_sketch = t_setup;
       r.ms_apply = 0.0;
       r.ms_solve = t_solve;
@@ -1349,6 +1437,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       rp.certificate = h.cert;
       rp.lam_top = h.lam_top;
       rp.backoffs = h.backoffs;
+      rp.workgroups = implicit ? 1 : W;
       rp.ms_sketch = t_sk;
       rp.ms_apply = t_ap;
       rp.ms_solve = t_so;

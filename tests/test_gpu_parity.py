@@ -419,3 +419,15 @@ def test_step_backoff_recovers_from_a_too_large_step(ctx):
     assert res.status == binding.OK, res.report
     assert 1 <= res.report["backoffs"] <= 6
     assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= 1.5e-9
+
+
+def test_autotuned_workgroups_solve_matches_the_closed_form(ctx):
+    P = inputs.make_ridge(3000, 300, 1.5, 1e-4, seed=38)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, P.lam)
+    Ls = ridge.objective(X64, y64, P.lam, ws)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), P.lam, 12, 1e-9, batch=32, max_epochs=100, step_scale=4.0,
+                         stop_rule=binding.STOP_GAP, f_star=Ls, workgroups=-1)
+    assert res.status == binding.OK, res.report
+    assert res.report["workgroups"] in (3, 5, 10)   # ceil(300 / 128), ceil(300 / 64), ceil(300 / 32)
+    assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= 1.5e-9
