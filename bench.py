@@ -60,24 +60,8 @@ def log(args, *a):
 
 def make_problem_gpu(cfg, seed):
     """The synthetic recipe of paper_1602_02350_amd.inputs, drawn on the GPU: x_i ~ N(0, U diag(j^-a) U^T)."""
-    import torch
-    n, d = cfg["n"], cfg["d"]
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    G = torch.randn(d, d, generator=g, device="cuda", dtype=torch.float64)
-    Q, R = torch.linalg.qr(G)
-    U = Q * torch.sign(torch.diagonal(R))[None, :]
-    j = torch.arange(1, d + 1, device="cuda", dtype=torch.float64)
-    spec = j ** (-cfg["alpha"]) + cfg.get("floor", 0.0)
-    M = (spec.sqrt()[:, None] * U.T).float().contiguous()
-    X = torch.empty(n, d, device="cuda", dtype=torch.float32)
-    for r0 in range(0, n, 65536):
-        r1 = min(n, r0 + 65536)
-        X[r0:r1] = torch.randn(r1 - r0, d, generator=g, device="cuda") @ M
-    w0 = torch.randn(d, generator=g, device="cuda", dtype=torch.float64)
-    noise = torch.randn(n, generator=g, device="cuda", dtype=torch.float64) * math.sqrt(0.01)
-    y = (X.double() @ w0 + noise).float()
-    return X, y
+    from paper_1602_02350_amd import inputs
+    return inputs.make_ridge_torch(cfg["n"], cfg["d"], cfg["alpha"], seed, floor=cfg.get("floor", 0.0))
 
 
 def reference_optimum(X, y, lam):

@@ -137,3 +137,26 @@ def uneven_batch_shapes(cfg, seed):
         lam = float(np.exp(rng.uniform(np.log(cfg["lam_lo"]), np.log(cfg["lam_hi"]))))
         out.append((n, d, a, lam, d // 16))
     return out
+
+
+def make_ridge_torch(n: int, d: int, alpha: float, seed: int, noise_var: float = 0.01, floor: float = 0.0,
+                     device: str = "cuda", block: int = 65536):
+    """The same recipe drawn with torch's generator on a device, for the large workloads: returns X
+    (n x d FP32) and y (n FP32) as device tensors. (A different random stream from make_ridge.)"""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    G = torch.randn(d, d, generator=g, device=device, dtype=torch.float64)
+    Q, R = torch.linalg.qr(G)
+    U = Q * torch.sign(torch.diagonal(R))[None, :]
+    j = torch.arange(1, d + 1, device=device, dtype=torch.float64)
+    spec = j ** (-float(alpha)) + float(floor)
+    M = (spec.sqrt()[:, None] * U.T).float().contiguous()
+    X = torch.empty(n, d, device=device, dtype=torch.float32)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        X[r0:r1] = torch.randn(r1 - r0, d, generator=g, device=device) @ M
+    w0 = torch.randn(d, generator=g, device=device, dtype=torch.float64)
+    noise = torch.randn(n, generator=g, device=device, dtype=torch.float64) * float(noise_var) ** 0.5
+    y = (X.double() @ w0 + noise).float()
+    return X, y

@@ -1,0 +1,138 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configuration bench.py times
+(k, b, the tuned step scale and epoch length, autotuned workgroups), on outputs the FP64 oracle
+computes directly: the sketch from the same Omega, sampled preconditioned rows, the full gradient
+at a random point and the closed-form optimum. Each stage's error against the oracle is printed
+(pytest -s) and bounded by what its arithmetic allows:
+  * sketch: |lam~_gpu - lam~_orc| <= 8 u_eff lam~_1 with u_eff = 2^-24 sqrt(d) (FP32 GEMMs) or 2^-8
+    (BF16 GEMMs), and the two preconditioners agree on random probes;
+  * rows: each x~_i close to P^{-1/2} x_i formed in FP64 from the GPU's own U~ and lam~ (this
+    isolates the apply arithmetic): within 8 u_eff in FP32; with BF16 GEMM inputs within
+    2^-8 (4 ||x_i|| / (s ||x~_i||) + 1), the cancellation of x_i / s by the low-rank term;
+  * gradient: within 1e-5 of the exact map P^{-1/2}(X^T (X w - y)/n + lambda w), w = P^{-1/2} w~;
+  * solve: L(w) - L* <= eps with L* from the Cholesky closed form.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import precond, ridge, sketch
+from paper_1602_02350_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+# workload -> (tuned step scale, epoch factor) as bench.py finds them
+TUNED = {"fp32_n100000_d1000": (64.0, 0.0625), "mixed_n500000_d2048": (64.0, 0.0625)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module", params=list(TUNED))
+def full(request, ctx):
+    name = request.param
+    cfg = inputs.WORKLOADS[name]
+    X, y = inputs.make_ridge_torch(cfg["n"], cfg["d"], cfg["alpha"], inputs.BASE_SEED + 11, floor=cfg["floor"])
+    torch.cuda.synchronize()
+    out = dict(name=name, cfg=cfg, X=X, y=y, X64=X.double().cpu().numpy(), y64=y.double().cpu().numpy(),
+               mixed=name.startswith("mixed"))
+    out["prec"] = binding.PREC_MIXED if out["mixed"] else binding.PREC_FP32
+    yield out
+    del out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_sketch_stage(ctx, full):
+    cfg, X64 = full["cfg"], full["X64"]
+    k, d = cfg["k"], cfg["d"]
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 12)
+    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), precision=full["prec"])
+    assert rc == binding.OK
+    Uo, lo, _ = sketch.sketch(X64, Om.T.astype(np.float64), k)
+    lg = lam.cpu().numpy()
+    u_eff = 2.0 ** -8 if full["mixed"] else 2.0 ** -24 * np.sqrt(d)
+    err = np.max(np.abs(lg - lo)) / lo[0]
+    Pg = precond.sketched_preconditioner(U64.cpu().numpy(), lg, cfg["lam"])
+    Po = precond.sketched_preconditioner(Uo, lo, cfg["lam"])
+    V = np.random.default_rng(0).standard_normal((d, 8))
+    perr = _rel(Pg @ V, Po @ V)
+    print(f"\n[{full['name']}] sketch: max |d lam~| / lam~_1 = {err:.3e} (bound {8 * u_eff:.1e}); "
+          f"P^-1/2 probe rel err = {perr:.3e}")
+    assert err <= 8 * u_eff
+    assert perr < (5e-2 if full["mixed"] else 1e-4)
+    full["U32"], full["lam"] = U, lam
+
+
+def test_apply_stage_on_sampled_rows(ctx, full):
+    if "U32" not in full:
+        pytest.skip("sketch stage did not run")
+    cfg, X64 = full["cfg"], full["X64"]
+    n, d = X64.shape
+    Xt, reg, beta = ctx.precondition_apply(full["X"], full["U32"], full["lam"], cfg["lam"], bf16=full["mixed"])
+    Pm = precond.sketched_preconditioner(full["U32"].cpu().numpy().astype(np.float64), full["lam"].cpu().numpy(),
+                                         cfg["lam"])
+    rows = np.random.default_rng(1).choice(n, 256, replace=False)
+    got = Xt[torch.from_numpy(rows).cuda()].float().cpu().numpy().astype(np.float64)
+    ref = X64[rows] @ Pm
+    rn = np.linalg.norm(ref, axis=1)
+    row_err = np.linalg.norm(got - ref, axis=1) / rn
+    if full["mixed"]:
+        # The low-rank correction Z (U~ D)^T is formed from BF16-rounded X and U~ (2^-8 relative) and
+        # cancels most of x_i / s along the top directions, so its rounding error scales with
+        # ||x_i|| max_r |D_r| <= ||x_i|| / s rather than with ||x~_i||; the output adds one BF16 rounding.
+        lam_g = full["lam"].cpu().numpy()
+        s = np.sqrt(max(lam_g[-1], 0.0) + cfg["lam"])
+        amp = np.linalg.norm(X64[rows], axis=1) / (s * rn)
+        tol = 4 * 2.0 ** -8 * amp + 2.0 ** -8
+        worst = int(np.argmax(row_err / tol))
+        print(f"\n[{full['name']}] preconditioned rows: max row rel err = {row_err.max():.3e}; worst row "
+              f"{row_err[worst]:.3e} vs bound {tol[worst]:.3e} (cancellation factor {amp[worst]:.1f})")
+        assert np.all(row_err < tol)
+    else:
+        tol = 8 * 2.0 ** -24 * np.sqrt(d)
+        print(f"\n[{full['name']}] preconditioned rows: max row rel err = {row_err.max():.3e} (bound {tol:.1e})")
+        assert row_err.max() < tol
+    del Xt, reg, beta
+
+
+def test_gradient_stage(ctx, full):
+    if "U32" not in full:
+        pytest.skip("sketch stage did not run")
+    cfg, X64, y64 = full["cfg"], full["X64"], full["y64"]
+    n, d = X64.shape
+    wt = inputs.random_vector(d, seed=13, scale=0.1).astype(np.float32)
+    g, obj = ctx.full_gradient(full["X"], full["y"], full["U32"], full["lam"], cfg["lam"], torch.from_numpy(wt).cuda())
+    Pm = precond.sketched_preconditioner(full["U32"].cpu().numpy().astype(np.float64), full["lam"].cpu().numpy(),
+                                         cfg["lam"])
+    w = Pm @ wt.astype(np.float64)
+    go = Pm @ (X64.T @ (X64 @ w - y64) / n + cfg["lam"] * w)
+    err = _rel(g.cpu().numpy().astype(np.float64), go)
+    oerr = abs(obj - ridge.objective(X64, y64, cfg["lam"], w)) / ridge.objective(X64, y64, cfg["lam"], w)
+    print(f"\n[{full['name']}] full gradient: rel err = {err:.3e}, objective rel err = {oerr:.3e} (bound 1e-5)")
+    assert err < 1e-5 and oerr < 1e-6
+
+
+def test_solve_stage(ctx, full):
+    cfg, X64, y64 = full["cfg"], full["X64"], full["y64"]
+    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    Ls = ridge.objective(X64, y64, cfg["lam"], ws)
+    c, mf = TUNED[full["name"]]
+    n = X64.shape[0]
+    res = ctx.svrg_solve(full["X"], full["y"], cfg["lam"], cfg["k"], cfg["eps"], batch=cfg["b"],
+                         steps=max(1, int(round(mf * n / cfg["b"]))), max_epochs=60, stop_rule=binding.STOP_GAP,
+                         f_star=Ls, step_scale=c, seed=inputs.BASE_SEED + 2, precision=full["prec"], workgroups=-1)
+    w = res.w.double().cpu().numpy()
+    so = ridge.suboptimality(X64, cfg["lam"], w, ws)
+    print(f"\n[{full['name']}] solve: status {res.status}, {res.report['epochs']} epochs, "
+          f"L(w) - L* = {so:.3e} (eps {cfg['eps']:.0e}), ||w - w*|| / ||w*|| = {_rel(w, ws):.3e}, "
+          f"{res.report['workgroups']} workgroups")
+    assert res.status == binding.OK, res.report
+    assert so <= cfg["eps"] * 1.0001
