@@ -210,7 +210,8 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
 }
 
 // Sketch of Alg. 2 with one block. Fills ws buffers "U32" (d x k), "UT32" (k x d), "U64", "lam",
-// and, if want_z, "Z" = X U~ (n x k) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
+// and, if want_z, "Z" = X U~ (n x k, leading dimension gemm_wide_kpad(k), zero up to the next multiple
+// of 16) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
 // flags_out (device, 2 ints, nullable): where CholeskyQR's breakdown flags go; when given, the call
 // does not wait for them and *rank_def is left unchanged (the caller reads the flags later).
 // st_in / sfx: the stream to use and a suffix for the names of its workspace buffers (so that
@@ -280,8 +281,9 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   WS(VkT, float, std::string("VkT") + sfx, (size_t)k * l);
   SCS_CHECK(launch_lift(st, Q, d, l, V, order, k, theta, U64, U32, UT32, lam, VkT));
   if (want_z) {
-    WS(Z, float, std::string("Z") + sfx, (size_t)n * k);
-    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, k));
+    const int64_t kz = gemm_wide_kpad(k);
+    WS(Z, float, std::string("Z") + sfx, (size_t)n * kz);
+    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, kz, true));
   }
   if (flags_out) return SCS_OK;
   int hflags[2] = {0, 0};
@@ -292,16 +294,19 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
 }
 
 // Preconditioned rows: Xt = X/s + Z (U D)^T (ld ldt), reg = sqrt(n lambda)(U (U D)^T + I/s), beta = row norms.
+// Z: n x k with leading dimension gemm_wide_kpad(k), zero up to the next multiple of 16.
 int apply_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* U32, const float* Z,
                const double* lam, int k, double lambda, int gemm_bf16, int out_bf16, void* Xt, void* reg,
                int64_t ldt, float* beta, SolveState* state, hipStream_t st_in = nullptr, const std::string& sfx = "") {
   hipStream_t st = st_in ? st_in : ctx->stream;
-  WS(UD, float, "UD32" + sfx, (size_t)d * k);
+  const int64_t kz = gemm_wide_kpad(k), drows = gemm_wide_bt_rows(d);
+  WS(UD, float, "UD32" + sfx, (size_t)drows * kz);
+  WS(Up, float, "Upad32" + sfx, (size_t)drows * kz);
   WS(scal, double, "scal" + sfx, 2);
-  SCS_CHECK(launch_precond_setup(st, lam, k, lambda, n, U32, d, UD, scal, state));
-  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Z, n, k, k, UD, d, k, 1.0f, X, ldx, 0.f, scal, 0.f, nullptr,
+  SCS_CHECK(launch_precond_setup(st, lam, k, lambda, n, U32, d, UD, Up, kz, scal, state));
+  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Z, n, k, kz, UD, d, kz, 1.0f, X, ldx, 0.f, scal, 0.f, nullptr,
                                 out_bf16, Xt, ldt, beta));
-  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, U32, d, k, k, UD, d, k, (float)std::sqrt((double)n * lambda),
+  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Up, d, k, kz, UD, d, kz, (float)std::sqrt((double)n * lambda),
                                 nullptr, 0, 0.f, nullptr, 0.f, scal + 1, out_bf16, reg, ldt, beta ? beta + n : nullptr));
   return SCS_OK;
 }
@@ -465,8 +470,9 @@ int scs_precondition_apply(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   }
   WS(UT, float, "UT_apply", (size_t)k * d);
   SCS_CHECK(launch_transpose_f32(st, U, d, k, UT));
-  WS(Z, float, "Z_apply", (size_t)n * k);
-  SCS_CHECK(launch_gemm_nt_longk(st, xt_bf16, X, n, d, ldx, UT, k, d, Z, k));
+  const int64_t kz = gemm_wide_kpad(k);
+  WS(Z, float, "Z_apply", (size_t)n * kz);
+  SCS_CHECK(launch_gemm_nt_longk(st, xt_bf16, X, n, d, ldx, UT, k, d, Z, kz, true));
   return apply_impl(ctx, X, n, d, ldx, U, Z, lam, k, lambda, xt_bf16, xt_bf16, Xt_out, reg_out, ldt, beta_out,
                     nullptr);
 }
@@ -1282,7 +1288,8 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     float* beta = beta_all + (int64_t)j * N;
     SolveState* st0 = states + (int64_t)j * ny;
     if (implicit) {
-      SCS_CHECK(launch_implicit_beta(st, xn2, ws<float>(ctx, "Z", 0), ut, lam64, k_used, n, d, lambdas[j], beta));
+      SCS_CHECK(launch_implicit_beta(st, xn2, ws<float>(ctx, "Z", 0), gemm_wide_kpad(k_used), ut, lam64, k_used, n,
+                                     d, lambdas[j], beta));
     } else if (k_used > 0) {
       SCS_CHECK(apply_impl(ctx, X, n, d, ldx, ws<float>(ctx, "U32", 0), ws<float>(ctx, "Z", 0), lam64, k_used,
                            lambdas[j], mixed, mixed, xt, rg, ldt, beta, st0));
@@ -1345,6 +1352,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     a.n = n;
     a.d = d;
     q.Z = implicit ? ws<float>(ctx, "Z", 0) : nullptr;
+    q.ldz = gemm_wide_kpad(k_used);
     a.Xt = (char*)xt_all + (size_t)(implicit ? 0 : j) * n * ldt * es;
     a.ldx = ldt;
     a.reg = (char*)reg_all + (size_t)(implicit ? 0 : j) * d * ldt * es;

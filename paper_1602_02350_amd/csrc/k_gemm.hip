@@ -10,11 +10,34 @@
 // consumes k = kq + 4*(lane/16) + r, which sums the same 16 products as the natural order); the
 // BF16 16x16x16 instruction takes the same four values rounded to BF16 (RNE) with FP32 accumulation.
 // Output layout of both 16x16 instructions: acc[r] = C[4*(lane/16) + r][lane % 16].
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "scs_internal.h"
 
 namespace scs {
 
 namespace {
+
+// Workgroups of `fn` that fit on the current device at once (cached per kernel, LDS size and
+// device); 0 when the runtime cannot say.
+int resident_blocks(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_tuple(fn, lds, dev);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const int r = per_cu * cus;
+  cache[key] = r;
+  return r;
+}
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
@@ -56,7 +79,7 @@ template <int NB, bool BF16>
 __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restrict__ A, int64_t M, int64_t K,
                                                             int64_t lda, const float* __restrict__ Bt, int64_t N,
                                                             int64_t ldb, float* __restrict__ C, int64_t ldc,
-                                                            bool a_al, bool b_al) {
+                                                            int64_t nst, bool a_al, bool b_al) {
   constexpr int BN = NB * 16;
   constexpr int LDS_W = kLkBK + kLkPad;
   __shared__ float As[kLkBM * LDS_W];
@@ -123,128 +146,209 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
       for (int r = 0; r < 4; ++r) {
         int64_t row = m0 + wave * 32 + rbk * 16 + 4 * (lane >> 4) + r;
         int64_t col = cb * 16 + (lane & 15);
-        if (row < M && col < N) C[row * ldc + col] = acc[rbk][cb][r];
+        if (row < M && col < nst) C[row * ldc + col] = acc[rbk][cb][r];
       }
 }
 
 // ------------------------------------------------------------------ NT, wide N, short K
-constexpr int kWdBM = 64, kWdBN = 64;
+// C = alpha A Bt^T + beta C0 (+ diag where row == col). A is M x KP and Bt is (N rounded up to 64) x KP
+// with KP = gemm_wide_kpad(K) (16, 32, 64, 128 or 160). Bt is zero past K and past N; A is zero from K
+// to the next multiple of 16 and its 16-column blocks past that are ignored. The only load that needs
+// a guard is A's row, clamped once per tile. The MFMA runs transposed, D = Bt_chunk A^T, so
+// that acc[r] = C[row0 + lane % 16][col0 + 4 (lane / 16) + r]: each lane ends with four consecutive
+// columns of one row and the epilogue reads C0 and writes C with 16-byte (8-byte for BF16) accesses
+// straight from registers. Each wave owns 16 rows whose A fragments stay in registers for the whole
+// tile; Bt is streamed through LDS in 64-row chunks, double-buffered (rounded to BF16 once at staging
+// in BF16 mode), and the next C0 chunk is fetched as soon as the current one is used. Workgroups
+// loop over row tiles (grid sized to the resident capacity).
+// K <= 64: 512 threads (128-row tiles), four waves per SIMD; wider K holds more A fragments per lane:
+// 256 threads (64-row tiles), three or two waves per SIMD.
+constexpr int wd_threads(int nkq) { return nkq <= 4 ? 512 : 256; }
+constexpr int wd_waves(int nkq) { return nkq <= 4 ? 4 : (nkq <= 8 ? 3 : 2); }
+constexpr int kWdBN = 64;                       // output columns per chunk
 
-template <bool BF16, bool OUT_BF16>
-__global__ __launch_bounds__(256) void gemm_nt_wide_kernel(const float* __restrict__ A, int64_t M, int64_t K,
-                                                           int64_t lda, const float* __restrict__ Bt, int64_t N,
-                                                           int64_t ldb, float alpha, const float* __restrict__ C0,
-                                                           int64_t ldc0, float beta, const double* beta_dev,
-                                                           float diag, const double* diag_dev, void* Cout,
-                                                           int64_t ldc, float* __restrict__ rownorm2, int KP,
-                                                           bool a_al, bool b_al, bool c0_al, bool out_al) {
+template <bool BF16, bool OUT_BF16, int NKQ, bool VEC>
+__global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_kernel(
+    const float* __restrict__ A, int64_t M, int64_t lda, const float* __restrict__ Bt, int N, int64_t ldb,
+    float alpha, const float* __restrict__ C0, int64_t ldc0, float beta, const double* beta_dev, float diag,
+    const double* diag_dev, void* Cout, int64_t ldc, float* __restrict__ rownorm2, int nq) {
   extern __shared__ float S[];
-  const int LW = KP + 4;
-  constexpr int CW = kWdBN + 4;
-  float* As = S;                  // kWdBM x LW
-  float* Bs = S + kWdBM * LW;     // kWdBN x LW
-  float* Cs = Bs + kWdBN * LW;    // kWdBM x CW: the MFMA tile, re-read by rows for the epilogue
+  constexpr int KP = 16 * NKQ;                 // A blocks q >= nq (K rounded up to 16, over 16) count as zero
+  constexpr int LW = KP + 4, LH = KP + 8;      // LDS row strides: floats, BF16 halves
+  constexpr int BUF = BF16 ? kWdBN * LH / 2 : kWdBN * LW;
+  constexpr int kWdThreads = wd_threads(NKQ);
+  constexpr int kWdBM = 16 * (kWdThreads / 64);   // rows per tile: 16 per wave
+  constexpr int RB = (kWdBN * 4 * NKQ + kWdThreads - 1) / kWdThreads;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * kWdBM;
+  const int rl = lane & 15, g4 = 4 * (lane >> 4);
+  constexpr int kv = 4 * NKQ;                  // float4 per Bt row
+  constexpr int ne = kWdBN * kv;               // float4 per chunk
+  const int nch = (N + kWdBN - 1) / kWdBN;
+  const int64_t ntiles = (M + kWdBM - 1) / kWdBM;
   if (beta_dev) beta = (float)beta_dev[0];
   if (diag_dev) diag = (float)diag_dev[0];
-  const int kv = KP / 4;
-  for (int e = tid; e < kWdBM * kv; e += 256) {
-    int r = e / kv, c4 = e % kv;
-    *reinterpret_cast<float4*>(&As[r * LW + 4 * c4]) = load4(A, lda, M, K, m0 + r, 4 * c4, a_al);
-  }
-  // epilogue mapping: lane owns columns cc..cc+3 of rows 4p + lane/16 (p = 0..3) of its wave's 16 rows,
-  // so 16 lanes move one contiguous 256-byte row segment
-  const int cc = 4 * (lane & 15);
-  float rn[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t n0 = 0; n0 < N; n0 += kWdBN) {
-    __syncthreads();
-    for (int e = tid; e < kWdBN * kv; e += 256) {
-      int r = e / kv, c4 = e % kv;
-      *reinterpret_cast<float4*>(&Bs[r * LW + 4 * c4]) = load4(Bt, ldb, N, K, n0 + r, 4 * c4, b_al);
-    }
-    __syncthreads();
-    f4v acc[4];
+
+  // staging slot j of this thread: float4 e = tid + threads j of the chunk, row e / kv, column 4 (e % kv);
+  // a slot past the chunk re-reads the chunk's first float4 and is not stored
+  f4v rb[RB];
+  auto load_b = [&](int c) {
+    const float* base = Bt + (int64_t)c * kWdBN * ldb;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (int kq = 0; kq < KP; kq += 16) {
-      const int ko = kq + 4 * (lane >> 4);
-      float4 a = *reinterpret_cast<const float4*>(&As[(wave * 16 + (lane & 15)) * LW + ko]);
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kWdThreads * j;
+      const int off = (ne % kWdThreads == 0 || e < ne) ? (e / kv) * (int)ldb + 4 * (e % kv) : 0;
+      rb[j] = *reinterpret_cast<const f4v*>(base + off);
+    }
+  };
+  auto stash_b = [&](int bsel) {
+    float* base = S + bsel * BUF;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kWdThreads * j;
+      if (ne % kWdThreads == 0 || e < ne) {
+        const int r = e / kv, c4 = e % kv;
+        if constexpr (BF16) {
+          const uint2 h = make_uint2(pack_bf16x2(rb[j][0], rb[j][1]), pack_bf16x2(rb[j][2], rb[j][3]));
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + r * LH + 4 * c4) = h;
+        } else {
+          *reinterpret_cast<f4v*>(base + r * LW + 4 * c4) = rb[j];
+        }
+      }
+    }
+  };
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * kWdBM + wave * 16 + rl;
+    const bool row_ok = row < M;
+    const int64_t rowc = row_ok ? row : M - 1;
+    // A fragments: lane holds A[row][16 q + g4 .. +3]
+    float4 af[NKQ];
+    s4v ah[NKQ];
+    {
+      const float* arow = A + rowc * lda + g4;
+#pragma unroll
+      for (int q = 0; q < NKQ; ++q) {
+        float4 v = *reinterpret_cast<const float4*>(arow + 16 * q);
+        if (q >= nq) v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (BF16) {
+          const uint32_t lo = pack_bf16x2(v.x, v.y), hi = pack_bf16x2(v.z, v.w);
+          ah[q] = s4v{(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
+        } else {
+          af[q] = v;
+        }
+      }
+    }
+    const float* xrow = C0 ? C0 + rowc * ldc0 : nullptr;
+    float4 xc[4];
+    auto load_x = [&](int c) {
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        float4 b = *reinterpret_cast<const float4*>(&Bs[(cb * 16 + (lane & 15)) * LW + ko]);
-        mfma16<BF16>(a, b, acc[cb]);
-      }
-    }
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Cs[(wave * 16 + 4 * (lane >> 4) + r) * CW + cb * 16 + (lane & 15)] = acc[cb][r];
-    __syncthreads();
-    const int64_t col = n0 + cc;
-    if (col < N) {
-      const bool full = col + 3 < N;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int rl = wave * 16 + 4 * p + (lane >> 4);
-        const int64_t row = m0 + rl;
-        if (row >= M) continue;
-        float4 t = *reinterpret_cast<const float4*>(&Cs[rl * CW + cc]);
-        float v[4] = {alpha * t.x, alpha * t.y, alpha * t.z, alpha * t.w};
-        if (C0) {
-          float4 c = load4(C0, ldc0, M, N, row, col, c0_al);
-          v[0] = fmaf(beta, c.x, v[0]);
-          v[1] = fmaf(beta, c.y, v[1]);
-          v[2] = fmaf(beta, c.z, v[2]);
-          v[3] = fmaf(beta, c.w, v[3]);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (row == col + q) v[q] += diag;
-        if constexpr (OUT_BF16) {
-          uint16_t h[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            h[q] = f32_to_bf16(v[q]);
-            v[q] = bf16_to_f32(h[q]);
-          }
-          uint16_t* o = reinterpret_cast<uint16_t*>(Cout) + row * ldc + col;
-          if (full && out_al) {
-            uint2 w;
-            w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-            w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-            *reinterpret_cast<uint2*>(o) = w;
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (col + q < N) o[q] = h[q];
-          }
+        const int col = c * kWdBN + cb * 16 + g4;
+        if (!xrow) {
+          xc[cb] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else if constexpr (VEC) {
+          xc[cb] = *reinterpret_cast<const float4*>(xrow + min(col, N - 4));
         } else {
-          float* o = reinterpret_cast<float*>(Cout) + row * ldc + col;
-          if (full && out_al) {
-            *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
-          } else {
+          xc[cb] = make_float4(xrow[min(col, N - 1)], xrow[min(col + 1, N - 1)], xrow[min(col + 2, N - 1)],
+                               xrow[min(col + 3, N - 1)]);
+        }
+      }
+    };
+    float rn = 0.f;
+
+    __syncthreads();   // the previous tile's chunk buffers are free
+    load_b(0);
+    stash_b(0);
+    if (nch > 1) load_b(1);
+    load_x(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      f4v acc[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (col + q < N) o[q] = v[q];
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
+      const float* base = S + (c & 1) * BUF;
+#pragma unroll
+      for (int q = 0; q < NKQ; ++q) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if constexpr (BF16) {
+            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
+                                                         (cb * 16 + rl) * LH + 16 * q + g4);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv, ah[q], acc[cb], 0, 0, 0);
+          } else {
+            const float4 bv = *reinterpret_cast<const float4*>(base + (cb * 16 + rl) * LW + 16 * q + g4);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv.x, af[q].x, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv.y, af[q].y, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv.z, af[q].z, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv.w, af[q].w, acc[cb], 0, 0, 0);
           }
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (col + q < N) rn[p] = fmaf(v[q], v[q], rn[p]);
+        __builtin_amdgcn_sched_barrier(0);   // keeps each step's LDS reads next to their MFMAs
       }
-    }
-  }
-  if (rownorm2) {
+      if (c + 1 < nch) {
+        stash_b((c + 1) & 1);
+        if (c + 2 < nch) load_b(c + 2);
+      }
+      // epilogue
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      float t = rn[p];
-      t += __shfl_xor(t, 1);
-      t += __shfl_xor(t, 2);
-      t += __shfl_xor(t, 4);
-      t += __shfl_xor(t, 8);
-      int64_t row = m0 + wave * 16 + 4 * p + (lane >> 4);
-      if ((lane & 15) == 0 && row < M) rownorm2[row] = t;
+      for (int cb = 0; cb < 4; ++cb) {
+        const int col = c * kWdBN + cb * 16 + g4;
+        float v[4] = {alpha * acc[cb][0], alpha * acc[cb][1], alpha * acc[cb][2], alpha * acc[cb][3]};
+        if (xrow) {
+          v[0] = fmaf(beta, xc[cb].x, v[0]);
+          v[1] = fmaf(beta, xc[cb].y, v[1]);
+          v[2] = fmaf(beta, xc[cb].z, v[2]);
+          v[3] = fmaf(beta, xc[cb].w, v[3]);
+        }
+        if (diag != 0.f) {
+          const int64_t dq = row - col;   // v[dq] sits on the diagonal when 0 <= dq < 4
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (dq == q) v[q] += diag;
+        }
+        uint32_t lo = 0, hi = 0;
+        if constexpr (OUT_BF16) {
+          lo = pack_bf16x2(v[0], v[1]);
+          hi = pack_bf16x2(v[2], v[3]);
+          v[0] = __uint_as_float(lo << 16);
+          v[1] = __uint_as_float(lo & 0xffff0000u);
+          v[2] = __uint_as_float(hi << 16);
+          v[3] = __uint_as_float(hi & 0xffff0000u);
+        }
+        if (row_ok && col < N) {
+          if constexpr (VEC) {
+            if constexpr (OUT_BF16)
+              *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(Cout) + row * ldc + col) = make_uint2(lo, hi);
+            else
+              *reinterpret_cast<float4*>(reinterpret_cast<float*>(Cout) + row * ldc + col) =
+                  make_float4(v[0], v[1], v[2], v[3]);
+            rn = fmaf(v[0], v[0], rn);
+            rn = fmaf(v[1], v[1], rn);
+            rn = fmaf(v[2], v[2], rn);
+            rn = fmaf(v[3], v[3], rn);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (col + q < N) {
+                if constexpr (OUT_BF16)
+                  reinterpret_cast<uint16_t*>(Cout)[row * ldc + col + q] =
+                      (uint16_t)((q < 2 ? lo : hi) >> (16 * (q & 1)));
+                else
+                  reinterpret_cast<float*>(Cout)[row * ldc + col + q] = v[q];
+                rn = fmaf(v[q], v[q], rn);
+              }
+            }
+          }
+        }
+      }
+      if (c + 1 < nch) load_x(c + 1);   // lands during the next chunk's staging and MFMA
+      __syncthreads();
+    }
+    if (rownorm2) {
+      float t = rn;
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      if (g4 == 0 && row_ok) rownorm2[row] = t;
     }
   }
 }
@@ -372,12 +476,12 @@ bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (
 
 template <bool BF16>
 int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt,
-                   int64_t N, int64_t ldb, float* C, int64_t ldc) {
+                   int64_t N, int64_t ldb, float* C, int64_t ldc, int64_t nst) {
   dim3 grid((unsigned)cdiv(M, kLkBM));
   bool aa = aligned16(A, lda), ba = aligned16(Bt, ldb);
 #define SCS_LK(NBV) \
   case NBV:         \
-    gemm_nt_longk_kernel<NBV, BF16><<<grid, 256, 0, st>>>(A, M, K, lda, Bt, N, ldb, C, ldc, aa, ba); break;
+    gemm_nt_longk_kernel<NBV, BF16><<<grid, 256, 0, st>>>(A, M, K, lda, Bt, N, ldb, C, ldc, nst, aa, ba); break;
   switch (nb) {
     SCS_LK(1) SCS_LK(2) SCS_LK(3) SCS_LK(4) SCS_LK(5) SCS_LK(6) SCS_LK(7) SCS_LK(8) SCS_LK(9)
     default:
@@ -413,11 +517,21 @@ int tn_dispatch(hipStream_t st, int nb, const float* A, int64_t R, int64_t M, in
 }  // namespace
 
 int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
-                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc) {
+                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16) {
   if (M <= 0 || N <= 0) return SCS_OK;
   int nb = (int)cdiv(N, 16);
-  return bf16 ? longk_dispatch<true>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc)
-              : longk_dispatch<false>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc);
+  const int64_t nst = pad16 ? 16 * (int64_t)nb : N;   // columns N.. of the last 16 are zero
+  if (nst > ldc) {
+    set_error("gemm_nt_longk: ldc smaller than the stored width");
+    return SCS_EINVAL;
+  }
+  return bf16 ? longk_dispatch<true>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst)
+              : longk_dispatch<false>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+}
+
+int gemm_wide_kpad(int64_t K) {
+  const int64_t q = cdiv(K < 1 ? 1 : K, 16);
+  return q <= 2 ? (int)(16 * q) : (q <= 4 ? 64 : (q <= 8 ? 128 : 160));
 }
 
 int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
@@ -429,28 +543,50 @@ int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int
     set_error("gemm_nt_wide: K > 160");
     return SCS_EINVAL;
   }
-  int KP = (int)cdiv(K < 1 ? 1 : K, 16) * 16;
-  size_t bytes = ((size_t)(kWdBM + kWdBN) * (KP + 4) + (size_t)kWdBM * (kWdBN + 4)) * sizeof(float);
-  dim3 grid((unsigned)cdiv(M, kWdBM));
-  bool aa = aligned16(A, lda), ba = aligned16(Bt, ldb);
-  bool ca = C0 ? aligned16(C0, ldc0) : false;
-  bool oa = out_bf16 ? ((uintptr_t)C % 8 == 0 && ldc % 4 == 0) : aligned16(C, ldc);
-  const void* fn;
-  if (bf16) fn = out_bf16 ? (const void*)gemm_nt_wide_kernel<true, true> : (const void*)gemm_nt_wide_kernel<true, false>;
-  else fn = out_bf16 ? (const void*)gemm_nt_wide_kernel<false, true> : (const void*)gemm_nt_wide_kernel<false, false>;
-  if (bytes > 65536) SCS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-#define SCS_WD(B1, B2)                                                                                          \
-  gemm_nt_wide_kernel<B1, B2><<<grid, 256, bytes, st>>>(A, M, K, lda, Bt, N, ldb, alpha, C0, ldc0, beta,     \
-                                                         beta_dev, diag, diag_dev, C, ldc, rownorm2, KP, aa, ba, ca, oa)
-  if (bf16) {
-    if (out_bf16) SCS_WD(true, true);
-    else SCS_WD(true, false);
-  } else {
-    if (out_bf16) SCS_WD(false, true);
-    else SCS_WD(false, false);
+  const int KP = gemm_wide_kpad(K), NK = KP / 16;
+  if (lda < KP || ldb < KP || !aligned16(A, lda) || !aligned16(Bt, ldb) || N > (1 << 30) ||
+      cdiv(N, kWdBN) * kWdBN * ldb > (int64_t)1 << 31) {
+    set_error("gemm_nt_wide: A and Bt need 16-byte aligned rows of at least gemm_wide_kpad(K) values, and Bt at "
+              "most 2^31 elements (rows rounded up to 64)");
+    return SCS_EINVAL;
   }
-#undef SCS_WD
-  SCS_HIP(hipGetLastError());
+  const int Ni = (int)N, nq = (int)cdiv(K < 1 ? 1 : K, 16);
+  const bool vec = N % 4 == 0 && (C0 == nullptr || aligned16(C0, ldc0)) &&
+                   (out_bf16 ? ((uintptr_t)C % 8 == 0 && ldc % 4 == 0) : aligned16(C, ldc));
+  const size_t bytes = bf16 ? (size_t)2 * kWdBN * (KP + 8) * 2 : (size_t)2 * kWdBN * (KP + 4) * 4;
+  const void* fn = nullptr;
+#define SCS_WD_PICK(NKV)                                                                                         \
+  if (bf16) {                                                                                                    \
+    if (out_bf16) fn = vec ? (const void*)gemm_nt_wide_kernel<true, true, NKV, true>                             \
+                           : (const void*)gemm_nt_wide_kernel<true, true, NKV, false>;                           \
+    else fn = vec ? (const void*)gemm_nt_wide_kernel<true, false, NKV, true>                                     \
+                  : (const void*)gemm_nt_wide_kernel<true, false, NKV, false>;                                   \
+  } else {                                                                                                       \
+    if (out_bf16) fn = vec ? (const void*)gemm_nt_wide_kernel<false, true, NKV, true>                            \
+                           : (const void*)gemm_nt_wide_kernel<false, true, NKV, false>;                          \
+    else fn = vec ? (const void*)gemm_nt_wide_kernel<false, false, NKV, true>                                    \
+                  : (const void*)gemm_nt_wide_kernel<false, false, NKV, false>;                                  \
+  }
+  switch (NK) {
+    case 1: SCS_WD_PICK(1) break;
+    case 2: SCS_WD_PICK(2) break;
+    case 4: SCS_WD_PICK(4) break;
+    case 8: SCS_WD_PICK(8) break;
+    default: SCS_WD_PICK(10) break;
+  }
+#undef SCS_WD_PICK
+  if (bytes > 65536) SCS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  const int threads = wd_threads(NK);
+  const int res = resident_blocks(fn, threads, bytes);
+  if (res <= 0) {
+    set_error("gemm_nt_wide: no resident workgroup capacity reported for this shape");
+    return SCS_EDEVICE;
+  }
+  const int64_t grid = std::min<int64_t>(cdiv(M, 16 * (threads / 64)), (int64_t)res);
+  void* args[] = {(void*)&A,    (void*)&M,    (void*)&lda,  (void*)&Bt,       (void*)&Ni,   (void*)&ldb,
+                  (void*)&alpha, (void*)&C0,  (void*)&ldc0, (void*)&beta,     (void*)&beta_dev, (void*)&diag,
+                  (void*)&diag_dev, (void*)&C, (void*)&ldc, (void*)&rownorm2, (void*)&nq};
+  SCS_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(threads), args, bytes, st));
   return SCS_OK;
 }
 

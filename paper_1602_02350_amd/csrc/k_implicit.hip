@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kImpThreads) void inner_implicit_kernel(const Batch
           if (c + 3 < d) p = fmaf(x4.w, dx[c + 3], p);
         }
         p *= is;
-        const float* zr = Z + (int64_t)i * k;
+        const float* zr = Z + (int64_t)i * q.ldz;
         for (int r = lane; r < k; r += 64) p = fmaf(zr[r], vv[r], p);
       } else {
         const int jj = (int)(i - (uint32_t)n);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kImpThreads) void inner_implicit_kernel(const Batch
       float gz = 0.f;
       for (int j = 0; j < b; ++j) {
         const uint32_t i = (uint32_t)sidx[j];
-        const float zv = i < (uint32_t)n ? Z[(int64_t)i * k + r] : sq * UT[(int64_t)r * d + (int)(i - (uint32_t)n)];
+        const float zv = i < (uint32_t)n ? Z[(int64_t)i * q.ldz + r] : sq * UT[(int64_t)r * d + (int)(i - (uint32_t)n)];
         gz = fmaf(gam[j], zv, gz);
       }
       const float nda = da[r] - eta * Ds[r] * gz;
@@ -169,15 +169,15 @@ __global__ __launch_bounds__(kImpThreads) void inner_implicit_kernel(const Batch
 
 // beta_i = ||x~_i||^2 = ||x_i||^2 / s^2 + z_i^T (2 D / s + D^2) z_i for data rows and
 // n lambda (1/s^2 + u_j^T (2 D / s + D^2) u_j) for regularizer rows, without forming x~.
-__global__ void implicit_beta_kernel(const float* xnorm2, const float* Z, const float* UT, const double* lam, int k,
-                                     int64_t n, int64_t d, double lambda, float* beta) {
+__global__ void implicit_beta_kernel(const float* xnorm2, const float* Z, int64_t ldz, const float* UT,
+                                     const double* lam, int k, int64_t n, int64_t d, double lambda, float* beta) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n + d) return;
   const double s = sqrt(fmax(k > 0 ? lam[k - 1] : 0.0, 0.0) + lambda);
   double acc = 0.0;
   for (int r = 0; r < k; ++r) {
     const double D = 1.0 / sqrt(fmax(lam[r], 0.0) + lambda) - 1.0 / s;
-    const double z = i < n ? (double)Z[i * k + r] : (double)UT[(int64_t)r * d + (i - n)];
+    const double z = i < n ? (double)Z[i * ldz + r] : (double)UT[(int64_t)r * d + (i - n)];
     acc += z * z * (2.0 * D / s + D * D);
   }
   beta[i] = i < n ? (float)((double)xnorm2[i] / (s * s) + acc) : (float)((double)n * lambda * (1.0 / (s * s) + acc));
@@ -197,10 +197,10 @@ int launch_inner_implicit_batched(hipStream_t st, const BatchProb* P, int nprob,
   return SCS_OK;
 }
 
-int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, const float* UT, const double* lam, int k,
-                         int64_t n, int64_t d, double lambda, float* beta) {
-  implicit_beta_kernel<<<dim3((unsigned)cdiv(n + d, 256)), dim3(256), 0, st>>>(xnorm2, Z, UT, lam, k, n, d, lambda,
-                                                                               beta);
+int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, int64_t ldz, const float* UT,
+                         const double* lam, int k, int64_t n, int64_t d, double lambda, float* beta) {
+  implicit_beta_kernel<<<dim3((unsigned)cdiv(n + d, 256)), dim3(256), 0, st>>>(xnorm2, Z, ldz, UT, lam, k, n, d,
+                                                                               lambda, beta);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -333,16 +333,25 @@ __global__ void lift_kernel(const double* Q, int64_t d, int l, const double* V, 
   if (e < k) lam[e] = fmax(theta[order[e]], 0.0);
 }
 
-// s = sqrt(lam_k + lambda); D_i = 1/sqrt(lam_i + lambda) - 1/s; UD = U diag(D);
+// s = sqrt(lam_k + lambda); D_i = 1/sqrt(lam_i + lambda) - 1/s; UD = U diag(D) and Up = U, both with
+// leading dimension ldu and zero past column k and past row d (up to drows rows);
 // scal[0] = 1/s (row scale of the apply), scal[1] = sqrt(n lambda)/s (diagonal of the regularizer rows).
 __global__ void precond_setup_kernel(const double* lam, int k, double lambda, int64_t n, const float* U32,
-                                     int64_t d, float* UD, double* scal, SolveState* state) {
+                                     int64_t d, int64_t drows, float* UD, float* Up, int64_t ldu, double* scal,
+                                     SolveState* state) {
   double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < d * k) {
-    int i = (int)(e % k);
-    double D = 1.0 / sqrt(fmax(lam[i], 0.0) + lambda) - 1.0 / s;
-    UD[e] = (float)((double)U32[e] * D);
+  if (e < drows * ldu) {
+    const int64_t r = e / ldu;
+    const int i = (int)(e - r * ldu);
+    float ud = 0.f, u = 0.f;
+    if (r < d && i < k) {
+      double D = 1.0 / sqrt(fmax(lam[i], 0.0) + lambda) - 1.0 / s;
+      u = U32[r * k + i];
+      ud = (float)((double)u * D);
+    }
+    UD[e] = ud;
+    Up[e] = u;
   }
   if (e == 0) {
     scal[0] = 1.0 / s;
@@ -446,9 +455,10 @@ int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double*
 }
 
 int launch_precond_setup(hipStream_t st, const double* lam, int k, double lambda, int64_t n, const float* U32,
-                         int64_t d, float* UD, double* scal, SolveState* state) {
-  precond_setup_kernel<<<dim3((unsigned)cdiv(d * k, 256)), dim3(256), 0, st>>>(lam, k, lambda, n, U32, d, UD,
-                                                                               scal, state);
+                         int64_t d, float* UD, float* Up, int64_t ldu, double* scal, SolveState* state) {
+  const int64_t drows = gemm_wide_bt_rows(d);
+  precond_setup_kernel<<<dim3((unsigned)cdiv(drows * ldu, 256)), dim3(256), 0, st>>>(lam, k, lambda, n, U32, d, drows,
+                                                                                     UD, Up, ldu, scal, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -84,11 +84,14 @@ __device__ __forceinline__ double warp_max_d(double v) {
 }
 
 // FP32 -> BF16 with round-to-nearest-even (NaN kept quiet).
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// FP32 -> BF16 with round-to-nearest-even (gfx950 converts in hardware, v_cvt_pk_bf16_f32).
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// two values in one word, the first in the low half
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const f32x2_v v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_v));
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -163,8 +166,13 @@ int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n
 int64_t sampler_scratch_len(int64_t N);
 
 // gemm (MFMA)
+// pad16: also store columns N .. (N rounded up to 16) - 1, which come out zero
 int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
-                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc);
+                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16 = false);
+// Leading dimension (and zero-padded width) the wide GEMM wants for operands with K columns.
+int gemm_wide_kpad(int64_t K);
+// Rows the wide GEMM reads from Bt: N rounded up to 64.
+inline int64_t gemm_wide_bt_rows(int64_t N) { return (N + 63) / 64 * 64; }
 int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
                         const float* Bt, int64_t N, int64_t ldb, float alpha, const float* C0, int64_t ldc0,
                         float beta, const double* beta_dev, float diag, const double* diag_dev, int out_bf16,
@@ -185,8 +193,10 @@ int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V
 // vector / small kernels
 int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double* V, const int* order, int k,
                 const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT);
+// UD = U diag(D) and a copy of U, both gemm_wide_bt_rows(d) x ldu (ldu = gemm_wide_kpad(k)), zero past
+// k and past d; scal = {1/s, sqrt(n lambda)/s}.
 int launch_precond_setup(hipStream_t st, const double* lam, int k, double lambda, int64_t n, const float* U32,
-                         int64_t d, float* UD, double* scal, SolveState* state);
+                         int64_t d, float* UD, float* Up, int64_t ldu, double* scal, SolveState* state);
 int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,
                   const SolveState* state);
@@ -257,7 +267,8 @@ struct BatchProb {
   double eps, f_star;
   const uint64_t* cum;   // cumulative integer sampling weights over N = n + d components
   int64_t N;
-  const float* Z;        // n x k (X U~) for the implicit inner loop, else unused
+  const float* Z;        // n x k (X U~, leading dimension ldz) for the implicit inner loop, else unused
+  int64_t ldz;
   int64_t draws;         // m b draws per epoch
   int32_t* idx;          // kSampleGroup epochs of draws
   float* scale;
@@ -272,8 +283,8 @@ int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, co
 // implicit preconditioned rows (k_implicit.hip): one workgroup per problem; inner.Xt holds X itself
 int launch_inner_implicit_batched(hipStream_t st, const BatchProb* P, int nprob, int64_t max_d, int max_k, int max_b,
                                   int epoch_slot, int64_t epoch);
-int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, const float* UT, const double* lam, int k,
-                         int64_t n, int64_t d, double lambda, float* beta);
+int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, int64_t ldz, const float* UT,
+                         const double* lam, int k, int64_t n, int64_t d, double lambda, float* beta);
 int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
                                  int* host_stop);
 // Shared-X gradient of many problems: R = X W^T (gemm), then R[i][p] -= Y[p % ny][i] with per-block

@@ -4,7 +4,8 @@ computes directly: the sketch from the same Omega, sampled preconditioned rows, 
 at a random point and the closed-form optimum. Each stage's error against the oracle is printed
 (pytest -s) and bounded by what its arithmetic allows:
   * sketch: |lam~_gpu - lam~_orc| <= 8 u_eff lam~_1 with u_eff = 2^-24 sqrt(d) (FP32 GEMMs) or 2^-8
-    (BF16 GEMMs), and the two preconditioners agree on random probes;
+    (BF16 GEMMs), the two preconditioners agree on random probes, and the average condition
+    number they achieve (Sec. 4.2) agrees within 1 %; the largest principal angle is printed;
   * rows: each x~_i close to P^{-1/2} x_i formed in FP64 from the GPU's own U~ and lam~ (this
     isolates the apply arithmetic): within 8 u_eff in FP32; with BF16 GEMM inputs within
     2^-8 (4 ||x_i|| / (s ||x~_i||) + 1), the cancellation of x_i / s by the low-rank term;
@@ -64,10 +65,19 @@ def test_sketch_stage(ctx, full):
     Po = precond.sketched_preconditioner(Uo, lo, cfg["lam"])
     V = np.random.default_rng(0).standard_normal((d, 8))
     perr = _rel(Pg @ V, Po @ V)
+    # largest principal angle between the two k-dimensional subspaces, and the average condition
+    # number each preconditioner achieves on C + lambda I (Sec. 4.2) next to that of C + lambda I
+    sv = np.linalg.svd(Uo.T @ U64.cpu().numpy(), compute_uv=False)
+    sin_max = float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
+    H = full.setdefault("H", ridge.hessian(X64, cfg["lam"]))
+    k_hat = ridge.average_condition(H)
+    kt_g, kt_o = ridge.average_condition(Pg @ H @ Pg), ridge.average_condition(Po @ H @ Po)
     print(f"\n[{full['name']}] sketch: max |d lam~| / lam~_1 = {err:.3e} (bound {8 * u_eff:.1e}); "
-          f"P^-1/2 probe rel err = {perr:.3e}")
+          f"P^-1/2 probe rel err = {perr:.3e}; sin theta_max = {sin_max:.3e}; "
+          f"kappa^ = {k_hat:.4g} -> kappa~ = {kt_g:.4g} (oracle sketch {kt_o:.4g})")
     assert err <= 8 * u_eff
     assert perr < (5e-2 if full["mixed"] else 1e-4)
+    assert abs(kt_g - kt_o) <= 1e-2 * kt_o and kt_g < k_hat
     full["U32"], full["lam"] = U, lam
 
 
@@ -122,7 +132,7 @@ def test_gradient_stage(ctx, full):
 
 def test_solve_stage(ctx, full):
     cfg, X64, y64 = full["cfg"], full["X64"], full["y64"]
-    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    ws = ridge.closed_form(X64, y64, cfg["lam"])  # (recomputes C + lambda I; the sketch stage may not have run)
     Ls = ridge.objective(X64, y64, cfg["lam"], ws)
     c, mf = TUNED[full["name"]]
     n = X64.shape[0]
