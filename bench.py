@@ -313,7 +313,7 @@ def main():
         for name, kk in (("precond", k), ("plain", 0)):
             best = None
             fallback = None   # best final objective when nothing reaches eps within the epoch cap
-            mfs = (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0) if not (big and kk == 0) else (0.25, 1.0)
+            mfs = (1 / 64, 1 / 32, 0.0625, 0.125, 0.25, 0.5, 1.0, 2.0) if not (big and kk == 0) else (0.25, 1.0)
             cs = (1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0) if not (big and kk == 0) else (1.0, 4.0, 16.0)
             for mf in mfs:
                 for c in cs:

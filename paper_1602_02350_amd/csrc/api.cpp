@@ -921,7 +921,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     o_idx[p] = t_idx;
     t_idx += (int64_t)G * m[p] * b;
     o_ut[p] = t_ut;
-    t_ut += (int64_t)k[p] * d[p];
+    t_ut += cdiv((int64_t)k[p] * d[p], 4) * 4;  // 16-byte aligned blocks
     o_lam[p] = t_lam;
     t_lam += k[p];
     max_N = std::max(max_N, n[p] + d[p]);

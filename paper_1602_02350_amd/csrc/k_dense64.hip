@@ -44,17 +44,21 @@ __global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_
   }
 }
 
-// Cholesky G = R^T R (upper R) and R^{-1}, one workgroup, R packed in LDS (l (l + 1) / 2 doubles).
-// Right-looking with one barrier per column: phase j reads the finished diagonal entry p_j and the
-// unscaled row j, updates the trailing triangle with S[a][c] -= S[j][a] S[j][c] / p_j, and scales
+// Cholesky G = R^T R (upper R) and R^{-1}, one workgroup, R packed in LDS (l (l + 1) / 2 doubles,
+// then the l reciprocal diagonal entries). Right-looking with one barrier per column: phase j reads
+// the finished diagonal entry p_j and the unscaled row j, updates the trailing triangle with
+// S[a][c] -= S[j][a] S[j][c] / p_j (a wave per row a, lanes over columns c >= a), and scales
 // row j - 1 (which nothing reads in that phase) by 1/sqrt(p_{j-1}). The inverse X = R^{-1} is then
 // formed one column per wave by back substitution in axpy form: x = e_j, and for q = j, ..., 0:
-// x_q /= R[q][q], x_i -= R[i][q] x_q (i < q); lane t keeps x_t, x_{t+64}, x_{t+128} in registers.
+// x_q *= 1/R[q][q], x_i -= R[i][q] x_q (i < q); lane t keeps x_t, x_{t+64}, x_{t+128} in registers
+// and the entries of R for step q - 1 are read from LDS while step q runs.
 // flag: 0 on success, 1 if a pivot is not positive relative to the largest diagonal entry of G
 // (that pivot is replaced by 1 so the factor stays finite).
 constexpr int kCholThreads = 512;
 
 __device__ __forceinline__ int packed_up(int i, int j, int l) { return i * (2 * l - i + 1) / 2 + (j - i); }
+// offset of row i of the packed triangle, so that R[i][j] = S[packed_row(i, l) + j] for j >= i
+__device__ __forceinline__ int packed_row(int i, int l) { return i * (2 * l - i - 1) / 2; }
 
 __device__ __forceinline__ double readlane_d(double v, int src) {
   const long long b = __double_as_longlong(v);
@@ -66,22 +70,26 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
 __global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* G, int l, double* Rinv, int* flag) {
   extern __shared__ double S[];
   __shared__ double s_dmax;
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  double* rdiag = S + l * (l + 1) / 2;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nwave = nt >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over it stay scalar
   for (int e = tid; e < l * l; e += nt) {
     int i = e / l, j = e % l;
-    if (j >= i) S[packed_up(i, j, l)] = G[e];
+    if (j >= i) S[packed_row(i, l) + j] = G[e];
   }
-  if (tid == 0) {
+  __syncthreads();
+  if (wave == 0) {  // largest diagonal entry: one wave, lanes over the diagonal
     double m = 0.0;
-    for (int j = 0; j < l; ++j) m = fmax(m, fabs(G[j * l + j]));
-    s_dmax = m;
+    for (int j = lane; j < l; j += 64) m = fmax(m, fabs(S[packed_row(j, l) + j]));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) s_dmax = m;
   }
   __syncthreads();
   const double dmax = s_dmax;
   int bad = 0;
   double p_prev = 1.0;
   auto pivot = [&](int j) {
-    double p = S[packed_up(j, j, l)];
+    double p = S[packed_row(j, l) + j];
     if (!(p > 1e-30 * dmax) || !isfinite(p)) {
       bad = 1;
       p = 1.0;
@@ -90,14 +98,17 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* 
   };
   auto finish_row = [&](int r, double p) {
     const double sp = sqrt(p), isp = 1.0 / sp;
-    for (int c = r + tid; c < l; c += nt) S[packed_up(r, c, l)] = c == r ? sp : S[packed_up(r, c, l)] * isp;
+    const int row = packed_row(r, l);
+    for (int c = r + tid; c < l; c += nt) S[row + c] = c == r ? sp : S[row + c] * isp;
+    if (tid == 0) rdiag[r] = isp;
   };
   for (int j = 0; j < l; ++j) {
     const double p = pivot(j), ip = 1.0 / p;
+    const int rowj = packed_row(j, l);
     for (int a = j + 1 + wave; a < l; a += nwave) {
-      const double ra = S[packed_up(j, a, l)] * ip;
-      const int base = packed_up(a, a, l) - a;  // row a of the packed triangle starts at column a
-      for (int c = a + lane; c < l; c += 64) S[base + c] -= ra * S[packed_up(j, c, l)];
+      const double ra = S[rowj + a] * ip;
+      const int rowa = packed_row(a, l);
+      for (int c = a + lane; c < l; c += 64) S[rowa + c] -= ra * S[rowj + c];
     }
     if (j > 0) finish_row(j - 1, p_prev);
     p_prev = p;
@@ -105,24 +116,41 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* 
   }
   finish_row(l - 1, p_prev);
   __syncthreads();
-  for (int j = wave; j < l; j += nwave) {
-    double x[3];
+  int roff[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) x[r] = (lane + 64 * r == j) ? 1.0 : 0.0;
+  for (int r = 0; r < 3; ++r) roff[r] = packed_row(min(lane + 64 * r, l - 1), l);
+  for (int j = wave; j < l; j += nwave) {
+    // S reads use in-bounds clamped addresses (lanes past the triangle read a valid entry that the
+    // update then ignores), so the loop has no per-lane branches
+    double x[3], sv[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int i = lane + 64 * r;
+      x[r] = i == j ? 1.0 : 0.0;
+      sv[r] = S[roff[r] + max(j, min(i, l - 1))];
+    }
+    double rq = rdiag[j];
     for (int q = j; q >= 0; --q) {
+      // entries for step q - 1, read while step q runs
+      double sn[3];
+      const int qn = max(q - 1, 0);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) sn[r] = S[roff[r] + max(qn, min(lane + 64 * r, l - 1))];
+      const double rq_next = rdiag[qn];
       const int slot = q >> 6, owner = q & 63;  // uniform across the wave
       const double mine = slot == 0 ? x[0] : (slot == 1 ? x[1] : x[2]);
-      const double xq = readlane_d(mine, owner) / S[packed_up(q, q, l)];
+      const double xq = readlane_d(mine, owner) * rq;
       if (lane == owner) {
         if (slot == 0) x[0] = xq;
         else if (slot == 1) x[1] = xq;
         else x[2] = xq;
       }
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int i = lane + 64 * r;
-        if (i < q) x[r] -= S[packed_up(i, q, l)] * xq;
-      }
+      for (int r = 0; r < 3; ++r)
+        if (lane + 64 * r < q) x[r] -= sv[r] * xq;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) sv[r] = sn[r];
+      rq = rq_next;
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -159,7 +187,7 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
 }
 
 int launch_chol_inv64(hipStream_t st, const double* G, int l, double* Rinv, int* flag) {
-  const size_t bytes = (size_t)l * (l + 1) / 2 * sizeof(double);
+  const size_t bytes = ((size_t)l * (l + 1) / 2 + l) * sizeof(double);
   if (l > 192 || (int64_t)bytes + 1024 > max_lds_bytes()) {
     set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
     return SCS_EINVAL;

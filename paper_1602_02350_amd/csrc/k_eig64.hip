@@ -2,7 +2,7 @@
 // the projected block, here B = (XQ)^T (XQ) / n), in FP64, l = k + p <= 136:
 //  1. Householder reduction to tridiagonal form, T = Qh^T B Qh, Qh = H_0 H_1 ... H_{l-3}
 //     (one workgroup, B in LDS; reflector j is stored with its scale tau_j);
-//  2. every eigenvalue of T by bisection on Sturm counts (one thread per eigenvalue, so the
+//  2. every eigenvalue of T by multisection on Sturm counts (G lanes per eigenvalue, so the
 //     eigenvalues come out sorted);
 //  3. the eigenvectors of T by inverse iteration with a partially pivoted LU of T - theta I (one
 //     thread per eigenvector); members of groups of eigenvalues closer than 1e-10 ||T|| are redone
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
   extern __shared__ double A[];  // l x l
   __shared__ double vv[kEigMaxL], ww[kEigMaxL];
   __shared__ double sred[kEigThreads / 64];
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nwave = nt >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over it stay scalar
   for (int e = tid; e < l * l; e += nt) A[e] = B[e];
   __syncthreads();
   for (int j = 0; j + 2 < l; ++j) {
@@ -99,38 +100,54 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
   }
 }
 
+// 1/q from the hardware estimate refined by two Newton steps (q is kept away from zero by pivmin).
+__device__ __forceinline__ double recip_d(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 // Number of eigenvalues of T below x: negative pivots of the LDL^T factorization of T - x I.
 __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, int l, double x, double pivmin) {
   double q = sd[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
+#pragma unroll 8  // the broadcast LDS reads of several steps go out together
   for (int i = 1; i < l; ++i) {
-    q = (sd[i] - x) - se2[i - 1] / q;
+    q = (sd[i] - x) - se2[i - 1] * recip_d(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
   return cnt;
 }
 
-// One solve (T - theta_t I) z_new = z on column t of zz with the stored LU factors of thread t,
-// rescaled to unit max norm. Arrays are laid out [i * l + t].
-__device__ void inv_solve(const double* u0, const double* u1, const double* u2, const double* mlt,
-                          const double* swp, double* zz, int l, int t) {
+// One solve (T - theta_t I) z_new = z on column t of zz with the stored LU factors of thread t
+// (u0 holds the reciprocals of the pivots), rescaled to unit max norm. Arrays are laid out
+// [i * l + t]; the value carried from row i to row i + 1 stays in a register.
+__device__ void inv_solve(const double* __restrict__ u0, const double* __restrict__ u1,
+                          const double* __restrict__ u2, const double* __restrict__ mlt,
+                          const double* __restrict__ swp, double* __restrict__ zz, int l, int t) {
+  double cur = zz[t];
+  // unrolled so that the factor loads of several rows are in flight at once
+#pragma unroll 8
   for (int i = 0; i + 1 < l; ++i) {
-    const int64_t o = (int64_t)i * l + t, o1 = o + l;
-    double ri = zz[o], ri1 = zz[o1];
+    const int64_t o = (int64_t)i * l + t;
+    double nxt = zz[o + l];
     if (swp[o] != 0.0) {
-      const double tmp = ri;
-      ri = ri1;
-      ri1 = tmp;
+      const double tmp = cur;
+      cur = nxt;
+      nxt = tmp;
     }
-    zz[o] = ri;
-    zz[o1] = ri1 - mlt[o] * ri;
+    zz[o] = cur;
+    cur = nxt - mlt[o] * cur;
   }
+  zz[(int64_t)(l - 1) * l + t] = cur;
   double z1 = 0.0, z2 = 0.0, nz = 0.0;
+#pragma unroll 8
   for (int i = l - 1; i >= 0; --i) {
     const int64_t o = (int64_t)i * l + t;
-    const double zi = (zz[o] - u1[o] * z1 - u2[o] * z2) / u0[o];
+    const double zi = (zz[o] - u1[o] * z1 - u2[o] * z2) * u0[o];
     zz[o] = zi;
     z2 = z1;
     z1 = zi;
@@ -189,7 +206,7 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
   // the Sturm count at G interior points of [a, b] together and keep the subinterval where the
   // count passes t, so count(a) <= t < count(b) holds throughout and [a, b] shrinks (G+1)-fold
   // per round.
-  const int G = l <= 128 ? 8 : (l <= 256 ? 4 : 1);
+  const int G = l <= 128 ? 8 : (l <= 256 ? 4 : 1);  // more lanes only add FP64 issue pressure on the CU
   const int lane = tid & 63;
   if (tid < G * l) {
     const int t = tid / G, s = tid % G;
@@ -218,8 +235,9 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
   if (tid < l) {
     const int t = tid;
     const double th = sth[t];
-    // LU of T - th I with row interchanges: row i of U holds up to two super-diagonals; a zero
-    // pivot (th is an eigenvalue) is replaced by a tiny multiple of ||T||, as inverse iteration wants
+    // LU of T - th I with row interchanges: row i of U holds up to two super-diagonals (u0 keeps the
+    // reciprocal pivot); a zero pivot (th is an eigenvalue) is replaced by a tiny multiple of ||T||,
+    // as inverse iteration wants
     const double tiny = 1e-15 * nrm;
     double ca = sd[0] - th, cb = l > 1 ? se[0] : 0.0;
     for (int i = 0; i + 1 < l; ++i) {
@@ -228,7 +246,7 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
       if (fabs(ca) >= fabs(nc)) {
         const double piv = ca != 0.0 ? ca : tiny;
         const double m = nc / piv;
-        u0[o] = piv;
+        u0[o] = 1.0 / piv;
         u1[o] = cb;
         u2[o] = 0.0;
         mlt[o] = m;
@@ -237,7 +255,7 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
         cb = nb;
       } else {
         const double m = ca / nc;
-        u0[o] = nc;
+        u0[o] = 1.0 / nc;
         u1[o] = na;
         u2[o] = nb;
         mlt[o] = m;
@@ -246,7 +264,7 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
         cb = -m * nb;
       }
     }
-    u0[(int64_t)(l - 1) * l + t] = ca != 0.0 ? ca : tiny;
+    u0[(int64_t)(l - 1) * l + t] = 1.0 / (ca != 0.0 ? ca : tiny);
     u1[(int64_t)(l - 1) * l + t] = 0.0;
     u2[(int64_t)(l - 1) * l + t] = 0.0;
     // three solves from a fixed start vector (different per thread)
@@ -311,7 +329,8 @@ __global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const doub
       wcol[c] = tj * s;
     }
     __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    const int lane = tid & 63, nwave = nt >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = wave; i < m; i += nwave) {
       const double vi = vv[i];
       double* row = Zs + (r0 + i) * l;

@@ -308,7 +308,8 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
   dim3 block(kInnerThreads);
   if (W > 1) {
     // The workgroups of a problem wait on each other, so they must all be resident: problems go in
-    // groups that fit the device at once, one cooperative launch per group.
+    // groups that fit the device at once, one launch per group (ordinary launches: the stream runs
+    // nothing else meanwhile, every group fits the idle device, and every wait is bounded).
     static int resident = 0;  // co-resident workgroups of this instantiation on the device
     if (resident == 0) {
       int per_cu = 0, dev = 0, cus = 0;
@@ -327,10 +328,8 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
     for (int p0 = 0; p0 < nprob; p0 += group) {
       const BatchProb* Pg = P + p0;
       int cnt = nprob - p0 < group ? nprob - p0 : group;
-      dim3 grid((unsigned)(cnt * W));
-      void* args[] = {&Pg, &cnt, &slot, &epoch};
-      SCS_HIP(hipLaunchCooperativeKernel((const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>, grid, block, args, 0,
-                                         st));
+      inner_epoch_batched_kernel<RPT, CPT, BF16><<<dim3((unsigned)(cnt * W)), block, 0, st>>>(Pg, cnt, slot, epoch);
+      SCS_HIP(hipGetLastError());
     }
   } else {
     dim3 grid((unsigned)nprob);
@@ -352,16 +351,14 @@ int launch_bc(hipStream_t st, const BatchProb* P, int nprob, int W, int cpt, int
   return SCS_EINVAL;
 }
 
+// W <= 16 active workgroups (W xcd_stride <= 128 in the grid) are always resident together on the
+// otherwise idle device; an ordinary launch avoids the cooperative queue's extra latency on both
+// sides of every epoch, and every wait is bounded.
 template <int RPT, int CPT, bool BF16>
 int launch_t(hipStream_t st, InnerArgs& a) {
   dim3 grid((unsigned)(a.W * a.xcd_stride)), block(kInnerThreads);
-  if (a.W > 1) {
-    void* args[] = {&a};
-    SCS_HIP(hipLaunchCooperativeKernel((const void*)inner_epoch_kernel<RPT, CPT, BF16>, grid, block, args, 0, st));
-  } else {
-    inner_epoch_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(a);
-    SCS_HIP(hipGetLastError());
-  }
+  inner_epoch_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(a);
+  SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
 

@@ -28,30 +28,55 @@ __device__ __forceinline__ double block_sum_d(double v, double* sred) {
 }
 
 // out_j = v_j/s + sum_i UT[i][j] D_i (sum_l UT[i][l] v_l); k = 0 gives out = v.
-// UT is k x d (FP32). tbuf: k doubles of LDS. Both phases read UT along rows (coalesced) and keep
-// several independent loads in flight per lane; one workgroup, so the result is deterministic.
-template <typename VIN>
+// UT is k x d (FP32), the sums are FP64; one workgroup, so the result is deterministic. v is staged
+// in LDS (vs, kVsMax doubles) when it fits; tbuf holds the k coefficients. Phase 1 gives each wave
+// R rows of UT at a time and phase 2 four threads to each four consecutive columns (a quarter of the
+// rows each), with float4 loads when the rows of UT are 16-byte aligned, so every lane keeps many
+// independent loads in flight.
+// emit(j, value) receives out_j.
+constexpr int kVsMax = 4096;
+template <typename VIN, typename EMIT>
 __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* __restrict__ lam, int k, int64_t d,
-                                   double lambda, const VIN* __restrict__ v, double* __restrict__ out,
-                                   double* tbuf) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                   double lambda, const VIN* __restrict__ v, double* vs, double* tbuf, EMIT emit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform: scalar loops
   const int dd = (int)d;
+  const bool staged = dd <= kVsMax;
+  if (staged) {
+    for (int j = threadIdx.x; j < dd; j += blockDim.x) vs[j] = (double)v[j];
+    __syncthreads();
+  }
+  auto vj = [&](int j) { return staged ? vs[j] : (double)v[j]; };
   if (k == 0) {
-    for (int j = threadIdx.x; j < dd; j += blockDim.x) out[j] = (double)v[j];
+    for (int j = threadIdx.x; j < dd; j += blockDim.x) emit(j, vj(j));
     __syncthreads();
     return;
   }
   const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  const bool v4 = (dd & 3) == 0 && (reinterpret_cast<uintptr_t>(UT) & 15) == 0;
+  const int d4 = dd >> 2;
   constexpr int R = 4;  // rows of UT per wave and pass
   for (int i0 = wave * R; i0 < k; i0 += kVecWaves * R) {
     double acc[R] = {0.0, 0.0, 0.0, 0.0};
-    const float* r0 = UT + (int64_t)i0 * d;
-#pragma unroll 4
-    for (int j = lane; j < dd; j += 64) {
-      const double vj = (double)v[j];
+    if (v4) {
+      for (int j4 = lane; j4 < d4; j4 += 64) {
+        const double v0 = vj(4 * j4), v1 = vj(4 * j4 + 1), v2 = vj(4 * j4 + 2), v3 = vj(4 * j4 + 3);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (i0 + r < k) acc[r] += (double)r0[(int64_t)r * d + j] * vj;
+        for (int r = 0; r < R; ++r) {
+          if (i0 + r < k) {
+            const float4 u = reinterpret_cast<const float4*>(UT + (int64_t)(i0 + r) * d)[j4];
+            acc[r] += (double)u.x * v0 + (double)u.y * v1 + (double)u.z * v2 + (double)u.w * v3;
+          }
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int j = lane; j < dd; j += 64) {
+        const double x = vj(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (i0 + r < k) acc[r] += (double)UT[(int64_t)(i0 + r) * d + j] * x;
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -60,32 +85,68 @@ __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* _
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < dd; j += blockDim.x) {
-    double acc = 0.0;
+  if (v4) {
+    // four threads per column quad, each summing every fourth row of UT, then combined in order
+    const int part = threadIdx.x & 3;
+    for (int j4base = 0; j4base < d4; j4base += (int)blockDim.x >> 2) {
+      const int j4 = j4base + ((int)threadIdx.x >> 2);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (j4 < d4) {
+#pragma unroll 8
+        for (int i = part; i < k; i += 4) {
+          const float4 u = reinterpret_cast<const float4*>(UT + (int64_t)i * d)[j4];
+          const double t = tbuf[i];
+          a0 += (double)u.x * t;
+          a1 += (double)u.y * t;
+          a2 += (double)u.z * t;
+          a3 += (double)u.w * t;
+        }
+      }
+      // lanes 4q .. 4q+3 hold the four parts of one quad: (p0 + p1) + (p2 + p3)
+      a0 += __shfl_xor(a0, 1);
+      a1 += __shfl_xor(a1, 1);
+      a2 += __shfl_xor(a2, 1);
+      a3 += __shfl_xor(a3, 1);
+      a0 += __shfl_xor(a0, 2);
+      a1 += __shfl_xor(a1, 2);
+      a2 += __shfl_xor(a2, 2);
+      a3 += __shfl_xor(a3, 2);
+      if (j4 < d4 && part == 0) {
+        emit(4 * j4, vj(4 * j4) / s + a0);
+        emit(4 * j4 + 1, vj(4 * j4 + 1) / s + a1);
+        emit(4 * j4 + 2, vj(4 * j4 + 2) / s + a2);
+        emit(4 * j4 + 3, vj(4 * j4 + 3) / s + a3);
+      }
+    }
+  } else {
+    for (int j = threadIdx.x; j < dd; j += blockDim.x) {
+      double acc = 0.0;
 #pragma unroll 16
-    for (int i = 0; i < k; ++i) acc += (double)UT[(int64_t)i * d + j] * tbuf[i];
-    out[j] = (double)v[j] / s + acc;
+      for (int i = 0; i < k; ++i) acc += (double)UT[(int64_t)i * d + j] * tbuf[i];
+      emit(j, vj(j) / s + acc);
+    }
   }
   __syncthreads();
 }
 
 __device__ __forceinline__ void premap_body(const float* UT, const double* lam, int k, int64_t d, double lambda,
-                                            const float* wt, float* w, float* trace_row, double* tmp) {
+                                            const float* wt, float* w, float* trace_row) {
   __shared__ double tbuf[256];
-  pmhalf_apply_block<float>(UT, lam, k, d, lambda, wt, tmp, tbuf);
-  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
-    float x = (float)tmp[j];
-    w[j] = x;
-    if (trace_row) trace_row[j] = x;
-  }
+  __shared__ double vs[kVsMax];
+  pmhalf_apply_block<float>(UT, lam, k, d, lambda, wt, vs, tbuf, [&](int j, double x) {
+    const float f = (float)x;
+    w[j] = f;
+    if (trace_row) trace_row[j] = f;
+  });
 }
 
 __global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, const double* lam, int k, int64_t d,
                                                              double lambda, const float* wt, float* w,
                                                              float* trace_row, double* tmp,
                                                              const SolveState* state) {
+  (void)tmp;
   if (state && state->done) return;
-  premap_body(UT, lam, k, d, lambda, wt, w, trace_row, tmp);
+  premap_body(UT, lam, k, d, lambda, wt, w, trace_row);
 }
 
 // One workgroup per problem: w = P^{-1/2} w~ at the snapshot (skipped once a problem is done), or,
@@ -94,10 +155,10 @@ __global__ __launch_bounds__(kVecThreads) void premap_batched_kernel(const Batch
                                                                      float* const* w_out) {
   const BatchProb& q = P[blockIdx.x];
   if (final_out) {
-    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, w_out[blockIdx.x], nullptr, q.tmp);
+    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, w_out[blockIdx.x], nullptr);
   } else {
     if (q.state->done) return;
-    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, q.w32, nullptr, q.tmp);
+    premap_body(q.UT, q.lam, q.k, q.d, q.lambda, q.wt, q.w32, nullptr);
   }
 }
 
@@ -144,6 +205,7 @@ __device__ int finalize_body(const double* g_in, int grows, const double* rsq_pa
                              double* tmp, SolveState* state, int stop_rule, double eps, double f_star, float* wt_cur,
                              const float* wt_prev, int first) {
   __shared__ double tbuf[256];
+  __shared__ double vs[kVsMax];
   __shared__ double sred[kVecWaves];
   __shared__ int s_action;
   // g = (1/n) sum of the partial rows (fixed order) + lambda w, written over the first row of g2
@@ -160,7 +222,7 @@ __device__ int finalize_body(const double* g_in, int grows, const double* rsq_pa
   }
   __syncthreads();
   // mu = P^{-1/2} g
-  pmhalf_apply_block<double>(UT, lam, k, d, lambda, g, tmp, tbuf);
+  pmhalf_apply_block<double>(UT, lam, k, d, lambda, g, vs, tbuf, [&](int j, double x) { tmp[j] = x; });
   double gn = 0.0, wn = 0.0;
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double m = tmp[j];
