@@ -237,7 +237,7 @@ def bench_batch(args, cfg):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = ctx.svrg_solve_batched(Xs, ys, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
-                                     f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=150,
+                                     f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=600,
                                      stop_rule=binding.STOP_GAP, step_scale=c,
                                      precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
