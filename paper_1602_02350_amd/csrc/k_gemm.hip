@@ -150,6 +150,160 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
       }
 }
 
+// ------------------------------------------------------------------ NT, long K, A in registers
+// The same product as gemm_nt_longk for 16-byte aligned rows of A (X): each wave owns 16 rows of A
+// and reads its MFMA fragments straight from global memory into registers, one K chunk ahead
+// (lane (r, g) holds A[row0 + r][k0 + 16 q + 4 g .. +3]); Bt's K chunk (N <= 144 rows) is staged
+// through LDS, double-buffered and rounded to BF16 once in BF16 mode. One barrier per chunk;
+// workgroups loop over 128-row tiles (grid sized to the resident capacity). The last chunk, where
+// K may end inside it, is loaded with guards.
+constexpr int kLrThreads = 512;
+constexpr int kLrBM = 16 * (kLrThreads / 64);
+
+template <int NB, bool BF16>
+__global__ __launch_bounds__(kLrThreads, 4) void gemm_nt_longk_reg_kernel(const float* __restrict__ A, int64_t M,
+                                                                       int64_t K, int64_t lda,
+                                                                       const float* __restrict__ Bt, int64_t N,
+                                                                       int64_t ldb, float* __restrict__ C,
+                                                                       int64_t ldc, int64_t nst) {
+  constexpr int KC = BF16 ? 64 : 32;          // K per chunk
+  constexpr int NQ = KC / 16;                  // MFMA K steps per chunk
+  constexpr int BN = NB * 16;
+  constexpr int LW = KC + 4, LH = KC + 8;      // LDS row strides (floats / BF16 halves)
+  constexpr int BUF = BF16 ? BN * LH / 2 : BN * LW;
+  constexpr int NE = BN * (KC / 4);            // float4 per Bt chunk
+  constexpr int RB = (NE + kLrThreads - 1) / kLrThreads;
+  __shared__ float S[2 * BUF];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rl = lane & 15, g4 = 4 * (lane >> 4);
+  const int64_t nch = (K + KC - 1) / KC;
+  const int64_t ntiles = (M + kLrBM - 1) / kLrBM;
+
+  f4v rb[RB];
+  auto load_b = [&](int64_t c) {
+    const int64_t k0 = c * KC;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kLrThreads * j;
+      const int r = e / (KC / 4), c4 = e % (KC / 4);
+      const int64_t k = k0 + 4 * c4;
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (e < NE && r < N) {
+        const float* p = Bt + (int64_t)r * ldb + k;
+        if (k + 3 < K) {
+          v[0] = p[0];
+          v[1] = p[1];
+          v[2] = p[2];
+          v[3] = p[3];
+        } else {
+          if (k < K) v[0] = p[0];
+          if (k + 1 < K) v[1] = p[1];
+          if (k + 2 < K) v[2] = p[2];
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto stash_b = [&](int bsel) {
+    float* base = S + bsel * BUF;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kLrThreads * j;
+      if (e < NE) {
+        const int r = e / (KC / 4), c4 = e % (KC / 4);
+        if constexpr (BF16) {
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + r * LH + 4 * c4) =
+              make_uint2(pack_bf16x2(rb[j][0], rb[j][1]), pack_bf16x2(rb[j][2], rb[j][3]));
+        } else {
+          *reinterpret_cast<f4v*>(base + r * LW + 4 * c4) = rb[j];
+        }
+      }
+    }
+  };
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * kLrBM + wave * 16 + rl;
+    const float* arow = A + (row < M ? row : M - 1) * lda + g4;
+    f4v af[NQ], an[NQ];   // chunks c and c + 1
+    auto load_a = [&](int64_t c, f4v (&dst)[NQ]) {
+      const int64_t k0 = c * KC;
+      if (k0 + KC <= K) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dst[q] = *reinterpret_cast<const f4v*>(arow + k0 + 16 * q);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int64_t k = k0 + 16 * q + g4;
+          f4v v = {0.f, 0.f, 0.f, 0.f};
+          if (k + 3 < K) {
+            v = *reinterpret_cast<const f4v*>(arow + k0 + 16 * q);
+          } else {
+            const float* p = arow + k0 + 16 * q;
+            if (k < K) v[0] = p[0];
+            if (k + 1 < K) v[1] = p[1];
+            if (k + 2 < K) v[2] = p[2];
+          }
+          dst[q] = v;
+        }
+      }
+    };
+    f4v acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
+
+    __syncthreads();   // the previous tile's chunk buffers are free
+    load_b(0);
+    stash_b(0);
+    if (nch > 1) load_b(1);
+    load_a(0, af);
+    __syncthreads();
+    for (int64_t c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load_a(c + 1, an);
+      const float* base = S + (int)(c & 1) * BUF;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if constexpr (BF16) {
+          const uint32_t lo = pack_bf16x2(af[q][0], af[q][1]), hi = pack_bf16x2(af[q][2], af[q][3]);
+          const s4v ah = {(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) {
+            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
+                                                         (cb * 16 + rl) * LH + 16 * q + g4);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bv, acc[cb], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) {
+            const f4v bv = *reinterpret_cast<const f4v*>(base + (cb * 16 + rl) * LW + 16 * q + g4);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q][0], bv[0], acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q][1], bv[1], acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q][2], bv[2], acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q][3], bv[3], acc[cb], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (c + 1 < nch) {
+        stash_b((int)((c + 1) & 1));
+        if (c + 2 < nch) load_b(c + 2);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) af[q] = an[q];
+      }
+      __syncthreads();
+    }
+    // acc[cb][r] = C[row0 + 4 (lane / 16) + r][16 cb + lane % 16]
+    const int64_t r0 = tile * kLrBM + wave * 16 + g4;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = r0 + r;
+        const int64_t cc = cb * 16 + rl;
+        if (rr < M && cc < nst) C[rr * ldc + cc] = acc[cb][r];
+      }
+  }
+}
+
 // ------------------------------------------------------------------ NT, wide N, short K
 // C = alpha A Bt^T + beta C0 (+ diag where row == col). A is M x KP and Bt is (N rounded up to 64) x KP
 // with KP = gemm_wide_kpad(K) (16, 32, 64, 128 or 160). Bt is zero past K and past N; A is zero from K
@@ -474,9 +628,39 @@ __global__ __launch_bounds__(256) void residual_batched_kernel(float* R, int64_t
 
 bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
+template <int NB, bool BF16>
+int longk_reg_launch(hipStream_t st, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt, int64_t N,
+                     int64_t ldb, float* C, int64_t ldc, int64_t nst) {
+  const void* fn = (const void*)gemm_nt_longk_reg_kernel<NB, BF16>;
+  const int res = resident_blocks(fn, kLrThreads, 0);
+  if (res <= 0) {
+    set_error("gemm_nt_longk: no resident workgroup capacity reported");
+    return SCS_EDEVICE;
+  }
+  const int64_t grid = std::min<int64_t>(cdiv(M, kLrBM), (int64_t)res);
+  gemm_nt_longk_reg_kernel<NB, BF16><<<dim3((unsigned)grid), dim3(kLrThreads), 0, st>>>(A, M, K, lda, Bt, N, ldb, C,
+                                                                                      ldc, nst);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
 template <bool BF16>
 int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt,
                    int64_t N, int64_t ldb, float* C, int64_t ldc, int64_t nst) {
+  if (aligned16(A, lda)) {
+    switch (nb) {
+      case 1: return longk_reg_launch<1, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 2: return longk_reg_launch<2, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 3: return longk_reg_launch<3, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 4: return longk_reg_launch<4, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 5: return longk_reg_launch<5, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 6: return longk_reg_launch<6, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 7: return longk_reg_launch<7, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 8: return longk_reg_launch<8, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 9: return longk_reg_launch<9, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      default: break;
+    }
+  }
   dim3 grid((unsigned)cdiv(M, kLkBM));
   bool aa = aligned16(A, lda), ba = aligned16(Bt, ldb);
 #define SCS_LK(NBV) \
