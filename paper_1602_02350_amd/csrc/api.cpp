@@ -73,10 +73,14 @@ T* ws(scs_ctx* c, const std::string& name, size_t count) {
   T* var = ws<T>(ctx, name, (size_t)(count));    \
   if (!var) return SCS_ENOMEM;
 
+// events: the per-epoch decision points the host waits on before it reads that epoch's stop flag.
+// They carry no system-scope fence (a fence would write back L2 before every inner loop): the flag
+// is a system-scope store of its own, and a stale read only lets the host queue a few more epochs,
+// which return at once on the device's done flag. tevents: timing only, also without the fence.
 int ensure_events(scs_ctx* c, size_t count, size_t tcount = 0) {
   while (c->events.size() < count) {
     hipEvent_t e;
-    SCS_HIP(hipEventCreate(&e));
+    SCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence | hipEventDisableTiming));
     c->events.push_back(e);
   }
   while (c->tevents.size() < tcount) {
