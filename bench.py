@@ -188,6 +188,7 @@ def bench_path(args, cfg):
         t0 = time.perf_counter()
         res = ctx.svrg_solve_path(X, Y, list(lams), k, eps, f_star=fs, batch=b, epoch_factor=mf, max_epochs=150,
                                   stop_rule=binding.STOP_GAP, step_scale=c, implicit_apply=int(args.implicit_apply),
+                                  workgroups=max(args.workgroups, 0),
                                   precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
         if it >= args.warmup:
@@ -238,7 +239,7 @@ def bench_batch(args, cfg):
         t0 = time.perf_counter()
         res = ctx.svrg_solve_batched(Xs, ys, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
                                      f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=600,
-                                     stop_rule=binding.STOP_GAP, step_scale=c,
+                                     stop_rule=binding.STOP_GAP, step_scale=c, workgroups=max(args.workgroups, 0),
                                      precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
         if it >= args.warmup:

@@ -70,7 +70,10 @@ typedef struct scs_opts {
   int average;            /* 1: snapshot = average of the m inner iterates (Alg. 1); 0: last iterate */
   int precision;          /* SCS_PREC_* (default SCS_PREC_FP32) */
   int workgroups;         /* inner-loop workgroups per problem; 0 = chosen from d; -1 = autotuned: timed on the
-                             problem's own rows on first use per (d, b, precision), cached in the context */
+                             problem's own rows on first use per (d, b, precision), cached in the context
+                             (single solves). Batched and path solves take a positive value as given (at
+                             least one per 512 columns of the widest problem, at most 16) and otherwise use
+                             one per 256 columns */
   uint64_t seed;          /* seed of the Gaussian test matrix and of the index stream */
   const float* omega;     /* optional device (k+p) x d row-major Gaussian test matrix (transposed Omega); NULL = drawn from seed */
   const int32_t* indices; /* optional device index stream, max_epochs x m x b entries in [0, n+d); NULL = drawn from seed */

@@ -896,8 +896,11 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   const int b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
   const int es = mixed ? 2 : 4;
   constexpr int G = 8;  // epochs of index streams drawn per sampling launch
-  // one workgroup per problem while its row fits 512 columns; wider problems get W cooperating ones
-  const int W = (int)cdiv(max_d, 512);
+  // W cooperating workgroups per problem (the same for every problem of the batch): opts.workgroups
+  // when positive, else one per 256 columns of the widest problem (measured: 256-column slices beat
+  // both 512 and 128 on the uneven batch); a slice never exceeds 512 columns
+  const int W = (int)std::min<int64_t>(
+      16, std::max<int64_t>(cdiv(max_d, 512), o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(max_d, 256)));
 
   // ---- per-problem sizes and arena offsets (elements)
   std::vector<int64_t> ldt(nprob), m(nprob), nwg(nprob), o_xt(nprob), o_reg(nprob), o_beta(nprob), o_vec(nprob),
@@ -1217,7 +1220,10 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   const int P = nl * ny, b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
   const int es = mixed ? 2 : 4;
   constexpr int G = 8;
-  const int W = (int)cdiv(d, 512);
+  // W cooperating workgroups per solve: opts.workgroups when positive, else one per 256 columns
+  // (measured on the 1024-column path: 256-column slices beat 512 and 128)
+  const int W = (int)std::min<int64_t>(
+      16, std::max<int64_t>(cdiv(d, 512), o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(d, 256)));
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
   const int64_t m = epoch_steps(o, n, b);
   const int64_t N = n + d;

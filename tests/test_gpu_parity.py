@@ -293,12 +293,12 @@ def test_batched_equals_single_solves(ctx, mixed):
     single solves with one workgroup per inner loop."""
     probs = _uneven_batch(UNEVEN)
     common = dict(batch=16, steps=50, max_epochs=3, stop_rule=binding.STOP_EPOCHS, step_scale=1.0, seed=99,
-                  precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+                  precision=binding.PREC_MIXED if mixed else binding.PREC_FP32, workgroups=1)
     Xs = [dev(P.X) for P, _ in probs]
     ys = [dev(P.y) for P, _ in probs]
     rc, wb, reps = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 0.0, **common)
     for i, (P, k) in enumerate(probs):
-        r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, workgroups=1, **common)
+        r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, **common)
         assert reps[i]["status"] == r.status, (i, reps[i]["status"], r.status)
         assert torch.equal(wb[i], r.w), (i, rel(host(wb[i]), host(r.w)))
         assert reps[i]["epochs"] == r.report["epochs"] and reps[i]["k_used"] == k
@@ -310,11 +310,16 @@ def test_batched_wide_problem_uses_cooperating_workgroups(ctx):
     common = dict(batch=32, steps=40, max_epochs=2, stop_rule=binding.STOP_EPOCHS, step_scale=1.0, seed=5)
     Xs = [dev(P.X) for P, _ in probs]
     ys = [dev(P.y) for P, _ in probs]
-    rc, wb, _ = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 0.0, **common)
-    assert rc == binding.OK
-    for i, (P, k) in enumerate(probs):
-        r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, workgroups=2, **common)   # W = ceil(600 / 512)
-        assert torch.equal(wb[i], r.w), i
+    # the default is ceil(600 / 256) = 3 cooperating workgroups per problem; 2 (= ceil(600 / 512), the
+    # fewest allowed) and 3 must both match single solves with the same count
+    for W in (2, 0):
+        rc, wb, reps = ctx.svrg_solve_batched(Xs, ys, [P.lam for P, _ in probs], [k for _, k in probs], 0.0,
+                                              workgroups=W, **common)
+        assert rc == binding.OK
+        for i, (P, k) in enumerate(probs):
+            assert reps[i]["workgroups"] == (W or 3)
+            r = ctx.svrg_solve(Xs[i], ys[i], P.lam, k, 0.0, workgroups=W or 3, **common)
+            assert torch.equal(wb[i], r.w), (W, i)
 
 
 WELL_POSED = [(1500, 100, 2.0, 1e-4, 10), (700, 37, 1.2, 1e-3, 2), (3000, 257, 1.5, 1e-4, 16),
