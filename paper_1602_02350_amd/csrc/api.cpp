@@ -233,15 +233,16 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, om));
     OmT = om;
   }
-  // T = X Omega (n x l)
-  WS(T, float, std::string("T") + sfx, (size_t)n * l);
-  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, OmT, l, d, T, l));
+  // T = X Omega (n x l, leading dimension l rounded up to 16 and zero-filled)
+  const int64_t lp = cdiv(l, 16) * 16;
+  WS(T, float, std::string("T") + sfx, (size_t)n * lp);
+  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, OmT, l, d, T, lp, true));
   // Y = X^T T (d x l), split over row chunks, summed in FP64
-  int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 512), std::max<int64_t>(1, 1024 / cdiv(d, 64))));
+  int64_t nchunks = gemm_tn_splitk_chunks(n, d, l, X, ldx, T, lp);
   int64_t chunk = cdiv(n, nchunks);
   nchunks = cdiv(n, chunk);
   WS(part, float, std::string("partial") + sfx, (size_t)nchunks * d * l);
-  SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, l, part, chunk, nchunks));
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
   WS(Y, double, std::string("Y64") + sfx, (size_t)d * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
   // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
@@ -263,13 +264,13 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Q, l, nullptr, 0));
   SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QT32, d));  // Q^T = R2^{-T} Q1^T
   // Rayleigh-Ritz: Wq = X Q (n x l), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
-  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * l);
-  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, l, d, Wq, l));
-  int64_t nch2 = std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 256)));
+  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * lp);
+  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, l, d, Wq, lp, true));
+  int64_t nch2 = gemm_tn_splitk_chunks(n, l, l, Wq, lp, Wq, lp);
   int64_t chunk2 = cdiv(n, nch2);
   nch2 = cdiv(n, chunk2);
   WS(part2, float, std::string("partial2") + sfx, (size_t)nch2 * l * l);
-  SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, l, Wq, l, l, part2, chunk2, nch2));
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, lp, Wq, l, lp, part2, chunk2, nch2));
   WS(B, double, std::string("B64") + sfx, (size_t)l * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)l * l, 1.0 / (double)n, B));
   WS(V, double, std::string("V64") + sfx, (size_t)l * l);
@@ -287,7 +288,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   if (want_z) {
     const int64_t kz = gemm_wide_kpad(k);
     WS(Z, float, std::string("Z") + sfx, (size_t)n * kz);
-    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, l, VkT, k, l, Z, kz, true));
+    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, lp, VkT, k, l, Z, kz, true));
   }
   if (flags_out) return SCS_OK;
   int hflags[2] = {0, 0};
@@ -1256,9 +1257,11 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   WS(desc, BatchProb, "p_desc", P);
   WS(draw_pre, int64_t, "p_prefix", (int64_t)P + 1);
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
-  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 512), std::max<int64_t>(1, 1024 / cdiv(d, 64))));
-  const int64_t chunk = cdiv(n, nch), nchunks = cdiv(n, chunk);
   constexpr int kPc = 128;  // problems per GEMM call (the MFMA kernels take up to 144 columns)
+  // the residual matrix R (n x P, a workspace buffer) is the split-K GEMM's B operand, at column offsets
+  // that are multiples of kPc: its rows are 16-byte aligned exactly when P is a multiple of 4
+  const int64_t nch = gemm_tn_splitk_chunks(n, d, std::min(kPc, P), X, ldx, nullptr, P);
+  const int64_t chunk = cdiv(n, nch), nchunks = cdiv(n, chunk);
   WS(part, float, "p_partial", nchunks * d * kPc);
   SCS_HIP(hipMemsetAsync(states, 0, sizeof(SolveState) * P, st));
   SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * P * d, st));

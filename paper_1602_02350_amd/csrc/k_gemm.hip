@@ -304,6 +304,175 @@ __global__ __launch_bounds__(kLrThreads, 4) void gemm_nt_longk_reg_kernel(const 
   }
 }
 
+// ------------------------------------------------------------------ TN split-K, A in registers
+// partial[chunk] = A[rows of chunk]^T B[rows of chunk] for 16-byte aligned rows of A and B (M x N per
+// chunk, row-major). Wave w owns 16 TC columns of A (TC = 4 for N <= 64, else 2), starting at
+// m_base = blockIdx.x 8 16 TC + 16 TC w. Lane (r, g) loads A[row][m_base + TC r .. + TC - 1] as one
+// vector (16 lanes cover 16 TC contiguous floats of a row, 4 rows per instruction), and component c
+// of it feeds output tile c: rows m = m_base + TC i + c. With the FP32 16x16x4 MFMA a K step is 4
+// rows (lane group g supplies row g); with the BF16 16x16x16 MFMA a K step is 16 rows (lane group g
+// supplies rows 4 g .. 4 g + 3, from four loads). B's rows are staged through LDS in tiles of 64
+// rows, double-buffered (FP32 row-major; BF16 transposed and rounded once), one barrier per tile;
+// the A loads of the next K step are issued before the MFMAs of the current one.
+constexpr int kTgThreads = 512;
+constexpr int tg_tc(int nb) { return nb <= 4 ? 4 : 2; }
+constexpr int tg_cols(int nb) { return (kTgThreads / 64) * 16 * tg_tc(nb); }  // columns of A per workgroup
+
+template <int NB, bool BF16>
+__global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __restrict__ A, int64_t R, int64_t M,
+                                                                 int64_t lda, const float* __restrict__ B, int64_t N,
+                                                                 int64_t ldb, float* __restrict__ partial,
+                                                                 int64_t chunk_rows) {
+  constexpr int TC = tg_tc(NB);                // output tiles (columns of A per lane)
+  constexpr int KS = BF16 ? 16 : 4;            // rows per K step
+  constexpr int KR = 64;                       // rows per staged B tile
+  constexpr int SPT = KR / KS;                 // K steps per tile
+  constexpr int BN = NB * 16;
+  constexpr int LF = BN + 4;                   // FP32 tile: [KR][LF] floats
+  constexpr int LH = KR + 8;                   // BF16 tile: [BN][LH] halves (transposed)
+  constexpr int BUF = BF16 ? BN * LH / 2 : KR * LF;
+  constexpr int NE = KR * BN / 4;              // float4 per B tile
+  constexpr int RB = (NE + kTgThreads - 1) / kTgThreads;
+  constexpr int NL = BF16 ? 4 : 1;             // loads of A per lane and K step
+  typedef float tcv __attribute__((ext_vector_type(TC)));
+  __shared__ float S[2 * BUF];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rl = lane & 15, g = lane >> 4;
+  const int64_t m_base = (int64_t)blockIdx.x * tg_cols(NB) + 16 * TC * wave;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk_rows;
+  const int64_t r1 = r0 + chunk_rows < R ? r0 + chunk_rows : R;
+  const int64_t nrows = r1 > r0 ? r1 - r0 : 0;
+  const int64_t ntile = (nrows + KR - 1) / KR;
+  const int64_t mcol = m_base + TC * rl;        // this lane's first column of A
+  const bool wave_on = m_base < M;              // uniform
+
+  f4v rbuf[RB];
+  auto load_b = [&](int64_t t) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kTgThreads * j;
+      const int r = e / (BN / 4), c4 = e % (BN / 4);
+      const int64_t row = r0 + t * KR + r;
+      const int64_t n = 4 * c4;
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (e < NE && row < r1) {
+        const float* p = B + row * ldb + n;
+        if (n + 3 < N) {
+          v = *reinterpret_cast<const f4v*>(p);
+        } else {
+          if (n < N) v[0] = p[0];
+          if (n + 1 < N) v[1] = p[1];
+          if (n + 2 < N) v[2] = p[2];
+        }
+      }
+      rbuf[j] = v;
+    }
+  };
+  auto stash_b = [&](int bsel) {
+    float* base = S + bsel * BUF;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = tid + kTgThreads * j;
+      if (e < NE) {
+        const int r = e / (BN / 4), c4 = e % (BN / 4);
+        if constexpr (BF16) {
+          uint16_t* h = reinterpret_cast<uint16_t*>(base);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) h[(4 * c4 + v) * LH + r] = f32_to_bf16(rbuf[j][v]);
+        } else {
+          *reinterpret_cast<f4v*>(base + r * LF + 4 * c4) = rbuf[j];
+        }
+      }
+    }
+  };
+  // A rows of K step s (global step index) for this lane
+  auto load_a = [&](int64_t s, tcv (&x)[NL]) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int64_t row = r0 + s * KS + (BF16 ? 4 * g + u : g);
+      tcv v;
+#pragma unroll
+      for (int c = 0; c < TC; ++c) v[c] = 0.f;
+      if (wave_on && row < r1) {
+        const float* p = A + row * lda + mcol;
+        if (mcol + TC - 1 < M) {
+          v = *reinterpret_cast<const tcv*>(p);
+        } else {
+#pragma unroll
+          for (int c = 0; c < TC; ++c)
+            if (mcol + c < M) v[c] = p[c];
+        }
+      }
+      x[u] = v;
+    }
+  };
+
+  f4v acc[TC][NB];
+#pragma unroll
+  for (int c = 0; c < TC; ++c)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[c][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nsteps = ntile * SPT;
+  tcv xa[NL], xn[NL];
+  if (ntile > 0) {
+    load_b(0);
+    stash_b(0);
+    if (ntile > 1) load_b(1);
+    load_a(0, xa);
+  }
+  __syncthreads();
+  for (int64_t t = 0; t < ntile; ++t) {
+    const float* base = S + (int)(t & 1) * BUF;
+#pragma unroll
+    for (int ss = 0; ss < SPT; ++ss) {
+      const int64_t s = t * SPT + ss;
+      if (s + 1 < nsteps) load_a(s + 1, xn);
+      if (wave_on) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          if constexpr (BF16) {
+            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
+                                                         (16 * cb + rl) * LH + ss * KS + 4 * g);
+#pragma unroll
+            for (int c = 0; c < TC; ++c) {
+              const uint32_t lo = pack_bf16x2(xa[0][c], xa[1][c]), hi = pack_bf16x2(xa[2][c], xa[3][c]);
+              const s4v av = {(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
+              acc[c][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[c][cb], 0, 0, 0);
+            }
+          } else {
+            const float bv = base[(ss * KS + g) * LF + 16 * cb + rl];
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+              acc[c][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][c], bv, acc[c][cb], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NL; ++u) xa[u] = xn[u];
+    }
+    if (t + 1 < ntile) {
+      stash_b((int)((t + 1) & 1));
+      if (t + 2 < ntile) load_b(t + 2);
+    }
+    __syncthreads();
+  }
+  // acc[c][cb][r] = out[m_base + TC (4 (lane / 16) + r) + c][16 cb + lane % 16]
+  if (!wave_on) return;
+  float* out = partial + (int64_t)blockIdx.y * M * N;
+#pragma unroll
+  for (int c = 0; c < TC; ++c)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m_base + TC * (4 * g + r) + c;
+        const int64_t n = 16 * cb + rl;
+        if (m < M && n < N) out[m * N + n] = acc[c][cb][r];
+      }
+}
+
 // ------------------------------------------------------------------ NT, wide N, short K
 // C = alpha A Bt^T + beta C0 (+ diag where row == col). A is M x KP and Bt is (N rounded up to 64) x KP
 // with KP = gemm_wide_kpad(K) (16, 32, 64, 128 or 160). Bt is zero past K and past N; A is zero from K
@@ -680,6 +849,22 @@ int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K,
 template <bool BF16>
 int tn_dispatch(hipStream_t st, int nb, const float* A, int64_t R, int64_t M, int64_t lda, const float* B, int64_t N,
                 int64_t ldb, float* partial, int64_t chunk_rows, int64_t nchunks) {
+  if (aligned16(A, lda) && aligned16(B, ldb)) {
+    const dim3 g((unsigned)cdiv(M, nb <= 4 ? tg_cols(4) : tg_cols(9)), (unsigned)nchunks), blk(kTgThreads);
+#define SCS_TG(NBV)                                                                                        \
+  case NBV:                                                                                                \
+    gemm_tn_reg_kernel<NBV, BF16><<<g, blk, 0, st>>>(A, R, M, lda, B, N, ldb, partial, chunk_rows); \
+    break;
+    switch (nb) {
+      SCS_TG(1) SCS_TG(2) SCS_TG(3) SCS_TG(4) SCS_TG(5) SCS_TG(6) SCS_TG(7) SCS_TG(8) SCS_TG(9)
+      default:
+        set_error("gemm_tn_splitk: N > 144");
+        return SCS_EINVAL;
+    }
+#undef SCS_TG
+    SCS_HIP(hipGetLastError());
+    return SCS_OK;
+  }
   dim3 grid((unsigned)cdiv(M, kTnBM), (unsigned)nchunks);
   bool aa = aligned16(A, lda), ba = aligned16(B, ldb);
 #define SCS_TN(NBV)                                                                                             \
@@ -772,6 +957,22 @@ int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int
                   (void*)&diag_dev, (void*)&C, (void*)&ldc, (void*)&rownorm2, (void*)&nq};
   SCS_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(threads), args, bytes, st));
   return SCS_OK;
+}
+
+int64_t gemm_tn_splitk_chunks(int64_t R, int64_t M, int64_t N, const float* A, int64_t lda, const float* B,
+                              int64_t ldb) {
+  if (R <= 0 || M <= 0 || N <= 0) return 1;
+  if (aligned16(A, lda) && aligned16(B, ldb)) {
+    // one workgroup per CU is resident: as many row chunks as fill the device once
+    const int nb = (int)cdiv(N, 16);
+    const int64_t slabs = cdiv(M, nb <= 4 ? tg_cols(4) : tg_cols(9));
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+      cus = 256;
+    return std::max<int64_t>(1, std::min<int64_t>(cdiv(R, 256), cus / slabs));
+  }
+  return std::max<int64_t>(1, std::min<int64_t>(cdiv(R, 512), std::max<int64_t>(1, 1024 / cdiv(M, 64))));
 }
 
 int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,

@@ -177,6 +177,9 @@ int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int
                         const float* Bt, int64_t N, int64_t ldb, float alpha, const float* C0, int64_t ldc0,
                         float beta, const double* beta_dev, float diag, const double* diag_dev, int out_bf16,
                         void* C, int64_t ldc, float* rownorm2);
+// Row chunks for gemm_tn_splitk over R rows (the same operands as the launch that follows).
+int64_t gemm_tn_splitk_chunks(int64_t R, int64_t M, int64_t N, const float* A, int64_t lda, const float* B,
+                              int64_t ldb);
 int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,
                           const float* B, int64_t N, int64_t ldb, float* partial, int64_t chunk_rows,
                           int64_t nchunks);
