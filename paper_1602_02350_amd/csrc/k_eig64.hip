@@ -122,39 +122,87 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
   return cnt;
 }
 
-// One solve (T - theta_t I) z_new = z on column t of zz with the stored LU factors of thread t
-// (u0 holds the reciprocals of the pivots), rescaled to unit max norm. Arrays are laid out
-// [i * l + t]; the value carried from row i to row i + 1 stays in a register.
-__device__ void inv_solve(const double* __restrict__ u0, const double* __restrict__ u1,
-                          const double* __restrict__ u2, const double* __restrict__ mlt,
-                          const double* __restrict__ swp, double* __restrict__ zz, int l, int t) {
-  double cur = zz[t];
-  // unrolled so that the factor loads of several rows are in flight at once
-#pragma unroll 8
-  for (int i = 0; i + 1 < l; ++i) {
-    const int64_t o = (int64_t)i * l + t;
-    double nxt = zz[o + l];
-    if (swp[o] != 0.0) {
-      const double tmp = cur;
-      cur = nxt;
-      nxt = tmp;
+// One inverse-iteration solve (T - th I) z_new = sc_in z on column t of zz (element i at [i * l + t]).
+// The partially pivoted LU of T - th I is rebuilt inside the forward sweep (row interchange when the
+// sub-diagonal entry is the larger; pivots below tiny in magnitude are raised to tiny, as inverse
+// iteration wants), so that sweep reads only T and z; rows of U (reciprocal pivot, first and second
+// super-diagonal) go to u0, u1, u2 at [i * l + t] for the backward sweep. Rows are processed in
+// groups of kSolveRows whose loads are issued together (clamped indices keep them unconditional).
+// Returns 1 / max|z_new|; *n2 receives sum z_new^2.
+constexpr int kSolveRows = 8;
+
+__device__ __forceinline__ double inv_solve(double* __restrict__ u0, double* __restrict__ u1,
+                                            double* __restrict__ u2, const double* sd, const double* se,
+                                            double th, double tiny, double* __restrict__ zz, int l, int t,
+                                            double sc_in, double* n2) {
+  double ca = sd[0] - th, cb = se[0];  // the carried row: entries at columns i and i + 1
+  double cur = zz[t] * sc_in;
+  for (int i0 = 0; i0 + 1 < l; i0 += kSolveRows) {
+    double nxt[kSolveRows], na[kSolveRows], nb[kSolveRows], nc[kSolveRows];
+#pragma unroll
+    for (int j = 0; j < kSolveRows; ++j) {
+      const int i = min(i0 + j, l - 2);
+      nxt[j] = zz[(i + 1) * l + t];
+      na[j] = sd[i + 1] - th;
+      nb[j] = se[i + 1];  // zero for the last row
+      nc[j] = se[i];
     }
+#pragma unroll
+    for (int j = 0; j < kSolveRows; ++j) {
+      const int i = i0 + j;
+      if (i + 1 >= l) break;  // uniform
+      const bool s = fabs(ca) < fabs(nc[j]);
+      double piv = s ? nc[j] : ca;
+      if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
+      const double r = recip_d(piv);
+      const double m = (s ? ca : nc[j]) * r;
+      const double v1 = s ? na[j] : cb;
+      const double x = nxt[j] * sc_in;
+      const double pa = s ? x : cur, pb = s ? cur : x;  // right-hand side of the pivot row, of the other
+      const int o = i * l + t;
+      u0[o] = r;
+      u1[o] = v1;
+      u2[o] = s ? nb[j] : 0.0;
+      zz[o] = pa;
+      cur = pb - m * pa;
+      ca = (s ? cb : na[j]) - m * v1;
+      cb = s ? -m * nb[j] : nb[j];
+    }
+  }
+  {
+    double piv = ca;
+    if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
+    const int o = (l - 1) * l + t;
+    u0[o] = recip_d(piv);
+    u1[o] = 0.0;
+    u2[o] = 0.0;
     zz[o] = cur;
-    cur = nxt - mlt[o] * cur;
   }
-  zz[(int64_t)(l - 1) * l + t] = cur;
-  double z1 = 0.0, z2 = 0.0, nz = 0.0;
-#pragma unroll 8
-  for (int i = l - 1; i >= 0; --i) {
-    const int64_t o = (int64_t)i * l + t;
-    const double zi = (zz[o] - u1[o] * z1 - u2[o] * z2) * u0[o];
-    zz[o] = zi;
-    z2 = z1;
-    z1 = zi;
-    nz = fmax(nz, fabs(zi));
+  double z1 = 0.0, z2 = 0.0, nz = 0.0, ss = 0.0;
+  for (int i0 = l - 1; i0 >= 0; i0 -= kSolveRows) {
+    double a0[kSolveRows], a1[kSolveRows], a2[kSolveRows], zv[kSolveRows];
+#pragma unroll
+    for (int j = 0; j < kSolveRows; ++j) {
+      const int o = max(i0 - j, 0) * l + t;
+      a0[j] = u0[o];
+      a1[j] = u1[o];
+      a2[j] = u2[o];
+      zv[j] = zz[o];
+    }
+#pragma unroll
+    for (int j = 0; j < kSolveRows; ++j) {
+      const int i = i0 - j;
+      if (i < 0) break;  // uniform
+      const double zi = (zv[j] - a1[j] * z1 - a2[j] * z2) * a0[j];
+      zz[i * l + t] = zi;
+      z2 = z1;
+      z1 = zi;
+      nz = fmax(nz, fabs(zi));
+      ss += zi * zi;
+    }
   }
-  const double inv = nz > 0.0 ? 1.0 / nz : 1.0;
-  for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] *= inv;
+  *n2 = ss;
+  return nz > 0.0 ? 1.0 / nz : 1.0;
 }
 
 __device__ void start_vector(double* zz, int l, int t) {
@@ -162,19 +210,23 @@ __device__ void start_vector(double* zz, int l, int t) {
     zz[(int64_t)i * l + t] = 1.0 + 0.25 * (double)(((uint32_t)(i + 1) * 2654435761u + (uint32_t)t * 40503u) % 997u) / 997.0;
 }
 
+__device__ void scale_col(double* zz, int l, int t, double sc) {
+  for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] *= sc;
+}
+
 __device__ void normalize2(double* zz, int l, int t) {
   double n2 = 0.0;
   for (int i = 0; i < l; ++i) n2 += zz[(int64_t)i * l + t] * zz[(int64_t)i * l + t];
-  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-  for (int i = 0; i < l; ++i) zz[(int64_t)i * l + t] *= inv;
+  scale_col(zz, l, t, n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0);
 }
 
-// Eigenpairs of the symmetric tridiagonal T (diagonal dd, off-diagonal ee). work: 5 l^2 doubles (the LU
-// factors of T - theta_t I); the vectors live in LDS.
+// Eigenpairs of the symmetric tridiagonal T (diagonal dd, off-diagonal ee). The vectors live in
+// LDS; the rows of U of the solves (3 l^2 doubles) follow them in LDS when ULDS, else they go to work.
+template <bool ULDS>
 __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* dd, const double* ee, int l,
                                                                   double* theta, double* Z, double* work) {
   extern __shared__ double zz[];  // l x l: the inverse-iteration vectors, element i of vector t at [i * l + t]
-  __shared__ double sd[kEigMaxL], se[kEigMaxL], se2[kEigMaxL], sth[kEigMaxL];
+  __shared__ double sd[kEigMaxL], se[kEigMaxL], se2[kEigMaxL], sth[kEigMaxL], csc[kEigMaxL];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < l; i += nt) {
     sd[i] = dd[i];
@@ -195,13 +247,12 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
   if (nrm == 0.0) nrm = 1.0;
   const double pivmin = 1e-290 * fmax(1.0, maxe2);
   const double abstol = 1e-16 * nrm;
-  // per-thread work arrays, element i of thread t at [i * l + t] (coalesced across threads)
+  // rows of U of each thread's solve, element i of thread t at [i * l + t] (coalesced across threads)
   const int64_t L2 = (int64_t)l * l;
-  double* u0 = work;
-  double* u1 = work + L2;
-  double* u2 = work + 2 * L2;
-  double* mlt = work + 3 * L2;
-  double* swp = work + 4 * L2;
+  double* ub = ULDS ? zz + L2 : work;
+  double* u0 = ub;
+  double* u1 = ub + L2;
+  double* u2 = ub + 2 * L2;
   // The t-th smallest eigenvalue by multisection: G lanes of one wave (G a power of two) evaluate
   // the Sturm count at G interior points of [a, b] together and keep the subinterval where the
   // count passes t, so count(a) <= t < count(b) holds throughout and [a, b] shrinks (G+1)-fold
@@ -232,45 +283,17 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
     }
   }
   __syncthreads();
+  // a zero pivot (th is an eigenvalue) is replaced by a tiny multiple of ||T||
+  const double tiny = 1e-15 * nrm;
   if (tid < l) {
+    // three solves from a fixed start vector (different per thread); the max-norm scaling of each
+    // result is applied as the next solve reads it, the final 2-norm scaling on the way out
     const int t = tid;
     const double th = sth[t];
-    // LU of T - th I with row interchanges: row i of U holds up to two super-diagonals (u0 keeps the
-    // reciprocal pivot); a zero pivot (th is an eigenvalue) is replaced by a tiny multiple of ||T||,
-    // as inverse iteration wants
-    const double tiny = 1e-15 * nrm;
-    double ca = sd[0] - th, cb = l > 1 ? se[0] : 0.0;
-    for (int i = 0; i + 1 < l; ++i) {
-      const double na = sd[i + 1] - th, nb = i + 2 < l ? se[i + 1] : 0.0, nc = se[i];
-      const int64_t o = (int64_t)i * l + t;
-      if (fabs(ca) >= fabs(nc)) {
-        const double piv = ca != 0.0 ? ca : tiny;
-        const double m = nc / piv;
-        u0[o] = 1.0 / piv;
-        u1[o] = cb;
-        u2[o] = 0.0;
-        mlt[o] = m;
-        swp[o] = 0.0;
-        ca = na - m * cb;
-        cb = nb;
-      } else {
-        const double m = ca / nc;
-        u0[o] = 1.0 / nc;
-        u1[o] = na;
-        u2[o] = nb;
-        mlt[o] = m;
-        swp[o] = 1.0;
-        ca = cb - m * na;
-        cb = -m * nb;
-      }
-    }
-    u0[(int64_t)(l - 1) * l + t] = 1.0 / (ca != 0.0 ? ca : tiny);
-    u1[(int64_t)(l - 1) * l + t] = 0.0;
-    u2[(int64_t)(l - 1) * l + t] = 0.0;
-    // three solves from a fixed start vector (different per thread)
     start_vector(zz, l, t);
-    for (int rep = 0; rep < 3; ++rep) inv_solve(u0, u1, u2, mlt, swp, zz, l, t);
-    normalize2(zz, l, t);
+    double sc = 1.0, n2 = 0.0;
+    for (int rep = 0; rep < 3; ++rep) sc = inv_solve(u0, u1, u2, sd, se, th, tiny, zz, l, t, sc, &n2);
+    csc[t] = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
   }
   __syncthreads();
   // Eigenvalues within 1e-10 ||T|| of their predecessor do not determine their inverse-iteration
@@ -282,9 +305,14 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
     if (tid == 0) {
       int g0 = t - 1;
       while (g0 > 0 && sth[g0] - sth[g0 - 1] <= ortol) --g0;
+      for (int j = g0; j < t; ++j) {  // earlier members in unit 2-norm, in place
+        if (csc[j] != 1.0) scale_col(zz, l, j, csc[j]);
+        csc[j] = 1.0;
+      }
       start_vector(zz, l, t);
       for (int rep = 0; rep < 3; ++rep) {
-        inv_solve(u0, u1, u2, mlt, swp, zz, l, t);
+        double n2 = 0.0;
+        scale_col(zz, l, t, inv_solve(u0, u1, u2, sd, se, sth[t], tiny, zz, l, t, 1.0, &n2));
         for (int j = g0; j < t; ++j) {
           double dot = 0.0;
           for (int i = 0; i < l; ++i) dot += zz[(int64_t)i * l + j] * zz[(int64_t)i * l + t];
@@ -292,10 +320,14 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
         }
         normalize2(zz, l, t);
       }
+      csc[t] = 1.0;
     }
     __syncthreads();
   }
-  for (int e = tid; e < l * l; e += nt) Z[e] = zz[e];
+  for (int e = tid; e < l * l; e += nt) {
+    const int i = e / l;
+    Z[e] = zz[e] * csc[e - i * l];
+  }
 }
 
 // V = Qh Z = H_0 (H_1 (... (H_{l-3} Z))): reflector j acts on rows j+1 .. l-1. Z in LDS; each
@@ -359,7 +391,7 @@ int max_lds_eig() {
 
 }  // namespace
 
-int eig64_work_len(int l) { return 8 * l * l + 4 * l; }
+int eig64_work_len(int l) { return 5 * l * l + 4 * l; }
 
 int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V, double* theta, int* order) {
   const size_t bytes = (size_t)l * l * sizeof(double);
@@ -372,7 +404,7 @@ int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V
   double* ee = dd + l;                       // l
   double* tau = ee + l;                      // l
   double* Zt = tau + l;                      // l x l
-  double* tw = Zt + (int64_t)l * l;          // 6 l^2: the tridiagonal solver's per-thread arrays
+  double* tw = Zt + (int64_t)l * l;          // 3 l^2: rows of U of the inverse-iteration solves
   if (bytes > 65536) {
     SCS_HIP(hipFuncSetAttribute((const void*)tridiag64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     SCS_HIP(hipFuncSetAttribute((const void*)backtransform64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -380,9 +412,19 @@ int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V
   }
   tridiag64_kernel<<<1, 512, bytes, st>>>(B, l, dd, ee, Vh, tau);  // 512 threads: fewer waves at each barrier
   SCS_HIP(hipGetLastError());
-  if (bytes > 65536)
-    SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  tridiag_eig_kernel<<<1, kEigThreads, bytes, st>>>(dd, ee, l, theta, Zt, tw);
+  // the rows of U of the inverse-iteration solves join the vectors in LDS when both fit
+  const size_t ebytes = 4 * bytes;
+  if ((int64_t)ebytes + 8192 <= max_lds_eig()) {  // static LDS: 5760 bytes
+    if (ebytes > 65536)
+      SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ebytes));
+    tridiag_eig_kernel<true><<<1, kEigThreads, ebytes, st>>>(dd, ee, l, theta, Zt, tw);
+  } else {
+    if (bytes > 65536)
+      SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes));
+    tridiag_eig_kernel<false><<<1, kEigThreads, bytes, st>>>(dd, ee, l, theta, Zt, tw);
+  }
   SCS_HIP(hipGetLastError());
   backtransform64_kernel<<<1, kEigThreads, bytes, st>>>(Zt, Vh, tau, l, V, theta, order);
   SCS_HIP(hipGetLastError());
