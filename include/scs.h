@@ -81,7 +81,8 @@ typedef struct scs_opts {
                              (rows of epochs after the stop rule held are left untouched) */
   double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's
                              end; -1 for epochs never enqueued because the stop rule had held */
-  int timing;             /* 1: time every full-gradient pass and inner-loop launch with HIP events (report.ms_grad, ms_inner) */
+  int timing;             /* 1: time every inner-loop launch with HIP events (report.ms_inner); 2: also every
+                             full-gradient pass (report.ms_grad). Each event adds a few microseconds between kernels */
   double epoch_factor;    /* with steps = 0 and epoch_factor > 0: m = ceil(epoch_factor n / b) per problem (default 0) */
   int implicit_apply;     /* scs_svrg_solve_path only: 1 = never form the preconditioned rows; the inner loop uses
                              x_i and z_i = U~^T x_i, O(d + k) per row (FP32 rows; needs d <= 2048, k <= 128) */
@@ -99,7 +100,8 @@ typedef struct scs_report {
   double certificate;     /* ||grad||^2 (lam~_1 + lambda)/(2 lambda); ||grad||^2/(2 lambda) for k = 0 */
   double lam_top;         /* lam~_1 (largest sketched eigenvalue; 0 if k = 0) */
   double ms_sketch, ms_apply, ms_solve; /* stage times */
-  double ms_grad, ms_inner; /* with opts.timing: summed durations of the full-gradient passes and inner-loop launches */
+  double ms_grad, ms_inner; /* summed durations of the full-gradient passes (opts.timing >= 2) and inner-loop launches
+                               (opts.timing >= 1) */
   int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
   int backoffs;             /* rejected snapshots: each restored the previous one and halved the step */
   int workgroups;           /* inner-loop workgroups used per problem */

@@ -572,8 +572,13 @@ int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const voi
   return SCS_OK;
 }
 
-int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
-                   int k, double eps, const scs_opts* opts, float* w_out, scs_report* report) {
+// The single solve. CholeskyQR's breakdown flags are written to host-pinned memory and read at the
+// first stop decision, so the host never waits for the sketch: in the rare breakdown case the work
+// queued so far is discarded and the solve runs again with P = I (sketch_failed), reporting
+// SCS_SKETCH_RANK_DEFICIENT as before.
+static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                           double lambda, int k, double eps, const scs_opts* opts, float* w_out, scs_report* report,
+                           bool sketch_failed) {
   if (!ctx || !y || !w_out) {
     set_error("null argument");
     return SCS_EINVAL;
@@ -602,14 +607,16 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   // rows used by the inner loop start on 256-byte boundaries, so a workgroup's column slice of a
   // gathered row covers whole cache lines
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
-  // Synchronizing events: dec[s] after the stop decision of snapshot s (just before the inner loop of
-  // epoch s). Timing-only events: 0 start, 1 sketch done, 2 preconditioner done, 3 end of solve,
-  // 4 + s end of epoch s; with timing, 4 + S + s and 5 + 2S + s bracket the gradient pass of s and
-  // 6 + 3S + s opens the inner loop of s.
-  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)(o.timing ? 6 + 4 * S : 4 + S)));
-  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
-  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
-  hipEvent_t* dec = ctx->events.data();
+  // Events (each one recorded between two kernels costs a few microseconds of dispatch, so an epoch
+  // records one, or more only when timing is asked for): 0 start, 1 sketch done, 2 preconditioner
+  // done, 3 end of solve, 4 + s end of epoch s (also the point where the host reads the stop flag of
+  // snapshot s); with timing >= 1, 6 + 3S + s opens the inner loop of s; with timing >= 2,
+  // 4 + S + s and 5 + 2S + s bracket the gradient pass of s.
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)(o.timing ? 6 + 4 * S : 4 + S)));
+  // host-pinned: S + 1 stop flags, then CholeskyQR's two breakdown flags
+  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 3));
+  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 3));
+  int* chol_flags = ctx->stop_flags + S + 1;
   hipEvent_t* tev = ctx->tevents.data();
   hipEvent_t ev_start = tev[0], ev_sketch = tev[1], ev_apply = tev[2], ev_end = tev[3];
   auto ev_epoch = [&](int s) { return tev[4 + s]; };
@@ -622,12 +629,12 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
 
   // ---- sketch (Alg. 3, Block Lanczos step)
-  int k_used = k;
-  bool rank_def = false;
-  if (k > 0) {
-    SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, &rank_def));
-    if (rank_def) k_used = 0;
-  }
+  int k_used = sketch_failed ? 0 : k;
+  const bool rank_def = sketch_failed;
+  if (k_used > 0) SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, nullptr, chol_flags));
+  auto sketch_broke = [&]() {
+    return k_used > 0 && (__atomic_load_n(chol_flags, __ATOMIC_ACQUIRE) || __atomic_load_n(chol_flags + 1, __ATOMIC_ACQUIRE));
+  };
   SCS_HIP(hipEventRecord(ev_sketch, st));
 
   // ---- preconditioned rows and smoothness (Alg. 3, x~_i, b_j, beta_i)
@@ -698,9 +705,8 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   WS(idxb, int32_t, "idx", (size_t)kSampleGroup * m * b);
   WS(scale, float, "scale", (size_t)kSampleGroup * m * b);
   WS(xbuf, uint64_t, "xbuf", (size_t)2 * 16 * 64);
-  SCS_HIP(hipMemsetAsync(wt, 0, sizeof(float) * d, st));
-  SCS_HIP(hipMemsetAsync(wt_prev, 0, sizeof(float) * d, st));
-  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * 16 * 64, st));
+  SCS_CHECK(launch_zero3(st, wt, (int64_t)sizeof(float) * d, wt_prev, (int64_t)sizeof(float) * d, xbuf,
+                         (int64_t)sizeof(uint64_t) * 2 * 16 * 64));
 
   InnerArgs a{};
   a.n = n;
@@ -730,18 +736,16 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
 
   constexpr int kLookahead = 3;
   int last_epoch = -1;
+  bool redo = false;
   for (int s = 0; s <= S; ++s) {
     float* trace_row = (o.trace_w && s < S) ? o.trace_w + (int64_t)s * d : nullptr;
     SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w32, trace_row, tmp, state));
-    if (o.timing) SCS_HIP(hipEventRecord(ev_g0(s), st));
+    if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g0(s), st));
     SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
-    if (o.timing) SCS_HIP(hipEventRecord(ev_g1(s), st));
+    if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g1(s), st));
     SCS_CHECK(launch_grad_finish(st, gpart, grsq, nwg, n, d, w32, lambda, UT32, U32, lam, k_used, mu, g64, tmp, state,
                                  o.stop_rule, eps, o.f_star, wt, wt_prev, s == 0 ? 1 : 0, ctx->stop_flags + s));
-    if (s == S) {
-      SCS_HIP(hipEventRecord(dec[s], st));
-      break;
-    }
+    if (s == S) break;
     const int64_t mb = m * b, slot = s % kSampleGroup;
     if (slot == 0) {
       const int64_t cnt = (int64_t)std::min(kSampleGroup, S - s) * mb;
@@ -751,17 +755,21 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     a.idx = o.indices ? o.indices + (int64_t)s * mb : idxb + slot * mb;
     a.scale = scale + slot * mb;
     a.step_base = (uint32_t)((uint64_t)s * (uint64_t)m);
-    SCS_HIP(hipEventRecord(dec[s], st));
     if (o.timing) SCS_HIP(hipEventRecord(ev_i0(s), st));
     SCS_CHECK(launch_inner_epoch(st, a, rows_bf16));
     SCS_HIP(hipEventRecord(ev_epoch(s), st));
     last_epoch = s;
-    // Keep kLookahead epochs queued ahead of the host's view: once the decision taken at snapshot
-    // s - kLookahead + 1 says the solve is finished, the epochs already queued after it are no-ops
-    // (every kernel returns on the device's done flag) and nothing more is enqueued.
+    // Keep kLookahead epochs queued ahead of the host's view: once the stop flag of snapshot
+    // s - kLookahead + 1 (written before that epoch's inner loop) says the solve is finished, the
+    // epochs already queued after it are no-ops (every kernel returns on the device's done flag) and
+    // nothing more is enqueued.
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
-      SCS_HIP(hipEventSynchronize(dec[q]));
+      SCS_HIP(hipEventSynchronize(ev_epoch(q)));
+      if (sketch_broke()) {
+        redo = true;
+        break;
+      }
       if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
     }
   }
@@ -771,6 +779,8 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
   SolveState hs;
   SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
   SCS_HIP(hipStreamSynchronize(st));
+  if (redo || sketch_broke())
+    return svrg_solve_impl(ctx, X, n, d, ldx, y, lambda, k, eps, opts, w_out, report, true);
 
   int status = SCS_OK;
   if (hs.status == SCS_ENONFINITE || hs.status == SCS_EDEVICE) {
@@ -815,7 +825,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     if (o.timing) {
       // launches that did work: the inner loops of hs.epochs epochs and the gradient passes before them
       // (plus the final evaluation when every epoch ran)
-      int ng = std::min(S + 1, hs.epochs + 1), ni = hs.epochs;
+      int ng = o.timing >= 2 ? std::min(S + 1, hs.epochs + 1) : 0, ni = hs.epochs;
       double sg = 0.0, si = 0.0;
       for (int s = 0; s < ng; ++s) {
         float ms = 0.f;
@@ -834,6 +844,11 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
     }
   }
   return status;
+}
+
+int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
+                   int k, double eps, const scs_opts* opts, float* w_out, scs_report* report) {
+  return svrg_solve_impl(ctx, X, n, d, ldx, y, lambda, k, eps, opts, w_out, report, false);
 }
 
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,
@@ -962,10 +977,10 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   SCS_HIP(hipMemsetAsync(flags_all, 0, sizeof(int) * 2 * nprob, st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
 
-  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)4 + S));
+  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s)
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + S));
   SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
   std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
-  hipEvent_t* dec = ctx->events.data();
   hipEvent_t* tev = ctx->tevents.data();
   SCS_HIP(hipEventRecord(tev[0], st));
 
@@ -1127,18 +1142,14 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, wg_pre[nv], wg_pre[nprob] - wg_pre[nv], max_d_s, 0));
     SCS_CHECK(launch_grad_finish_batched(st, desc, nprob, d_cb, cb_pre[nprob], s == 0 ? 1 : 0, done_count,
                                          ctx->stop_flags + s));
-    if (s == S) {
-      SCS_HIP(hipEventRecord(dec[s], st));
-      break;
-    }
+    if (s == S) break;
     const int slot = s % G;
     if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, nprob, d_dr, dr_pre[nprob], o.seed, s, G));
-    SCS_HIP(hipEventRecord(dec[s], st));
     SCS_CHECK(launch_inner_epoch_batched(st, desc, nprob, W, max_slice, b, mixed, slot, s));
     SCS_HIP(hipEventRecord(tev[4 + s], st));
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
-      SCS_HIP(hipEventSynchronize(dec[q]));
+      SCS_HIP(hipEventSynchronize(tev[4 + q]));
       if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
     }
   }
@@ -1267,10 +1278,10 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * P * d, st));
   SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * P * 2 * W * 64, st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
-  SCS_CHECK(ensure_events(ctx, (size_t)S + 1, (size_t)4 + S));
+  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s)
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + S));
   SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
   std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
-  hipEvent_t* dec = ctx->events.data();
   hipEvent_t* tev = ctx->tevents.data();
   SCS_HIP(hipEventRecord(tev[0], st));
 
@@ -1404,19 +1415,15 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       SCS_CHECK(launch_reduce_partials_t(st, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d));
     }
     SCS_CHECK(launch_grad_finalize_batched(st, desc, P, s == 0 ? 1 : 0, done_count, ctx->stop_flags + s));
-    if (s == S) {
-      SCS_HIP(hipEventRecord(dec[s], st));
-      break;
-    }
+    if (s == S) break;
     const int slot = s % G;
     if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, P, draw_pre, dpre[P], o.seed, s, G));
-    SCS_HIP(hipEventRecord(dec[s], st));
     if (implicit) SCS_CHECK(launch_inner_implicit_batched(st, desc, P, d, k_used, b, slot, s));
     else SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
     SCS_HIP(hipEventRecord(tev[4 + s], st));
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
-      SCS_HIP(hipEventSynchronize(dec[q]));
+      SCS_HIP(hipEventSynchronize(tev[4 + q]));
       if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
     }
   }

@@ -425,7 +425,30 @@ __global__ void precond_setup_kernel(const double* lam, int k, double lambda, in
   }
 }
 
+// Zeroes up to three buffers of 4-byte words in one launch (a, b, c may be null with count 0).
+__global__ void zero3_kernel(uint32_t* a, int64_t na, uint32_t* b, int64_t nb, uint32_t* c, int64_t nc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < na) a[e] = 0u;
+  if (e < nb) b[e] = 0u;
+  if (e < nc) c[e] = 0u;
+}
+
 }  // namespace
+
+int launch_zero3(hipStream_t st, void* a, int64_t abytes, void* b, int64_t bbytes, void* c, int64_t cbytes) {
+  if ((abytes | bbytes | cbytes) & 3) {
+    set_error("zero3: sizes must be multiples of 4 bytes");
+    return SCS_EINVAL;
+  }
+  const int64_t na = a ? abytes / 4 : 0, nb = b ? bbytes / 4 : 0, nc = c ? cbytes / 4 : 0;
+  const int64_t mx = std::max(na, std::max(nb, nc));
+  if (mx == 0) return SCS_OK;
+  zero3_kernel<<<(unsigned)cdiv(mx, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(a), na,
+                                                         reinterpret_cast<uint32_t*>(b), nb,
+                                                         reinterpret_cast<uint32_t*>(c), nc);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
 
 int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,

@@ -200,6 +200,8 @@ int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double*
 // k and past d; scal = {1/s, sqrt(n lambda)/s}.
 int launch_precond_setup(hipStream_t st, const double* lam, int k, double lambda, int64_t n, const float* U32,
                          int64_t d, float* UD, float* Up, int64_t ldu, double* scal, SolveState* state);
+// zeroes up to three device buffers (sizes in bytes, multiples of 4; null buffers are skipped) in one launch
+int launch_zero3(hipStream_t st, void* a, int64_t abytes, void* b, int64_t bbytes, void* c, int64_t cbytes);
 int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,
                   const SolveState* state);

@@ -96,6 +96,23 @@ def test_rank_deficient_sketch_is_reported(ctx):
     assert rc == binding.SKETCH_RANK_DEFICIENT
 
 
+@pytest.mark.parametrize("max_epochs", [2, 12])
+def test_rank_deficient_solve_falls_back_to_plain(ctx, max_epochs):
+    """A zero test matrix Omega makes CholeskyQR break down; the solve learns it only once epochs are
+    queued (at its first stop decision, or at the end when there is none), then redoes itself with
+    P = I: status SKETCH_RANK_DEFICIENT and the same weights, bit for bit, as a k = 0 solve."""
+    P = _problem(700, 40, seed=21)
+    X, y = dev(P.X), dev(P.y)
+    om = torch.zeros(4 + 5, 40, device="cuda")
+    common = dict(batch=8, steps=40, max_epochs=max_epochs, stop_rule=binding.STOP_EPOCHS, seed=5, workgroups=1)
+    res = ctx.svrg_solve(X, y, 1e-2, 4, 1e-30, omega=om, **common)
+    ref = ctx.svrg_solve(X, y, 1e-2, 0, 1e-30, **common)
+    assert res.status == binding.SKETCH_RANK_DEFICIENT
+    assert ref.status == binding.OK
+    assert res.report["k_used"] == 0 and res.report["epochs"] == ref.report["epochs"] == max_epochs
+    assert torch.equal(res.w, ref.w)
+
+
 # ------------------------------------------------------------------ preconditioning
 def _sketch_inputs(d, k, seed):
     U = inputs.random_orthonormal(d, k, seed)
