@@ -36,7 +36,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* sred) {
 // emit(j, value) receives out_j.
 constexpr int kVsMax = 4096;
 template <typename VIN, typename EMIT>
-__device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* __restrict__ lam, int k, int64_t d,
+__device__ __forceinline__ void pmhalf_apply_block(const float* __restrict__ UT, const double* __restrict__ lam, int k, int64_t d,
                                    double lambda, const VIN* __restrict__ v, double* vs, double* tbuf, EMIT emit) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform: scalar loops
@@ -56,16 +56,35 @@ __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* _
   const bool v4 = (dd & 3) == 0 && (reinterpret_cast<uintptr_t>(UT) & 15) == 0;
   const int d4 = dd >> 2;
   constexpr int R = 4;  // rows of UT per wave and pass
-  for (int i0 = wave * R; i0 < k; i0 += kVecWaves * R) {
+  const int nwave = (int)blockDim.x >> 6;
+  for (int i0 = wave * R; i0 < k; i0 += nwave * R) {
     double acc[R] = {0.0, 0.0, 0.0, 0.0};
     if (v4) {
-      for (int j4 = lane; j4 < d4; j4 += 64) {
-        const double v0 = vj(4 * j4), v1 = vj(4 * j4 + 1), v2 = vj(4 * j4 + 2), v3 = vj(4 * j4 + 3);
+      // S column quads per lane and pass, all R x S loads issued before the first is used (clamped
+      // indices keep them unconditional); the sums run in the order j4 = lane, lane + 64, ...
+      constexpr int S = 4;
+      for (int jb = 0; jb < d4; jb += 64 * S) {
+        float4 u[R][S];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (i0 + r < k) {
-            const float4 u = reinterpret_cast<const float4*>(UT + (int64_t)(i0 + r) * d)[j4];
-            acc[r] += (double)u.x * v0 + (double)u.y * v1 + (double)u.z * v2 + (double)u.w * v3;
+        for (int q = 0; q < S; ++q) {
+          const int j4 = jb + lane + 64 * q;
+          const int jc = j4 < d4 ? j4 : d4 - 1;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int ir = i0 + r < k ? i0 + r : k - 1;
+            u[r][q] = reinterpret_cast<const float4*>(UT + (int64_t)ir * d)[jc];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          const int j4 = jb + lane + 64 * q;
+          if (j4 < d4) {
+            const double v0 = vj(4 * j4), v1 = vj(4 * j4 + 1), v2 = vj(4 * j4 + 2), v3 = vj(4 * j4 + 3);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              if (i0 + r < k)
+                acc[r] += (double)u[r][q].x * v0 + (double)u[r][q].y * v1 + (double)u[r][q].z * v2 +
+                          (double)u[r][q].w * v3;
           }
         }
       }
@@ -92,14 +111,25 @@ __device__ void pmhalf_apply_block(const float* __restrict__ UT, const double* _
       const int j4 = j4base + ((int)threadIdx.x >> 2);
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (j4 < d4) {
-#pragma unroll 8
-        for (int i = part; i < k; i += 4) {
-          const float4 u = reinterpret_cast<const float4*>(UT + (int64_t)i * d)[j4];
-          const double t = tbuf[i];
-          a0 += (double)u.x * t;
-          a1 += (double)u.y * t;
-          a2 += (double)u.z * t;
-          a3 += (double)u.w * t;
+        // rows part, part + 4, ... in groups of 16, the group's loads issued together
+        constexpr int NB = 16;
+        for (int ib = part; ib < k; ib += 4 * NB) {
+          float4 u[NB];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const int i = ib + 4 * q < k ? ib + 4 * q : k - 1;
+            u[q] = reinterpret_cast<const float4*>(UT + (int64_t)i * d)[j4];
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            if (ib + 4 * q < k) {
+              const double t = tbuf[ib + 4 * q];
+              a0 += (double)u[q].x * t;
+              a1 += (double)u[q].y * t;
+              a2 += (double)u[q].z * t;
+              a3 += (double)u[q].w * t;
+            }
+          }
         }
       }
       // lanes 4q .. 4q+3 hold the four parts of one quad: (p0 + p1) + (p2 + p3)
@@ -200,7 +230,7 @@ __global__ __launch_bounds__(256) void grad_colreduce_batched_kernel(const Batch
 
 // Finish of the gradient at the snapshot for one problem (one workgroup); returns the action taken
 // (0 continue, 1 converged, 2 diverged and restored, 3 non-finite input), the same in every thread.
-__device__ int finalize_body(const double* g_in, int grows, const double* rsq_part, int nwg, int64_t n, int64_t d,
+__device__ __forceinline__ int finalize_body(const double* g_in, int grows, const double* rsq_part, int nwg, int64_t n, int64_t d,
                              const float* w, double lambda, const float* UT, const double* lam, int k, float* mu,
                              double* tmp, SolveState* state, int stop_rule, double eps, double f_star, float* wt_cur,
                              const float* wt_prev, int first) {
