@@ -116,6 +116,68 @@ def cpu_baseline(args, X, y, cfg, k, c, m, epochs_needed, seed):
                        f"the GPU")}
 
 
+def _oracle_cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_path(args, X, Y, lams, k, c, m, b, epochs, seed):
+    """The FP64 oracle on the host for a regularization path: the shared sketch once, then, for the
+    first lambda and first y, the preconditioner, the components and one SVRG epoch, each timed; the
+    total scales the per-lambda part by the number of lambdas and the epoch by every solve's epoch
+    count."""
+    import numpy as np
+    from oracle import precond, sampling, sketch, svrg
+    from paper_1602_02350_amd import inputs
+    Xh = X.cpu().numpy().astype(np.float64)
+    yh = Y[0].cpu().numpy().astype(np.float64)
+    n, d = Xh.shape
+    t0 = time.perf_counter()
+    Om = inputs.gaussian((d, k + 5), seed=seed).astype(np.float64)
+    U, lam_t, _ = sketch.sketch(Xh, Om, k)
+    t_sk = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Pm = precond.sketched_preconditioner(U, lam_t, float(lams[0]))
+    comp = precond.Components(Xh, yh, float(lams[0]), Pm)
+    W = sampling.quantize_weights(comp.smoothness())
+    eta = c / svrg.beta_hat(comp)
+    t_lam = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    svrg.svrg(comp, np.zeros(d), m, eta, 1, b, lambda s: sampling.draw_indices(W, seed, s, m * b))
+    t_ep = time.perf_counter() - t0
+    value = t_sk + len(lams) * t_lam + t_ep * sum(epochs)
+    return {"value": value, "unit": "s", "cores": _oracle_cores(), "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on the full {n}x{d} X: shared sketch timed ({t_sk:.2f} s), one lambda's "
+                       f"preconditioner and components timed ({t_lam:.2f} s, scaled by {len(lams)} lambdas), one "
+                       f"SVRG epoch of one solve timed ({t_ep:.2f} s, scaled by the {sum(epochs)} epochs all "
+                       f"solves needed on the GPU)")}
+
+
+def cpu_baseline_batch(args, Xs, ys, shapes, c, reps, seeds, sample=4):
+    """The FP64 oracle on the host for the first `sample` problems of a batch (preprocessing plus
+    `cpu_epochs` epochs each, scaled to the epochs each needed), scaled to the whole batch by
+    sum over problems of n d (1 + epochs)."""
+    tot_s, w_s, w_all = 0.0, 0.0, 0.0
+    for p, (n, d, a, lam, k) in enumerate(shapes):
+        w_all += n * d * (1 + reps[p]["epochs"])
+    cores = 1
+    for p in range(sample):
+        n, d, a, lam, k = shapes[p]
+        r = cpu_baseline(args, Xs[p], ys[p], {"b": 64, "lam": lam}, k, c, reps[p]["steps"], reps[p]["epochs"],
+                         seeds[p])
+        tot_s += r["value"]
+        cores = r["cores"]
+        w_s += n * d * (1 + reps[p]["epochs"])
+    value = tot_s * w_all / w_s
+    return {"value": value, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on problems 0..{sample - 1} of the batch (preprocessing plus "
+                       f"{args.cpu_epochs} epochs each, scaled to the epochs each needed: {tot_s:.2f} s), scaled "
+                       f"to all {len(shapes)} problems by sum of n d (1 + epochs)")}
+
+
 KERNEL_SOURCES = {"inner_epoch": "k_inner.hip", "grad_partial": "k_grad.hip"}
 
 
@@ -153,7 +215,7 @@ def bench_path(args, cfg):
     """All 8 x 32 solves of a regularization path with one shared sketch, timed to L - L* <= eps each."""
     import numpy as np
     import torch
-    from paper_1602_02350_amd import binding
+    from paper_1602_02350_amd import binding, inputs
     n, d, k, b, eps, ny, nl = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["eps"], cfg["ny"], cfg["nl"]
     mixed = args.precision == "mixed"
     seed = 20160207 + 3
@@ -189,7 +251,7 @@ def bench_path(args, cfg):
         t0 = time.perf_counter()
         res = ctx.svrg_solve_path(X, Y, list(lams), k, eps, f_star=fs, batch=b, epoch_factor=mf, max_epochs=150,
                                   stop_rule=binding.STOP_GAP, step_scale=c, implicit_apply=int(args.implicit_apply),
-                                  workgroups=max(args.workgroups, 0),
+                                  workgroups=max(args.workgroups, 0), timing=1,
                                   precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
         if it >= args.warmup:
@@ -203,6 +265,21 @@ def bench_path(args, cfg):
     st = {}
     for r in reps:
         st[r["status"]] = st.get(r["status"], 0) + 1
+    # inner-loop launches shared by all solves: gathered rows (x~_i; implicit: x_i and z_i) with their
+    # indices and weights, over the summed launch time
+    row_bytes = 4 * (d + k) if args.implicit_apply else d * (2 if mixed else 4)
+    inner_bytes = sum(r["epochs"] * r["steps"] * b * (row_bytes + 8) for r in reps)
+    inner_ms = reps[0]["ms_inner"]
+    inner_gbs = inner_bytes / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else None
+    roof = {"kernel": "inner_implicit_batched" if args.implicit_apply else "inner_epoch_batched", "bound": "hbm",
+            "achieved": inner_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": inner_gbs / HBM_PEAK_GBS if inner_gbs else None, "traffic": None,
+            "bytes_total": inner_bytes, "launches": reps[0]["n_inner"], "ms_total": inner_ms,
+            "note": "aggregate over all solves of each shared launch; every solve's steps are a latency-bound chain"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline_path(args, X, Y, lams, k, c, reps[0]["steps"], b, ep, inputs.BASE_SEED + 5)
     _multi_line(args, f"seconds to L(w)-L(w*)<={eps} for all {nl * ny} solves of a regularization path "
                       f"(shared sketch, 1 GPU)", statistics.median(times),
                 {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "ny": ny, "nl": nl,
@@ -212,7 +289,8 @@ def bench_path(args, cfg):
                  "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
                  "implicit_apply": bool(args.implicit_apply),
                  "stage_ms": {"sketch": reps[0]["ms_sketch"], "apply": reps[0]["ms_apply"],
-                              "solve": reps[0]["ms_solve"]}})
+                              "solve": reps[0]["ms_solve"]},
+                 "roofline": roof, "cpu_baseline": cpu})
     ctx.close()
 
 
@@ -241,7 +319,7 @@ def bench_batch(args, cfg):
         res = ctx.svrg_solve_batched(Xs, ys, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
                                      f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=600,
                                      stop_rule=binding.STOP_GAP, step_scale=c, workgroups=max(args.workgroups, 0),
-                                     precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+                                     timing=1, precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
         torch.cuda.synchronize()
         if it >= args.warmup:
             times.append(time.perf_counter() - t0)
@@ -252,6 +330,19 @@ def bench_batch(args, cfg):
     for r in reps:
         st[r["status"]] = st.get(r["status"], 0) + 1
     nd = sum(n * d for n, d, _, _, _ in shapes)
+    inner_bytes = sum(reps[p]["epochs"] * reps[p]["steps"] * cfg["b"] * (shapes[p][1] * (2 if mixed else 4) + 8)
+                      for p in range(len(shapes)))
+    inner_ms = reps[0]["ms_inner"]
+    inner_gbs = inner_bytes / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else None
+    roof = {"kernel": "inner_epoch_batched", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS if inner_gbs else None, "traffic": None,
+            "bytes_total": inner_bytes, "launches": reps[0]["n_inner"], "ms_total": inner_ms,
+            "note": "aggregate over all problems of each shared launch; every problem's steps are a latency-bound chain"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline_batch(args, Xs, ys, shapes, c, reps,
+                                 [20160207 + 1000 + p for p in range(len(shapes))])
     _multi_line(args, f"seconds to L(w)-L(w*)<={cfg['eps']} for all {len(shapes)} uneven problems (1 GPU)",
                 statistics.median(times),
                 {"workload": args.workload, "nprob": len(shapes), "n": [cfg["n_lo"], cfg["n_hi"]],
@@ -260,7 +351,8 @@ def bench_batch(args, cfg):
                 {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
                  "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
                  "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
-                 "stage_ms": {"setup": reps[0]["ms_sketch"], "solve": reps[0]["ms_solve"]}})
+                 "stage_ms": {"setup": reps[0]["ms_sketch"], "solve": reps[0]["ms_solve"]},
+                 "roofline": roof, "cpu_baseline": cpu})
     ctx.close()
 
 

@@ -101,7 +101,8 @@ typedef struct scs_report {
   double lam_top;         /* lam~_1 (largest sketched eigenvalue; 0 if k = 0) */
   double ms_sketch, ms_apply, ms_solve; /* stage times */
   double ms_grad, ms_inner; /* summed durations of the full-gradient passes (opts.timing >= 2) and inner-loop launches
-                               (opts.timing >= 1) */
+                               (opts.timing >= 1); batched and path solves: the shared inner-loop launches of all
+                               problems (every report holds the same figure), no ms_grad */
   int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
   int backoffs;             /* rejected snapshots: each restored the previous one and halved the step */
   int workgroups;           /* inner-loop workgroups used per problem */

@@ -977,8 +977,9 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   SCS_HIP(hipMemsetAsync(flags_all, 0, sizeof(int) * 2 * nprob, st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
 
-  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s)
-  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + S));
+  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s);
+  // with timing, 4 + S + s opens the inner loop of epoch s
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + (o.timing ? 2 * S : S)));
   SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
   std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
   hipEvent_t* tev = ctx->tevents.data();
@@ -1136,6 +1137,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
 
   // ---- epochs of all problems in shared launches (Alg. 1 per problem)
   constexpr int kLookahead = 3;
+  int epochs_launched = 0;
   for (int s = 0; s <= S; ++s) {
     SCS_CHECK(launch_premap_batched(st, desc, nprob, 0, nullptr));
     SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, 0, wg_pre[nv], max_d_v, 1));
@@ -1145,8 +1147,10 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     if (s == S) break;
     const int slot = s % G;
     if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, nprob, d_dr, dr_pre[nprob], o.seed, s, G));
+    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
     SCS_CHECK(launch_inner_epoch_batched(st, desc, nprob, W, max_slice, b, mixed, slot, s));
     SCS_HIP(hipEventRecord(tev[4 + s], st));
+    epochs_launched = s + 1;
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
       SCS_HIP(hipEventSynchronize(tev[4 + q]));
@@ -1163,6 +1167,13 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   float t_setup = 0.f, t_solve = 0.f;
   hipEventElapsedTime(&t_setup, tev[0], tev[1]);
   hipEventElapsedTime(&t_solve, tev[1], tev[3]);
+  double t_inner = 0.0;  // shared inner-loop launches of every epoch enqueued (timing only)
+  if (o.timing)
+    for (int s = 0; s < epochs_launched; ++s) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, tev[4 + S + s], tev[4 + s]);
+      t_inner += ms;
+    }
   for (int p = 0; p < nprob; ++p) {
     const SolveState& h = hs[sidx[p]];
     int status = SCS_OK;
@@ -1190,6 +1201,8 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
       r.ms_sketch = t_setup;
       r.ms_apply = 0.0;
       r.ms_solve = t_solve;
+      r.ms_inner = t_inner;
+      r.n_inner = o.timing ? epochs_launched : 0;
     }
   }
   if (worst == SCS_ENONFINITE) set_error("non-finite value in X or y of at least one problem");
@@ -1278,8 +1291,9 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * P * d, st));
   SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * P * 2 * W * 64, st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
-  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s)
-  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + S));
+  // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s);
+  // with timing, 4 + S + s opens the inner loop of epoch s
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + (o.timing ? 2 * S : S)));
   SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 1));
   std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 1));
   hipEvent_t* tev = ctx->tevents.data();
@@ -1402,6 +1416,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
 
   // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X
   constexpr int kLookahead = 3;
+  int epochs_launched = 0;
   for (int s = 0; s <= S; ++s) {
     SCS_CHECK(launch_premap_batched(st, desc, P, 0, nullptr));
     for (int c0 = 0; c0 < P; c0 += kPc) {
@@ -1418,9 +1433,11 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     if (s == S) break;
     const int slot = s % G;
     if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, P, draw_pre, dpre[P], o.seed, s, G));
+    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
     if (implicit) SCS_CHECK(launch_inner_implicit_batched(st, desc, P, d, k_used, b, slot, s));
     else SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
     SCS_HIP(hipEventRecord(tev[4 + s], st));
+    epochs_launched = s + 1;
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
       SCS_HIP(hipEventSynchronize(tev[4 + q]));
@@ -1441,6 +1458,13 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   hipEventElapsedTime(&t_sk, tev[0], tev[1]);
   hipEventElapsedTime(&t_ap, tev[1], tev[2]);
   hipEventElapsedTime(&t_so, tev[2], tev[3]);
+  double t_inner = 0.0;  // shared inner-loop launches of every epoch enqueued (timing only)
+  if (o.timing)
+    for (int s = 0; s < epochs_launched; ++s) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, tev[4 + S + s], tev[4 + s]);
+      t_inner += ms;
+    }
   int worst = SCS_OK;
   for (int p = 0; p < P; ++p) {
     const SolveState& h = hs[p];
@@ -1469,6 +1493,8 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       rp.ms_sketch = t_sk;
       rp.ms_apply = t_ap;
       rp.ms_solve = t_so;
+      rp.ms_inner = t_inner;
+      rp.n_inner = o.timing ? epochs_launched : 0;
     }
   }
   if (worst == SCS_ENONFINITE) set_error("non-finite value in X or Y");
