@@ -60,8 +60,11 @@ def log(args, *a):
 
 
 def make_problem_gpu(cfg, seed):
-    """The synthetic recipe of paper_1602_02350_amd.inputs, drawn on the GPU: x_i ~ N(0, U diag(j^-a) U^T)."""
+    """The synthetic recipes of paper_1602_02350_amd.inputs, drawn on the GPU: x_i ~ N(0, U diag(j^-a) U^T),
+    or, for the paper's own synthetic workload, singular values q^-a and unit-norm rows."""
     from paper_1602_02350_amd import inputs
+    if cfg.get("spectral_rows"):
+        return inputs.make_spectral_rows_torch(cfg["n"], cfg["d"], cfg["alpha"], seed)
     return inputs.make_ridge_torch(cfg["n"], cfg["d"], cfg["alpha"], seed, floor=cfg.get("floor", 0.0))
 
 
@@ -356,6 +359,80 @@ def bench_batch(args, cfg):
     ctx.close()
 
 
+def bench_curves(args, cfg):
+    """The paper's synthetic workload (Sec. 5, Fig. 2): both methods run a fixed budget of epochs
+    (m = 2n/b steps each, eta = c / beta_hat with c tuned per method on another seed by the lowest
+    objective after 15 epochs); reports the suboptimality of every epoch's snapshot and the seconds
+    the preconditioned solve needs to reach the best suboptimality plain SVRG reaches in its budget."""
+    import torch
+    from paper_1602_02350_amd import binding, inputs
+    n, d, k, b, lam = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["lam"]
+    S = args.plain_epochs
+    seed = inputs.BASE_SEED + 7
+    X, y = make_problem_gpu(cfg, seed)
+    ws, Ls, H = reference_optimum(X, y, lam)
+    torch.cuda.synchronize()
+    m = 2 * n // b
+    ctx = binding.Context(0)
+
+    def run(kk, c, epochs, s_, trace=None, timing=0):
+        return ctx.svrg_solve(X, y, lam, kk, 0.0, batch=b, steps=m, max_epochs=epochs, stop_rule=binding.STOP_EPOCHS,
+                              step_scale=c, seed=s_, trace_w=trace, timing=timing, workgroups=args.workgroups)
+
+    tuned = {}
+    for name, kk in (("precond", k), ("plain", 0)):
+        best = None
+        for c in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0):
+            r = run(kk, c, 15, seed + 1000)
+            obj = r.report["objective"]
+            log(args, f"tune {name} c={c}: status={r.status} objective={obj:.9g}")
+            if r.status == binding.OK and (best is None or obj < best[1]):
+                best = (c, obj)
+        tuned[name] = best[0]
+    log(args, "tuned", tuned)
+    curves, ms, reps, secs = {}, {}, {}, {}
+    for name, kk in (("precond", k), ("plain", 0)):
+        tr = torch.empty(S, d, device="cuda", dtype=torch.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = run(kk, tuned[name], S, seed, trace=tr, timing=1)
+        torch.cuda.synchronize()
+        secs[name] = time.perf_counter() - t0
+        # snapshot entering epoch s (s >= 1) is the result of epochs 0 .. s-1; the last is the returned w
+        so = [subopt(H, tr[s], ws) for s in range(1, S)] + [subopt(H, r.w, ws)]
+        curves[name], ms[name], reps[name] = so, list(r.epoch_ms), r
+    target = min(curves["plain"])
+    hit = next((s for s, v in enumerate(curves["precond"]) if v <= target), None)
+    t_pre = 1e-3 * ms["precond"][hit] if hit is not None else None
+    t_plain = 1e-3 * ms["plain"][int(min(range(S), key=lambda s: curves["plain"][s]))]
+    rp = reps["precond"].report
+    row_bytes = d * 4
+    inner_bytes = m * b * (row_bytes + 8)
+    inner_ms = rp["ms_inner"] / max(1, rp["n_inner"])
+    inner_gbs = inner_bytes / (inner_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline(args, X, y, cfg, k, tuned["precond"], m, (hit + 1) if hit is not None else S, seed)
+    _multi_line(args, "seconds for the preconditioned solve to reach the lowest suboptimality plain SVRG reaches in "
+                      f"{S} epochs (1 GPU)", t_pre,
+                {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "lambda": lam, "epochs": S,
+                 "steps_per_epoch": m, "spectrum": f"singular values q^-{cfg['alpha']}, unit-norm rows",
+                 "parallelism": "1 GPU"},
+                {"steps": 1, "warmup": 0, "ms_per_step": 1e3 * t_pre if t_pre else None,
+                 "dtype": "f32", "plain_svrg_s": t_plain, "speedup_vs_plain": (t_plain / t_pre) if t_pre else None,
+                 "target_suboptimality": target, "epochs_to_target": {"precond": (hit + 1) if hit is not None else None,
+                                                                      "plain": int(min(range(S), key=lambda s: curves["plain"][s])) + 1},
+                 "step_scale": tuned, "solve_s": secs,
+                 "suboptimality_per_epoch": {name: [float(f"{v:.4g}") for v in curves[name]] for name in curves},
+                 "roofline": {"kernel": "inner_epoch", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": None,
+                              "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms,
+                              "us_per_step": 1e3 * inner_ms / m},
+                 "cpu_baseline": cpu})
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -371,6 +448,8 @@ def main():
         return bench_path(args, cfg)
     if "nprob" in cfg:
         return bench_batch(args, cfg)
+    if cfg.get("spectral_rows"):
+        return bench_curves(args, cfg)
     mixed = (args.precision == "mixed") if args.precision else args.workload.startswith("mixed")
     prec = binding.PREC_MIXED if mixed else binding.PREC_FP32
     n, d, k, b, lam, eps = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["lam"], cfg["eps"]
@@ -492,7 +571,8 @@ def main():
         "dtype": "bf16+f32" if mixed else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "lambda": lam, "eps": eps,
-                   "spectrum": f"j^-{cfg['alpha']}" + (f"+{cfg['floor']}" if cfg.get("floor") else ""),
+                   "spectrum": (f"singular values q^-{cfg['alpha']}, unit-norm rows" if cfg.get("spectral_rows")
+                                else f"j^-{cfg['alpha']}" + (f"+{cfg['floor']}" if cfg.get("floor") else "")),
                    "parallelism": "1 GPU"},
         "plain_svrg_s": t_plain,
         "plain_reached_eps": plain_ok,

@@ -12,6 +12,11 @@ Recipe (row-major, one instance per row, X is n x d):
   * w0 ~ N(0, I_d);  y = X w0 + e with e ~ N(0, noise_var).
   * Omega ~ N(0,1)^{d x l} for the range finder.
 Spectra are power laws spec_j = j^{-alpha} (j = 1..d), optionally with a floor.
+
+The synthetic workload of the paper's experiments (Sec. 5) is drawn differently: X has exactly
+the singular values q^{-alpha} (q = 1..d) with uniformly random singular vectors (X = V diag(s) U^T,
+V an n x d matrix with orthonormal columns from the QR of a Gaussian matrix, U Haar), every example
+(row) is then scaled to unit norm, and y = X w* + z with w* ~ N(0, I_d), z ~ N(0, 0.1).
 """
 from __future__ import annotations
 
@@ -102,6 +107,50 @@ def integer_weights(N: int, seed: int, max_weight: int = 1 << 20, zero_frac: flo
     return w
 
 
+def make_spectral_rows(n: int, d: int, alpha: float, seed: int, noise_var: float = 0.1,
+                       dtype=np.float32, normalize: bool = True):
+    """The paper's synthetic regression data (n >= d): singular values q^{-alpha} with uniformly random
+    singular vectors, rows scaled to unit norm (skipped with normalize=False), y = X w* + z.
+    Returns (X, y, w*); X and y in `dtype`."""
+    assert n >= d
+    rng_v = np.random.default_rng([seed, 21])
+    rng_u = np.random.default_rng([seed, 22])
+    rng_w = np.random.default_rng([seed, 23])
+    rng_e = np.random.default_rng([seed, 24])
+    V, R = np.linalg.qr(rng_v.standard_normal((n, d)))
+    V = V * np.sign(np.diag(R))[None, :]
+    U = haar_orthogonal(d, rng_u)
+    s = np.arange(1, d + 1, dtype=np.float64) ** (-float(alpha))
+    X = (V * s[None, :]) @ U.T
+    if normalize:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    w = rng_w.standard_normal(d)
+    y = X @ w + rng_e.standard_normal(n) * np.sqrt(noise_var)
+    return X.astype(dtype), y.astype(dtype), w
+
+
+def make_spectral_rows_torch(n: int, d: int, alpha: float, seed: int, noise_var: float = 0.1,
+                             device: str = "cuda"):
+    """make_spectral_rows drawn with torch's generator on a device (a different random stream):
+    X (n x d FP32) and y (n FP32) as device tensors."""
+    import torch
+    assert n >= d
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    V, R = torch.linalg.qr(torch.randn(n, d, generator=g, device=device, dtype=torch.float64))
+    V = V * torch.sign(torch.diagonal(R))[None, :]
+    del R
+    Q, R = torch.linalg.qr(torch.randn(d, d, generator=g, device=device, dtype=torch.float64))
+    U = Q * torch.sign(torch.diagonal(R))[None, :]
+    s = torch.arange(1, d + 1, device=device, dtype=torch.float64) ** (-float(alpha))
+    X = (V * s[None, :]) @ U.T
+    del V
+    X /= X.norm(dim=1, keepdim=True)
+    w = torch.randn(d, generator=g, device=device, dtype=torch.float64)
+    y = X @ w + torch.randn(n, generator=g, device=device, dtype=torch.float64) * float(noise_var) ** 0.5
+    return X.float().contiguous(), y.float()
+
+
 def random_vector(d: int, seed: int, scale: float = 1.0) -> np.ndarray:
     return np.random.default_rng([seed, 10]).standard_normal(d) * scale
 
@@ -123,6 +172,12 @@ WORKLOADS = {
     # lambda ~ logU[1e-6, 1e-3], k = floor(d / 16); BF16 rows in the inner loop.
     "batch256_uneven": dict(nprob=256, n_lo=1000, n_hi=50000, d_lo=64, d_hi=512, a_lo=1.0, a_hi=2.5,
                             lam_lo=1e-6, lam_hi=1e-3, b=64, eps=1e-6, floor=0.0),
+    # the paper's synthetic data (Sec. 5): 20000 unit-norm examples in d = 5000 with singular values
+    # 1/q (linear decay) and 1/q^2 (quadratic decay), lambda = 1e-8, k = 30
+    "synth_linear_n20000_d5000": dict(n=20000, d=5000, alpha=1.0, lam=1e-8, k=30, b=64, eps=1e-6,
+                                      spectral_rows=True),
+    "synth_quadratic_n20000_d5000": dict(n=20000, d=5000, alpha=2.0, lam=1e-8, k=30, b=64, eps=1e-6,
+                                         spectral_rows=True),
 }
 
 

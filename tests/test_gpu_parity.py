@@ -214,6 +214,31 @@ def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16):
     assert rel(host(wt) - wt0, step) < tol
 
 
+# ------------------------------------------------------------------ the paper's synthetic data
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_papers_synthetic_data_tracks_the_oracle(ctx, alpha):
+    """The experiments' synthetic regression (Sec. 5: singular values 1/q or 1/q^2, unit-norm examples,
+    lambda = 1e-8, k = 30) at n = 6000, d = 4200, wider than the 4096 entries the P^{-1/2} apply stages
+    in LDS, so it runs the unstaged path. Same Omega and index stream as the oracle: after three epochs
+    the GPU's distance to w* matches the oracle's trajectory and its suboptimality."""
+    n, d, lam, k, b = 6000, 4200, 1e-8, 30, 64
+    X, y, _ = inputs.make_spectral_rows(n, d, alpha, seed=inputs.BASE_SEED + 50)
+    X64, y64 = X.astype(np.float64), y.astype(np.float64)
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 51)
+    m, S = n // b, 3
+    idx = inputs.index_stream(n + d, S * m * b, seed=79).reshape(S, -1)
+    res = ctx.svrg_solve(dev(X), dev(y), lam, k, 0.0, omega=dev(Om), indices=dev(idx, torch.int32), steps=m, batch=b,
+                         max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=8.0)
+    assert res.status == binding.OK, res.report
+    wo, _, info = svrg.scsvrg(X64, y64, lam, k, Om.T.astype(np.float64), m, S, b, lambda s: idx[s], c=8.0)
+    ws = ridge.closed_form(X64, y64, lam)
+    wg = host(res.w).astype(np.float64)
+    assert rel(wg - ws, wo - ws) < 5e-2, rel(wg - ws, wo - ws)
+    so_g, so_o = ridge.suboptimality(X64, lam, wg, ws), ridge.suboptimality(X64, lam, wo, ws)
+    assert abs(so_g - so_o) <= 0.1 * so_o, (so_g, so_o)
+    assert abs(res.report["eta"] - info["eta"]) <= 1e-4 * info["eta"]
+
+
 # ------------------------------------------------------------------ whole solve
 def test_solve_with_injected_randomness_tracks_the_oracle(ctx):
     cfg = inputs.WORKLOADS["small_n2000_d100"]
