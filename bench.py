@@ -5,7 +5,7 @@ One step = one full solve with the sketched preconditioner (sketch, precondition
 epochs, output map) followed by one plain-SVRG solve of the same problem, both stopping as soon
 as the objective gap at an epoch's snapshot is <= eps. Inputs are resident in HBM before timing.
 The step size c (eta = c / beta_hat) is tuned per method on a separate seed before timing, as in
-the paper's protocol (Sec. 5: eta tuned per method, m proportional to n).
+the paper's protocol (Sec. 6: eta tuned per method, m proportional to n).
 
 Prints one JSON line. Reported beside the headline number:
   * roofline: the inner-loop kernel (the dominant kernel by time), algorithmic bytes per launch
@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--plain-epochs", type=int, default=60, help="epoch cap of the plain-SVRG solves")
     ap.add_argument("--implicit-apply", action="store_true",
                     help="path workload: inner loop on x_i and z_i instead of formed preconditioned rows")
+    ap.add_argument("--uniform-sampling", action="store_true",
+                    help="draw components uniformly (original SVRG) instead of proportionally to beta_i")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -360,7 +362,7 @@ def bench_batch(args, cfg):
 
 
 def bench_curves(args, cfg):
-    """The paper's synthetic workload (Sec. 5, Fig. 2): both methods run a fixed budget of epochs
+    """The paper's synthetic workload (Sec. 6, Fig. 2): both methods run a fixed budget of epochs
     (m = 2n/b steps each, eta = c / beta_hat with c tuned per method on another seed by the lowest
     objective after 15 epochs); reports the suboptimality of every epoch's snapshot and the seconds
     the preconditioned solve needs to reach the best suboptimality plain SVRG reaches in its budget."""
@@ -467,7 +469,8 @@ def main():
     def solve(kk, c, mf, s, timing=0, max_epochs=60):
         return ctx.svrg_solve(X, y, lam, kk, eps, batch=b, steps=max(1, int(round(mf * n / b))),
                               max_epochs=max_epochs, stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=c, seed=s,
-                              precision=prec, workgroups=args.workgroups, timing=int(timing))
+                              precision=prec, workgroups=args.workgroups, timing=int(timing),
+                              uniform_sampling=int(args.uniform_sampling))
 
     if args.copy_calibration:
         src = torch.empty(256 * 2 ** 20 // 4, device="cuda", dtype=torch.float32).fill_(1.0)
@@ -573,6 +576,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "lambda": lam, "eps": eps,
                    "spectrum": (f"singular values q^-{cfg['alpha']}, unit-norm rows" if cfg.get("spectral_rows")
                                 else f"j^-{cfg['alpha']}" + (f"+{cfg['floor']}" if cfg.get("floor") else "")),
+                   "sampling": "uniform" if args.uniform_sampling else "proportional to beta_i",
                    "parallelism": "1 GPU"},
         "plain_svrg_s": t_plain,
         "plain_reached_eps": plain_ok,

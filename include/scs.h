@@ -86,6 +86,9 @@ typedef struct scs_opts {
   double epoch_factor;    /* with steps = 0 and epoch_factor > 0: m = ceil(epoch_factor n / b) per problem (default 0) */
   int implicit_apply;     /* scs_svrg_solve_path only: 1 = never form the preconditioned rows; the inner loop uses
                              x_i and z_i = U~^T x_i, O(d + k) per row (FP32 rows; needs d <= 2048, k <= 128) */
+  int uniform_sampling;   /* 1: draw the n + d components uniformly, q_i = 1/(n+d) (the uniform sampling of
+                             Johnson and Zhang, Sec. 4.2) instead of q_i proportional to beta_i (Xiao and Zhang,
+                             the default 0); eta = c / beta_hat either way, so c is tuned per sampling rule */
 } scs_opts;
 
 typedef struct scs_report {
@@ -117,7 +120,7 @@ int scs_create(scs_ctx** out, int device, void* hip_stream);
 int scs_destroy(scs_ctx* ctx);
 
 /*
- * Randomized sketch (Alg. 2 with one Krylov block, Sec. 3.2): Y = X^T (X Omega),
+ * Randomized sketch (Alg. 2 with one Krylov block, Sec. 4.3): Y = X^T (X Omega),
  * Q = orth(Y) by CholeskyQR2 in FP64, B = (X Q)^T (X Q) / n, B = V Theta V^T by
  * Jacobi in FP64, lam~ = Theta_{1..k} (descending, clamped >= 0), U~ = Q V_{:,1..k}.
  * The lam~ estimate the eigenvalues of C = X^T X / n (Eq. (covSpec)), i.e. the
@@ -131,7 +134,7 @@ int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
 
 /*
  * Preconditioner of Eq. (condSketch), P^{-1/2} = sum_i u_i u_i^T/sqrt(lam_i+lambda) + (I - U U^T)/sqrt(lam_k+lambda),
- * applied to every row (Alg. 3, x~_i = P^{-1/2} x_i) and to the regularizer rows b_j = P^{-1/2} e_j (Sec. 4.1):
+ * applied to every row (Alg. 3, x~_i = P^{-1/2} x_i) and to the regularizer rows b_j = P^{-1/2} e_j (Sec. 5.1):
  *   Xt_out  (n x d, ld ldt): x~_i = x_i / s + U~ (D (U~^T x_i)),  s = sqrt(lam_k + lambda), D_j = 1/sqrt(lam_j + lambda) - 1/s
  *   reg_out (d x d, ld ldt): sqrt(n lambda) b_j  (so that the n+d components are 1/2 (n+d)/n (a_i^T w - t_i)^2)
  *   beta_out (n + d, nullable): ||x~_i||^2 then ||sqrt(n lambda) b_j||^2 (proportional to the smoothness beta_i of Alg. 3)
@@ -143,7 +146,7 @@ int scs_precondition_apply(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
                            int xt_bf16, void* Xt_out, void* reg_out, int64_t ldt, float* beta_out);
 
 /*
- * Full gradient of the preconditioned objective at w~ (Alg. 1, the snapshot gradient; Sec. 4.1):
+ * Full gradient of the preconditioned objective at w~ (Alg. 1, the snapshot gradient; Sec. 5.1):
  *   grad L~(w~) = P^{-1/2} [ X^T (X w - y)/n + lambda w ],  w = P^{-1/2} w~,
  * which equals X~^T (X~ w~ - y)/n + lambda P^{-1} w~ (the n+d-component form) and is
  * evaluated with X itself so that its fixed point is exactly that of L.

@@ -13,7 +13,7 @@ columns of a d x n matrix; every formula here is transposed accordingly).
 Modules
   ridge     objective, gradient, closed form, suboptimality, condition numbers
   sketch    randomized range finder + Rayleigh-Ritz (Alg. 2 with one block)
-  precond   the sketched / exact preconditioners and the n+d components (Sec. 4)
+  precond   the sketched / exact preconditioners and the n+d components (Sec. 5)
   sampling  Philox4x32-10, integer-weight inverse-CDF sampler, Box-Muller
   svrg      SVRG (Alg. 1, minibatch form) and the whole pipeline (Alg. 3)
 

@@ -1,4 +1,4 @@
-"""Preconditioners and the preconditioned n+d components in FP64 (Sec. 4).
+"""Preconditioners and the preconditioned n+d components in FP64 (Sec. 5).
 
 Test infrastructure only (see oracle/__init__.py).
 """
@@ -14,7 +14,7 @@ def _f64(a):
 def sketched_preconditioner(U, lam_t, lam):
     """Dense P^{-1/2} = sum_{i<=k} u_i u_i^T / sqrt(lam_i + lam) + (I - sum u_i u_i^T)/sqrt(lam_k + lam).
 
-    [Sec. 4.4, Eq. (condSketch)]; lam_t are the sketched eigenvalue estimates
+    [Sec. 5.4, Eq. (condSketch)]; lam_t are the sketched eigenvalue estimates
     (the squared singular values sigma_i^2), in descending order. With k = 0
     (U of width 0) the preconditioner is the identity (plain SVRG).
     """
@@ -33,7 +33,7 @@ def sketched_preconditioner(U, lam_t, lam):
 
 
 def exact_preconditioner(C, lam, k):
-    """The same formula with the true top-k eigenpairs of C.  [Sec. 4.3]"""
+    """The same formula with the true top-k eigenpairs of C.  [Sec. 5.3]"""
     ev, V = np.linalg.eigh(_f64(C))
     order = np.argsort(ev)[::-1]
     ev, V = ev[order], V[:, order]
@@ -41,7 +41,7 @@ def exact_preconditioner(C, lam, k):
 
 
 class Components:
-    """The n+d components of the preconditioned objective.  [Sec. 4.1]
+    """The n+d components of the preconditioned objective.  [Sec. 5.1]
 
       l_i(w)     = (n+d)/n * 1/2 (w^T xt_i - y_i)^2,   xt_i = P^{-1/2} x_i,  i = 1..n
       l_{n+j}(w) = lam (n+d) * 1/2 (w^T b_j)^2,        b_j  = P^{-1/2} e_j,  j = 1..d

@@ -69,7 +69,7 @@ def kappa_hat(X, lam):
 
 
 def kappa_tilde(X, lam, P_mhalf):
-    """tr / lambda_min of P^{-1/2}(C + lam I)P^{-1/2}.  [Sec. 4.2, Thm. (condEffect)]"""
+    """tr / lambda_min of P^{-1/2}(C + lam I)P^{-1/2}.  [Sec. 5.2, Thm. (condEffect)]"""
     Pm = _f64(P_mhalf)
     return average_condition(Pm @ hessian(X, lam) @ Pm)
 
@@ -84,6 +84,6 @@ def speedup_ratio(eigs, k):
 
 
 def predicted_kappa(eigs, lam, k):
-    """(k lambda_k + sum_{i>k} lambda_i)/lam + d.  [Sec. 4.3, Eq. (exactCondSketchCond)]"""
+    """(k lambda_k + sum_{i>k} lambda_i)/lam + d.  [Sec. 5.3, Eq. (exactCondSketchCond)]"""
     ev = _f64(eigs)
     return float((k * ev[k - 1] + ev[k:].sum()) / lam + ev.size)

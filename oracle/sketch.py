@@ -1,9 +1,9 @@
-"""Randomized sketch of the data matrix in FP64 (Sec. 3.2, Alg. 2; Sec. 4.4).
+"""Randomized sketch of the data matrix in FP64 (Sec. 4.3, Alg. 2; Sec. 5.4).
 
 Test infrastructure only (see oracle/__init__.py).
 
 The paper runs Block Lanczos on Xbar = n^{-1/2} X (instances as columns,
-Sec. 4.3), so Xbar Xbar^T = C and the squared singular values it returns
+Sec. 5.3), so Xbar Xbar^T = C and the squared singular values it returns
 approximate the eigenvalues of C. In this package's row layout (X is n x d)
 that operator is A = n^{-1/2} X^T (d x n).
 """

@@ -38,18 +38,20 @@ def _component_grads(comp: Components, idx, w):
 
 
 def beta_hat(comp: Components):
-    """Average smoothness (1/N) sum_i beta_i.  [Sec. 3.1, Eq. (conditionSVRG)]"""
+    """Average smoothness (1/N) sum_i beta_i.  [Sec. 4.2, Eq. (conditionSVRG)]"""
     return float(comp.smoothness().mean())
 
 
-def svrg(comp: Components, w_bar0, m, eta, S, b, epoch_indices, average=True):
+def svrg(comp: Components, w_bar0, m, eta, S, b, epoch_indices, average=True, q=None):
     """Alg. 1 on F = (1/N) sum_i l_i, with minibatches of b i.i.d. draws.
 
     epoch_indices(s) returns the m*b component indices (0-based) used in epoch
-    s = 0..S-1, step t using entries [t*b, (t+1)*b). Returns the final snapshot
-    and the list of snapshots after each epoch.
+    s = 0..S-1, step t using entries [t*b, (t+1)*b). q are the sampling
+    probabilities the draws follow: beta_i / sum beta (the default, Alg. 1), or
+    e.g. 1/N for the uniform sampling of the original SVRG (Sec. 4.2). Returns
+    the final snapshot and the list of snapshots after each epoch.
     """
-    q = comp.probabilities()
+    q = comp.probabilities() if q is None else np.asarray(q, dtype=np.float64)
     N = comp.N
     w_bar = np.asarray(w_bar0, dtype=np.float64).copy()
     snapshots = []

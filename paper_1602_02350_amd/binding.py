@@ -46,6 +46,7 @@ class ScsOpts(ctypes.Structure):
         ("timing", ctypes.c_int),
         ("epoch_factor", ctypes.c_double),
         ("implicit_apply", ctypes.c_int),
+        ("uniform_sampling", ctypes.c_int),
     ]
 
 

@@ -686,7 +686,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   // ---- sampling weights (Alg. 1: q_i = beta_i / sum beta)
   WS(cum, uint64_t, "cum", (size_t)N);
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
-  SCS_CHECK(launch_sampler_prepare(st, beta, N, cum, scr, sampler_scratch_len(N), state));
+  SCS_CHECK(launch_sampler_prepare(st, beta, N, cum, scr, sampler_scratch_len(N), state, o.uniform_sampling));
   SCS_HIP(hipEventRecord(ev_apply, st));
 
   // ---- SVRG epochs (Alg. 1)
@@ -1054,7 +1054,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   }
   for (int p = 0; p < nprob; ++p)
     SCS_CHECK(launch_sampler_prepare(st, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], scr,
-                                     sampler_scratch_len(max_N), states + sidx[p]));
+                                     sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling));
   SCS_HIP(hipEventRecord(tev[1], st));
 
   // ---- descriptors and flattened-grid prefixes
@@ -1345,7 +1345,8 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
       SCS_CHECK(launch_fill_scaled_identity(st, d, std::sqrt((double)n * lambdas[j]), mixed, rtmp, beta + n));
       SCS_HIP(hipMemcpy2DAsync(rg, ldt * es, rtmp, d * es, d * es, d, hipMemcpyDeviceToDevice, st));
     }
-    SCS_CHECK(launch_sampler_prepare(st, beta, N, cum_all + (int64_t)j * N, scr, sampler_scratch_len(N), st0));
+    SCS_CHECK(launch_sampler_prepare(st, beta, N, cum_all + (int64_t)j * N, scr, sampler_scratch_len(N), st0,
+                                     o.uniform_sampling));
     for (int r = 1; r < ny; ++r)
       SCS_HIP(hipMemcpyAsync(st0 + r, st0, sizeof(SolveState), hipMemcpyDeviceToDevice, st));
   }

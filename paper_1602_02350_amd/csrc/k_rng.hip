@@ -65,8 +65,9 @@ __global__ void beta_stats_partial(const float* beta, int64_t N, double* part) {
 }
 
 // Quantize to W_i = max(1, rint(beta_i * scale)) (0 for beta_i = 0) and scan one tile (inclusive).
+// uniform: every component gets weight 1 (q_i = 1/N) while the sum of beta still goes to the state
 __global__ void quantize_scan_tile(const float* beta, int64_t N, const double* part, int nparts, uint64_t* cum,
-                                   uint64_t* tile_sum, SolveState* state) {
+                                   uint64_t* tile_sum, SolveState* state, int uniform) {
   __shared__ double s_scale;
   __shared__ uint64_t s_warp[kScanThreads / 64];
   if (threadIdx.x == 0) {
@@ -92,7 +93,9 @@ __global__ void quantize_scan_tile(const float* beta, int64_t N, const double* p
     uint64_t wq = 0;
     if (i < N) {
       double b = (double)beta[i];
-      if (b > 0.0) {
+      if (uniform) {
+        wq = 1ull;
+      } else if (b > 0.0) {
         double r = rint(b * scale);
         wq = r < 1.0 ? 1ull : (uint64_t)r;
       }
@@ -241,7 +244,7 @@ int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out) {
 int64_t sampler_scratch_len(int64_t N) { return 2 * kStatBlocks + cdiv(N, kScanTile) + 1; }
 
 int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
-                           int64_t scratch_len, SolveState* state) {
+                           int64_t scratch_len, SolveState* state, int uniform) {
   if (N <= 0) return SCS_EINVAL;
   if (scratch_len < sampler_scratch_len(N)) return SCS_EINVAL;
   double* part = scratch;
@@ -250,7 +253,7 @@ int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_
   beta_stats_partial<<<kStatBlocks, 256, 0, st>>>(beta, N, part);
   SCS_HIP(hipGetLastError());
   quantize_scan_tile<<<dim3((unsigned)ntiles), dim3(kScanThreads), 0, st>>>(beta, N, part, kStatBlocks, cum, tiles,
-                                                                            state);
+                                                                            state, uniform);
   SCS_HIP(hipGetLastError());
   scan_tile_sums<<<1, 256, 0, st>>>(tiles, ntiles);
   SCS_HIP(hipGetLastError());

@@ -157,8 +157,9 @@ constexpr int kMaxBackoffs = 6;  // a further rejected snapshot ends the solve w
 // ---------------------------------------------------------------- launchers (defined in the .hip files)
 // rng
 int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out);
+// uniform != 0: q_i = 1/N for every component instead of q_i proportional to beta_i
 int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
-                           int64_t scratch_len, SolveState* state);
+                           int64_t scratch_len, SolveState* state, int uniform = 0);
 int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
                   int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state);
 int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,

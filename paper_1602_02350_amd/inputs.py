@@ -13,7 +13,7 @@ Recipe (row-major, one instance per row, X is n x d):
   * Omega ~ N(0,1)^{d x l} for the range finder.
 Spectra are power laws spec_j = j^{-alpha} (j = 1..d), optionally with a floor.
 
-The synthetic workload of the paper's experiments (Sec. 5) is drawn differently: X has exactly
+The synthetic workload of the paper's experiments (Sec. 6) is drawn differently: X has exactly
 the singular values q^{-alpha} (q = 1..d) with uniformly random singular vectors (X = V diag(s) U^T,
 V an n x d matrix with orthonormal columns from the QR of a Gaussian matrix, U Haar), every example
 (row) is then scaled to unit norm, and y = X w* + z with w* ~ N(0, I_d), z ~ N(0, 0.1).
@@ -172,7 +172,7 @@ WORKLOADS = {
     # lambda ~ logU[1e-6, 1e-3], k = floor(d / 16); BF16 rows in the inner loop.
     "batch256_uneven": dict(nprob=256, n_lo=1000, n_hi=50000, d_lo=64, d_hi=512, a_lo=1.0, a_hi=2.5,
                             lam_lo=1e-6, lam_hi=1e-3, b=64, eps=1e-6, floor=0.0),
-    # the paper's synthetic data (Sec. 5): 20000 unit-norm examples in d = 5000 with singular values
+    # the paper's synthetic data (Sec. 6): 20000 unit-norm examples in d = 5000 with singular values
     # 1/q (linear decay) and 1/q^2 (quadratic decay), lambda = 1e-8, k = 30
     "synth_linear_n20000_d5000": dict(n=20000, d=5000, alpha=1.0, lam=1e-8, k=30, b=64, eps=1e-6,
                                       spectral_rows=True),

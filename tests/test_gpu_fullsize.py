@@ -5,7 +5,7 @@ at a random point and the closed-form optimum. Each stage's error against the or
 (pytest -s) and bounded by what its arithmetic allows:
   * sketch: |lam~_gpu - lam~_orc| <= 8 u_eff lam~_1 with u_eff = 2^-24 sqrt(d) (FP32 GEMMs) or 2^-8
     (BF16 GEMMs), the two preconditioners agree on random probes, and the average condition
-    number they achieve (Sec. 4.2) agrees within 1 %; the largest principal angle is printed;
+    number they achieve (Sec. 5.2) agrees within 1 %; the largest principal angle is printed;
   * rows: each x~_i close to P^{-1/2} x_i formed in FP64 from the GPU's own U~ and lam~ (this
     isolates the apply arithmetic): within 8 u_eff in FP32; with BF16 GEMM inputs within
     2^-8 (4 ||x_i|| / (s ||x~_i||) + 1), the cancellation of x_i / s by the low-rank term;
@@ -66,7 +66,7 @@ def test_sketch_stage(ctx, full):
     V = np.random.default_rng(0).standard_normal((d, 8))
     perr = _rel(Pg @ V, Po @ V)
     # largest principal angle between the two k-dimensional subspaces, and the average condition
-    # number each preconditioner achieves on C + lambda I (Sec. 4.2) next to that of C + lambda I
+    # number each preconditioner achieves on C + lambda I (Sec. 5.2) next to that of C + lambda I
     sv = np.linalg.svd(Uo.T @ U64.cpu().numpy(), compute_uv=False)
     sin_max = float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
     H = full.setdefault("H", ridge.hessian(X64, cfg["lam"]))

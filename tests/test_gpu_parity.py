@@ -217,7 +217,7 @@ def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16):
 # ------------------------------------------------------------------ the paper's synthetic data
 @pytest.mark.parametrize("alpha", [1.0, 2.0])
 def test_papers_synthetic_data_tracks_the_oracle(ctx, alpha):
-    """The experiments' synthetic regression (Sec. 5: singular values 1/q or 1/q^2, unit-norm examples,
+    """The experiments' synthetic regression (Sec. 6: singular values 1/q or 1/q^2, unit-norm examples,
     lambda = 1e-8, k = 30) at n = 6000, d = 4200, wider than the 4096 entries the P^{-1/2} apply stages
     in LDS, so it runs the unstaged path. Same Omega and index stream as the oracle: after three epochs
     the GPU's distance to w* matches the oracle's trajectory and its suboptimality."""
@@ -255,6 +255,31 @@ def test_solve_with_injected_randomness_tracks_the_oracle(ctx):
     ws = ridge.closed_form(X64, y64, cfg["lam"])
     assert rel(host(res.w) - ws, wo - ws) < 2e-2      # same trajectory to FP32 accuracy of the sketch
     assert abs(res.report["eta"] - info["eta"]) <= 1e-4 * info["eta"]
+
+
+@pytest.mark.parametrize("k", [10, 0])
+def test_uniform_sampling_tracks_the_oracle(ctx, k):
+    """q_i = 1/(n+d) (the original SVRG's sampling, Sec. 4.2) instead of q_i proportional to beta_i: with
+    the same Omega and index stream the GPU solve follows the oracle's uniform-sampling trajectory."""
+    cfg = inputs.WORKLOADS["small_n2000_d100"]
+    P = inputs.make_ridge(cfg["n"], cfg["d"], cfg["alpha"], cfg["lam"], seed=inputs.BASE_SEED + 3)
+    n, d, b = cfg["n"], cfg["d"], cfg["b"]
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 4)
+    m, S, c = n // b, 4, 1.0
+    idx = inputs.index_stream(n + d, S * m * b, seed=78).reshape(S, -1)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, omega=dev(Om) if k else None,
+                         indices=dev(idx, torch.int32), steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS,
+                         step_scale=c, uniform_sampling=1)
+    assert res.status == binding.OK
+    Pm, _, _ = svrg.preconditioner_from_sketch(X64, cfg["lam"], k, Om.T.astype(np.float64))
+    comp = precond.Components(X64, y64, cfg["lam"], Pm)
+    eta = c / svrg.beta_hat(comp)
+    wt, _ = svrg.svrg(comp, np.zeros(d), m, eta, S, b, lambda s: idx[s], q=np.full(n + d, 1.0 / (n + d)))
+    wo = Pm @ wt
+    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    assert rel(host(res.w) - ws, wo - ws) < 2e-2
+    assert abs(res.report["eta"] - eta) <= 1e-4 * eta
 
 
 @pytest.mark.parametrize("k,mixed", [(10, False), (0, False), (10, True)])

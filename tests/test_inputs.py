@@ -1,4 +1,4 @@
-"""The paper's synthetic workload generator (Sec. 5): planted singular values, unit-norm examples and
+"""The paper's synthetic workload generator (Sec. 6): planted singular values, unit-norm examples and
 the label model, checked against their definitions."""
 import numpy as np
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's preconditioner and n+d components (Sec. 4 and the appendix)."""
+"""Pins of the oracle's preconditioner and n+d components (Sec. 5 and the appendix)."""
 import numpy as np
 import pytest
 
@@ -42,7 +42,7 @@ def test_exact_preconditioner_spectrum_random(problem):
 
 
 def test_whitening_is_optimal(problem):
-    """k = d gives P = C + lam I, P^{-1/2}(C+lam I)P^{-1/2} = I and kappa~ = d (Sec. 1, Sec. 4.2)."""
+    """k = d gives P = C + lam I, P^{-1/2}(C+lam I)P^{-1/2} = I and kappa~ = d (Sec. 1, Sec. 5.2)."""
     C = ridge.correlation(problem.X)
     d = C.shape[0]
     Pm, _, _ = precond.exact_preconditioner(C, problem.lam, d)
@@ -52,7 +52,7 @@ def test_whitening_is_optimal(problem):
 
 
 def test_change_of_variables(problem):
-    """Lt(w~) = L(P^{-1/2} w~) for the n+d components (Eq. (condRidge), Sec. 4.1)."""
+    """Lt(w~) = L(P^{-1/2} w~) for the n+d components (Eq. (condRidge), Sec. 5.1)."""
     _, _, Pm = _sketched(problem, 6)
     comp = precond.Components(problem.X, problem.y, problem.lam, Pm)
     rng = np.random.default_rng(5)
@@ -66,7 +66,7 @@ def test_change_of_variables(problem):
 
 
 def test_components_average_to_objective():
-    """(1/(n+d)) sum_i l_i(w) = Lt(w), summing the components one by one (Sec. 4.1)."""
+    """(1/(n+d)) sum_i l_i(w) = Lt(w), summing the components one by one (Sec. 5.1)."""
     P = inputs.make_ridge(25, 6, 1.0, 1e-2, seed=22, dtype=np.float64)
     _, _, Pm = _sketched(P, 2)
     comp = precond.Components(P.X, P.y, P.lam, Pm)

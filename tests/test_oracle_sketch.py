@@ -1,4 +1,4 @@
-"""Pins of the oracle's randomized sketch (Alg. 2; Sec. 4.4 lemmas)."""
+"""Pins of the oracle's randomized sketch (Alg. 2; Sec. 5.4 lemmas)."""
 import numpy as np
 import pytest
 
@@ -72,7 +72,7 @@ def test_deeper_krylov_space_is_at_least_as_accurate():
 @pytest.mark.parametrize("alpha,lam,k", [(2.0, 1e-4, 10), (1.5, 1e-5, 20)])
 def test_sketch_quality_bounds_hold_in_most_seeds(alpha, lam, k):
     """Per-vector bound |lam~_i - lam_i| <= eps' lam_{k+1} (Eq. (perVec), eps' = 1/2) and the three
-    eigenvalue bounds of Sec. 4.4 (lambda_1 <= 17; lambda_i <= 2(lam_i+lam)/(lam_k+lam) for i > k;
+    eigenvalue bounds of Sec. 5.4 (lambda_1 <= 17; lambda_i <= 2(lam_i+lam)/(lam_k+lam) for i > k;
     lambda_d >= lam/(19(lam_k+lam))) hold with probability >= 9/10; checked over 20 seeds."""
     P = inputs.make_ridge(1500, 100, alpha, lam, seed=35, dtype=np.float64)
     C = ridge.correlation(P.X)

@@ -113,3 +113,27 @@ def test_last_iterate_snapshot_option():
     assert not np.allclose(w_avg, w_last)
     ws = ridge.closed_form(P.X, P.y, P.lam)
     assert ridge.suboptimality(P.X, P.lam, w_last, ws) < ridge.suboptimality(P.X, P.lam, np.zeros(5), ws)
+
+
+def test_uniform_sampling_is_the_original_svrg_step():
+    """With q_i = 1/N the estimator is grad l_i(w) - grad l_i(w~) + grad F(w~), the original SVRG step
+    (Sec. 4.2): one epoch of b = 1 steps written out here from the component gradients alone."""
+    P, comp = _tiny(seed=43, n=7, d=3, lam=0.2)
+    N, m, eta = comp.N, 6, 0.05
+    idx = np.array([3, 0, 8, 5, 9, 1])
+    w0 = np.array([0.3, -0.2, 0.1])
+    w_ref, acc = w0.copy(), np.zeros(3)
+    mu = sum(comp.grad(i, w0) for i in range(N)) / N
+    for i in idx:
+        w_ref = w_ref - eta * (comp.grad(i, w_ref) - comp.grad(i, w0) + mu)
+        acc += w_ref
+    wb, _ = svrg.svrg(comp, w0, m, eta, 1, 1, lambda s: idx, q=np.full(N, 1.0 / N))
+    assert np.allclose(wb, acc / m, rtol=1e-13, atol=1e-15)
+
+
+def test_uniform_sampling_estimator_is_unbiased():
+    P, comp = _tiny(seed=44)
+    w, wb = np.array([0.4, -1.0, 0.2]), np.array([-0.3, 0.5, 0.1])
+    vbar = comp.full_gradient(wb)
+    mean = sum(comp.grad(i, w) - comp.grad(i, wb) + vbar for i in range(comp.N)) / comp.N
+    assert np.allclose(mean, comp.full_gradient(w), rtol=1e-12, atol=1e-14)
