@@ -35,6 +35,97 @@ __device__ __forceinline__ double block_sum_d(double v, double* sred) {
 // independent loads in flight.
 // emit(j, value) receives out_j.
 constexpr int kVsMax = 4096;
+constexpr int kApplyR = 4;  // rows of UT per wave in phase 1
+
+// Phase 1 with float4 loads for rows i0 .. i0 + 3 (one wave; d a multiple of 4, UT 16-byte aligned):
+// tb[i] = (sum_j UT[i][j] v_j) (1/sqrt(lam_i + lambda) - 1/s). Each lane takes the column quads
+// lane, lane + 64, ... in order, four per pass with all 16 float4 loads issued before the first is
+// used (clamped indices keep them unconditional); the lanes' sums are then added across the wave.
+template <typename VJ>
+__device__ __forceinline__ void pmhalf_rows_v4(const float* __restrict__ UT, const double* __restrict__ lam, int k,
+                                               int64_t d, double lambda, double s, int i0, int lane, VJ vj,
+                                               double* tb) {
+  constexpr int R = kApplyR, S = 4;
+  const int d4 = (int)(d >> 2);
+  double acc[R] = {0.0, 0.0, 0.0, 0.0};
+  for (int jb = 0; jb < d4; jb += 64 * S) {
+    float4 u[R][S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int j4 = jb + lane + 64 * q;
+      const int jc = j4 < d4 ? j4 : d4 - 1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int ir = i0 + r < k ? i0 + r : k - 1;
+        u[r][q] = reinterpret_cast<const float4*>(UT + (int64_t)ir * d)[jc];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int j4 = jb + lane + 64 * q;
+      if (j4 < d4) {
+        const double v0 = vj(4 * j4), v1 = vj(4 * j4 + 1), v2 = vj(4 * j4 + 2), v3 = vj(4 * j4 + 3);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (i0 + r < k)
+            acc[r] += (double)u[r][q].x * v0 + (double)u[r][q].y * v1 + (double)u[r][q].z * v2 +
+                      (double)u[r][q].w * v3;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double t = wave_sum_d_fast(acc[r]);
+    if (lane == 0 && i0 + r < k) tb[i0 + r] = t * (1.0 / sqrt(fmax(lam[i0 + r], 0.0) + lambda) - 1.0 / s);
+  }
+}
+
+// Phase 2 with float4 loads for column quad j4: four consecutive lanes (part = lane & 3) each sum
+// every fourth row of UT, in groups of 16 rows whose loads are issued together, and the four parts
+// are combined as (p0 + p1) + (p2 + p3); the lane with part 0 emits out_j = v_j/s + the sum for the
+// quad's four columns. Every lane of the wave must call it (j4 >= d4 contributes nothing).
+template <typename VJ, typename EMIT>
+__device__ __forceinline__ void pmhalf_quad_v4(const float* __restrict__ UT, const double* tb, int k, int64_t d,
+                                               double s, int j4, int part, VJ vj, EMIT emit) {
+  const int d4 = (int)(d >> 2);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (j4 < d4) {
+    constexpr int NB = 16;
+    for (int ib = part; ib < k; ib += 4 * NB) {
+      float4 u[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int i = ib + 4 * q < k ? ib + 4 * q : k - 1;
+        u[q] = reinterpret_cast<const float4*>(UT + (int64_t)i * d)[j4];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (ib + 4 * q < k) {
+          const double t = tb[ib + 4 * q];
+          a0 += (double)u[q].x * t;
+          a1 += (double)u[q].y * t;
+          a2 += (double)u[q].z * t;
+          a3 += (double)u[q].w * t;
+        }
+      }
+    }
+  }
+  a0 += __shfl_xor(a0, 1);
+  a1 += __shfl_xor(a1, 1);
+  a2 += __shfl_xor(a2, 1);
+  a3 += __shfl_xor(a3, 1);
+  a0 += __shfl_xor(a0, 2);
+  a1 += __shfl_xor(a1, 2);
+  a2 += __shfl_xor(a2, 2);
+  a3 += __shfl_xor(a3, 2);
+  if (j4 < d4 && part == 0) {
+    emit(4 * j4, vj(4 * j4) / s + a0);
+    emit(4 * j4 + 1, vj(4 * j4 + 1) / s + a1);
+    emit(4 * j4 + 2, vj(4 * j4 + 2) / s + a2);
+    emit(4 * j4 + 3, vj(4 * j4 + 3) / s + a3);
+  }
+}
+
 template <typename VIN, typename EMIT>
 __device__ __forceinline__ void pmhalf_apply_block(const float* __restrict__ UT, const double* __restrict__ lam, int k, int64_t d,
                                    double lambda, const VIN* __restrict__ v, double* vs, double* tbuf, EMIT emit) {
@@ -55,47 +146,20 @@ __device__ __forceinline__ void pmhalf_apply_block(const float* __restrict__ UT,
   const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
   const bool v4 = (dd & 3) == 0 && (reinterpret_cast<uintptr_t>(UT) & 15) == 0;
   const int d4 = dd >> 2;
-  constexpr int R = 4;  // rows of UT per wave and pass
+  constexpr int R = kApplyR;  // rows of UT per wave and pass
   const int nwave = (int)blockDim.x >> 6;
   for (int i0 = wave * R; i0 < k; i0 += nwave * R) {
-    double acc[R] = {0.0, 0.0, 0.0, 0.0};
     if (v4) {
-      // S column quads per lane and pass, all R x S loads issued before the first is used (clamped
-      // indices keep them unconditional); the sums run in the order j4 = lane, lane + 64, ...
-      constexpr int S = 4;
-      for (int jb = 0; jb < d4; jb += 64 * S) {
-        float4 u[R][S];
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-          const int j4 = jb + lane + 64 * q;
-          const int jc = j4 < d4 ? j4 : d4 - 1;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int ir = i0 + r < k ? i0 + r : k - 1;
-            u[r][q] = reinterpret_cast<const float4*>(UT + (int64_t)ir * d)[jc];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-          const int j4 = jb + lane + 64 * q;
-          if (j4 < d4) {
-            const double v0 = vj(4 * j4), v1 = vj(4 * j4 + 1), v2 = vj(4 * j4 + 2), v3 = vj(4 * j4 + 3);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-              if (i0 + r < k)
-                acc[r] += (double)u[r][q].x * v0 + (double)u[r][q].y * v1 + (double)u[r][q].z * v2 +
-                          (double)u[r][q].w * v3;
-          }
-        }
-      }
-    } else {
+      pmhalf_rows_v4(UT, lam, k, d, lambda, s, i0, lane, vj, tbuf);
+      continue;
+    }
+    double acc[R] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-      for (int j = lane; j < dd; j += 64) {
-        const double x = vj(j);
+    for (int j = lane; j < dd; j += 64) {
+      const double x = vj(j);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (i0 + r < k) acc[r] += (double)UT[(int64_t)(i0 + r) * d + j] * x;
-      }
+      for (int r = 0; r < R; ++r)
+        if (i0 + r < k) acc[r] += (double)UT[(int64_t)(i0 + r) * d + j] * x;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -105,49 +169,10 @@ __device__ __forceinline__ void pmhalf_apply_block(const float* __restrict__ UT,
   }
   __syncthreads();
   if (v4) {
-    // four threads per column quad, each summing every fourth row of UT, then combined in order
+    // four threads per column quad
     const int part = threadIdx.x & 3;
-    for (int j4base = 0; j4base < d4; j4base += (int)blockDim.x >> 2) {
-      const int j4 = j4base + ((int)threadIdx.x >> 2);
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      if (j4 < d4) {
-        // rows part, part + 4, ... in groups of 16, the group's loads issued together
-        constexpr int NB = 16;
-        for (int ib = part; ib < k; ib += 4 * NB) {
-          float4 u[NB];
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            const int i = ib + 4 * q < k ? ib + 4 * q : k - 1;
-            u[q] = reinterpret_cast<const float4*>(UT + (int64_t)i * d)[j4];
-          }
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            if (ib + 4 * q < k) {
-              const double t = tbuf[ib + 4 * q];
-              a0 += (double)u[q].x * t;
-              a1 += (double)u[q].y * t;
-              a2 += (double)u[q].z * t;
-              a3 += (double)u[q].w * t;
-            }
-          }
-        }
-      }
-      // lanes 4q .. 4q+3 hold the four parts of one quad: (p0 + p1) + (p2 + p3)
-      a0 += __shfl_xor(a0, 1);
-      a1 += __shfl_xor(a1, 1);
-      a2 += __shfl_xor(a2, 1);
-      a3 += __shfl_xor(a3, 1);
-      a0 += __shfl_xor(a0, 2);
-      a1 += __shfl_xor(a1, 2);
-      a2 += __shfl_xor(a2, 2);
-      a3 += __shfl_xor(a3, 2);
-      if (j4 < d4 && part == 0) {
-        emit(4 * j4, vj(4 * j4) / s + a0);
-        emit(4 * j4 + 1, vj(4 * j4 + 1) / s + a1);
-        emit(4 * j4 + 2, vj(4 * j4 + 2) / s + a2);
-        emit(4 * j4 + 3, vj(4 * j4 + 3) / s + a3);
-      }
-    }
+    for (int j4base = 0; j4base < d4; j4base += (int)blockDim.x >> 2)
+      pmhalf_quad_v4(UT, tbuf, k, d, s, j4base + ((int)threadIdx.x >> 2), part, vj, emit);
   } else {
     for (int j = threadIdx.x; j < dd; j += blockDim.x) {
       double acc = 0.0;
@@ -228,6 +253,24 @@ __global__ __launch_bounds__(256) void grad_colreduce_batched_kernel(const Batch
   colreduce_body(q.gpart, q.nwg, q.d, q.g64, blockIdx.x - cb_prefix[p], blockIdx.y);
 }
 
+// g_j = (1/n) sum of the grows partial rows of column j (fixed order) + lambda w_j
+__device__ __forceinline__ double grad_entry(const double* g_in, int grows, int64_t j, int64_t d, int64_t n,
+                                             double lambda, const float* w) {
+  double acc = 0.0;
+  if (grows == kColSplit) {
+#pragma unroll
+    for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
+  } else {
+    for (int q = 0; q < grows; ++q) acc += g_in[(int64_t)q * d + j];
+  }
+  return acc / (double)n + lambda * (double)w[j];
+}
+
+__device__ __forceinline__ int finalize_tail(const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w,
+                                             double lambda, const double* lam, int k, float* mu, const double* tmp,
+                                             SolveState* state, int stop_rule, double eps, double f_star,
+                                             float* wt_cur, const float* wt_prev, int first);
+
 // Finish of the gradient at the snapshot for one problem (one workgroup); returns the action taken
 // (0 continue, 1 converged, 2 diverged and restored, 3 non-finite input), the same in every thread.
 __device__ __forceinline__ int finalize_body(const double* g_in, int grows, const double* rsq_part, int nwg, int64_t n, int64_t d,
@@ -236,23 +279,24 @@ __device__ __forceinline__ int finalize_body(const double* g_in, int grows, cons
                              const float* wt_prev, int first) {
   __shared__ double tbuf[256];
   __shared__ double vs[kVsMax];
-  __shared__ double sred[kVecWaves];
-  __shared__ int s_action;
   // g = (1/n) sum of the partial rows (fixed order) + lambda w, written over the first row of g2
   double* g = const_cast<double*>(g_in);
-  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
-    double acc = 0.0;
-    if (grows == kColSplit) {
-#pragma unroll
-      for (int q = 0; q < kColSplit; ++q) acc += g_in[(int64_t)q * d + j];
-    } else {
-      for (int q = 0; q < grows; ++q) acc += g_in[(int64_t)q * d + j];
-    }
-    g[j] = acc / (double)n + lambda * (double)w[j];
-  }
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) g[j] = grad_entry(g_in, grows, j, d, n, lambda, w);
   __syncthreads();
   // mu = P^{-1/2} g
   pmhalf_apply_block<double>(UT, lam, k, d, lambda, g, vs, tbuf, [&](int j, double x) { tmp[j] = x; });
+  return finalize_tail(rsq_part, nwg, n, d, w, lambda, lam, k, mu, tmp, state, stop_rule, eps, f_star, wt_cur,
+                       wt_prev, first);
+}
+
+// The rest of the finish once tmp holds mu = P^{-1/2} g: norms, objective, stop rules, the action
+// taken (same in every thread), and mu in FP32 or the restored snapshot.
+__device__ __forceinline__ int finalize_tail(const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w,
+                                             double lambda, const double* lam, int k, float* mu, const double* tmp,
+                                             SolveState* state, int stop_rule, double eps, double f_star,
+                                             float* wt_cur, const float* wt_prev, int first) {
+  __shared__ double sred[kVecWaves];
+  __shared__ int s_action;
   double gn = 0.0, wn = 0.0;
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
     double m = tmp[j];
@@ -345,6 +389,74 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(cons
     const int before = atomicAdd(done_count, 1);
     if (before + 1 == nprob && host_stop) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
+}
+
+// The P^{-1/2} apply of a single problem over several workgroups, for large k d: the same per-row and
+// per-quad arithmetic as pmhalf_apply_block (so the results are bit-identical), with phase 1 on
+// ceil(k / 4) one-wave workgroups and phase 2 on 256-thread workgroups of 64 column quads, so that
+// U~^T streams through many CUs instead of one. tb (k doubles, global) carries the coefficients.
+constexpr int64_t kSplitApplyMin = int64_t(1) << 17;  // k d from which the split kernels are used
+
+bool split_apply(const float* UT, int k, int64_t d) {
+  return k > 0 && (d & 3) == 0 && (reinterpret_cast<uintptr_t>(UT) & 15) == 0 && (int64_t)k * d >= kSplitApplyMin;
+}
+
+template <typename VIN>
+__global__ __launch_bounds__(64) void pmhalf_rows_kernel(const float* UT, const double* lam, int k, int64_t d,
+                                                         double lambda, const VIN* v, double* tb,
+                                                         const SolveState* state) {
+  if (state && state->done) return;
+  const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  pmhalf_rows_v4(UT, lam, k, d, lambda, s, (int)blockIdx.x * kApplyR, (int)threadIdx.x & 63,
+                 [&](int j) { return (double)v[j]; }, tb);
+}
+
+// phase 2 of the premap: w = P^{-1/2} w~ (and the trace row)
+__global__ __launch_bounds__(256) void premap_cols_kernel(const float* UT, const double* lam, int k, int64_t d,
+                                                          double lambda, const float* wt, const double* tb, float* w,
+                                                          float* trace_row, const SolveState* state) {
+  if (state && state->done) return;
+  const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  pmhalf_quad_v4(UT, tb, k, d, s, (int)blockIdx.x * 64 + ((int)threadIdx.x >> 2), (int)threadIdx.x & 3,
+                 [&](int j) { return (double)wt[j]; }, [&](int j, double x) {
+                   const float f = (float)x;
+                   w[j] = f;
+                   if (trace_row) trace_row[j] = f;
+                 });
+}
+
+// gradient finish, step 1: g = (1/n) sum of the partial rows + lambda w over the first row of g2
+__global__ __launch_bounds__(256) void grad_sum_kernel(double* g2, int64_t n, int64_t d, const float* w, double lambda,
+                                                       const SolveState* state) {
+  if (state->done) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < d) g2[j] = grad_entry(g2, kColSplit, j, d, n, lambda, w);
+}
+
+// step 3: mu = P^{-1/2} g into tmp
+__global__ __launch_bounds__(256) void grad_mu_cols_kernel(const float* UT, const double* lam, int k, int64_t d,
+                                                           double lambda, const double* g, const double* tb,
+                                                           double* tmp, const SolveState* state) {
+  if (state->done) return;
+  const double s = sqrt(fmax(lam[k - 1], 0.0) + lambda);
+  pmhalf_quad_v4(UT, tb, k, d, s, (int)blockIdx.x * 64 + ((int)threadIdx.x >> 2), (int)threadIdx.x & 3,
+                 [&](int j) { return g[j]; }, [&](int j, double x) { tmp[j] = x; });
+}
+
+// step 4: the finish once tmp holds mu (one workgroup), with the host flag of grad_finalize_kernel
+__global__ __launch_bounds__(kVecThreads) void grad_tail_kernel(
+    const double* rsq_part, int nwg, int64_t n, int64_t d, const float* w, double lambda, const double* lam, int k,
+    float* mu, const double* tmp, SolveState* state, int stop_rule, double eps, double f_star, float* wt_cur,
+    const float* wt_prev, int first, int* host_stop) {
+  if (state->done) {
+    if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
+  const int action = finalize_tail(rsq_part, nwg, n, d, w, lambda, lam, k, mu, tmp, state, stop_rule, eps, f_star,
+                                   wt_cur, wt_prev, first);
+  if (host_stop && threadIdx.x == 0)
+    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 0, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void rownorm_kernel(const float* X, int64_t n, int64_t d, int64_t ldx, float* out) {
@@ -484,6 +596,14 @@ int launch_premap(hipStream_t st, const float* UT, const float* U, const double*
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,
                   const SolveState* state) {
   (void)U;
+  if (split_apply(UT, k, d)) {  // tmp (d >= k doubles) carries the coefficients between the two phases
+    pmhalf_rows_kernel<float><<<(unsigned)cdiv(k, kApplyR), 64, 0, st>>>(UT, lam, k, d, lambda, wt, tmp, state);
+    SCS_HIP(hipGetLastError());
+    premap_cols_kernel<<<(unsigned)cdiv(d >> 2, 64), 256, 0, st>>>(UT, lam, k, d, lambda, wt, tmp, w, trace_row,
+                                                                    state);
+    SCS_HIP(hipGetLastError());
+    return SCS_OK;
+  }
   premap_kernel<<<1, kVecThreads, 0, st>>>(UT, lam, k, d, lambda, wt, w, trace_row, tmp, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
@@ -496,6 +616,20 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
   grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
   SCS_HIP(hipGetLastError());
   (void)U;
+  if (split_apply(UT, k, d)) {  // g over row 0 of g_tmp, the coefficients in row 1, mu in tmp
+    grad_sum_kernel<<<(unsigned)cdiv(d, 256), 256, 0, st>>>(g_tmp, n, d, w, lambda, state);
+    SCS_HIP(hipGetLastError());
+    pmhalf_rows_kernel<double><<<(unsigned)cdiv(k, kApplyR), 64, 0, st>>>(UT, lam, k, d, lambda, g_tmp, g_tmp + d,
+                                                                         state);
+    SCS_HIP(hipGetLastError());
+    grad_mu_cols_kernel<<<(unsigned)cdiv(d >> 2, 64), 256, 0, st>>>(UT, lam, k, d, lambda, g_tmp, g_tmp + d, tmp,
+                                                                     state);
+    SCS_HIP(hipGetLastError());
+    grad_tail_kernel<<<1, kVecThreads, 0, st>>>(rsq_part, nwg, n, d, w, lambda, lam, k, mu, tmp, state, stop_rule,
+                                                eps, f_star, wt_cur, wt_prev, first, host_stop);
+    SCS_HIP(hipGetLastError());
+    return SCS_OK;
+  }
   grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp,
                                                   state, stop_rule, eps, f_star, wt_cur, wt_prev, first, host_stop);
   SCS_HIP(hipGetLastError());
