@@ -395,7 +395,9 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(cons
 // per-quad arithmetic as pmhalf_apply_block (so the results are bit-identical), with phase 1 on
 // ceil(k / 4) one-wave workgroups and phase 2 on 256-thread workgroups of 64 column quads, so that
 // U~^T streams through many CUs instead of one. tb (k doubles, global) carries the coefficients.
-constexpr int64_t kSplitApplyMin = int64_t(1) << 17;  // k d from which the split kernels are used
+// Measured break-even of 14-epoch solves: one workgroup is 1-2 us per epoch faster at k d = 16384
+// (d = 512, k = 32), the split 2.5 us faster at k d = 20000 (d = 1000, k = 20) and 7 us at 50000.
+constexpr int64_t kSplitApplyMin = 20000;  // k d from which the split kernels are used
 
 bool split_apply(const float* UT, int k, int64_t d) {
   return k > 0 && (d & 3) == 0 && (reinterpret_cast<uintptr_t>(UT) & 15) == 0 && (int64_t)k * d >= kSplitApplyMin;
