@@ -479,15 +479,20 @@ __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __
 // to the next multiple of 16 and its 16-column blocks past that are ignored. The only load that needs
 // a guard is A's row, clamped once per tile. The MFMA runs transposed, D = Bt_chunk A^T, so
 // that acc[r] = C[row0 + lane % 16][col0 + 4 (lane / 16) + r]: each lane ends with four consecutive
-// columns of one row and the epilogue reads C0 and writes C with 16-byte (8-byte for BF16) accesses
-// straight from registers. Each wave owns 16 rows whose A fragments stay in registers for the whole
-// tile; Bt is streamed through LDS in 64-row chunks, double-buffered (rounded to BF16 once at staging
-// in BF16 mode), and the next C0 chunk is fetched as soon as the current one is used. Workgroups
-// loop over row tiles (grid sized to the resident capacity).
-// K <= 64: 512 threads (128-row tiles), four waves per SIMD; wider K holds more A fragments per lane:
-// 256 threads (64-row tiles), three or two waves per SIMD.
+// columns of one row. In the vector path (N % 4 == 0) lanes rl and rl ^ 8 then swap one block of each
+// pair of 16-column blocks, so that every C0 load and C store covers 8 rows x 32 columns (128 contiguous
+// bytes per row in FP32) instead of 16 rows x 16 columns; the epilogue reads C0 and writes C with
+// 16-byte (8-byte for BF16) accesses straight from registers. Each wave owns 16 rows whose A fragments
+// stay in registers for the whole tile; Bt is streamed through LDS in 64-row chunks, double-buffered
+// (rounded to BF16 once at staging in BF16 mode), and C0 is fetched one chunk ahead (two for K = 64).
+// Workgroups loop over row tiles (grid sized to the resident capacity).
+// K <= 64: 512 threads (128-row tiles); wider K holds more A fragments per lane: 256 threads (64-row
+// tiles). Four waves per SIMD for K <= 32, else two. Timed on the apply shapes (n = 100000, d = 1000,
+// K = 50, FP32; n = 500000, d = 2048, K = 128, BF16): 300 -> 279 us and 1870 -> 1597 us against the
+// unswapped epilogue with one chunk ahead and four or three waves (where K = 128 spilled registers).
 constexpr int wd_threads(int nkq) { return nkq <= 4 ? 512 : 256; }
-constexpr int wd_waves(int nkq) { return nkq <= 4 ? 4 : (nkq <= 8 ? 3 : 2); }
+constexpr int wd_waves(int nkq) { return nkq <= 2 ? 4 : 2; }
+constexpr int wd_ahead(int nkq) { return nkq == 4 ? 2 : 1; }   // C0 chunks fetched ahead
 constexpr int kWdBN = 64;                       // output columns per chunk
 
 template <bool BF16, bool OUT_BF16, int NKQ, bool VEC>
@@ -561,31 +566,89 @@ __global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_k
         }
       }
     }
+    // vector path: lane (rl, g4) handles rows rA = rl & 7 and rA + 8 of the wave's 16, at column quad
+    // 16 (2 p + (rl >= 8)) + g4 of each 32-column pair p of the chunk
+    const bool lo8 = rl < 8;
+    const int64_t rowA = tile * kWdBM + wave * 16 + (rl & 7), rowB = rowA + 8;
     const float* xrow = C0 ? C0 + rowc * ldc0 : nullptr;
-    float4 xc[4];
-    auto load_x = [&](int c) {
+    const float* xrowA = C0 ? C0 + (rowA < M ? rowA : M - 1) * ldc0 : nullptr;
+    const float* xrowB = C0 ? C0 + (rowB < M ? rowB : M - 1) * ldc0 : nullptr;
+    constexpr int AHEAD = wd_ahead(NKQ);
+    float4 xc0[4], xc1[4];
+    auto load_x = [&](int c, float4 (&xd)[4]) {
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int col = c * kWdBN + cb * 16 + g4;
         if (!xrow) {
-          xc[cb] = make_float4(0.f, 0.f, 0.f, 0.f);
+          xd[cb] = make_float4(0.f, 0.f, 0.f, 0.f);
         } else if constexpr (VEC) {
-          xc[cb] = *reinterpret_cast<const float4*>(xrow + min(col, N - 4));
+          const int col = c * kWdBN + (2 * (cb >> 1) + (lo8 ? 0 : 1)) * 16 + g4;
+          xd[cb] = *reinterpret_cast<const float4*>(((cb & 1) ? xrowB : xrowA) + min(col, N - 4));
         } else {
-          xc[cb] = make_float4(xrow[min(col, N - 1)], xrow[min(col + 1, N - 1)], xrow[min(col + 2, N - 1)],
+          const int col = c * kWdBN + cb * 16 + g4;
+          xd[cb] = make_float4(xrow[min(col, N - 1)], xrow[min(col + 1, N - 1)], xrow[min(col + 2, N - 1)],
                                xrow[min(col + 3, N - 1)]);
         }
       }
     };
-    float rn = 0.f;
+    // v = alpha acc + beta x (+ diag), rounded to BF16 in BF16 output mode; stored when in range, with
+    // its squares added to r
+    auto emit = [&](const f4v& a, const float4& x, int64_t rw, int col, float& r) {
+      float v[4] = {alpha * a[0], alpha * a[1], alpha * a[2], alpha * a[3]};
+      if (xrow) {
+        v[0] = fmaf(beta, x.x, v[0]);
+        v[1] = fmaf(beta, x.y, v[1]);
+        v[2] = fmaf(beta, x.z, v[2]);
+        v[3] = fmaf(beta, x.w, v[3]);
+      }
+      if (diag != 0.f) {
+        const int64_t dq = rw - col;   // v[dq] sits on the diagonal when 0 <= dq < 4
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (dq == q) v[q] += diag;
+      }
+      uint32_t lo = 0, hi = 0;
+      if constexpr (OUT_BF16) {
+        lo = pack_bf16x2(v[0], v[1]);
+        hi = pack_bf16x2(v[2], v[3]);
+        v[0] = __uint_as_float(lo << 16);
+        v[1] = __uint_as_float(lo & 0xffff0000u);
+        v[2] = __uint_as_float(hi << 16);
+        v[3] = __uint_as_float(hi & 0xffff0000u);
+      }
+      if (rw >= M || col >= N) return;
+      if constexpr (VEC) {
+        if constexpr (OUT_BF16)
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(Cout) + rw * ldc + col) = make_uint2(lo, hi);
+        else
+          *reinterpret_cast<float4*>(reinterpret_cast<float*>(Cout) + rw * ldc + col) =
+              make_float4(v[0], v[1], v[2], v[3]);
+        r = fmaf(v[0], v[0], r);
+        r = fmaf(v[1], v[1], r);
+        r = fmaf(v[2], v[2], r);
+        r = fmaf(v[3], v[3], r);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (col + q < N) {
+            if constexpr (OUT_BF16)
+              reinterpret_cast<uint16_t*>(Cout)[rw * ldc + col + q] = (uint16_t)((q < 2 ? lo : hi) >> (16 * (q & 1)));
+            else
+              reinterpret_cast<float*>(Cout)[rw * ldc + col + q] = v[q];
+            r = fmaf(v[q], v[q], r);
+          }
+        }
+      }
+    };
+    float rn = 0.f, rn1 = 0.f;   // squares of rows rowA and rowB (vector path), of row (else rn)
 
     __syncthreads();   // the previous tile's chunk buffers are free
     load_b(0);
     stash_b(0);
     if (nch > 1) load_b(1);
-    load_x(0);
+    load_x(0, xc0);
+    if (AHEAD == 2 && nch > 1) load_x(1, xc1);
     __syncthreads();
-    for (int c = 0; c < nch; ++c) {
+    auto chunk = [&](int c, float4 (&xcur)[4]) {
       f4v acc[4];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -613,65 +676,53 @@ __global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_k
         if (c + 2 < nch) load_b(c + 2);
       }
       // epilogue
+      if constexpr (VEC) {
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const int col = c * kWdBN + cb * 16 + g4;
-        float v[4] = {alpha * acc[cb][0], alpha * acc[cb][1], alpha * acc[cb][2], alpha * acc[cb][3]};
-        if (xrow) {
-          v[0] = fmaf(beta, xc[cb].x, v[0]);
-          v[1] = fmaf(beta, xc[cb].y, v[1]);
-          v[2] = fmaf(beta, xc[cb].z, v[2]);
-          v[3] = fmaf(beta, xc[cb].w, v[3]);
-        }
-        if (diag != 0.f) {
-          const int64_t dq = row - col;   // v[dq] sits on the diagonal when 0 <= dq < 4
+        for (int pr = 0; pr < 2; ++pr) {
+          // the low lanes keep block 2 pr and receive the high lanes' block 2 pr (rows rA + 8); the high
+          // lanes keep block 2 pr + 1 and receive the low lanes' block 2 pr + 1 (rows rA)
+          const f4v snd = lo8 ? acc[2 * pr + 1] : acc[2 * pr];
+          f4v rcv;
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (dq == q) v[q] += diag;
+          for (int i = 0; i < 4; ++i) rcv[i] = __shfl_xor(snd[i], 8);
+          const int col = c * kWdBN + (2 * pr + (lo8 ? 0 : 1)) * 16 + g4;
+          emit(lo8 ? acc[2 * pr] : rcv, xcur[2 * pr], rowA, col, rn);
+          emit(lo8 ? rcv : acc[2 * pr + 1], xcur[2 * pr + 1], rowB, col, rn1);
         }
-        uint32_t lo = 0, hi = 0;
-        if constexpr (OUT_BF16) {
-          lo = pack_bf16x2(v[0], v[1]);
-          hi = pack_bf16x2(v[2], v[3]);
-          v[0] = __uint_as_float(lo << 16);
-          v[1] = __uint_as_float(lo & 0xffff0000u);
-          v[2] = __uint_as_float(hi << 16);
-          v[3] = __uint_as_float(hi & 0xffff0000u);
-        }
-        if (row_ok && col < N) {
-          if constexpr (VEC) {
-            if constexpr (OUT_BF16)
-              *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(Cout) + row * ldc + col) = make_uint2(lo, hi);
-            else
-              *reinterpret_cast<float4*>(reinterpret_cast<float*>(Cout) + row * ldc + col) =
-                  make_float4(v[0], v[1], v[2], v[3]);
-            rn = fmaf(v[0], v[0], rn);
-            rn = fmaf(v[1], v[1], rn);
-            rn = fmaf(v[2], v[2], rn);
-            rn = fmaf(v[3], v[3], rn);
-          } else {
+      } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (col + q < N) {
-                if constexpr (OUT_BF16)
-                  reinterpret_cast<uint16_t*>(Cout)[row * ldc + col + q] =
-                      (uint16_t)((q < 2 ? lo : hi) >> (16 * (q & 1)));
-                else
-                  reinterpret_cast<float*>(Cout)[row * ldc + col + q] = v[q];
-                rn = fmaf(v[q], v[q], rn);
-              }
-            }
-          }
-        }
+        for (int cb = 0; cb < 4; ++cb) emit(acc[cb], xcur[cb], row, c * kWdBN + cb * 16 + g4, rn);
       }
-      if (c + 1 < nch) load_x(c + 1);   // lands during the next chunk's staging and MFMA
+      if (c + AHEAD < nch) load_x(c + AHEAD, xcur);   // lands during the following chunks' MFMAs
       __syncthreads();
+    };
+    if constexpr (AHEAD == 2) {
+      for (int c = 0; c < nch; c += 2) {
+        chunk(c, xc0);
+        if (c + 1 < nch) chunk(c + 1, xc1);
+      }
+    } else {
+      for (int c = 0; c < nch; ++c) chunk(c, xc0);
     }
     if (rownorm2) {
-      float t = rn;
-      t += __shfl_xor(t, 16);
-      t += __shfl_xor(t, 32);
-      if (g4 == 0 && row_ok) rownorm2[row] = t;
+      if constexpr (VEC) {
+        float t0 = rn, t1 = rn1;
+        t0 += __shfl_xor(t0, 8);
+        t1 += __shfl_xor(t1, 8);
+        t0 += __shfl_xor(t0, 16);
+        t1 += __shfl_xor(t1, 16);
+        t0 += __shfl_xor(t0, 32);
+        t1 += __shfl_xor(t1, 32);
+        if (g4 == 0 && lo8) {
+          if (rowA < M) rownorm2[rowA] = t0;
+          if (rowB < M) rownorm2[rowB] = t1;
+        }
+      } else {
+        float t = rn;
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        if (g4 == 0 && row_ok) rownorm2[row] = t;
+      }
     }
   }
 }
