@@ -155,18 +155,21 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
 // and reads its MFMA fragments straight from global memory into registers, one K chunk ahead
 // (lane (r, g) holds A[row0 + r][k0 + 16 q + 4 g .. +3]); Bt's K chunk (N <= 144 rows) is staged
 // through LDS, double-buffered and rounded to BF16 once in BF16 mode. One barrier per chunk;
-// workgroups loop over 128-row tiles (grid sized to the resident capacity). The last chunk, where
-// K may end inside it, is loaded with guards.
-constexpr int kLrThreads = 512;
-constexpr int kLrBM = 16 * (kLrThreads / 64);
+// workgroups loop over row tiles (grid sized to the resident capacity). The last chunk, where K may
+// end inside it, is loaded with guards.
+// BF16: 512 threads (128-row tiles), four waves per SIMD; FP32: 256 threads (64-row tiles), three waves
+// per SIMD. Timed at n = 100000, K = 1000, N = 55 (FP32): 190 -> 172 us; at n = 500000, K = 2048,
+// N = 133 (BF16) the 512-thread kernel stays fastest (1170 us against 1280-1350 us for 256 threads or
+// two waves per SIMD, although it spills some registers there).
+constexpr int lr_threads(bool bf16) { return bf16 ? 512 : 256; }
+constexpr int lr_waves(bool bf16) { return bf16 ? 4 : 3; }
 
 template <int NB, bool BF16>
-__global__ __launch_bounds__(kLrThreads, 4) void gemm_nt_longk_reg_kernel(const float* __restrict__ A, int64_t M,
-                                                                       int64_t K, int64_t lda,
-                                                                       const float* __restrict__ Bt, int64_t N,
-                                                                       int64_t ldb, float* __restrict__ C,
-                                                                       int64_t ldc, int64_t nst) {
+__global__ __launch_bounds__(lr_threads(BF16), lr_waves(BF16)) void gemm_nt_longk_reg_kernel(
+    const float* __restrict__ A, int64_t M, int64_t K, int64_t lda, const float* __restrict__ Bt, int64_t N,
+    int64_t ldb, float* __restrict__ C, int64_t ldc, int64_t nst) {
   constexpr int KC = BF16 ? 64 : 32;          // K per chunk
+  constexpr int kLrThreads = lr_threads(BF16), kLrBM = 16 * (kLrThreads / 64);
   constexpr int NQ = KC / 16;                  // MFMA K steps per chunk
   constexpr int BN = NB * 16;
   constexpr int LW = KC + 4, LH = KC + 8;      // LDS row strides (floats / BF16 halves)
@@ -852,6 +855,7 @@ template <int NB, bool BF16>
 int longk_reg_launch(hipStream_t st, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt, int64_t N,
                      int64_t ldb, float* C, int64_t ldc, int64_t nst) {
   const void* fn = (const void*)gemm_nt_longk_reg_kernel<NB, BF16>;
+  constexpr int kLrThreads = lr_threads(BF16), kLrBM = 16 * (kLrThreads / 64);
   const int res = resident_blocks(fn, kLrThreads, 0);
   if (res <= 0) {
     set_error("gemm_nt_longk: no resident workgroup capacity reported");
