@@ -186,6 +186,138 @@ __device__ __forceinline__ void grad_partial_body(const float* __restrict__ X, i
   }
 }
 
+// Column-split variant for rows too wide to sit in one wave's registers (d > 2048, 16-byte aligned
+// rows). The four waves of a workgroup share every row: wave q holds columns [256 NCW q, 256 NCW (q + 1))
+// (lane l, chunk c: columns 256 NCW q + 4 (64 c + l) .. + 3). For each row pair the waves' partial dot
+// products meet in LDS (two slots, one barrier per pair) and are added in wave order 0, 1, 2, 3, so all
+// waves hold the same r_i; each wave then accumulates r_i x_i over its own columns (Kahan), and wave 0
+// alone adds r_i^2. The next pair's loads are issued before the current pair is reduced.
+template <int NCW>
+__device__ __forceinline__ void grad_partial_split_body(const float* __restrict__ X, int64_t n, int64_t d,
+                                                        int64_t ldx, const float* __restrict__ y,
+                                                        const float* __restrict__ w, float* __restrict__ part,
+                                                        double* __restrict__ rsq_part, int64_t wg, int64_t nwg) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t rows_per_wg = cdiv(n, nwg);
+  const int64_t r0 = wg * rows_per_wg;
+  const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
+  const int64_t cbase = (int64_t)wave * 256 * NCW;
+
+  float4 wv[NCW];
+  float acc[NCW][4], cmp[NCW][4];
+  bool valid[NCW];
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) {
+    const int64_t col = cbase + 4 * (c * 64 + lane);
+    valid[c] = col < d;   // d % 4 == 0: a quad is wholly inside or outside
+    wv[c] = valid[c] ? make_float4(w[col], w[col + 1], w[col + 2], w[col + 3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[c][v] = cmp[c][v] = 0.f;
+  }
+  double rsq = 0.0;
+  __shared__ float sdot[2][kGradWaves][2];
+  int slot = 0;
+
+  auto load_pair = [&](int64_t rr, float4 (&A)[NCW], float4 (&B)[NCW], float& ya_, float& yb_) {
+    const int64_t ra = rr, rb = rr + 1 < r1 ? rr + 1 : rr;
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+      const int64_t col = cbase + 4 * (c * 64 + lane);
+      if (valid[c]) {
+        vload(X + ra * ldx + col, A[c]);
+        vload(X + rb * ldx + col, B[c]);
+      } else {
+        A[c] = B[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    ya_ = y[ra];
+    yb_ = y[rb];
+  };
+  auto kahan = [&](float r, const float4 (&A)[NCW]) {
+#pragma unroll
+    for (int c = 0; c < NCW; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float t = fmaf(r, comp(A[c], v), -cmp[c][v]);
+        const float s1 = acc[c][v] + t;
+        cmp[c][v] = (s1 - acc[c][v]) - t;
+        acc[c][v] = s1;
+      }
+  };
+  // rows rr and rr + 1 (has_b false: the pair is the block's last row alone)
+  auto reduce_pair = [&](const float4 (&A)[NCW], const float4 (&B)[NCW], float ya, float yb, bool has_b) {
+    float da = 0.f, db = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCW; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        da = fmaf(comp(A[c], v), comp(wv[c], v), da);
+        db = fmaf(comp(B[c], v), comp(wv[c], v), db);
+      }
+    da = warp_sum(da);
+    db = warp_sum(db);
+    if (lane == 0) {
+      sdot[slot][wave][0] = da;
+      sdot[slot][wave][1] = db;
+    }
+    __syncthreads();
+    float sa = sdot[slot][0][0], sb = sdot[slot][0][1];
+#pragma unroll
+    for (int q = 1; q < kGradWaves; ++q) {
+      sa += sdot[slot][q][0];
+      sb += sdot[slot][q][1];
+    }
+    slot ^= 1;   // the other slot was last read before this pair's barrier
+    sa -= ya;
+    sb -= yb;
+    if (wave == 0) rsq += (double)sa * sa + (has_b ? (double)sb * sb : 0.0);
+    kahan(sa, A);
+    if (has_b) kahan(sb, B);
+  };
+
+  if (r0 < r1) {
+    float4 xa[NCW], xb[NCW], na[NCW], nb[NCW];
+    float ya, yb, nya, nyb;
+    int64_t r = r0;   // uniform over the workgroup, so every barrier is reached by all waves
+    load_pair(r, xa, xb, ya, yb);
+    for (;;) {
+      const bool more = r + 2 < r1;
+      if (more) load_pair(r + 2, na, nb, nya, nyb);
+      reduce_pair(xa, xb, ya, yb, r + 1 < r1);
+      r += 2;
+      if (!more) break;
+      const bool more2 = r + 2 < r1;
+      if (more2) load_pair(r + 2, xa, xb, ya, yb);
+      reduce_pair(na, nb, nya, nyb, r + 1 < r1);
+      r += 2;
+      if (!more2) break;
+    }
+  }
+
+  float* out = part + wg * d;
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) {
+    const int64_t col = cbase + 4 * (c * 64 + lane);
+    if (valid[c]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[col + v] = acc[c][v] - cmp[c][v];
+    }
+  }
+  if (wave == 0 && lane == 0) rsq_part[wg] = rsq;
+}
+
+template <int NCW>
+__global__ __launch_bounds__(kGradThreads) void grad_partial_split_kernel(const float* __restrict__ X, int64_t n,
+                                                                          int64_t d, int64_t ldx,
+                                                                          const float* __restrict__ y,
+                                                                          const float* __restrict__ w,
+                                                                          float* __restrict__ part,
+                                                                          double* __restrict__ rsq_part,
+                                                                          const SolveState* state) {
+  if (state && state->done) return;
+  grad_partial_split_body<NCW>(X, n, d, ldx, y, w, part, rsq_part, blockIdx.x, gridDim.x);
+}
+
 template <int VEC, int NCH>
 __global__ __launch_bounds__(kGradThreads) void grad_partial_kernel(const float* __restrict__ X, int64_t n,
                                                                     int64_t d, int64_t ldx,
@@ -215,6 +347,14 @@ template <int VEC, int NCH>
 int launch_t(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, const float* w,
              float* part, double* rsq_part, int nwg, const SolveState* state) {
   grad_partial_kernel<VEC, NCH><<<nwg, kGradThreads, 0, st>>>(X, n, d, ldx, y, w, part, rsq_part, state);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+template <int NCW>
+int launch_split(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, const float* w,
+                 float* part, double* rsq_part, int nwg, const SolveState* state) {
+  grad_partial_split_kernel<NCW><<<nwg, kGradThreads, 0, st>>>(X, n, d, ldx, y, w, part, rsq_part, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
@@ -265,7 +405,11 @@ int launch_grad_partial(hipStream_t st, const float* X, int64_t n, int64_t d, in
     if (nch <= 2) return launch_t<4, 2>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
     if (nch <= 4) return launch_t<4, 4>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
     if (nch <= 8) return launch_t<4, 8>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
-    if (nch <= 20) return launch_t<4, 20>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    // wider rows: columns split over the workgroup's waves (a row per wave spilled registers at d = 5000)
+    if (nch <= 12) return launch_split<3>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 16) return launch_split<4>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 20) return launch_split<5>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
+    if (nch <= 32) return launch_split<8>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);
   } else {
     int64_t nch = cdiv(d, 64);
     if (nch <= 1) return launch_t<1, 1>(st, X, n, d, ldx, y, w, part, rsq_part, nwg, state);

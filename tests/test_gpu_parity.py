@@ -155,10 +155,13 @@ def test_apply_with_padded_rows(ctx):
 
 # ------------------------------------------------------------------ full gradient
 @pytest.mark.parametrize("n,d,k", [(1000, 64, 8), (4099, 257, 20), (1001, 30, 0), (20000, 1000, 50),
-                                   (333, 7, 2), (6000, 2048, 0), (3000, 1100, 120), (1000, 2048, 128)])
+                                   (333, 7, 2), (6000, 2048, 0), (3000, 1100, 120), (1000, 2048, 128),
+                                   (1003, 5000, 30), (2000, 2052, 0), (401, 6000, 0)])
 def test_full_gradient_matches_oracle(ctx, n, d, k):
-    """Where k d >= 20000 (d = 1000 with k = 50, d = 1100 and d = 2048 with k > 0) the P^{-1/2} applies
-    run split over many workgroups."""
+    """Where k d >= 20000 (d = 1000 with k = 50, d >= 1100 with k > 0) the P^{-1/2} applies run split
+    over many workgroups. For d > 2048 the gradient pass splits each row's columns over the waves of a
+    workgroup (2052, 5000 and 6000 columns: 3, 5 and 8 chunks of 256 per wave; n = 1003 leaves a
+    workgroup with an odd number of rows)."""
     P = _problem(n, d, seed=11 + d)
     lam_reg = 1e-4
     wt = inputs.random_vector(d, seed=d)
