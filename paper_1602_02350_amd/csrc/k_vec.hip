@@ -427,12 +427,36 @@ __global__ __launch_bounds__(256) void premap_cols_kernel(const float* UT, const
                  });
 }
 
-// gradient finish, step 1: g = (1/n) sum of the partial rows + lambda w over the first row of g2
-__global__ __launch_bounds__(256) void grad_sum_kernel(double* g2, int64_t n, int64_t d, const float* w, double lambda,
-                                                       const SolveState* state) {
-  if (state->done) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < d) g2[j] = grad_entry(g2, kColSplit, j, d, n, lambda, w);
+// gradient finish, step 1: g = (1/n) sum of the workgroup partial rows + lambda w, 64 columns per
+// workgroup. Wave q forms row group q's sum exactly as colreduce_body does (four row slices, each
+// added in row order, then ((s0 + s1) + s2) + s3), and wave 0 adds the kColSplit group sums in group
+// order and finishes as grad_entry does: g is bit-identical to colreduce followed by grad_entry, in
+// one launch instead of two.
+__global__ __launch_bounds__(64 * kColSplit) void grad_colsum_kernel(const float* part, int nwg, int64_t n, int64_t d,
+                                                                      const float* w, double lambda, double* g,
+                                                                      const SolveState* state) {
+  if (state && state->done) return;
+  __shared__ double sg[kColSplit][64];
+  const int c = threadIdx.x & 63, by = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  const int R = (nwg + kColSplit - 1) / kColSplit;
+  const int r0 = by * R, r1 = r0 + R < nwg ? r0 + R : nwg;
+  double sl[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < d) {
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs) {
+#pragma unroll 4
+      for (int q = r0 + rs; q < r1; q += 4) sl[rs] += (double)part[(int64_t)q * d + j];
+    }
+  }
+  sg[by][c] = ((sl[0] + sl[1]) + sl[2]) + sl[3];
+  __syncthreads();
+  if (by == 0 && j < d) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kColSplit; ++q) acc += sg[q][c];
+    g[j] = acc / (double)n + lambda * (double)w[j];
+  }
 }
 
 // step 3: mu = P^{-1/2} g into tmp
@@ -615,11 +639,9 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
                        const float* w, double lambda, const float* UT, const float* U, const double* lam, int k,
                        float* mu, double* g_tmp, double* tmp, SolveState* state, int stop_rule, double eps,
                        double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
-  grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
-  SCS_HIP(hipGetLastError());
   (void)U;
   if (split_apply(UT, k, d)) {  // g over row 0 of g_tmp, the coefficients in row 1, mu in tmp
-    grad_sum_kernel<<<(unsigned)cdiv(d, 256), 256, 0, st>>>(g_tmp, n, d, w, lambda, state);
+    grad_colsum_kernel<<<(unsigned)cdiv(d, 64), 64 * kColSplit, 0, st>>>(part, nwg, n, d, w, lambda, g_tmp, state);
     SCS_HIP(hipGetLastError());
     pmhalf_rows_kernel<double><<<(unsigned)cdiv(k, kApplyR), 64, 0, st>>>(UT, lam, k, d, lambda, g_tmp, g_tmp + d,
                                                                          state);
@@ -632,6 +654,8 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
     SCS_HIP(hipGetLastError());
     return SCS_OK;
   }
+  grad_colreduce_kernel<<<dim3((unsigned)cdiv(d, 64), kColSplit), dim3(256), 0, st>>>(part, nwg, d, g_tmp, state);
+  SCS_HIP(hipGetLastError());
   grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp,
                                                   state, stop_rule, eps, f_star, wt_cur, wt_prev, first, host_stop);
   SCS_HIP(hipGetLastError());
