@@ -43,14 +43,21 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over it stay scalar
   for (int e = tid; e < l * l; e += nt) A[e] = B[e];
   __syncthreads();
-  for (int j = 0; j + 2 < l; ++j) {
-    const int m = l - j - 1, r0 = j + 1;
+  // sigma of column j = sum of squares below its first sub-diagonal entry; for j + 1 it is gathered
+  // during column j's rank-2 update (lane 0 of each wave updates column j + 1 of its rows) and the
+  // partial sums travel with the update's closing barrier, so a column costs four barriers
+  __shared__ double ssig[kEigThreads / 64];
+  double sig;
+  {
     double part = 0.0;
-    for (int i = 1 + tid; i < m; i += nt) {
-      const double x = A[(r0 + i) * l + j];
+    for (int i = 2 + tid; i < l; i += nt) {
+      const double x = A[i * l];
       part += x * x;
     }
-    const double sig = eig_block_sum(part, sred);
+    sig = eig_block_sum(part, sred);
+  }
+  for (int j = 0; j + 2 < l; ++j) {
+    const int m = l - j - 1, r0 = j + 1;
     const double x0 = A[r0 * l + j];
     double beta = x0, tau = 0.0, scal = 0.0;
     if (sig > 0.0) {
@@ -70,25 +77,48 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
       tau_out[j] = tau;
     }
     __syncthreads();
-    if (tau == 0.0) continue;  // uniform: every thread holds the same tau
+    if (tau == 0.0) {  // uniform: every thread holds the same tau; no update, sigma of j + 1 read directly
+      double part = 0.0;
+      for (int i = 2 + tid; i < m; i += nt) {
+        const double x = A[(r0 + i) * l + r0];
+        part += x * x;
+      }
+      sig = eig_block_sum(part, sred);
+      continue;
+    }
+    // w = tau A v, with lane 0 of each wave adding up w_i v_i over its rows
+    double pw = 0.0;
     for (int i = wave; i < m; i += nwave) {
       double acc = 0.0;
       for (int c = lane; c < m; c += 64) acc += A[(r0 + i) * l + r0 + c] * vv[c];
       acc = wave_sum_d_fast(acc);
-      if (lane == 0) ww[i] = tau * acc;
+      if (lane == 0) {
+        const double wi = tau * acc;
+        ww[i] = wi;
+        pw += wi * vv[i];
+      }
     }
+    if (lane == 0) sred[wave] = pw;
     __syncthreads();
     double pp = 0.0;
-    for (int i = tid; i < m; i += nt) pp += ww[i] * vv[i];
-    const double al = -0.5 * tau * eig_block_sum(pp, sred);
+    for (int q = 0; q < nwave; ++q) pp += sred[q];
+    const double al = -0.5 * tau * pp;
     for (int i = tid; i < m; i += nt) ww[i] += al * vv[i];
     __syncthreads();
+    double ps = 0.0;
     for (int i = wave; i < m; i += nwave) {
       const double vi = vv[i], wi = ww[i];
       double* row = A + (r0 + i) * l + r0;
-      for (int c = lane; c < m; c += 64) row[c] -= vi * ww[c] + wi * vv[c];
+      for (int c = lane; c < m; c += 64) {
+        const double x = row[c] - (vi * ww[c] + wi * vv[c]);
+        row[c] = x;
+        if (c == 0 && i >= 2) ps += x * x;   // column j + 1 below its first sub-diagonal entry
+      }
     }
+    if (lane == 0) ssig[wave] = ps;
     __syncthreads();
+    sig = 0.0;
+    for (int q = 0; q < nwave; ++q) sig += ssig[q];
   }
   if (tid == 0) {
     if (l >= 2) {
