@@ -13,6 +13,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 8;
 constexpr int kScanTile = kScanThreads * kScanPerThread;
+constexpr int kMaxStatParts = 256;  // partial (max, sum) pairs the scan kernel stages in LDS
 
 // Gaussian element e: Philox call c = e / 4, counter (c_lo, c_hi, 0, 1); two Box-Muller pairs.
 __global__ void gaussian_kernel(uint64_t seed, int64_t count, float* out) {
@@ -70,11 +71,16 @@ __global__ void quantize_scan_tile(const float* beta, int64_t N, const double* p
                                    uint64_t* tile_sum, SolveState* state, int uniform) {
   __shared__ double s_scale;
   __shared__ uint64_t s_warp[kScanThreads / 64];
+  __shared__ double s_part[2 * kMaxStatParts];
+  // the partials reach LDS in one coalesced pass; thread 0 then combines them in order from LDS (a
+  // serial walk over global memory had cost about 40 us per launch)
+  for (int e = threadIdx.x; e < 2 * nparts; e += blockDim.x) s_part[e] = part[e];
+  __syncthreads();
   if (threadIdx.x == 0) {
     double mx = 0.0, sm = 0.0;
     for (int p = 0; p < nparts; ++p) {
-      mx = (isnan(mx) || isnan(part[2 * p])) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(mx, part[2 * p]);
-      sm += part[2 * p + 1];
+      mx = (isnan(mx) || isnan(s_part[2 * p])) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(mx, s_part[2 * p]);
+      sm += s_part[2 * p + 1];
     }
     int lg = 0;
     while (((int64_t)1 << lg) < (N < 2 ? 2 : N)) ++lg;
@@ -229,6 +235,7 @@ __global__ void index_scale_kernel(const uint64_t* cum, int64_t N, int64_t n_row
 }
 
 constexpr int kStatBlocks = 256;
+static_assert(kStatBlocks <= kMaxStatParts, "the scan kernel stages at most kMaxStatParts partials");
 
 }  // namespace
 
