@@ -121,11 +121,13 @@ int scs_destroy(scs_ctx* ctx);
 
 /*
  * Randomized sketch (Alg. 2 with one Krylov block, Sec. 4.3): Y = X^T (X Omega),
- * Q = orth(Y) by CholeskyQR2 in FP64, B = (X Q)^T (X Q) / n, B = V Theta V^T by
- * Jacobi in FP64, lam~ = Theta_{1..k} (descending, clamped >= 0), U~ = Q V_{:,1..k}.
+ * Q = orth(Y) by CholeskyQR2 in FP64, B = (X Q)^T (X Q) / n, B = V Theta V^T by a
+ * symmetric tridiagonal eigensolver in FP64 (Householder reduction, multisection for
+ * the eigenvalues, inverse iteration for the vectors), lam~ = Theta_{1..k}
+ * (descending, clamped >= 0), U~ = Q V_{:,1..k}.
  * The lam~ estimate the eigenvalues of C = X^T X / n (Eq. (covSpec)), i.e. the
  * squared singular values of n^{-1/2} X.
- *   X: n x d (ld ldx); k in [1, d]; k + p <= min(d, n, 140).
+ *   X: n x d (ld ldx); k in [1, d]; k + p <= min(d, n, 136).
  *   U_out: d x k row-major FP32 (ld k); U64_out (nullable): d x k FP64; lam_out: k FP64.
  * Returns SCS_SKETCH_RANK_DEFICIENT if the Gram matrix of Y is not positive definite.
  */

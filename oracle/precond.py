@@ -62,6 +62,21 @@ class Components:
         self.Xt = X @ Pm                      # row i is (P^{-1/2} x_i)^T (P symmetric)
         self.B = Pm.copy()                    # row j is b_j^T = (P^{-1/2} e_j)^T
 
+    @classmethod
+    def from_rows(cls, Xt, B, y, lam):
+        """The same n+d components with their rows given directly: x~_i = row i of Xt (n x d) and
+        b_j = row j of B (d x d), e.g. rows already rounded to the precision an implementation stores.
+        The components, objective and smoothness are defined from the rows alone.  [Sec. 5.1]"""
+        self = cls.__new__(cls)
+        self.Xt, self.B = _f64(Xt), _f64(B)
+        self.n, self.d = self.Xt.shape
+        assert self.B.shape == (self.d, self.d)
+        self.N = self.n + self.d
+        self.lam = float(lam)
+        self.y = _f64(y)
+        self.P_mhalf = None
+        return self
+
     def value(self, i, w):
         if i < self.n:
             r = self.Xt[i] @ w - self.y[i]

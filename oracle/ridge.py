@@ -48,6 +48,27 @@ def closed_form(X, y, lam):
     return sla.cho_solve(sla.cho_factor(H, lower=True), rhs)
 
 
+def closed_forms(X, Y, lams):
+    """w*(lam, y) for every lam in lams and every row y of Y, and L(w*): the normal equations of
+    closed_form with the correlation matrix and the right-hand sides formed once.  [Sec. 3]
+
+    Returns (W, L) with W of shape (len(lams), len(Y), d) and L of shape (len(lams), len(Y)).
+    """
+    X, Y = _f64(X), _f64(np.atleast_2d(Y))
+    n, d = X.shape
+    C = X.T @ X / n
+    B = X.T @ Y.T / n                            # d x ny
+    yy = np.einsum("ij,ij->i", Y, Y) / n
+    W = np.empty((len(lams), Y.shape[0], d))
+    L = np.empty((len(lams), Y.shape[0]))
+    for j, lam in enumerate(lams):
+        Ws = sla.cho_solve(sla.cho_factor(C + lam * np.eye(d), lower=True), B)   # d x ny
+        W[j] = Ws.T
+        # L(w) = 1/2 w^T (C + lam I) w - w^T X^T y / n + y^T y / (2n), evaluated at w*
+        L[j] = 0.5 * np.einsum("ir,ir->r", Ws, (C + lam * np.eye(d)) @ Ws) - np.einsum("ir,ir->r", Ws, B) + 0.5 * yy
+    return W, L
+
+
 def suboptimality(X, lam, w, w_star):
     """L(w) - L(w*) = 1/2 (w - w*)^T (C + lam I) (w - w*), exact for a quadratic."""
     e = _f64(w) - _f64(w_star)

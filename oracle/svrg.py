@@ -42,14 +42,15 @@ def beta_hat(comp: Components):
     return float(comp.smoothness().mean())
 
 
-def svrg(comp: Components, w_bar0, m, eta, S, b, epoch_indices, average=True, q=None):
+def svrg(comp: Components, w_bar0, m, eta, S, b, epoch_indices, average=True, q=None, trace=None):
     """Alg. 1 on F = (1/N) sum_i l_i, with minibatches of b i.i.d. draws.
 
     epoch_indices(s) returns the m*b component indices (0-based) used in epoch
     s = 0..S-1, step t using entries [t*b, (t+1)*b). q are the sampling
     probabilities the draws follow: beta_i / sum beta (the default, Alg. 1), or
     e.g. 1/N for the uniform sampling of the original SVRG (Sec. 4.2). Returns
-    the final snapshot and the list of snapshots after each epoch.
+    the final snapshot and the list of snapshots after each epoch. If `trace` is
+    a list, every inner iterate w_t is appended to it (a copy), for inspection.
     """
     q = comp.probabilities() if q is None else np.asarray(q, dtype=np.float64)
     N = comp.N
@@ -67,6 +68,8 @@ def svrg(comp: Components, w_bar0, m, eta, S, b, epoch_indices, average=True, q=
             v = (diff / (N * q[it])[:, None]).sum(axis=0) / len(it) + v_bar
             w = w - eta * v
             acc += w
+            if trace is not None:
+                trace.append(w.copy())
         w_bar = acc / m if average else w
         snapshots.append(w_bar.copy())
     return w_bar, snapshots

@@ -6,8 +6,10 @@ library; the first call does, and raises if libscs.so has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -78,6 +80,19 @@ class ScsReport(ctypes.Structure):
 
 
 _lib = None
+# Contexts still open when the interpreter exits are destroyed by an atexit hook, which runs while
+# the HIP runtime is still alive; a destructor left to the final garbage collection could instead
+# run during the runtime's own teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -160,6 +175,7 @@ class Context:
         _check(L.scs_create(ctypes.byref(h), device, ctypes.c_void_p(stream)), "scs_create", False)
         self._h = h
         self._L = L
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -91,7 +91,9 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     col[q] = c_begin + 4 * (cgt + 32 * q);
-    colb[q] = (uint64_t)(col[q] < c_end ? col[q] : c_begin) * ES;
+    // columns past the slice (or past d, for a workgroup whose slice starts beyond the last column)
+    // load from column 0, which every row has; their values are masked out by cok
+    colb[q] = (uint64_t)(col[q] < c_end ? col[q] : 0) * ES;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int64_t c = col[q] + v;
@@ -310,14 +312,19 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
     // The workgroups of a problem wait on each other, so they must all be resident: problems go in
     // groups that fit the device at once, one launch per group (ordinary launches: the stream runs
     // nothing else meanwhile, every group fits the idle device, and every wait is bounded).
-    static int resident = 0;  // co-resident workgroups of this instantiation on the device
+    // co-resident workgroups of this instantiation, per device (computed on first use on each)
+    constexpr int kMaxDevices = 64;
+    static int resident_per_dev[kMaxDevices] = {};
+    int dev = 0;
+    SCS_HIP(hipGetDevice(&dev));
+    int resident = dev < kMaxDevices ? resident_per_dev[dev] : 0;
     if (resident == 0) {
-      int per_cu = 0, dev = 0, cus = 0;
+      int per_cu = 0, cus = 0;
       SCS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>,
                                                            kInnerThreads, 0));
-      SCS_HIP(hipGetDevice(&dev));
       SCS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       resident = per_cu * cus;
+      if (dev < kMaxDevices) resident_per_dev[dev] = resident;
     }
     int group = resident / W;
     if (group >= 8) group -= group % 8;  // keeps the W workgroups of a problem on one XCD

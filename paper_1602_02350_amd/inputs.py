@@ -215,3 +215,24 @@ def make_ridge_torch(n: int, d: int, alpha: float, seed: int, noise_var: float =
     noise = torch.randn(n, generator=g, device=device, dtype=torch.float64) * float(noise_var) ** 0.5
     y = (X.double() @ w0 + noise).float()
     return X, y
+
+
+def make_path_targets_torch(X, y0, ny: int, seed: int, noise_var: float = 0.01):
+    """ny right-hand sides for one X (ny x n FP32, device): row 0 is y0, row r >= 1 is X w_r + e_r with
+    its own planted w_r ~ N(0, I) and noise e_r ~ N(0, noise_var), from torch's generator."""
+    import torch
+    n, d = X.shape
+    g = torch.Generator(device=X.device)
+    g.manual_seed(seed)
+    Y = torch.empty(ny, n, device=X.device, dtype=torch.float32)
+    Y[0] = y0
+    for r in range(1, ny):
+        w0 = torch.randn(d, generator=g, device=X.device, dtype=torch.float64)
+        e = torch.randn(n, generator=g, device=X.device, dtype=torch.float64) * float(noise_var) ** 0.5
+        Y[r] = (X.double() @ w0 + e).float()
+    return Y
+
+
+def path_lambdas(cfg):
+    """The nl values of lambda of a path workload, log-spaced from lam_lo to lam_hi."""
+    return np.logspace(np.log10(cfg["lam_lo"]), np.log10(cfg["lam_hi"]), cfg["nl"])

@@ -117,3 +117,25 @@ def test_preconditioner_properties(problem):
     assert np.allclose(Pm, Pm2, atol=1e-14)
     # k = 0 is the identity (plain SVRG)
     assert np.array_equal(precond.sketched_preconditioner(np.zeros((5, 0)), np.zeros(0), lam), np.eye(5))
+
+
+def test_components_from_rows(problem):
+    """Components given by their rows (x~_i, b_j) are the same functions as those formed from X and
+    P^{-1/2} (Sec. 5.1); with rows that are no preconditioned pair at all, the full gradient is still
+    the brute-force average of the n+d component gradients."""
+    _, _, Pm = _sketched(problem, 5)
+    ref = precond.Components(problem.X, problem.y, problem.lam, Pm)
+    comp = precond.Components.from_rows(problem.X @ Pm, Pm, problem.y, problem.lam)
+    w = np.random.default_rng(8).standard_normal(problem.X.shape[1])
+    assert np.allclose(comp.full_gradient(w), ref.full_gradient(w), rtol=1e-12, atol=1e-15)
+    assert np.allclose(comp.smoothness(), ref.smoothness(), rtol=1e-12)
+    assert abs(comp.objective(w) - ref.objective(w)) <= 1e-12 * ref.objective(w)
+    rng = np.random.default_rng(9)
+    Xt, B, y = rng.standard_normal((7, 3)), rng.standard_normal((3, 3)), rng.standard_normal(7)
+    c2 = precond.Components.from_rows(Xt, B, y, 0.3)
+    w = rng.standard_normal(3)
+    brute = sum(c2.grad(i, w) for i in range(10)) / 10
+    assert np.allclose(c2.full_gradient(w), brute, rtol=1e-13, atol=1e-15)
+    # component 2 of the data rows and component 1 of the regularizer rows by hand
+    assert abs(c2.value(2, w) - 10 / 7 * 0.5 * (Xt[2] @ w - y[2]) ** 2) < 1e-13
+    assert abs(c2.value(8, w) - 0.3 * 10 * 0.5 * (B[1] @ w) ** 2) < 1e-13

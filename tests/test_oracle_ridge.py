@@ -102,3 +102,19 @@ def test_planted_mistake_objective_without_half_is_caught(lam, monkeypatch):
     e0 = np.eye(4)[0]
     fd = (ridge.objective(P.X, P.y, lam, ws + h * e0) - ridge.objective(P.X, P.y, lam, ws - h * e0)) / (2 * h)
     assert abs(fd) > 1e-3 * lam * abs(ws[0])
+
+
+def test_closed_forms_of_a_path_match_single_closed_forms():
+    """Many (lambda, y) normal-equation solves on one X equal the single closed form and objective."""
+    from paper_1602_02350_amd import inputs
+    P = inputs.make_ridge(300, 12, 1.5, 1e-3, seed=44, dtype=np.float64)
+    Y = np.stack([P.y, P.X @ np.arange(12.0) + 0.1, -P.y])
+    lams = [1e-4, 1e-2, 3.0]
+    W, L = ridge.closed_forms(P.X, Y, lams)
+    for j, lam in enumerate(lams):
+        for r in range(3):
+            ws = ridge.closed_form(P.X, Y[r], lam)
+            assert np.allclose(W[j, r], ws, rtol=1e-10, atol=1e-12)
+            assert abs(L[j, r] - ridge.objective(P.X, Y[r], lam, ws)) <= 1e-10 * abs(L[j, r])
+            # stationarity: the gradient vanishes at the solution
+            assert np.linalg.norm(ridge.gradient(P.X, Y[r], lam, W[j, r])) < 1e-9
