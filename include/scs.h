@@ -228,6 +228,27 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
                         int ny, const double* lambdas, int nl, int k, double eps, const double* f_star,
                         const scs_opts* opts, float* W_out, scs_report* reports);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): scs_full_gradient with the same arguments and results,
+ * running the same kernels, but with every scratch buffer taken from one fixed device array of
+ * SCS_NOALLOC_SCRATCH_BYTES that the library holds on each device until the process ends. The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *   The scratch it needs is 256-aligned pieces of: 4 k d (U~^T) + 4 d + 8 d + 128 d + 4 d bytes and,
+ *   with G = min(512, ceil(n / 8)) workgroups, 4 G d + 8 G bytes, plus the solver state. A problem
+ *   needing more returns SCS_EINVAL without launching anything (d = 2048, k = 128 needs about 5.6 MB).
+ *   obj_out (HOST, nullable): when given, the call copies the objective back, waits for the stream and
+ *   reports SCS_ENONFINITE like scs_full_gradient; when NULL it only enqueues work (nothing waits, nothing
+ *   is copied to the host), so it may be recorded into a graph.
+ * Every call on one device shares that device's array and leaves its contents behind (the solver
+ * state is cleared by a kernel at the start of each call). Calls that overlap in time on one device,
+ * from different streams or threads, race on the array and give undefined results.
+ */
+#define SCS_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int scs_full_gradient_noalloc(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                              const float* U, const double* lam, int k, double lambda,
+                              const float* wt, float* grad_out, double* obj_out);
+
 #ifdef __cplusplus
 }
 #endif

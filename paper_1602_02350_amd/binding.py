@@ -25,6 +25,7 @@ EXPORTED = [
     "scs_opts_default", "scs_status_string", "scs_last_error", "scs_create", "scs_destroy",
     "scs_sketch_build", "scs_precondition_apply", "scs_full_gradient", "scs_svrg_epoch",
     "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched", "scs_svrg_solve_path",
+    "scs_full_gradient_noalloc",
 ]
 
 
@@ -116,6 +117,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_sketch_build.argtypes = [vp, vp, i64, i64, i64, i32, P(ScsOpts), vp, vp, vp]
     L.scs_precondition_apply.argtypes = [vp, vp, i64, i64, i64, vp, vp, i32, dbl, i32, vp, vp, i64, vp]
     L.scs_full_gradient.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
+    L.scs_full_gradient_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
     L.scs_svrg_epoch.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, dbl, i32, i32, vp]
     L.scs_sample_indices.argtypes = [vp, vp, i64, u64, i32, i64, vp]
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
@@ -254,6 +256,20 @@ class Context:
                                          float(lam_reg), _ptr(wt), _ptr(g), ctypes.byref(obj)),
                "scs_full_gradient", False)
         return g, obj.value
+
+    def full_gradient_noalloc(self, X, y, U, lam, lam_reg: float, wt, g=None, want_obj: bool = True):
+        """The allocation-free variant: g (d, FP32) may be passed in; obj is None when want_obj is False."""
+        _dev(X, torch.float32)
+        n, d = X.shape
+        k = 0 if U is None else U.shape[1]
+        if g is None:
+            g = torch.empty(d, dtype=torch.float32, device=X.device)
+        obj = ctypes.c_double()
+        _check(self._L.scs_full_gradient_noalloc(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), _ptr(U), _ptr(lam), k,
+                                                 float(lam_reg), _ptr(wt), _ptr(g),
+                                                 ctypes.byref(obj) if want_obj else None),
+               "scs_full_gradient_noalloc", False)
+        return g, (obj.value if want_obj else None)
 
     def svrg_epoch(self, n, d, Xt, reg, beta, mu, idx, m, b, eta, average=True, workgroups=0, wt=None):
         bf16 = Xt.dtype == torch.bfloat16

@@ -377,6 +377,11 @@ int scs_create(scs_ctx** out, int device, void* hip_stream) {
     set_error("no such HIP device");
     return SCS_EINVAL;
   }
+  {
+    Guard g(device);
+    // device address of the allocation-free entry point's fixed scratch array on this device
+    SCS_CHECK(noalloc_scratch_init(device));
+  }
   auto* c = new scs_ctx();
   c->device = device;
   if (const char* e = std::getenv("SCS_XCD_STRIDE")) c->xcd_stride = std::max(1, std::atoi(e));
@@ -515,6 +520,16 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
   if (obj_out) *obj_out = hs.obj0;
   if (hs.status == SCS_ENONFINITE) return SCS_ENONFINITE;
   return SCS_OK;
+}
+
+int scs_full_gradient_noalloc(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
+                              const float* U, const double* lam, int k, double lambda, const float* wt,
+                              float* grad_out, double* obj_out) {
+  if (!ctx || !y || !wt || !grad_out || k < 0 || k > d || (k > 0 && (!U || !lam))) return SCS_EINVAL;
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  if (k > 256) return SCS_EINVAL;
+  Guard g(ctx->device);
+  return full_gradient_noalloc(ctx->device, ctx->stream, X, n, d, ldx, y, U, lam, k, lambda, wt, grad_out, obj_out);
 }
 
 int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,

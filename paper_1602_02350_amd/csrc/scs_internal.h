@@ -247,6 +247,14 @@ struct InnerArgs {
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
 int inner_default_workgroups(int64_t d);
 
+// ---------------------------------------------------------------- allocation-free entry (noalloc.hip)
+// Looks up the device address of the fixed scratch array on `device` (which must be current); once per device.
+int noalloc_scratch_init(int device);
+size_t noalloc_full_gradient_bytes(int64_t n, int64_t d, int k);
+int full_gradient_noalloc(int device, hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx,
+                          const float* y, const float* U, const double* lam, int k, double lambda, const float* wt,
+                          float* grad_out, double* obj_out);
+
 // ---------------------------------------------------------------- batched solves
 // One problem of a batched solve; an array of these lives in device memory and every batched
 // kernel finds its problem from its block index (flattened grids use the prefix arrays below).
