@@ -61,7 +61,7 @@ typedef struct scs_ctx scs_ctx;
 /* Options. Fill with scs_opts_default() and change what you need. */
 typedef struct scs_opts {
   int oversample;         /* p: range-finder width is k + p (default 5) */
-  int batch;              /* b: i.i.d. draws per inner step (default 64) */
+  int batch;              /* b: i.i.d. draws per inner step, 1..256 (default 64) */
   int64_t steps;          /* m: inner steps per epoch; 0 = ceil(epoch_factor n / b), or ceil(2 n / b) */
   double step_scale;      /* c: step eta = c / beta_hat with beta_hat = (1/(n+d)) sum_i beta_i (default 1) */
   int max_epochs;         /* S: epoch cap (default 30) */
@@ -89,6 +89,10 @@ typedef struct scs_opts {
   int uniform_sampling;   /* 1: draw the n + d components uniformly, q_i = 1/(n+d) (the uniform sampling of
                              Johnson and Zhang, Sec. 4.2) instead of q_i proportional to beta_i (Xiao and Zhang,
                              the default 0); eta = c / beta_hat either way, so c is tuned per sampling rule */
+  int wave_rows;          /* inner-loop layout (single solves): how each workgroup's 8 waves split the minibatch's
+                             rows, 1, 2 or 4 wave-rows of 8 / wave_rows waves (64 rows each at most; slices of at
+                             most 512, 128 or 64 columns); 0 = chosen from b and the slice width, or autotuned
+                             together with the workgroups when workgroups = -1 */
 } scs_opts;
 
 typedef struct scs_report {
@@ -165,12 +169,13 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
  *   w~ <- (1/m) sum_t w_t  (average = 1)  or  w_m  (average = 0).
  * q_i are the sampling probabilities of the quantized weights of `beta` (see scs_sample_indices).
  * Xt: n x d rows, reg: d x d rows, both with leading dimension ldt (a multiple of 4), FP32 or BF16 as
- * xt_bf16; beta: n + d, idx: m x b int32 in [0, n+d) (device); 1 <= b <= 64.
- * wt is updated in place; mu = grad L~(w~) (device FP32). workgroups = 0 chooses from d.
+ * xt_bf16; beta: n + d, idx: m x b int32 in [0, n+d) (device); 1 <= b <= 256.
+ * wt is updated in place; mu = grad L~(w~) (device FP32). workgroups = 0 chooses from d and b;
+ * wave_rows as scs_opts.wave_rows (0 = chosen from b and the slice width).
  */
 int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,
                    const float* beta, const float* mu, const int32_t* idx, int64_t m, int b,
-                   double eta, int average, int workgroups, float* wt);
+                   double eta, int average, int workgroups, int wave_rows, float* wt);
 
 /*
  * Importance sampling of Alg. 1 (q_i = beta_i / sum_j beta_j): the beta are quantized to

@@ -50,6 +50,7 @@ class ScsOpts(ctypes.Structure):
         ("epoch_factor", ctypes.c_double),
         ("implicit_apply", ctypes.c_int),
         ("uniform_sampling", ctypes.c_int),
+        ("wave_rows", ctypes.c_int),
     ]
 
 
@@ -118,7 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_precondition_apply.argtypes = [vp, vp, i64, i64, i64, vp, vp, i32, dbl, i32, vp, vp, i64, vp]
     L.scs_full_gradient.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
     L.scs_full_gradient_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
-    L.scs_svrg_epoch.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, dbl, i32, i32, vp]
+    L.scs_svrg_epoch.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, dbl, i32, i32, i32, vp]
     L.scs_sample_indices.argtypes = [vp, vp, i64, u64, i32, i64, vp]
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
     L.scs_svrg_solve.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), vp, P(ScsReport)]
@@ -271,12 +272,14 @@ class Context:
                "scs_full_gradient_noalloc", False)
         return g, (obj.value if want_obj else None)
 
-    def svrg_epoch(self, n, d, Xt, reg, beta, mu, idx, m, b, eta, average=True, workgroups=0, wt=None):
+    def svrg_epoch(self, n, d, Xt, reg, beta, mu, idx, m, b, eta, average=True, workgroups=0, wt=None,
+                   wave_rows=0):
         bf16 = Xt.dtype == torch.bfloat16
         ldt = Xt.stride(0)
         assert reg.stride(0) == ldt
         _check(self._L.scs_svrg_epoch(self._h, n, d, _ptr(Xt), _ptr(reg), ldt, int(bf16), _ptr(beta), _ptr(mu),
-                                      _ptr(idx), m, b, float(eta), int(average), int(workgroups), _ptr(wt)),
+                                      _ptr(idx), m, b, float(eta), int(average), int(workgroups), int(wave_rows),
+                                      _ptr(wt)),
                "scs_svrg_epoch", False)
         return wt
 

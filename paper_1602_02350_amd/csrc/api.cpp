@@ -32,7 +32,7 @@ struct scs_ctx {
   std::map<std::string, Buf> bufs;
   std::vector<hipEvent_t> events;   // synchronizing events (host waits on them)
   std::vector<hipEvent_t> tevents;  // timing-only events (no system-scope fence when recorded)
-  std::map<std::string, int> tuned_w;  // autotuned inner-loop workgroup counts per (d, b, precision)
+  std::map<std::string, std::pair<int, int>> tuned_w;  // autotuned inner-loop (workgroups, wave-rows) per (d, b, precision)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   std::vector<hipStream_t> side;       // extra streams for independent per-problem setup work
   std::vector<hipEvent_t> side_events;
@@ -136,31 +136,52 @@ int64_t epoch_steps(const scs_opts& o, int64_t n, int b) {
   return cdiv(2 * n, b);
 }
 
+// Widest column slice the batched inner loop takes for minibatch b (one wave-row up to b = 64,
+// two up to 128, four beyond).
+int64_t batched_max_slice(int b) { return b <= 64 ? 512 : b <= 128 ? 128 : 64; }
+
 int choose_workgroups(const scs_opts& o, int64_t d) {
   if (o.workgroups > 0) return o.workgroups;
-  return inner_default_workgroups(d);
+  // at least enough workgroups for the widest slice the minibatch's layout takes
+  return (int)std::min<int64_t>(16, std::max<int64_t>(inner_default_workgroups(d), cdiv(d, batched_max_slice(o.batch))));
 }
 
-// Measured choice of the inner loop's workgroup count (the width of each workgroup's column slice):
-// a few dozen steps of the epoch kernel on the problem's own rows, with a scratch snapshot, state and
-// exchange buffer, for each candidate; the fastest is kept in the context per (d, b, precision).
+// Measured choice of the inner loop's launch shape: the workgroup count W (the width of each
+// workgroup's column slice) and the wave-row count (how the workgroup's waves split the minibatch's
+// rows). A few dozen steps of the epoch kernel run on the problem's own rows, with a scratch
+// snapshot, state and exchange buffer, for each candidate; the fastest is kept in the context per
+// (d, b, precision).
 int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int bf16, const uint64_t* cum,
-                        int64_t N, uint64_t seed, int* W_out) {
+                        int64_t N, uint64_t seed, int* W_out, int* wr_out) {
   const std::string key = std::to_string(base.d) + "/" + std::to_string(base.b) + "/" + std::to_string(bf16);
   auto it = ctx->tuned_w.find(key);
   if (it != ctx->tuned_w.end()) {
-    *W_out = it->second;
+    *W_out = it->second.first;
+    *wr_out = it->second.second;
     return SCS_OK;
   }
-  std::vector<int> cand;
+  // a layout with wr wave-rows takes at most 64 rows per wave-row and slices of at most 512 (wr = 1),
+  // 128 (wr = 2) or 64 (wr = 4) columns
+  std::vector<std::pair<int, int>> cand;
   for (int cols : {128, 64, 32}) {
     const int W = (int)std::max<int64_t>(1, std::min<int64_t>(16, cdiv(base.d, cols)));
-    if (cdiv(cdiv(base.d, W), 4) * 4 > 512) continue;
-    if (std::find(cand.begin(), cand.end(), W) == cand.end()) cand.push_back(W);
+    const int64_t slice = cdiv(cdiv(base.d, W), 4) * 4;
+    for (int wr : {1, 2, 4}) {
+      const int64_t max_slice = wr == 1 ? 512 : wr == 2 ? 128 : 64;
+      if (cdiv(base.b, wr) > 64 || slice > max_slice) continue;
+      const std::pair<int, int> c{W, wr};
+      if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
   }
-  if (cand.size() <= 1) {
-    *W_out = cand.empty() ? inner_default_workgroups(base.d) : cand[0];
-    ctx->tuned_w[key] = *W_out;
+  if (cand.empty()) {
+    *W_out = inner_default_workgroups(base.d);
+    *wr_out = 0;
+    return SCS_OK;
+  }
+  if (cand.size() == 1) {
+    *W_out = cand[0].first;
+    *wr_out = cand[0].second;
+    ctx->tuned_w[key] = cand[0];
     return SCS_OK;
   }
   for (auto& e : ctx->tune_ev)
@@ -174,19 +195,21 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
   WS(tidx, int32_t, "at_idx", runs * mp * base.b);
   WS(tsc, float, "at_scale", runs * mp * base.b);
   WS(tstate, SolveState, "at_state", 1);
-  WS(txb, uint64_t, "at_xbuf", 2 * 16 * 64);
+  WS(txb, uint64_t, "at_xbuf", inner_xbuf_words(16));
   SCS_HIP(hipMemsetAsync(tmu, 0, sizeof(float) * base.d, st));
   SCS_CHECK(launch_sample(st, cum, N, base.n, seed, 0x7fff0000, mp * base.b, runs * mp * base.b, tidx, tsc, nullptr));
-  int best = cand[0], run = 0;
+  std::pair<int, int> best = cand[0];
+  int run = 0;
   float best_ms = 1e30f;
-  for (int W : cand) {
+  for (const auto& c : cand) {
     for (int rep = 0; rep < reps; ++rep, ++run) {
       SCS_HIP(hipMemsetAsync(twt, 0, sizeof(float) * base.d, st));
-      SCS_HIP(hipMemsetAsync(txb, 0, sizeof(uint64_t) * 2 * 16 * 64, st));
+      SCS_HIP(hipMemsetAsync(txb, 0, sizeof(uint64_t) * inner_xbuf_words(16), st));
       SCS_HIP(hipMemcpyAsync(tstate, base.state, sizeof(SolveState), hipMemcpyDeviceToDevice, st));
       InnerArgs a = base;
-      a.W = W;
-      a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+      a.W = c.first;
+      a.wave_rows = c.second;
+      a.xcd_stride = c.first > 1 ? ctx->xcd_stride : 1;
       a.m = mp;
       a.idx = tidx + (int64_t)run * mp * base.b;
       a.scale = tsc + (int64_t)run * mp * base.b;
@@ -204,12 +227,13 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
       SCS_HIP(hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]));
       if (ms < best_ms) {
         best_ms = ms;
-        best = W;
+        best = c;
       }
     }
   }
   ctx->tuned_w[key] = best;
-  *W_out = best;
+  *W_out = best.first;
+  *wr_out = best.second;
   return SCS_OK;
 }
 
@@ -534,9 +558,9 @@ int scs_full_gradient_noalloc(scs_ctx* ctx, const float* X, int64_t n, int64_t d
 
 int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,
                    const float* beta, const float* mu, const int32_t* idx, int64_t m, int b, double eta, int average,
-                   int workgroups, float* wt) {
+                   int workgroups, int wave_rows, float* wt) {
   if (!ctx || !Xt || !reg || !beta || !mu || !idx || !wt || n < 1 || d < 1 || ldt < d || ldt % 4 != 0 || m < 1 ||
-      b < 1 || b > 64 || !(eta > 0.0))
+      b < 1 || b > kInnerMaxB || !(eta > 0.0))
     return SCS_EINVAL;
   Guard g(ctx->device);
   hipStream_t st = ctx->stream;
@@ -551,9 +575,10 @@ int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const voi
   scs_opts o;
   scs_opts_default(&o);
   o.workgroups = workgroups;
+  o.batch = b;
   const int W = choose_workgroups(o, d);
-  WS(xbuf, uint64_t, "xbuf", (size_t)2 * W * 64);
-  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * 2 * W * 64, st));
+  WS(xbuf, uint64_t, "xbuf", (size_t)inner_xbuf_words(W));
+  SCS_HIP(hipMemsetAsync(xbuf, 0, sizeof(uint64_t) * inner_xbuf_words(W), st));
   InnerArgs a{};
   a.n = n;
   a.d = d;
@@ -576,6 +601,7 @@ int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const voi
   a.wt_prev = nullptr;
   a.xbuf = xbuf;
   a.state = state;
+  a.wave_rows = wave_rows;
   SCS_CHECK(launch_inner_epoch(st, a, xt_bf16));
   SolveState hs;
   SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -607,9 +633,9 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) ||
-      o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX) {
-    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
+  if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX) {
+    set_error("bad options: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -719,9 +745,9 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   constexpr int kSampleGroup = 8;
   WS(idxb, int32_t, "idx", (size_t)kSampleGroup * m * b);
   WS(scale, float, "scale", (size_t)kSampleGroup * m * b);
-  WS(xbuf, uint64_t, "xbuf", (size_t)2 * 16 * 64);
+  WS(xbuf, uint64_t, "xbuf", (size_t)inner_xbuf_words(16));
   SCS_CHECK(launch_zero3(st, wt, (int64_t)sizeof(float) * d, wt_prev, (int64_t)sizeof(float) * d, xbuf,
-                         (int64_t)sizeof(uint64_t) * 2 * 16 * 64));
+                         (int64_t)sizeof(uint64_t) * inner_xbuf_words(16)));
 
   InnerArgs a{};
   a.n = n;
@@ -743,10 +769,13 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   a.wt_prev = wt_prev;
   a.xbuf = xbuf;
   a.state = state;
+  a.wave_rows = o.wave_rows;
   if (o.workgroups < 0) {
-    SCS_CHECK(autotune_workgroups(ctx, st, a, rows_bf16, cum, N, o.seed, &W));
+    int wr = 0;
+    SCS_CHECK(autotune_workgroups(ctx, st, a, rows_bf16, cum, N, o.seed, &W, &wr));
     a.W = W;
     a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+    if (o.wave_rows == 0) a.wave_rows = wr;
   }
 
   constexpr int kLookahead = 3;
@@ -884,9 +913,9 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     set_error("batched solve: the gap rule needs f_star, one optimum per problem");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) || o.stop_rule < 0 ||
-      o.stop_rule > 2) {
-    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0");
+  if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2) {
+    set_error("bad options: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0");
     return SCS_EINVAL;
   }
   int64_t max_d = 0;
@@ -918,8 +947,8 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   std::stable_sort(kord.begin() + nv, kord.end(), bigger);
   std::vector<int> sidx(nprob);
   for (int i = 0; i < nprob; ++i) sidx[kord[i]] = i;
-  if (max_d > 16 * 512) {
-    set_error("batched solve: d > 8192");
+  if (max_d > 16 * batched_max_slice(o.batch)) {
+    set_error("batched solve: d > 8192 (2048 for batch > 64, 1024 for batch > 128)");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -930,8 +959,10 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   // W cooperating workgroups per problem (the same for every problem of the batch): opts.workgroups
   // when positive, else one per 256 columns of the widest problem (measured: 256-column slices beat
   // both 512 and 128 on the uneven batch); a slice never exceeds 512 columns
+  const int64_t maxs = batched_max_slice(o.batch);
   const int W = (int)std::min<int64_t>(
-      16, std::max<int64_t>(cdiv(max_d, 512), o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(max_d, 256)));
+      16, std::max<int64_t>(cdiv(max_d, maxs),
+                            o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(max_d, std::min<int64_t>(256, maxs))));
 
   // ---- per-problem sizes and arena offsets (elements)
   std::vector<int64_t> ldt(nprob), m(nprob), nwg(nprob), o_xt(nprob), o_reg(nprob), o_beta(nprob), o_vec(nprob),
@@ -978,7 +1009,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   WS(sc_all, float, "b_scale", t_idx);
   WS(ut_all, float, "b_UT", std::max<int64_t>(t_ut, 1));
   WS(lam_all, double, "b_lam", std::max<int64_t>(t_lam, 1));
-  WS(xbuf_all, uint64_t, "b_xbuf", (int64_t)nprob * 2 * W * 64);
+  WS(xbuf_all, uint64_t, "b_xbuf", (int64_t)nprob * inner_xbuf_words(W));
   WS(states, SolveState, "b_state", nprob);
   WS(flags_all, int, "b_cholflags", 2 * nprob);
   WS(done_count, int, "b_done", 1);
@@ -988,7 +1019,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(max_N));
   SCS_HIP(hipMemsetAsync(states, 0, sizeof(SolveState) * nprob, st));
   SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * t_vec, st));  // wt and wt_prev start at 0
-  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * nprob * 2 * W * 64, st));
+  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * nprob * inner_xbuf_words(W), st));
   SCS_HIP(hipMemsetAsync(flags_all, 0, sizeof(int) * 2 * nprob, st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
 
@@ -1132,7 +1163,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     a.slice = cdiv(cdiv(d[p], W), 4) * 4;
     a.wt = q.wt;
     a.wt_prev = q.wt_prev;
-    a.xbuf = xbuf_all + (int64_t)p * 2 * W * 64;
+    a.xbuf = xbuf_all + (int64_t)p * inner_xbuf_words(W);
     a.state = q.state;
     max_slice = std::max(max_slice, a.slice);
     wg_pre[i + 1] = wg_pre[i] + nwg[p];
@@ -1250,9 +1281,10 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     set_error("path solve: omega, indices, trace_w must be NULL; the gap rule needs f_star for every solve");
     return SCS_EINVAL;
   }
-  if (o.batch < 1 || o.batch > 64 || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) || !(o.epoch_factor >= 0.0) || o.stop_rule < 0 ||
-      o.stop_rule > 2 || d > 16 * 512) {
-    set_error("bad options: need 1 <= batch <= 64, max_epochs >= 1, steps >= 0, step_scale > 0, d <= 8192");
+  if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2 || d > 16 * batched_max_slice(o.batch)) {
+    set_error("bad options: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0, and d <= 8192 "
+              "(2048 for batch > 64, 1024 for batch > 128)");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -1262,8 +1294,10 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   constexpr int G = 8;
   // W cooperating workgroups per solve: opts.workgroups when positive, else one per 256 columns
   // (measured on the 1024-column path: 256-column slices beat 512 and 128)
+  const int64_t maxs = batched_max_slice(o.batch);
   const int W = (int)std::min<int64_t>(
-      16, std::max<int64_t>(cdiv(d, 512), o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(d, 256)));
+      16, std::max<int64_t>(cdiv(d, maxs),
+                            o.workgroups > 0 ? (int64_t)o.workgroups : cdiv(d, std::min<int64_t>(256, maxs))));
   const int64_t ldt = cdiv(d, mixed ? 128 : 64) * (mixed ? 128 : 64);
   const int64_t m = epoch_steps(o, n, b);
   const int64_t N = n + d;
@@ -1290,7 +1324,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   WS(sc_all, float, "p_scale", (int64_t)P * G * m * b);
   WS(ut, float, "p_UT", std::max<int64_t>((int64_t)k * d, 1));
   WS(lam64, double, "p_lam", std::max(k, 1));
-  WS(xbuf_all, uint64_t, "p_xbuf", (int64_t)P * 2 * W * 64);
+  WS(xbuf_all, uint64_t, "p_xbuf", (int64_t)P * inner_xbuf_words(W));
   WS(states, SolveState, "p_state", P);
   WS(done_count, int, "p_done", 1);
   WS(desc, BatchProb, "p_desc", P);
@@ -1304,7 +1338,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   WS(part, float, "p_partial", nchunks * d * kPc);
   SCS_HIP(hipMemsetAsync(states, 0, sizeof(SolveState) * P, st));
   SCS_HIP(hipMemsetAsync(vec_all, 0, sizeof(float) * 2 * P * d, st));
-  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * P * 2 * W * 64, st));
+  SCS_HIP(hipMemsetAsync(xbuf_all, 0, sizeof(uint64_t) * P * inner_xbuf_words(W), st));
   SCS_HIP(hipMemsetAsync(done_count, 0, sizeof(int), st));
   // tev: 0 start, 1-2 stage ends, 3 end, 4 + s end of epoch s (where the host reads stop flag s);
   // with timing, 4 + S + s opens the inner loop of epoch s
@@ -1422,7 +1456,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
     a.slice = slice;
     a.wt = q.wt;
     a.wt_prev = q.wt_prev;
-    a.xbuf = xbuf_all + (int64_t)p * 2 * W * 64;
+    a.xbuf = xbuf_all + (int64_t)p * inner_xbuf_words(W);
     a.state = q.state;
     dpre[p + 1] = dpre[p] + (int64_t)G * m * b;
   }

@@ -9,7 +9,7 @@
 // Working on delta keeps FP32 rounding relative to the shrinking correction.
 //
 // Columns are split over W cooperating workgroups (each on its own CU); a workgroup holds its
-// slice of delta, mu and sum in registers (replicated over its 8 row groups) and gathers only
+// slice of delta, mu and sum in registers (replicated over its row groups) and gathers only
 // its slice of the b rows. The b partial dot products of a step are exchanged through global
 // memory: every workgroup posts its partials and a step counter, then sums all W partials in
 // the same fixed order, so all workgroups compute bit-identical c_j. Waits are bounded: a wait
@@ -26,7 +26,7 @@ namespace scs {
 
 namespace {
 
-constexpr int kInnerThreads = 512;  // 8 waves: 16 row groups x 32 column threads
+constexpr int kInnerThreads = 512;  // 8 waves
 constexpr uint32_t kPollBudget = 1u << 22;
 
 // Barrier for LDS traffic only: waits for this wave's LDS operations but not for its
@@ -48,24 +48,39 @@ __device__ __forceinline__ float rowgroup_sum(float v) {
   return __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
 }
 
-// Lane layout: lane = 4 * rg + cl and column thread cgt = 4 * wave + cl, so the 16 row groups that
-// share a column are in one wave and the update's sum over rows is a lane butterfly. Wave 0 also
-// owns the per-step communication: it sums the partial dot products, exchanges them with the
-// other workgroups, publishes the step coefficients and stages the index stream into LDS two
-// steps ahead. Every global load a wave issues is consumed at least one step later, except the
-// exchange polls, so no wait for one load also waits for a load issued after it (loads complete
-// in order per wave). Rows live in a two-slot ring whose roles alternate at compile time.
-// Data rows and regularizer rows share one leading dimension, so a row address is one
-// multiply-add from a base selected by the index range.
+// Layout: the workgroup's 8 waves form WR wave-rows of WC = 8 / WR waves. A wave-row owns 16 RPT
+// of the step's b rows (rows j = r0 + rg + 16 q, r0 = 16 RPT * wave-row) over all of the
+// workgroup's columns, so larger minibatches spread over more waves instead of more registers.
+// Inside a wave, lane = 4 * rg + cl: the 16 row groups that share a column are in one wave and a
+// sum over them is a lane butterfly; column thread cgt = 4 * (wave % WC) + cl owns columns
+// c_begin + 4 (cgt + 4 WC q) .. + 3 for q < CPT.
+// The first wave of each wave-row owns that wave-row's per-step communication: it sums the partial
+// dot products of its rows, exchanges them with the other workgroups, publishes the step
+// coefficients and stages its rows' indices into LDS two steps ahead, so the exchanges of the
+// wave-rows run side by side. With WR > 1 the update's sum over rows ends with one LDS round trip
+// that adds the wave-rows' sums in a fixed order (every wave-row then holds the same delta).
+// Every global load a wave issues is consumed at least one step later, except the exchange polls,
+// so no wait for one load also waits for a load issued after it (loads complete in order per
+// wave). Rows live in a two-slot ring whose roles alternate at compile time. Data rows and
+// regularizer rows share one leading dimension, so a row address is one multiply-add from a base
+// selected by the index range.
 // Workgroup w (0 <= w < a.W) of one problem's inner loop.
-template <int RPT, int CPT, bool BF16>
+template <int RPT, int CPT, int WR, bool BF16>
 __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w) {
   constexpr int ES = BF16 ? 2 : 4;          // bytes per element
+  constexpr int WC = 8 / WR;                // waves per wave-row
+  constexpr int CT = 4 * WC;                // column threads per wave-row
+  constexpr int RW = 16 * RPT;              // rows per wave-row
+  constexpr int PDS = CT + 4;               // row stride of the partial-dot array (floats)
+  constexpr int CS = 4 * CT * CPT;          // columns a wave-row covers
   const int tid = threadIdx.x, lane = tid & 63;
-  // wave index made provably uniform so that wave-0-only work compiles to scalar branches
+  // wave index made provably uniform so that wave-row and exchange-wave tests are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int rg = lane >> 2;                 // row group: rows j = rg + 16 q
-  const int cgt = wave * 4 + (lane & 3);    // column thread 0..31
+  const int wr = wave / WC;
+  const bool xwave = wave % WC == 0;        // this wave runs its wave-row's exchange
+  const int r0 = wr * RW;
+  const int rg = lane >> 2;                 // row group
+  const int cgt = (wave % WC) * 4 + (lane & 3);
   const int b = a.b, W = a.W;
   const uint32_t NR = (uint32_t)(a.n + a.d), n32 = (uint32_t)a.n;
   const int64_t c_begin = (int64_t)w * a.slice;
@@ -79,9 +94,10 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
       reinterpret_cast<const char*>((uintptr_t)a.reg - (uintptr_t)a.n * (uintptr_t)a.ldx * (uintptr_t)ES);
   const uint64_t ldb = (uint64_t)a.ldx * ES;
 
-  __shared__ float pd[64][36];
-  __shared__ float gam[64];
-  __shared__ int32_t s_idx[4][16][4];  // [step slot][row group][q]: index of row rg + 16q, staged by wave 0
+  __shared__ __align__(16) float pd[WR * RW * PDS];
+  __shared__ float gam[WR * RW];
+  __shared__ __align__(16) int32_t s_idx[4][WR][16][4];  // [step slot][wave-row][row group][q], by the exchange waves
+  __shared__ __align__(16) float red[WR > 1 ? WR : 1][WR > 1 ? CS : 4];
   __shared__ int s_abort;
 
   float dl[CPT][4], sm[CPT][4], smc[CPT][4], muv[CPT][4], w0[CPT][4];
@@ -90,7 +106,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   bool cok[CPT][4];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
-    col[q] = c_begin + 4 * (cgt + 32 * q);
+    col[q] = c_begin + 4 * (cgt + CT * q);
     // columns past the slice (or past d, for a workgroup whose slice starts beyond the last column)
     // load from column 0, which every row has; their values are masked out by cok
     colb[q] = (uint64_t)(col[q] < c_end ? col[q] : 0) * ES;
@@ -105,6 +121,8 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
       smc[q][v] = 0.f;
     }
   }
+  // a wave whose column threads all lie past the slice skips its row loads (its values are masked)
+  const bool wave_cols = (int64_t)4 * (wave % WC) * 4 < c_end - c_begin;
   const float eta = a.eta_from_state
                         ? (float)ldexp(a.step_scale * (double)a.n / a.state->beta_sum, -a.state->backoffs)
                         : (float)a.eta;
@@ -113,7 +131,8 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   // Row loads are unconditional from in-bounds addresses: rows j >= b get coefficient 0 and
   // columns outside the slice are zeroed before use.
   auto load_rows = [&](int slot, float4 (&buf)[RPT][CPT]) {
-    const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][rg][0]);
+    if (!wave_cols) return;
+    const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][wr][rg][0]);
     const int32_t ix[4] = {i0.x, i0.y, i0.z, i0.w};
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -132,20 +151,27 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
     }
   };
 
-  const int jj = lane < b ? lane : b - 1;
-  const int srg = lane & 15, sq = lane >> 4;  // where wave 0 lane j stages index j (j = srg + 16 sq)
-  // wave 0, two-slot rings alternating like the row buffers: a step consumes idxX (index of step
-  // t+2) and scX (scale of step t), both loaded one step earlier, and loads the other slot
+  // exchange-wave lane j serves row r0 + j of the step (j < RW); jj clamps it to a drawn row
+  const int myrow = r0 + lane;
+  const bool rowok = lane < RW && myrow < b;
+  const int jj = rowok ? myrow : b - 1;
+  const int srg = lane & 15, sq = lane >> 4;  // where lane j stages its row's index (j = srg + 16 sq)
+  // exchange waves, two-slot rings alternating like the row buffers: a step consumes idxX (index of
+  // step t+2) and scX (scale of step t), both loaded one step earlier, and loads the other slot
   int32_t idxA = 0, idxB = 0;
   float scA = 0.f, scB = 0.f;
-  if (wave == 0) {
-    s_idx[0][srg][sq] = lane < b ? a.idx[lane] : 0;
-    s_idx[1][srg][sq] = lane < b ? a.idx[(1 < mlast ? 1 : mlast) * b + lane] : 0;
+  if (xwave) {
+    s_idx[0][wr][srg][sq] = rowok ? a.idx[jj] : 0;
+    s_idx[1][wr][srg][sq] = rowok ? a.idx[(1 < mlast ? 1 : mlast) * b + jj] : 0;
     idxA = a.idx[(2 < mlast ? 2 : mlast) * b + jj];
     scA = a.scale[jj];
   }
-  lds_barrier();
   float4 bufA[RPT][CPT], bufB[RPT][CPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) bufA[q][c] = bufB[q][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+  lds_barrier();
   load_rows(0, bufA);
 
   // One inner step t on rows `cur`, prefetching the rows of step t+1 into `nxt`.
@@ -169,30 +195,34 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
       for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) p = fmaf(f4get(cur[q][c], v), dl[c][v], p);
-      pd[rg + 16 * q][cgt] = p;
+      pd[(r0 + rg + 16 * q) * PDS + cgt] = p;
     }
     lds_barrier();
-    if (wave == 0) {
-      const int j = lane;
+    if (xwave) {
       float cl = 0.f;
+      if (lane < RW) {
 #pragma unroll
-      for (int g = 0; g < 32; g += 4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(&pd[j][g]);
-        cl += (v4.x + v4.y) + (v4.z + v4.w);
+        for (int g = 0; g < CT; g += 4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(&pd[myrow * PDS + g]);
+          cl += (v4.x + v4.y) + (v4.z + v4.w);
+        }
       }
       if (W > 1) {
-        // post (step tag, value) as one 64-bit word; gather the W words of row j; a word is
+        // post (step tag, value) as one 64-bit word; gather the W words of this row; a word is
         // valid once its tag is this step's, so no fence is needed
         const int par = (int)(t & 1);
         const uint32_t target = a.step_base + (uint32_t)t + 1u;
-        uint64_t* slot = xb + (int64_t)par * W * 64;
-        __hip_atomic_store(&slot[(int64_t)w * 64 + j], ((uint64_t)target << 32) | __float_as_uint(cl),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t* slot = xb + (int64_t)par * W * kInnerMaxB + myrow;
+        const bool xrow = lane < RW;
+        if (xrow)
+          __hip_atomic_store(&slot[(int64_t)w * kInnerMaxB], ((uint64_t)target << 32) | __float_as_uint(cl),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t xv[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-          xv[v] = v < W ? __hip_atomic_load(&slot[v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : ((uint64_t)target << 32);
+          xv[v] = (v < W && xrow)
+                      ? __hip_atomic_load(&slot[v * kInnerMaxB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : ((uint64_t)target << 32);
         uint32_t polls = 0;
         bool bad = false;
         for (;;) {
@@ -209,7 +239,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 #pragma unroll
           for (int v = 0; v < 16; ++v)
             if ((uint32_t)(xv[v] >> 32) != target)
-              xv[v] = __hip_atomic_load(&slot[v * 64 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              xv[v] = __hip_atomic_load(&slot[v * kInnerMaxB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (__any(bad) && lane == 0) {
           s_abort = 1;
@@ -222,18 +252,22 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
           if (v < W) sum += __uint_as_float((uint32_t)xv[v]);  // same order in every workgroup
         cl = sum;
       }
-      gam[j] = j < b ? sc_use * cl / (float)b : 0.f;
-      s_idx[(t + 2) & 3][srg][sq] = j < b ? idx_use : 0;
+      if (lane < RW) {
+        gam[myrow] = rowok ? sc_use * cl / (float)b : 0.f;
+        s_idx[(t + 2) & 3][wr][srg][sq] = rowok ? idx_use : 0;
+      }
       // loads consumed at the next step, issued after the polls so the polls never wait for them
       idx_next = a.idx[(t + 3 < mlast ? t + 3 : mlast) * b + jj];
       sc_next = a.scale[(t + 1 < mlast ? t + 1 : mlast) * b + jj];
     }
     lds_barrier();
     if (s_abort) return false;
-    // (1/b) sum_j c_j a_j / (n q_j): this thread's rows, then the 8 row groups of the wave
+    // (1/b) sum_j c_j a_j / (n q_j): this thread's rows, then the 16 row groups of the wave, then
+    // (WR > 1) the wave-rows in order
     float g8[RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) g8[q] = gam[rg + 16 * q];
+    for (int q = 0; q < RPT; ++q) g8[q] = gam[r0 + rg + 16 * q];
+    float uu[CPT][4];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       float u[4] = {0.f, 0.f, 0.f, 0.f};
@@ -242,9 +276,39 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 #pragma unroll
         for (int v = 0; v < 4; ++v) u[v] = fmaf(g8[q], f4get(cur[q][c], v), u[v]);
 #pragma unroll
+      for (int v = 0; v < 4; ++v) uu[c][v] = rowgroup_sum(u[v]);
+    }
+    if constexpr (WR > 1) {
+      if (rg == 0) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+          *reinterpret_cast<float4*>(&red[wr][4 * (cgt + CT * c)]) =
+              make_float4(uu[c][0], uu[c][1], uu[c][2], uu[c][3]);
+      }
+      lds_barrier();
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        float4 s4 = *reinterpret_cast<const float4*>(&red[0][4 * (cgt + CT * c)]);
+#pragma unroll
+        for (int r = 1; r < WR; ++r) {
+          const float4 o4 = *reinterpret_cast<const float4*>(&red[r][4 * (cgt + CT * c)]);
+          s4.x += o4.x;
+          s4.y += o4.y;
+          s4.z += o4.z;
+          s4.w += o4.w;
+        }
+        uu[c][0] = s4.x;
+        uu[c][1] = s4.y;
+        uu[c][2] = s4.z;
+        uu[c][3] = s4.w;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float uu = cok[c][v] ? rowgroup_sum(u[v]) : 0.f;
-        dl[c][v] -= eta * (uu + muv[c][v]);
+        const float g = cok[c][v] ? uu[c][v] : 0.f;
+        dl[c][v] -= eta * (g + muv[c][v]);
         float y = dl[c][v] - smc[c][v];
         float s2 = sm[c][v] + y;
         smc[c][v] = (s2 - sm[c][v]) - y;
@@ -260,7 +324,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
     go = step(t, bufA, bufB, idxA, idxB, scA, scB) && step(t + 1, bufB, bufA, idxB, idxA, scB, scA);
   if (go && t < a.m) go = step(t, bufA, bufB, idxA, idxB, scA, scB);
 
-  if (!s_abort && rg == 0) {  // lanes 0..3 of every wave: one writer per column thread
+  if (!s_abort && wr == 0 && rg == 0) {  // lanes 0..3 of the first wave-row: one writer per column thread
     const float inv_m = 1.0f / (float)a.m;
 #pragma unroll
     for (int q = 0; q < CPT; ++q)
@@ -280,20 +344,20 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   }
 }
 
-template <int RPT, int CPT, bool BF16>
+template <int RPT, int CPT, int WR, bool BF16>
 __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a) {
   const int bid = blockIdx.x;
   if (bid % a.xcd_stride != 0) return;
   const int w = bid / a.xcd_stride;
   if (w >= a.W) return;
   if (a.state->done) return;
-  inner_epoch_body<RPT, CPT, BF16>(a, w);
+  inner_epoch_body<RPT, CPT, WR, BF16>(a, w);
 }
 
 // All problems of a batch: block w * nprob + p is workgroup w of problem p (with nprob a multiple
 // of 8 the W workgroups of a problem share an XCD). The epoch's index stream is slot `slot` of the
 // problem's sampled group.
-template <int RPT, int CPT, bool BF16>
+template <int RPT, int CPT, int WR, bool BF16>
 __global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(const BatchProb* P, int nprob, int slot,
                                                                             int64_t epoch) {
   const int p = blockIdx.x % nprob, w = blockIdx.x / nprob;
@@ -302,10 +366,10 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(cons
   a.idx = P[p].idx + slot * P[p].draws;
   a.scale = P[p].scale + slot * P[p].draws;
   a.step_base = (uint32_t)((uint64_t)epoch * (uint64_t)a.m);
-  inner_epoch_body<RPT, CPT, BF16>(a, w);
+  inner_epoch_body<RPT, CPT, WR, BF16>(a, w);
 }
 
-template <int RPT, int CPT, bool BF16>
+template <int RPT, int CPT, int WR, bool BF16>
 int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, int64_t epoch) {
   dim3 block(kInnerThreads);
   if (W > 1) {
@@ -320,8 +384,8 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
     int resident = dev < kMaxDevices ? resident_per_dev[dev] : 0;
     if (resident == 0) {
       int per_cu = 0, cus = 0;
-      SCS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)inner_epoch_batched_kernel<RPT, CPT, BF16>,
-                                                           kInnerThreads, 0));
+      SCS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void*)inner_epoch_batched_kernel<RPT, CPT, WR, BF16>, kInnerThreads, 0));
       SCS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       resident = per_cu * cus;
       if (dev < kMaxDevices) resident_per_dev[dev] = resident;
@@ -335,49 +399,88 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
     for (int p0 = 0; p0 < nprob; p0 += group) {
       const BatchProb* Pg = P + p0;
       int cnt = nprob - p0 < group ? nprob - p0 : group;
-      inner_epoch_batched_kernel<RPT, CPT, BF16><<<dim3((unsigned)(cnt * W)), block, 0, st>>>(Pg, cnt, slot, epoch);
+      inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<dim3((unsigned)(cnt * W)), block, 0, st>>>(Pg, cnt, slot, epoch);
       SCS_HIP(hipGetLastError());
     }
   } else {
     dim3 grid((unsigned)nprob);
-    inner_epoch_batched_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch);
+    inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch);
     SCS_HIP(hipGetLastError());
   }
   return SCS_OK;
 }
 
-template <int RPT, bool BF16>
-int launch_bc(hipStream_t st, const BatchProb* P, int nprob, int W, int cpt, int slot, int64_t epoch) {
-  switch (cpt) {
-    case 1: return launch_bt<RPT, 1, BF16>(st, P, nprob, W, slot, epoch);
-    case 2: return launch_bt<RPT, 2, BF16>(st, P, nprob, W, slot, epoch);
-    case 3: return launch_bt<RPT, 3, BF16>(st, P, nprob, W, slot, epoch);
-    case 4: return launch_bt<RPT, 4, BF16>(st, P, nprob, W, slot, epoch);
-  }
-  set_error("batched inner loop: column slice too wide (more than 512 columns per workgroup)");
-  return SCS_EINVAL;
-}
-
 // W <= 16 active workgroups (W xcd_stride <= 128 in the grid) are always resident together on the
 // otherwise idle device; an ordinary launch avoids the cooperative queue's extra latency on both
 // sides of every epoch, and every wait is bounded.
-template <int RPT, int CPT, bool BF16>
+template <int RPT, int CPT, int WR, bool BF16>
 int launch_t(hipStream_t st, InnerArgs& a) {
   dim3 grid((unsigned)(a.W * a.xcd_stride)), block(kInnerThreads);
-  inner_epoch_kernel<RPT, CPT, BF16><<<grid, block, 0, st>>>(a);
+  inner_epoch_kernel<RPT, CPT, WR, BF16><<<grid, block, 0, st>>>(a);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
 
-template <int RPT, bool BF16>
-int launch_c(hipStream_t st, InnerArgs& a, int cpt) {
-  switch (cpt) {
-    case 1: return launch_t<RPT, 1, BF16>(st, a);
-    case 2: return launch_t<RPT, 2, BF16>(st, a);
-    case 3: return launch_t<RPT, 3, BF16>(st, a);
-    case 4: return launch_t<RPT, 4, BF16>(st, a);
+// The instantiated layouts: WR = 1 with up to 4 row and 4 column groups per thread (b <= 64,
+// 512-column slices); WR = 2 and 4 with up to 2 column groups (128- and 64-column slices) and up to
+// 4 row groups (b <= 128 and 256).
+struct Layout {
+  int rpt, cpt, wr;
+};
+
+bool layout_ok(const Layout& L) {
+  if (L.rpt != 1 && L.rpt != 2 && L.rpt != 4) return false;
+  if (L.wr == 1) return L.cpt >= 1 && L.cpt <= 4;
+  if (L.wr == 2 || L.wr == 4) return L.cpt >= 1 && L.cpt <= 2;
+  return false;
+}
+
+// Rows per thread rounded up to an instantiated count.
+int round_rpt(int64_t r) { return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 8; }
+
+// Layout for b rows and a slice of `slice` columns: wave_rows > 0 is taken as given; 0 takes the
+// fewest wave-rows that hold b rows (64 each), the rule the batched launches use, so that a single
+// solve and the same problem inside a batch sum in the same order.
+Layout choose_layout(int b, int64_t slice, int wave_rows) {
+  int wr = wave_rows;
+  if (wr <= 0) {
+    wr = 1;
+    while (wr < 4 && cdiv(b, wr) > 64) wr *= 2;
   }
-  set_error("inner loop: column slice too wide (more than 512 columns per workgroup)");
+  Layout L;
+  L.wr = wr;
+  L.rpt = round_rpt(cdiv(cdiv(b, wr), 16));
+  L.cpt = (int)cdiv(slice, 16 * (8 / (wr > 0 ? wr : 1)));
+  return L;
+}
+
+template <bool BF16>
+int launch_layout(hipStream_t st, InnerArgs& a, const Layout& L) {
+#define SCS_INNER_CASE(R, C, WRV) \
+  if (L.rpt == R && L.cpt == C && L.wr == WRV) return launch_t<R, C, WRV, BF16>(st, a);
+  SCS_INNER_CASE(1, 1, 1) SCS_INNER_CASE(1, 2, 1) SCS_INNER_CASE(1, 3, 1) SCS_INNER_CASE(1, 4, 1)
+  SCS_INNER_CASE(2, 1, 1) SCS_INNER_CASE(2, 2, 1) SCS_INNER_CASE(2, 3, 1) SCS_INNER_CASE(2, 4, 1)
+  SCS_INNER_CASE(4, 1, 1) SCS_INNER_CASE(4, 2, 1) SCS_INNER_CASE(4, 3, 1) SCS_INNER_CASE(4, 4, 1)
+  SCS_INNER_CASE(1, 1, 2) SCS_INNER_CASE(1, 2, 2) SCS_INNER_CASE(2, 1, 2) SCS_INNER_CASE(2, 2, 2)
+  SCS_INNER_CASE(4, 1, 2) SCS_INNER_CASE(4, 2, 2)
+  SCS_INNER_CASE(1, 1, 4) SCS_INNER_CASE(1, 2, 4) SCS_INNER_CASE(2, 1, 4) SCS_INNER_CASE(2, 2, 4)
+  SCS_INNER_CASE(4, 1, 4) SCS_INNER_CASE(4, 2, 4)
+#undef SCS_INNER_CASE
+  set_error("inner loop: no kernel for this minibatch, slice width and wave-row count");
+  return SCS_EINVAL;
+}
+
+template <bool BF16>
+int launch_layout_batched(hipStream_t st, const BatchProb* P, int nprob, int W, const Layout& L, int slot,
+                          int64_t epoch) {
+#define SCS_INNER_CASE(R, C, WRV) \
+  if (L.rpt == R && L.cpt == C && L.wr == WRV) return launch_bt<R, C, WRV, BF16>(st, P, nprob, W, slot, epoch);
+  SCS_INNER_CASE(1, 1, 1) SCS_INNER_CASE(1, 2, 1) SCS_INNER_CASE(1, 3, 1) SCS_INNER_CASE(1, 4, 1)
+  SCS_INNER_CASE(2, 1, 1) SCS_INNER_CASE(2, 2, 1) SCS_INNER_CASE(2, 3, 1) SCS_INNER_CASE(2, 4, 1)
+  SCS_INNER_CASE(4, 1, 1) SCS_INNER_CASE(4, 2, 1) SCS_INNER_CASE(4, 3, 1) SCS_INNER_CASE(4, 4, 1)
+  SCS_INNER_CASE(4, 1, 2) SCS_INNER_CASE(4, 2, 2) SCS_INNER_CASE(4, 1, 4) SCS_INNER_CASE(4, 2, 4)
+#undef SCS_INNER_CASE
+  set_error("batched inner loop: no kernel for this minibatch and slice width");
   return SCS_EINVAL;
 }
 
@@ -393,36 +496,51 @@ int inner_default_workgroups(int64_t d) {
 }
 
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
-  if (a.b < 1 || a.b > 64 || a.m < 1 || a.W < 1 || a.W > 16) {
-    set_error("inner loop: need 1 <= b <= 64, m >= 1, 1 <= workgroups <= 16");
+  if (a.b < 1 || a.b > kInnerMaxB || a.m < 1 || a.W < 1 || a.W > 16) {
+    set_error("inner loop: need 1 <= b <= 256, m >= 1, 1 <= workgroups <= 16");
     return SCS_EINVAL;
   }
   if (a.ldx % 4 != 0 || a.ldr != a.ldx) {
     set_error("inner loop: data and regularizer rows need one leading dimension, a multiple of 4");
     return SCS_EINVAL;
   }
+  if (a.wave_rows != 0 && a.wave_rows != 1 && a.wave_rows != 2 && a.wave_rows != 4) {
+    set_error("inner loop: wave_rows must be 0, 1, 2 or 4");
+    return SCS_EINVAL;
+  }
   a.slice = cdiv(cdiv(a.d, a.W), 4) * 4;
-  int cpt = (int)cdiv(a.slice, 128);
-  int rpt = (int)cdiv(a.b, 16);
-  if (rpt <= 1) return bf16 ? launch_c<1, true>(st, a, cpt) : launch_c<1, false>(st, a, cpt);
-  if (rpt <= 2) return bf16 ? launch_c<2, true>(st, a, cpt) : launch_c<2, false>(st, a, cpt);
-  return bf16 ? launch_c<4, true>(st, a, cpt) : launch_c<4, false>(st, a, cpt);
+  const Layout L = choose_layout(a.b, a.slice, a.wave_rows);
+  if (!layout_ok(L)) {
+    set_error("inner loop: slice too wide or minibatch too large for the wave-row count (at most 512 columns "
+              "per workgroup with one wave-row, 128 with two, 64 with four; at most 64 rows per wave-row)");
+    return SCS_EINVAL;
+  }
+  return bf16 ? launch_layout<true>(st, a, L) : launch_layout<false>(st, a, L);
+}
+
+int inner_layout_wave_rows(int b, int64_t d, int W, int wave_rows) {
+  return choose_layout(b, cdiv(cdiv(d, W), 4) * 4, wave_rows).wr;
 }
 
 int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
                                int bf16, int epoch_slot, int64_t epoch) {
   if (nprob < 1) return SCS_OK;
-  if (max_b < 1 || max_b > 64 || W < 1 || W > 16) {
-    set_error("batched inner loop: need 1 <= b <= 64 and 1 <= workgroups <= 16");
+  if (max_b < 1 || max_b > kInnerMaxB || W < 1 || W > 16) {
+    set_error("batched inner loop: need 1 <= b <= 256 and 1 <= workgroups <= 16");
     return SCS_EINVAL;
   }
-  const int cpt = (int)cdiv(max_slice, 128), rpt = (int)cdiv(max_b, 16);
-  if (rpt <= 1) return bf16 ? launch_bc<1, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
-                            : launch_bc<1, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
-  if (rpt <= 2) return bf16 ? launch_bc<2, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
-                            : launch_bc<2, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
-  return bf16 ? launch_bc<4, true>(st, P, nprob, W, cpt, epoch_slot, epoch)
-              : launch_bc<4, false>(st, P, nprob, W, cpt, epoch_slot, epoch);
+  // one wave-row up to b = 64 (any slice up to 512 columns); beyond, 64 rows per wave-row
+  Layout L;
+  L.wr = max_b <= 64 ? 1 : max_b <= 128 ? 2 : 4;
+  L.rpt = L.wr == 1 ? round_rpt(cdiv(max_b, 16)) : 4;
+  L.cpt = (int)cdiv(max_slice, 16 * (8 / L.wr));
+  if (!layout_ok(L)) {
+    set_error("batched inner loop: column slice too wide for the minibatch (b > 64 needs slices of at most "
+              "128 columns, b > 128 at most 64)");
+    return SCS_EINVAL;
+  }
+  return bf16 ? launch_layout_batched<true>(st, P, nprob, W, L, epoch_slot, epoch)
+              : launch_layout_batched<false>(st, P, nprob, W, L, epoch_slot, epoch);
 }
 
 }  // namespace scs

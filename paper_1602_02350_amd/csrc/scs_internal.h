@@ -241,10 +241,17 @@ struct InnerArgs {
   uint32_t step_base;  // value of the step counters before this epoch
   float* wt;           // snapshot (in/out)
   float* wt_prev;      // copy of the incoming snapshot (nullable)
-  uint64_t* xbuf;      // 2 x W x 64 words: (step tag << 32) | partial dot product bits; zeroed per solve
+  uint64_t* xbuf;      // inner_xbuf_words(W) words: (step tag << 32) | partial dot product bits; zeroed per solve
   SolveState* state;
+  int wave_rows;       // 0 = chosen from b and the slice width; 1, 2 or 4: waves split over rows
 };
+// Largest minibatch of the inner loop, and the exchange words its workgroups post (two step parities
+// x W workgroups x kInnerMaxB rows).
+constexpr int kInnerMaxB = 256;
+inline int64_t inner_xbuf_words(int W) { return (int64_t)2 * W * kInnerMaxB; }
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
+// wave-row count launch_inner_epoch uses for (b, d, W, requested wave_rows)
+int inner_layout_wave_rows(int b, int64_t d, int W, int wave_rows);
 int inner_default_workgroups(int64_t d);
 
 // ---------------------------------------------------------------- allocation-free entry (noalloc.hip)

@@ -239,7 +239,7 @@ def _injected_rows(X, lam_reg, Pm, ldt, bf16):
     return dev_rows[0], dev_rows[1], vals[0], vals[1]
 
 
-def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed):
+def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed, wave_rows=0):
     """One inner loop (Alg. 1) on the GPU and in the oracle from the same rows, snapshot, snapshot
     gradient, step and index stream; the averaged step is compared element by element."""
     n, d = X.shape
@@ -255,7 +255,7 @@ def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed):
     idx = inputs.index_stream(n + d, m * b, seed=seed + 1)
     wt = dev(wt0)
     ctx.svrg_epoch(n, d, Xt_d, reg_d, dev(beta32), dev(mu64), dev(idx, torch.int32), m, b, eta, average=True,
-                   workgroups=W, wt=wt)
+                   workgroups=W, wt=wt, wave_rows=wave_rows)
     trace = []
     wo, _ = svrg.svrg(comp, wt0, m, eta, 1, b, lambda s: idx, average=True, q=q, trace=trace)
     step_o = wo - wt0
@@ -268,18 +268,26 @@ def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed):
     scale = epoch_scale(rows, 1.0 / (n * q), idx, trace, wt0, mu64, eta, b)
     scale = 8.0 * scale + 2 * U32 * (np.abs(wo) + np.abs(step_o))
     ratio = np.abs(step_g - step_o) / scale
-    print(f"\n[epoch n={n} d={d} b={b} m={m} W={W} bf16={bf16}] max |step - step_o| / bound = {ratio.max():.3f}; "
+    print(f"\n[epoch n={n} d={d} b={b} m={m} W={W} wave_rows={wave_rows} bf16={bf16}] "
+          f"max |step - step_o| / bound = {ratio.max():.3f}; "
           f"relative step error {rel(step_g, step_o):.2e}")
     assert np.all(ratio <= 1.0), (int(np.argmax(ratio)), float(ratio.max()))
 
 
-@pytest.mark.parametrize("n,d,k,b,W,bf16,ldt", [(400, 24, 4, 8, 1, False, 24), (2000, 100, 10, 64, 1, False, 100),
-                                                (2000, 100, 10, 64, 2, False, 128), (1500, 257, 12, 33, 3, False, 260),
-                                                (2000, 100, 10, 64, 1, True, 128), (900, 37, 0, 5, 1, False, 40),
-                                                (400, 24, 4, 8, 16, False, 24), (700, 61, 5, 40, 15, True, 64)])
-def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16, ldt):
+@pytest.mark.parametrize("n,d,k,b,W,bf16,ldt,wr", [
+    (400, 24, 4, 8, 1, False, 24, 0), (2000, 100, 10, 64, 1, False, 100, 0),
+    (2000, 100, 10, 64, 2, False, 128, 0), (1500, 257, 12, 33, 3, False, 260, 0),
+    (2000, 100, 10, 64, 1, True, 128, 0), (900, 37, 0, 5, 1, False, 40, 0),
+    (400, 24, 4, 8, 16, False, 24, 0), (700, 61, 5, 40, 15, True, 64, 0),
+    # minibatches past 64 rows (two and four wave-rows) and every layout on one shape
+    (3000, 100, 10, 100, 1, False, 100, 2), (3000, 100, 10, 128, 2, True, 128, 2),
+    (4000, 130, 10, 200, 3, False, 132, 4), (4000, 61, 5, 256, 1, False, 64, 4),
+    (2000, 100, 10, 37, 2, False, 100, 1), (2000, 100, 10, 37, 2, False, 100, 2),
+    (2000, 100, 10, 37, 2, False, 100, 4), (1500, 61, 5, 150, 15, True, 64, 4)])
+def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16, ldt, wr):
     """Small and ragged shapes, including more workgroups than column quads (W = 16 at d = 24 and
-    W = 15 at d = 61: the last workgroups own no column and only take part in the exchange)."""
+    W = 15 at d = 61: the last workgroups own no column and only take part in the exchange), minibatches
+    up to 256 rows and each split of a workgroup's waves over rows (wr wave-rows; 0 = the default)."""
     P = _problem(n, d, alpha=2.0, seed=13 + d)
     lam_reg = 1e-3
     if k:
@@ -287,7 +295,7 @@ def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16, ld
         Pm = precond.sketched_preconditioner(U.astype(np.float32).astype(np.float64), lt, lam_reg)
     else:
         Pm = np.eye(d)
-    _epoch_parity(ctx, P.X, P.y, lam_reg, Pm, b, 3 * n // b, W, bf16, ldt, 4.0, seed=n)
+    _epoch_parity(ctx, P.X, P.y, lam_reg, Pm, b, 3 * n // b, W, bf16, ldt, 4.0, seed=n, wave_rows=wr)
 
 
 @pytest.fixture(scope="module")
@@ -302,11 +310,16 @@ def bench_shape_rows():
 
 @pytest.mark.parametrize("W", [16, 8])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_epoch_at_the_benchmark_launch_shape(ctx, bench_shape_rows, W, bf16):
-    """The inner loop in the launch configuration the benchmark times (n = 100000, d = 1000, b = 64,
-    m = 98 steps, 16 or 8 cooperating workgroups of 64 or 128 columns, rows padded to 1024 columns)."""
+@pytest.mark.parametrize("b,wr", [(64, 0), (64, 1), (128, 2), (256, 4)])
+def test_epoch_at_the_benchmark_launch_shape(ctx, bench_shape_rows, W, bf16, b, wr):
+    """The inner loop at the benchmark's shape (n = 100000, d = 1000, rows padded to 1024 columns) with
+    16 or 8 cooperating workgroups of 64 or 128 columns, minibatches of 64 to 256 rows and the wave-row
+    split each uses; m = 6272 / b steps (98 at b = 64, the benchmark's epoch)."""
     P, Pm, cfg = bench_shape_rows
-    _epoch_parity(ctx, P.X, P.y, cfg["lam"], Pm, 64, 98, W, bf16, 1024, 64.0, seed=101)
+    if wr == 4 and W == 8:
+        pytest.skip("four wave-rows take slices of at most 64 columns")
+    _epoch_parity(ctx, P.X, P.y, cfg["lam"], Pm, b, 6272 // b, W, bf16, 1024, 64.0, seed=101,
+                  wave_rows=wr)
 
 
 # ------------------------------------------------------------------ the paper's synthetic data
