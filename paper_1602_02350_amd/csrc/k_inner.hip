@@ -34,6 +34,15 @@ constexpr uint32_t kPollBudget = 1u << 22;
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 
+typedef __attribute__((address_space(1))) const char gchar;
+typedef float f32x4_v __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const f32x4_v gf32x4;
+typedef __attribute__((address_space(1))) const u32x2_v gu32x2;
+typedef __attribute__((address_space(1))) const int32_t gint32;
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) uint64_t guint64;
+
 __device__ __forceinline__ float f4get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 
 // Sum of v over the 16 lanes of the wave with the same lane % 4 (the 16 row groups sharing a
@@ -77,7 +86,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   // wave index made provably uniform so that wave-row and exchange-wave tests are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / WC;
-  const bool xwave = wave % WC == 0;        // this wave runs its wave-row's exchange
+  const bool ldwave = wave % WC == 0;       // this wave stages its wave-row's indices and weights
   const int r0 = wr * RW;
   const int rg = lane >> 2;                 // row group
   const int cgt = (wave % WC) * 4 + (lane & 3);
@@ -86,7 +95,11 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   const int64_t c_begin = (int64_t)w * a.slice;
   const int64_t c_end = c_begin + a.slice < a.d ? c_begin + a.slice : a.d;
   const int64_t mlast = a.m - 1;
-  uint64_t* xb = a.xbuf;
+  // the pointers used every step are in the global address space, so their loads are not flat loads
+  // (which an LDS barrier's wait would also wait for)
+  guint64* xb = (guint64*)a.xbuf;
+  const gint32* gidx = (const gint32*)a.idx;
+  const gfloat* gscale = (const gfloat*)a.scale;
   const char* xt_base = reinterpret_cast<const char*>(a.Xt);
   // base for regularizer rows, offset so that row i >= n is at reg_base + i * ld (pointer arithmetic
   // done on integers; only ever dereferenced for i >= n)
@@ -96,20 +109,24 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 
   __shared__ __align__(16) float pd[WR * RW * PDS];
   __shared__ float gam[WR * RW];
-  __shared__ __align__(16) int32_t s_idx[4][WR][16][4];  // [step slot][wave-row][row group][q], by the exchange waves
+  __shared__ __align__(16) int32_t s_idx[4][WR][16][4];  // [step slot][wave-row][row group][q]
+  __shared__ float s_sc[2][WR * RW];                       // weights 1/(n q_i) of the rows of two steps
   __shared__ __align__(16) float red[WR > 1 ? WR : 1][WR > 1 ? CS : 4];
   __shared__ int s_abort;
 
   float dl[CPT][4], sm[CPT][4], smc[CPT][4], muv[CPT][4], w0[CPT][4];
   int64_t col[CPT];
   uint64_t colb[CPT];   // byte offset of the 4 columns loaded (inside the slice, a multiple of 4)
+  bool cin[CPT];        // the column group starts inside the slice
   bool cok[CPT][4];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     col[q] = c_begin + 4 * (cgt + CT * q);
-    // columns past the slice (or past d, for a workgroup whose slice starts beyond the last column)
-    // load from column 0, which every row has; their values are masked out by cok
-    colb[q] = (uint64_t)(col[q] < c_end ? col[q] : 0) * ES;
+    // column groups past the slice (or past d, for a workgroup whose slice starts beyond the last
+    // column) all load the first 16 bytes of the first data row, which stay in the CU's cache; their
+    // values are masked out by cok
+    cin[q] = col[q] < c_end;
+    colb[q] = (uint64_t)(cin[q] ? col[q] : 0) * ES;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int64_t c = col[q] + v;
@@ -121,8 +138,6 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
       smc[q][v] = 0.f;
     }
   }
-  // a wave whose column threads all lie past the slice skips its row loads (its values are masked)
-  const bool wave_cols = (int64_t)4 * (wave % WC) * 4 < c_end - c_begin;
   const float eta = a.eta_from_state
                         ? (float)ldexp(a.step_scale * (double)a.n / a.state->beta_sum, -a.state->backoffs)
                         : (float)a.eta;
@@ -130,47 +145,53 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 
   // Row loads are unconditional from in-bounds addresses: rows j >= b get coefficient 0 and
   // columns outside the slice are zeroed before use.
+  // Row loads go through global-address-space pointers: a generic (flat) load would also count as an
+  // LDS operation, and every LDS barrier's wait would then wait for the rows prefetched for the next step.
   auto load_rows = [&](int slot, float4 (&buf)[RPT][CPT]) {
-    if (!wave_cols) return;
     const int4 i0 = *reinterpret_cast<const int4*>(&s_idx[slot][wr][rg][0]);
     const int32_t ix[4] = {i0.x, i0.y, i0.z, i0.w};
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const uint32_t i = (uint32_t)ix[q] < NR ? (uint32_t)ix[q] : 0u;
-      const char* rowp = (i < n32 ? xt_base : reg_base) + (uint64_t)i * ldb;
+      const gchar* rowp = (const gchar*)((i < n32 ? xt_base : reg_base) + (uint64_t)i * ldb);
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
+        const gchar* p = cin[c] ? rowp + colb[c] : (const gchar*)xt_base;
         if constexpr (BF16) {
-          uint2 u = *reinterpret_cast<const uint2*>(rowp + colb[c]);
-          buf[q][c] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                                  __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+          const u32x2_v u = *reinterpret_cast<const gu32x2*>(p);
+          buf[q][c] = make_float4(__uint_as_float(u[0] << 16), __uint_as_float(u[0] & 0xffff0000u),
+                                  __uint_as_float(u[1] << 16), __uint_as_float(u[1] & 0xffff0000u));
         } else {
-          buf[q][c] = *reinterpret_cast<const float4*>(rowp + colb[c]);
+          const f32x4_v x = *reinterpret_cast<const gf32x4*>(p);
+          buf[q][c] = make_float4(x[0], x[1], x[2], x[3]);
         }
       }
     }
   };
 
-  // exchange-wave lane j serves row r0 + j of the step (j < RW); jj clamps it to a drawn row
+  // The exchange of a wave-row's partial sums runs in a wave with no column of the slice when the
+  // wave-row has one (its row loads all hit the cache, so its polls, which complete in order after
+  // them, do not wait for rows gathered from memory), else in the wave-row's first wave.
+  const bool xwave = (wave % WC) == ((int64_t)16 * (WC - 1) >= c_end - c_begin ? WC - 1 : 0);
+  // Lane j of the exchange and staging waves serves row r0 + j of the step (j < RW); jj clamps it to a
+  // drawn row
   const int myrow = r0 + lane;
   const bool rowok = lane < RW && myrow < b;
   const int jj = rowok ? myrow : b - 1;
   const int srg = lane & 15, sq = lane >> 4;  // where lane j stages its row's index (j = srg + 16 sq)
-  // exchange waves, two-slot rings alternating like the row buffers: a step consumes idxX (index of
-  // step t+2) and scX (scale of step t), both loaded one step earlier, and loads the other slot
+  // Staging waves, two-slot rings alternating like the row buffers: step t stages idxX (index of step
+  // t+2) and scX (weight of step t+1), both loaded one step earlier together with the rows, and loads
+  // the other slot
   int32_t idxA = 0, idxB = 0;
   float scA = 0.f, scB = 0.f;
-  if (xwave) {
-    s_idx[0][wr][srg][sq] = rowok ? a.idx[jj] : 0;
-    s_idx[1][wr][srg][sq] = rowok ? a.idx[(1 < mlast ? 1 : mlast) * b + jj] : 0;
-    idxA = a.idx[(2 < mlast ? 2 : mlast) * b + jj];
-    scA = a.scale[jj];
+  if (ldwave) {
+    s_idx[0][wr][srg][sq] = rowok ? gidx[jj] : 0;
+    s_idx[1][wr][srg][sq] = rowok ? gidx[(1 < mlast ? 1 : mlast) * b + jj] : 0;
+    if (lane < RW) s_sc[0][myrow] = gscale[jj];
   }
+  idxA = gidx[(2 < mlast ? 2 : mlast) * b + jj];
+  scA = gscale[(1 < mlast ? 1 : mlast) * b + jj];
   float4 bufA[RPT][CPT], bufB[RPT][CPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q)
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) bufA[q][c] = bufB[q][c] = make_float4(0.f, 0.f, 0.f, 0.f);
   lds_barrier();
   load_rows(0, bufA);
 
@@ -179,6 +200,12 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
   auto step = [&](int64_t t, float4 (&cur)[RPT][CPT], float4 (&nxt)[RPT][CPT], int32_t& idx_use, int32_t& idx_next,
                   float& sc_use, float& sc_next) -> bool {
     load_rows((int)((t + 1) & 3), nxt);
+    // consumed at the next step, queued behind this step's row loads. Every wave issues them (only the
+    // staging wave uses them; the others hit the cache): with the same loads in flight in every wave,
+    // the compiler's count of outstanding loads is exact, and the wait for this step's rows does not
+    // also wait for the rows just prefetched.
+    idx_next = gidx[(t + 3 < mlast ? t + 3 : mlast) * b + jj];
+    sc_next = gscale[(t + 2 < mlast ? t + 2 : mlast) * b + jj];
     // columns outside the slice (and padding past d) may hold anything: zero them, then partial
     // dot products over this workgroup's columns
 #pragma unroll
@@ -197,9 +224,14 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
         for (int v = 0; v < 4; ++v) p = fmaf(f4get(cur[q][c], v), dl[c][v], p);
       pd[(r0 + rg + 16 * q) * PDS + cgt] = p;
     }
+    if (ldwave) {
+      s_idx[(t + 2) & 3][wr][srg][sq] = rowok ? idx_use : 0;
+      if (lane < RW) s_sc[(t + 1) & 1][myrow] = sc_use;
+    }
     lds_barrier();
     if (xwave) {
       float cl = 0.f;
+      const float scl = lane < RW ? s_sc[t & 1][myrow] : 0.f;  // read before the exchange, used after it
       if (lane < RW) {
 #pragma unroll
         for (int g = 0; g < CT; g += 4) {
@@ -212,16 +244,18 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
         // valid once its tag is this step's, so no fence is needed
         const int par = (int)(t & 1);
         const uint32_t target = a.step_base + (uint32_t)t + 1u;
-        uint64_t* slot = xb + (int64_t)par * W * kInnerMaxB + myrow;
+        // words of (parity, wave-row, workgroup v) in blocks of 64 rows: a lane's W words are 512 bytes
+        // apart, which spreads them over the cache channels
+        guint64* slot = xb + ((int64_t)(par * WR + wr) * W) * 64 + lane;
         const bool xrow = lane < RW;
         if (xrow)
-          __hip_atomic_store(&slot[(int64_t)w * kInnerMaxB], ((uint64_t)target << 32) | __float_as_uint(cl),
+          __hip_atomic_store(&slot[(int64_t)w * 64], ((uint64_t)target << 32) | __float_as_uint(cl),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t xv[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
           xv[v] = (v < W && xrow)
-                      ? __hip_atomic_load(&slot[v * kInnerMaxB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      ? __hip_atomic_load(&slot[v * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                       : ((uint64_t)target << 32);
         uint32_t polls = 0;
         bool bad = false;
@@ -239,7 +273,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
 #pragma unroll
           for (int v = 0; v < 16; ++v)
             if ((uint32_t)(xv[v] >> 32) != target)
-              xv[v] = __hip_atomic_load(&slot[v * kInnerMaxB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              xv[v] = __hip_atomic_load(&slot[v * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (__any(bad) && lane == 0) {
           s_abort = 1;
@@ -252,13 +286,7 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
           if (v < W) sum += __uint_as_float((uint32_t)xv[v]);  // same order in every workgroup
         cl = sum;
       }
-      if (lane < RW) {
-        gam[myrow] = rowok ? sc_use * cl / (float)b : 0.f;
-        s_idx[(t + 2) & 3][wr][srg][sq] = rowok ? idx_use : 0;
-      }
-      // loads consumed at the next step, issued after the polls so the polls never wait for them
-      idx_next = a.idx[(t + 3 < mlast ? t + 3 : mlast) * b + jj];
-      sc_next = a.scale[(t + 1 < mlast ? t + 1 : mlast) * b + jj];
+      if (lane < RW) gam[myrow] = rowok ? scl * cl / (float)b : 0.f;
     }
     lds_barrier();
     if (s_abort) return false;

@@ -246,7 +246,7 @@ struct InnerArgs {
   int wave_rows;       // 0 = chosen from b and the slice width; 1, 2 or 4: waves split over rows
 };
 // Largest minibatch of the inner loop, and the exchange words its workgroups post (two step parities
-// x W workgroups x kInnerMaxB rows).
+// x up to 4 wave-rows x W workgroups x 64 rows = 2 W kInnerMaxB).
 constexpr int kInnerMaxB = 256;
 inline int64_t inner_xbuf_words(int W) { return (int64_t)2 * W * kInnerMaxB; }
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
