@@ -201,6 +201,22 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
                    scs_report* report);
 
 /*
+ * Autotuner of the solver's free parameters on the caller's problem: the minibatch b (32, 64, 128),
+ * the step scale c (eta = c / beta_hat, Alg. 1; 1 .. 512), the epoch length m = epoch_factor n / b
+ * (epoch_factor 1/64 .. 2; the paper takes m proportional to n, Sec. 6) and the inner loop's launch
+ * shape (workgroups and wave-rows, timed per b). Each candidate is a full scs_svrg_solve to the stop
+ * rule of `base` (certificate or gap; eps as given), scored by its wall time; the scan over c for a
+ * (b, m) stops at the first divergence or step halving, and once the time has risen twice in a row.
+ * Candidates draw Omega and the index stream from a seed derived from base->seed, never from it.
+ *   base (nullable): the options to start from; tuned (HOST): receives them with batch, step_scale,
+ *   epoch_factor (steps = 0), workgroups and wave_rows set, seed/timing/epoch_ms from base.
+ *   best_ms (HOST, nullable): the winner's wall time in milliseconds.
+ * Returns SCS_NOT_CONVERGED if no candidate met the stop rule within base->max_epochs.
+ */
+int scs_autotune(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
+                 int k, double eps, const scs_opts* base, scs_opts* tuned, double* best_ms);
+
+/*
  * Many independent ridge problems (uneven n, d, lambda, k) solved together: every problem's
  * sketch, preconditioning and SVRG epochs run as in scs_svrg_solve, with the epochs of all
  * problems advancing together inside shared launches (one persistent inner-loop launch per

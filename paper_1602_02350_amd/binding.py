@@ -25,7 +25,7 @@ EXPORTED = [
     "scs_opts_default", "scs_status_string", "scs_last_error", "scs_create", "scs_destroy",
     "scs_sketch_build", "scs_precondition_apply", "scs_full_gradient", "scs_svrg_epoch",
     "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched", "scs_svrg_solve_path",
-    "scs_full_gradient_noalloc",
+    "scs_full_gradient_noalloc", "scs_autotune",
 ]
 
 
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_precondition_apply.argtypes = [vp, vp, i64, i64, i64, vp, vp, i32, dbl, i32, vp, vp, i64, vp]
     L.scs_full_gradient.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
     L.scs_full_gradient_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
+    L.scs_autotune.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), P(ScsOpts), P(dbl)]
     L.scs_svrg_epoch.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, dbl, i32, i32, i32, vp]
     L.scs_sample_indices.argtypes = [vp, vp, i64, u64, i32, i64, vp]
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
@@ -324,6 +325,19 @@ class Context:
                                                 float(eps), fs, ctypes.byref(o), _ptr(W), reps),
                     "scs_svrg_solve_path")
         return rc, W, [r.as_dict() for r in reps]
+
+    def autotune(self, X, y, lam_reg: float, k: int, eps: float, **opts):
+        """Tuned options (a dict of the scs_opts fields) and the winner's wall time in milliseconds."""
+        _dev(X, torch.float32)
+        n, d = X.shape
+        o = self.opts(**opts)
+        t = ScsOpts()
+        ms = ctypes.c_double()
+        _check(self._L.scs_autotune(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), float(lam_reg), int(k), float(eps),
+                                    ctypes.byref(o), ctypes.byref(t), ctypes.byref(ms)), "scs_autotune", False)
+        tuned = {f: getattr(t, f) for f, _ in ScsOpts._fields_
+                 if f not in ("omega", "indices", "trace_w", "epoch_ms")}
+        return tuned, ms.value
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
         _dev(X, torch.float32)

@@ -4,6 +4,7 @@
 // only validates arguments, sizes scratch buffers, enqueues launches and reads status records.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <algorithm>
 #include <cstdlib>
@@ -893,6 +894,94 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
 int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
                    int k, double eps, const scs_opts* opts, float* w_out, scs_report* report) {
   return svrg_solve_impl(ctx, X, n, d, ldx, y, lambda, k, eps, opts, w_out, report, false);
+}
+
+int scs_autotune(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,
+                 int k, double eps, const scs_opts* base, scs_opts* tuned, double* best_ms_out) {
+  if (!ctx || !y || !tuned) {
+    set_error("autotune: null argument");
+    return SCS_EINVAL;
+  }
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  scs_opts o;
+  scs_opts_default(&o);
+  if (base) o = *base;
+  if (o.omega || o.indices || o.trace_w || o.stop_rule == SCS_STOP_EPOCHS) {
+    set_error("autotune: needs a stopping rule that ends the solve (certificate or gap) and no injected omega, "
+              "indices or trace");
+    return SCS_EINVAL;
+  }
+  o.epoch_ms = nullptr;
+  o.timing = 0;
+  o.steps = 0;
+  o.workgroups = -1;  // every candidate's inner-loop shape is itself timed (cached per (d, b, precision))
+  o.wave_rows = 0;
+  o.seed = o.seed ^ 0x5ca1ab1e5eedull;  // candidates never see the caller's random streams
+  Guard g(ctx->device);
+  WS(wt, float, "tune_w", (size_t)d);
+  // warm-up: first-use workspace and the inner-loop shape for b = 64
+  {
+    scs_opts w0 = o;
+    w0.max_epochs = 1;
+    w0.stop_rule = SCS_STOP_EPOCHS;
+    SCS_CHECK(svrg_solve_impl(ctx, X, n, d, ldx, y, lambda, k, eps, &w0, wt, nullptr, false));
+  }
+  const int bs[] = {32, 64, 128};
+  const double mfs[] = {1.0 / 64, 1.0 / 32, 1.0 / 16, 1.0 / 8, 1.0 / 4, 1.0 / 2, 1.0, 2.0};
+  const double cs[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512};
+  double best = 1e300;
+  scs_opts best_o = o;
+  bool found = false;
+  for (int b : bs) {
+    for (double mf : mfs) {
+      if (mf * (double)n / b < 1.0) continue;
+      int worse = 0;
+      double best_here = 1e300;
+      for (double c : cs) {
+        scs_opts t = o;
+        t.batch = b;
+        t.epoch_factor = mf;
+        t.step_scale = c;
+        scs_report rep;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = svrg_solve_impl(ctx, X, n, d, ldx, y, lambda, k, eps, &t, wt, &rep, false);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rc < 0) return rc;
+        if (rc == SCS_DIVERGED || rep.backoffs > 0) break;  // larger steps only diverge further
+        if (rc == SCS_OK || rc == SCS_SKETCH_RANK_DEFICIENT) {
+          if (ms < best) {
+            best = ms;
+            best_o = t;
+            best_o.workgroups = rep.workgroups;
+            found = true;
+          }
+          if (ms < best_here) {
+            best_here = ms;
+            worse = 0;
+          } else if (++worse >= 2) {
+            break;  // past the best step of this (b, m): the time has risen twice in a row
+          }
+        }
+      }
+    }
+  }
+  if (!found) {
+    set_error("autotune: no candidate reached the stopping rule within max_epochs");
+    return SCS_NOT_CONVERGED;
+  }
+  // the inner-loop shape the solves used (the context's cached choice for this b), then the caller's seed
+  auto it = ctx->tuned_w.find(std::to_string(d) + "/" + std::to_string(best_o.batch) + "/" +
+                              std::to_string(best_o.precision == SCS_PREC_MIXED ? 1 : 0));
+  if (it != ctx->tuned_w.end()) {
+    best_o.workgroups = it->second.first;
+    best_o.wave_rows = it->second.second;
+  }
+  best_o.seed = base ? base->seed : o.seed ^ 0x5ca1ab1e5eedull;
+  best_o.epoch_ms = base ? base->epoch_ms : nullptr;
+  best_o.timing = base ? base->timing : 0;
+  *tuned = best_o;
+  if (best_ms_out) *best_ms_out = best;
+  return SCS_OK;
 }
 
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,

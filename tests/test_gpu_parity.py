@@ -629,3 +629,24 @@ def test_autotuned_workgroups_solve_matches_the_closed_form(ctx):
     assert res.status == binding.OK, res.report
     assert res.report["workgroups"] in (3, 5, 10)   # ceil(300 / 128), ceil(300 / 64), ceil(300 / 32)
     assert ridge.suboptimality(X64, P.lam, host(res.w), ws) <= 1.5e-9
+
+
+# ------------------------------------------------------------------ the in-library autotuner
+def test_autotune_picks_options_that_reach_eps(ctx):
+    """scs_autotune scores (b, c, m, launch shape) by wall time to the stop rule; the options it returns must
+    themselves solve the problem to eps (gap against the oracle's FP64 optimum) with the caller's seed."""
+    P = _problem(6000, 120, alpha=1.5, seed=91)
+    lam, k, eps = 1e-4, 8, 1e-7
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    ws = ridge.closed_form(X64, y64, lam)
+    Ls = ridge.objective(X64, y64, lam, ws)
+    X, y = dev(P.X), dev(P.y)
+    with pytest.raises(binding.ScsError):
+        ctx.autotune(X, y, lam, k, eps, stop_rule=binding.STOP_EPOCHS)
+    tuned, ms = ctx.autotune(X, y, lam, k, eps, stop_rule=binding.STOP_GAP, f_star=Ls, max_epochs=60, seed=7)
+    print(f"\n[autotune] {tuned} {ms:.2f} ms")
+    assert tuned["batch"] in (32, 64, 128) and tuned["step_scale"] > 0 and tuned["epoch_factor"] > 0
+    assert tuned["seed"] == 7
+    r = ctx.svrg_solve(X, y, lam, k, eps, **tuned)
+    assert r.status == binding.OK, r.report
+    assert ridge.objective(X64, y64, lam, host(r.w)) - Ls <= 1.5 * eps
