@@ -108,3 +108,25 @@ def predicted_kappa(eigs, lam, k):
     """(k lambda_k + sum_{i>k} lambda_i)/lam + d.  [Sec. 5.3, Eq. (exactCondSketchCond)]"""
     ev = _f64(eigs)
     return float((k * ev[k - 1] + ev[k:].sum()) / lam + ev.size)
+
+
+def budget_lambdas(eigs, n, k):
+    """The regularization at which each method runs in O~(ndk) time (Sec. 2.2): preconditioned SVRG at
+    lambda = (k lambda_k + sum_{i>k} lambda_i)/(n k)  [Eq. (decay)], plain SVRG at
+    lambda = (sum_i lambda_i)/(n k)  [Eq. (decaySVRG)].
+
+    `eigs` are the eigenvalues of C (any order); k is 1-based. Returns (lambda_precond, lambda_plain).
+    """
+    ev = np.sort(_f64(eigs))[::-1]
+    pre = (k * ev[k - 1] + ev[k:].sum()) / (n * k)
+    plain = ev.sum() / (n * k)
+    return float(pre), float(plain)
+
+
+def budget_lambdas_estimated(top, trace, n, k):
+    """budget_lambdas with only the k largest eigenvalues known (e.g. sketched ones, descending) and the
+    trace of C: the tail sum is trace - sum(top). Equals budget_lambdas when `top` are the exact
+    eigenvalues and `trace` the exact trace. Returns (lambda_precond, lambda_plain)."""
+    t = np.maximum(_f64(top)[:k], 0.0)
+    tail = max(float(trace) - float(t.sum()), 0.0)
+    return float((k * t[k - 1] + tail) / (n * k)), float(float(trace) / (n * k))

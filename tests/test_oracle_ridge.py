@@ -118,3 +118,39 @@ def test_closed_forms_of_a_path_match_single_closed_forms():
             assert abs(L[j, r] - ridge.objective(P.X, Y[r], lam, ws)) <= 1e-10 * abs(L[j, r])
             # stationarity: the gradient vanishes at the solution
             assert np.linalg.norm(ridge.gradient(P.X, Y[r], lam, W[j, r])) < 1e-9
+
+
+# ------------------------------------------------------------------ the bias-complexity rule (Sec. 2.2)
+def test_budget_lambdas_on_hand_example():
+    g = read_golden("budget_lambda_diag.txt")
+    ev = np.array([float(v) for v in g["diag"][0]])
+    n, k = int(g["n"][0][0]), int(g["k"][0][0])
+    pre, plain = ridge.budget_lambdas(ev, n, k)
+    assert pre == pytest.approx(float(Fraction(int(g["pre_num"][0][0]), int(g["pre_den"][0][0]))), rel=1e-15)
+    assert plain == pytest.approx(float(Fraction(int(g["plain_num"][0][0]), int(g["plain_den"][0][0]))), rel=1e-15)
+    # the order in which the eigenvalues are given does not matter
+    assert ridge.budget_lambdas(ev[::-1], n, k) == (pre, plain)
+
+
+@pytest.mark.parametrize("alpha,k", [(1.0, 3), (2.0, 10), (1.5, 1)])
+def test_budget_ratio_is_the_speedup_ratio(alpha, k):
+    """Sec. 2.2: the ratio of the two regularizations is the speed-up ratio of Eq. (ratioRidge)."""
+    ev = np.arange(1, 61, dtype=np.float64) ** -alpha
+    pre, plain = ridge.budget_lambdas(ev, 1000, k)
+    assert plain / pre == pytest.approx(ridge.speedup_ratio(ev, k), rel=1e-13)
+    assert pre <= plain * (1 + 1e-14)  # equal at k = 1
+
+
+def test_budget_from_top_eigenvalues_and_trace():
+    """Knowing only the k largest eigenvalues and tr(C) gives the same values (the tail is the trace minus
+    the top sum); sketched (smaller) top values give a larger tail and so a larger lambda_precond."""
+    P = inputs.make_ridge(400, 12, 1.5, 1e-3, seed=21, dtype=np.float64)
+    C = ridge.correlation(P.X)
+    ev = np.sort(np.linalg.eigvalsh(C))[::-1]
+    k = 4
+    exact = ridge.budget_lambdas(ev, 400, k)
+    est = ridge.budget_lambdas_estimated(ev[:k], np.trace(C), 400, k)
+    assert est == pytest.approx(exact, rel=1e-12)
+    low = ridge.budget_lambdas_estimated(0.9 * ev[:k], np.trace(C), 400, k)
+    assert low[0] > exact[0] * (1 + 1e-9) or ev[k - 1] == 0.0
+    assert low[1] == pytest.approx(exact[1], rel=1e-14)
