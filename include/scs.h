@@ -93,6 +93,19 @@ typedef struct scs_opts {
                              rows, 1, 2 or 4 wave-rows of 8 / wave_rows waves (64 rows each at most; slices of at
                              most 512, 128 or 64 columns); 0 = chosen from b and the slice width, or autotuned
                              together with the workgroups when workgroups = -1 */
+  /* Warm starts and checkpoints (single solves). A solve stopped after S1 epochs with wt_out set, then
+     resumed with w0 = that snapshot, w0_preconditioned = 1 and epoch_offset = S1 (same X, y, lambda, k,
+     seed and options), reproduces the uninterrupted solve bit for bit (the sketch and every epoch's
+     index stream are functions of the seed and the epoch number). */
+  const float* w0;        /* optional device d: start point (default 0). In the original space (w), mapped to
+                             the solver's variable by w~ = P^{1/2} w, unless w0_preconditioned = 1 */
+  int w0_preconditioned;  /* 1: w0 is the solver's own variable w~ (for example a snapshot written to wt_out) */
+  int epoch_offset;       /* epoch s of this call draws the index stream of epoch s + epoch_offset */
+  float* wt_out;          /* optional device d: the final snapshot w~ (the checkpoint to resume from) */
+  int warm_start;         /* scs_svrg_solve_path only: 1 = solve the lambdas one after another in the order given
+                             (largest first is the usual continuation order), each lambda's ny solves starting
+                             from the previous lambda's solutions (a regularization path with warm starts,
+                             Sec. 2.2); 0 = all solves together from 0 */
 } scs_opts;
 
 typedef struct scs_report {
@@ -199,6 +212,20 @@ int scs_gaussian(scs_ctx* ctx, uint64_t seed, int64_t count, float* out);
 int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
                    double lambda, int k, double eps, const scs_opts* opts, float* w_out,
                    scs_report* report);
+
+/*
+ * The bias-complexity rule (Sec. 2.2): the regularization at which each method's runtime is O~(ndk),
+ *   lambda_precond = (k lam_k + sum_{i>k} lam_i) / (n k)   (Eq. (decay), preconditioned SVRG)
+ *   lambda_plain   = (sum_i lam_i) / (n k)                 (Eq. (decaySVRG), plain SVRG),
+ * lam_i the eigenvalues of C = X^T X / n. The k largest come from the sketch (as scs_sketch_build, with
+ * opts), the tail sum is tr(C) minus their sum, and tr(C) = ||X||_F^2 / n (FP64 sum of FP32 row norms).
+ * Sketched values are Rayleigh-Ritz values, at most the true ones, so the tail and lambda_precond err
+ * on the large side. Outputs are HOST doubles; the call waits for its stream.
+ *   k in [1, d], k + p <= min(d, n, 136). Returns SCS_SKETCH_RANK_DEFICIENT (values still written) if the
+ *   sketch lost rank.
+ */
+int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k,
+                                  const scs_opts* opts, double* lambda_precond, double* lambda_plain);
 
 /*
  * Autotuner of the solver's free parameters on the caller's problem: the minibatch b (32, 64, 128),

@@ -25,7 +25,7 @@ EXPORTED = [
     "scs_opts_default", "scs_status_string", "scs_last_error", "scs_create", "scs_destroy",
     "scs_sketch_build", "scs_precondition_apply", "scs_full_gradient", "scs_svrg_epoch",
     "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched", "scs_svrg_solve_path",
-    "scs_full_gradient_noalloc", "scs_autotune",
+    "scs_full_gradient_noalloc", "scs_autotune", "scs_regularization_for_budget",
 ]
 
 
@@ -51,6 +51,11 @@ class ScsOpts(ctypes.Structure):
         ("implicit_apply", ctypes.c_int),
         ("uniform_sampling", ctypes.c_int),
         ("wave_rows", ctypes.c_int),
+        ("w0", ctypes.c_void_p),
+        ("w0_preconditioned", ctypes.c_int),
+        ("epoch_offset", ctypes.c_int),
+        ("wt_out", ctypes.c_void_p),
+        ("warm_start", ctypes.c_int),
     ]
 
 
@@ -120,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_full_gradient.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
     L.scs_full_gradient_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, i32, dbl, vp, vp, P(dbl)]
     L.scs_autotune.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), P(ScsOpts), P(dbl)]
+    L.scs_regularization_for_budget.argtypes = [vp, vp, i64, i64, i64, i32, P(ScsOpts), P(dbl), P(dbl)]
     L.scs_svrg_epoch.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, dbl, i32, i32, i32, vp]
     L.scs_sample_indices.argtypes = [vp, vp, i64, u64, i32, i64, vp]
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
@@ -203,7 +209,7 @@ class Context:
         o = ScsOpts()
         self._L.scs_opts_default(ctypes.byref(o))
         for key, v in kw.items():
-            if key in ("omega", "indices", "trace_w"):
+            if key in ("omega", "indices", "trace_w", "w0", "wt_out"):
                 v = None if v is None else v.data_ptr()
             if not hasattr(o, key):
                 raise TypeError(f"unknown option {key}")
@@ -326,6 +332,17 @@ class Context:
                     "scs_svrg_solve_path")
         return rc, W, [r.as_dict() for r in reps]
 
+    def regularization_for_budget(self, X, k: int, **opts):
+        """(lambda_precond, lambda_plain, status) of the O~(ndk) budget (Sec. 2.2)."""
+        _dev(X, torch.float32)
+        n, d = X.shape
+        o = self.opts(**opts)
+        a, b = ctypes.c_double(), ctypes.c_double()
+        rc = _check(self._L.scs_regularization_for_budget(self._h, _ptr(X), n, d, X.stride(0), int(k),
+                                                          ctypes.byref(o), ctypes.byref(a), ctypes.byref(b)),
+                    "scs_regularization_for_budget")
+        return a.value, b.value, rc
+
     def autotune(self, X, y, lam_reg: float, k: int, eps: float, **opts):
         """Tuned options (a dict of the scs_opts fields) and the winner's wall time in milliseconds."""
         _dev(X, torch.float32)
@@ -336,7 +353,7 @@ class Context:
         _check(self._L.scs_autotune(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), float(lam_reg), int(k), float(eps),
                                     ctypes.byref(o), ctypes.byref(t), ctypes.byref(ms)), "scs_autotune", False)
         tuned = {f: getattr(t, f) for f, _ in ScsOpts._fields_
-                 if f not in ("omega", "indices", "trace_w", "epoch_ms")}
+                 if f not in ("omega", "indices", "trace_w", "epoch_ms", "w0", "wt_out")}
         return tuned, ms.value
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:

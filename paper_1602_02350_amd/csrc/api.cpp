@@ -547,6 +547,40 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
   return SCS_OK;
 }
 
+int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k,
+                                  const scs_opts* opts, double* lambda_precond, double* lambda_plain) {
+  if (!ctx || !lambda_precond || !lambda_plain) return SCS_EINVAL;
+  SCS_CHECK(validate_problem(X, n, d, ldx, 1.0));
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  const int l = k + o.oversample;
+  if (k < 1 || k > d || o.oversample < 0 || l > d || l > n || l > 136) {
+    set_error("budget regularization: need 1 <= k, k + p <= min(d, n, 136)");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  bool rd = false;
+  SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, false, &rd));
+  // ||X||_F^2 in FP64: the sampler's sum of the FP32 row norms
+  WS(rn, float, "budget_rownorm", (size_t)n);
+  WS(cum, uint64_t, "budget_cum", (size_t)n);
+  WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(n));
+  WS(state, SolveState, "budget_state", 1);
+  WS(out, double, "budget_out", 2);
+  SCS_CHECK(launch_zero3(st, state, (int64_t)sizeof(SolveState), nullptr, 0, nullptr, 0));
+  SCS_CHECK(launch_rownorm(st, X, n, d, ldx, rn));
+  SCS_CHECK(launch_sampler_prepare(st, rn, n, cum, scr, sampler_scratch_len(n), state));
+  SCS_CHECK(launch_budget_lambda(st, ws<double>(ctx, "lam", 0), k, state, n, out));
+  double h[2] = {0.0, 0.0};
+  SCS_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  *lambda_precond = h[0];
+  *lambda_plain = h[1];
+  return rd ? SCS_SKETCH_RANK_DEFICIENT : SCS_OK;
+}
+
 int scs_full_gradient_noalloc(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y,
                               const float* U, const double* lam, int k, double lambda, const float* wt,
                               float* grad_out, double* obj_out) {
@@ -635,8 +669,9 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     return SCS_EINVAL;
   }
   if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
-      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX) {
-    set_error("bad options: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0");
+      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2 || n + d > INT32_MAX || o.epoch_offset < 0 ||
+      (k > 256 && o.w0 && !o.w0_preconditioned)) {
+    set_error("bad options: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0, epoch_offset >= 0");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -749,6 +784,14 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   WS(xbuf, uint64_t, "xbuf", (size_t)inner_xbuf_words(16));
   SCS_CHECK(launch_zero3(st, wt, (int64_t)sizeof(float) * d, wt_prev, (int64_t)sizeof(float) * d, xbuf,
                          (int64_t)sizeof(uint64_t) * inner_xbuf_words(16)));
+  if (o.w0) {
+    // start point: the solver's variable as given, or w~ = P^{1/2} w0 (P = I when k = 0)
+    if (o.w0_preconditioned || k_used == 0)
+      SCS_HIP(hipMemcpyAsync(wt, o.w0, sizeof(float) * d, hipMemcpyDeviceToDevice, st));
+    else
+      SCS_CHECK(launch_pmhalf_inv(st, UT32, lam, k_used, d, lambda, o.w0, wt));
+    SCS_HIP(hipMemcpyAsync(wt_prev, wt, sizeof(float) * d, hipMemcpyDeviceToDevice, st));
+  }
 
   InnerArgs a{};
   a.n = n;
@@ -795,7 +838,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     if (slot == 0) {
       const int64_t cnt = (int64_t)std::min(kSampleGroup, S - s) * mb;
       if (o.indices) SCS_CHECK(launch_index_scale(st, cum, N, n, o.indices + (int64_t)s * mb, cnt, scale, state));
-      else SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s, mb, cnt, idxb, scale, state));
+      else SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s + o.epoch_offset, mb, cnt, idxb, scale, state));
     }
     a.idx = o.indices ? o.indices + (int64_t)s * mb : idxb + slot * mb;
     a.scale = scale + slot * mb;
@@ -820,6 +863,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   }
   // w = P^{-1/2} w~ with the same routine that produced the gradient's evaluation point
   SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w_out, nullptr, tmp, nullptr));
+  if (o.wt_out) SCS_HIP(hipMemcpyAsync(o.wt_out, wt, sizeof(float) * d, hipMemcpyDeviceToDevice, st));
   SCS_HIP(hipEventRecord(ev_end, st));
   SolveState hs;
   SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -994,8 +1038,8 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   scs_opts o;
   scs_opts_default(&o);
   if (opts) o = *opts;
-  if (o.omega || o.indices || o.trace_w) {
-    set_error("batched solve: omega, indices and trace_w must be NULL");
+  if (o.omega || o.indices || o.trace_w || o.w0 || o.wt_out || o.epoch_offset != 0 || o.warm_start) {
+    set_error("batched solve: omega, indices, trace_w, w0, wt_out must be NULL, epoch_offset and warm_start 0");
     return SCS_EINVAL;
   }
   if (o.stop_rule == SCS_STOP_GAP && !f_star) {
@@ -1345,9 +1389,12 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   return worst;
 }
 
-int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y, int ny,
-                        const double* lambdas, int nl, int k, double eps, const double* f_star, const scs_opts* opts,
-                        float* W_out, scs_report* reports) {
+// The regularization path. reuse_sketch: the sketch buffers of the context already hold this X's
+// sketch (an earlier stage of a warm-started path). W0 (device ny x d, nullable): start points in the
+// original space, w~ = P_lambda^{1/2} w0 for every lambda of the call.
+static int path_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y, int ny,
+                     const double* lambdas, int nl, int k, double eps, const double* f_star, const scs_opts* opts,
+                     float* W_out, scs_report* reports, bool reuse_sketch, const float* W0) {
   if (!ctx || !Y || !lambdas || !W_out || ny < 1 || nl < 1) {
     set_error("null argument, ny < 1 or nl < 1");
     return SCS_EINVAL;
@@ -1440,7 +1487,7 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   // ---- one sketch for every lambda (Alg. 2 does not involve lambda)
   int k_used = k;
   bool rank_def = false;
-  if (k > 0) {
+  if (k > 0 && !reuse_sketch) {
     SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, &rank_def));
     if (rank_def) k_used = 0;
   }
@@ -1552,6 +1599,13 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   SCS_HIP(hipMemcpyAsync(desc, hp.data(), sizeof(BatchProb) * P, hipMemcpyHostToDevice, st));
   SCS_HIP(hipMemcpyAsync(draw_pre, dpre.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, st));
   const float* W32 = vec_all + (int64_t)2 * P * d;
+  if (W0) {
+    for (int p = 0; p < P; ++p) {
+      SCS_CHECK(launch_pmhalf_inv(st, k_used > 0 ? ut : nullptr, lam64, k_used, d, lambdas[p / ny], W0 + (int64_t)(p % ny) * d,
+                                  hp[p].wt));
+      SCS_HIP(hipMemcpyAsync(hp[p].wt_prev, hp[p].wt, sizeof(float) * d, hipMemcpyDeviceToDevice, st));
+    }
+  }
 
   // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X
   constexpr int kLookahead = 3;
@@ -1638,6 +1692,33 @@ int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int6
   }
   if (worst == SCS_ENONFINITE) set_error("non-finite value in X or Y");
   if (worst == SCS_EDEVICE) set_error("inner loop: a cross-workgroup wait exceeded its budget");
+  return worst;
+}
+
+int scs_svrg_solve_path(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* Y, int ny,
+                        const double* lambdas, int nl, int k, double eps, const double* f_star, const scs_opts* opts,
+                        float* W_out, scs_report* reports) {
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.w0 || o.wt_out || o.epoch_offset != 0) {
+    set_error("path solve: w0, wt_out and epoch_offset apply to single solves (use warm_start for the path)");
+    return SCS_EINVAL;
+  }
+  if (!o.warm_start || nl == 1 || !W_out || ny < 1 || nl < 1 || !lambdas)
+    return path_impl(ctx, X, n, d, ldx, Y, ny, lambdas, nl, k, eps, f_star, opts, W_out, reports, false, nullptr);
+  // Continuation: lambda j's ny solves start from lambda j-1's solutions; one sketch for all lambdas.
+  std::vector<scs_report> local(reports ? 0 : (size_t)ny);
+  int worst = SCS_OK, k_stage = k;
+  for (int j = 0; j < nl; ++j) {
+    scs_report* rj = reports ? reports + (int64_t)j * ny : local.data();
+    const int rc = path_impl(ctx, X, n, d, ldx, Y, ny, lambdas + j, 1, k_stage, eps, f_star ? f_star + (int64_t)j * ny : nullptr,
+                             &o, W_out + (int64_t)j * ny * d, rj, j > 0 && k_stage > 0,
+                             j > 0 ? W_out + (int64_t)(j - 1) * ny * d : nullptr);
+    if (rc < 0) return rc;
+    if (j == 0 && rj[0].k_used == 0) k_stage = 0;  // the sketch lost rank: the path continues with P = I
+    if (worst >= 0) worst = std::max(worst, rc);
+  }
   return worst;
 }
 

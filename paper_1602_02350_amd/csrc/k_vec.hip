@@ -14,6 +14,7 @@ namespace scs {
 namespace {
 
 constexpr int kVecThreads = 1024;
+constexpr int kMaxPmhalfInvK = 256;
 constexpr int kVecWaves = kVecThreads / 64;
 
 __device__ __forceinline__ double block_sum_d(double v, double* sred) {
@@ -202,6 +203,28 @@ __global__ __launch_bounds__(kVecThreads) void premap_kernel(const float* UT, co
   (void)tmp;
   if (state && state->done) return;
   premap_body(UT, lam, k, d, lambda, wt, w, trace_row);
+}
+
+// w~ = P^{1/2} w = s w + U~ diag(sqrt(lam_i + lambda) - s) U~^T w, the inverse of the output map
+// w = P^{-1/2} w~ (Eq. (condSketch) with the powers 1/2): a start point given in the original space
+// becomes the solver's own variable. One workgroup, FP64 arithmetic on FP32 inputs; k = 0 copies w.
+__global__ __launch_bounds__(256) void pmhalf_inv_kernel(const float* UT, const double* lam, int k, int64_t d,
+                                                         double lambda, const float* w, float* wt) {
+  __shared__ double coef[kMaxPmhalfInvK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double s = k > 0 ? sqrt(fmax(lam[k - 1], 0.0) + lambda) : 1.0;
+  for (int i = wave; i < k; i += 4) {
+    double acc = 0.0;
+    for (int64_t j = lane; j < d; j += 64) acc += (double)UT[(int64_t)i * d + j] * (double)w[j];
+    acc = wave_sum_d_fast(acc);
+    if (lane == 0) coef[i] = (sqrt(fmax(lam[i], 0.0) + lambda) - s) * acc;
+  }
+  __syncthreads();
+  for (int64_t j = tid; j < d; j += 256) {
+    double v = s * (double)w[j];
+    for (int i = 0; i < k; ++i) v += (double)UT[(int64_t)i * d + j] * coef[i];
+    wt[j] = (float)v;
+  }
 }
 
 // One workgroup per problem: w = P^{-1/2} w~ at the snapshot (skipped once a problem is done), or,
@@ -658,6 +681,37 @@ int launch_grad_finish(hipStream_t st, const float* part, const double* rsq_part
   SCS_HIP(hipGetLastError());
   grad_finalize_kernel<<<1, kVecThreads, 0, st>>>(g_tmp, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp,
                                                   state, stop_rule, eps, f_star, wt_cur, wt_prev, first, host_stop);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+// Sec. 2.2: out[0] = (k lam_k + tail)/(n k) (Eq. (decay)), out[1] = tr(C)/(n k) (Eq. (decaySVRG)), with
+// tr(C) = sum_i ||x_i||^2 / n from the sampler's FP64 sum of the row norms and tail = tr(C) - sum of the
+// k sketched eigenvalues (clamped at 0).
+__global__ void budget_lambda_kernel(const double* lam, int k, const SolveState* state, int64_t n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double trace = state->beta_sum / (double)n;
+  double top = 0.0;
+  for (int i = 0; i < k; ++i) top += fmax(lam[i], 0.0);
+  const double tail = fmax(trace - top, 0.0);
+  const double nk = (double)n * (double)k;
+  out[0] = ((double)k * fmax(lam[k - 1], 0.0) + tail) / nk;
+  out[1] = trace / nk;
+}
+
+int launch_budget_lambda(hipStream_t st, const double* lam, int k, const SolveState* state, int64_t n, double* out) {
+  budget_lambda_kernel<<<1, 64, 0, st>>>(lam, k, state, n, out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_pmhalf_inv(hipStream_t st, const float* UT, const double* lam, int k, int64_t d, double lambda,
+                      const float* w, float* wt) {
+  if (k > kMaxPmhalfInvK) {
+    set_error("P^{1/2} map: k too large");
+    return SCS_EINVAL;
+  }
+  pmhalf_inv_kernel<<<1, 256, 0, st>>>(UT, lam, k, d, lambda, w, wt);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -206,6 +206,11 @@ int launch_zero3(hipStream_t st, void* a, int64_t abytes, void* b, int64_t bbyte
 int launch_premap(hipStream_t st, const float* UT, const float* U, const double* lam, int k, int64_t d,
                   double lambda, const float* wt, float* w, float* trace_row, double* tmp,
                   const SolveState* state);
+// the two regularizations of the O~(ndk) budget from k sketched eigenvalues and state->beta_sum = ||X||_F^2
+int launch_budget_lambda(hipStream_t st, const double* lam, int k, const SolveState* state, int64_t n, double* out);
+// wt = P^{1/2} w (k <= 256; k = 0 copies), one workgroup
+int launch_pmhalf_inv(hipStream_t st, const float* UT, const double* lam, int k, int64_t d, double lambda,
+                      const float* w, float* wt);
 int launch_rownorm(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, float* out);
 int launch_rownorm_bf16(hipStream_t st, const uint16_t* X, int64_t n, int64_t d, float* out);
 int launch_copy_bf16(hipStream_t st, const float* X, int64_t n, int64_t d, int64_t ldx, uint16_t* out);

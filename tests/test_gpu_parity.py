@@ -650,3 +650,101 @@ def test_autotune_picks_options_that_reach_eps(ctx):
     r = ctx.svrg_solve(X, y, lam, k, eps, **tuned)
     assert r.status == binding.OK, r.report
     assert ridge.objective(X64, y64, lam, host(r.w)) - Ls <= 1.5 * eps
+
+
+# ------------------------------------------------------------------ warm starts, checkpoints, the lambda rule
+def test_resume_from_a_checkpoint_reproduces_the_uninterrupted_solve(ctx):
+    """A solve stopped after 3 epochs (its snapshot written to wt_out) and resumed from that snapshot with
+    epoch_offset = 3 ends bit for bit where 6 uninterrupted epochs end (same sketch, same index streams)."""
+    P = _problem(4000, 150, alpha=1.5, seed=71)
+    X, y = dev(P.X), dev(P.y)
+    common = dict(batch=32, steps=60, stop_rule=binding.STOP_EPOCHS, step_scale=8.0, seed=11)
+    full_wt = torch.empty(150, device="cuda")
+    full = ctx.svrg_solve(X, y, 1e-4, 10, 0.0, max_epochs=6, wt_out=full_wt, **common)
+    ck = torch.empty(150, device="cuda")
+    first = ctx.svrg_solve(X, y, 1e-4, 10, 0.0, max_epochs=3, wt_out=ck, **common)
+    assert first.status == binding.OK and first.report["epochs"] == 3
+    res_wt = torch.empty(150, device="cuda")
+    resumed = ctx.svrg_solve(X, y, 1e-4, 10, 0.0, max_epochs=3, w0=ck, w0_preconditioned=1, epoch_offset=3,
+                             wt_out=res_wt, **common)
+    assert resumed.status == binding.OK and resumed.report["epochs"] == 3
+    assert torch.equal(resumed.w, full.w)
+    assert torch.equal(res_wt, full_wt)
+    # a wrong offset replays other index streams and ends elsewhere
+    other = ctx.svrg_solve(X, y, 1e-4, 10, 0.0, max_epochs=3, w0=ck, w0_preconditioned=1, epoch_offset=0, **common)
+    assert not torch.equal(other.w, full.w)
+
+
+@pytest.mark.parametrize("k", [0, 10])
+def test_warm_start_in_the_original_space(ctx, k):
+    """w0 given in the original space is mapped by P^{1/2}: started at the optimum the solve stops at its first
+    snapshot (no epoch), and started near it needs fewer epochs than from 0."""
+    P = _problem(5000, 120, alpha=1.5, seed=72)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    lam, eps = 1e-4, 1e-8
+    ws = ridge.closed_form(X64, y64, lam)
+    Ls = ridge.objective(X64, y64, lam, ws)
+    X, y = dev(P.X), dev(P.y)
+    common = dict(batch=32, epoch_factor=0.5, stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=8.0,
+                  max_epochs=300, seed=5)
+    cold = ctx.svrg_solve(X, y, lam, k, eps, **common)
+    at = ctx.svrg_solve(X, y, lam, k, eps, w0=dev(ws), **common)
+    near = ctx.svrg_solve(X, y, lam, k, eps, w0=dev(ws + 1e-3 * np.random.default_rng(1).standard_normal(120)),
+                          **common)
+    print(f"\n[warm start k={k}] epochs cold {cold.report['epochs']}, at w* {at.report['epochs']}, "
+          f"near w* {near.report['epochs']}")
+    assert cold.status == at.status == near.status == binding.OK
+    assert at.report["epochs"] == 0
+    assert near.report["epochs"] < cold.report["epochs"]
+    assert ridge.objective(X64, y64, lam, host(near.w)) - Ls <= 1.5 * eps
+
+
+def test_warm_started_path_reaches_every_closed_form_with_fewer_epochs(ctx):
+    """Continuation along a regularization path (Sec. 2.2): lambdas from large to small, each lambda's solves
+    start from the previous lambda's solutions; every solve reaches its closed form, in fewer epochs in total
+    than the same path solved from 0."""
+    n, d, k, ny = 4000, 160, 12, 2
+    P = _problem(n, d, alpha=1.5, seed=73)
+    X64 = P.X.astype(np.float64)
+    rng = np.random.default_rng(4)
+    Y64 = np.stack([P.y.astype(np.float64), X64 @ rng.standard_normal(d) + 0.1 * rng.standard_normal(n)])
+    Y32 = Y64.astype(np.float32)
+    lams = list(np.logspace(-2, -5, 7))
+    _, Lmat = ridge.closed_forms(X64, Y32.astype(np.float64), lams)
+    fs = [float(v) for v in Lmat.reshape(-1)]           # solve j * ny + r
+    eps = 1e-8
+    common = dict(batch=32, epoch_factor=0.25, stop_rule=binding.STOP_GAP, step_scale=8.0, max_epochs=120, seed=9)
+    X, Y = dev(P.X), dev(Y32)
+    rc_c, Wc, rep_c = ctx.svrg_solve_path(X, Y, lams, k, eps, f_star=fs, **common)
+    rc_w, Ww, rep_w = ctx.svrg_solve_path(X, Y, lams, k, eps, f_star=fs, warm_start=1, **common)
+    assert rc_c == binding.OK and rc_w == binding.OK
+    ep_c = sum(r["epochs"] for r in rep_c)
+    ep_w = sum(r["epochs"] for r in rep_w)
+    print(f"\n[path] total epochs cold {ep_c}, warm {ep_w}")
+    for p in range(len(lams) * ny):
+        j, r = divmod(p, ny)
+        gap = ridge.objective(X64, Y32[r].astype(np.float64), lams[j], host(Ww[p])) - fs[p]
+        assert gap <= 1.5 * eps, (p, gap)
+    assert ep_w < ep_c
+
+
+@pytest.mark.parametrize("n,d,k", [(3000, 40, 35), (5000, 200, 12)])
+def test_budget_regularization_matches_the_oracle(ctx, n, d, k):
+    """Sec. 2.2's two regularizations from the GPU sketch (same Omega as the oracle's sketch) and tr(C);
+    with k + p = d the sketch is exact and the values are those of the full spectrum."""
+    P = _problem(n, d, alpha=1.5, seed=74)
+    X64 = P.X.astype(np.float64)
+    p = min(5, d - k)
+    seed = 123
+    Om = sampling.gaussian(seed, (k + p) * d).astype(np.float32).reshape(k + p, d)   # the drawn Omega^T
+    pre, plain, rc = ctx.regularization_for_budget(dev(P.X), k, oversample=p, seed=seed)
+    assert rc == binding.OK
+    _, lt, _ = sketch.sketch(X64, Om.T.astype(np.float64), k)
+    trace = float(np.sum(X64 * X64)) / n
+    pre_o, plain_o = ridge.budget_lambdas_estimated(lt, trace, n, k)
+    print(f"\n[budget n={n} d={d} k={k}] GPU {pre:.6e} {plain:.6e}  oracle {pre_o:.6e} {plain_o:.6e}")
+    assert plain == pytest.approx(plain_o, rel=1e-6)
+    assert pre == pytest.approx(pre_o, rel=1e-4)
+    if k + p == d:
+        ev = np.linalg.eigvalsh(ridge.correlation(X64))
+        assert (pre, plain) == pytest.approx(ridge.budget_lambdas(ev, n, k), rel=1e-4)
