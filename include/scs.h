@@ -102,6 +102,10 @@ typedef struct scs_opts {
   int w0_preconditioned;  /* 1: w0 is the solver's own variable w~ (for example a snapshot written to wt_out) */
   int epoch_offset;       /* epoch s of this call draws the index stream of epoch s + epoch_offset */
   float* wt_out;          /* optional device d: the final snapshot w~ (the checkpoint to resume from) */
+  int no_graph;           /* batched and path solves: 1 = the host enqueues every epoch's kernels; 0 (default) = the
+                             epochs replay a captured hipGraph of 8 epochs whose kernels read the epoch number from
+                             the device (the same kernels in the same order: results are bit-identical). timing > 0
+                             uses the enqueued mode (its events sit between kernels) */
   int warm_start;         /* scs_svrg_solve_path only: 1 = solve the lambdas one after another in the order given
                              (largest first is the usual continuation order), each lambda's ny solves starting
                              from the previous lambda's solutions (a regularization path with warm starts,

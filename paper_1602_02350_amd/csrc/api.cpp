@@ -238,6 +238,72 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
   return SCS_OK;
 }
 
+// Device epoch clock of batched and path solves (two ints, see launch_clock_set).
+int* ctx_clock(scs_ctx* c) { return ws<int>(c, "epoch_clock", 2); }
+
+// Epochs of a batched or path solve from a captured graph: kEpochGroup epochs whose kernels read the
+// epoch number from the device clock are captured once and the graph is replayed, S / kEpochGroup
+// times at most; the host checks the stop flags of a replay's epochs while the next replay runs (the
+// kernels of finished problems return at once, as in the enqueued mode). On return *s_next is the
+// first epoch still to be enqueued by the caller (the remainder, and the final evaluation at epoch S)
+// and *stopped says whether every problem already met the stop rule. The stream runs only these
+// kernels, so the graph is recorded without memset or event nodes.
+template <class F>
+int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int* s_next, bool* stopped) {
+  *s_next = 0;
+  *stopped = false;
+  const int E = kEpochGroup, R = S / E;
+  if (R < 1) return SCS_OK;
+  int* clk = ctx_clock(ctx);
+  if (!clk) return SCS_ENOMEM;
+  SCS_CHECK(launch_clock_set(st, clk, 0, S));
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)4 + R));
+  // captured on the context's side stream (the caller's stream may be the null stream, which cannot
+  // be captured); the graph is launched on the caller's stream
+  SCS_CHECK(ensure_side_streams(ctx, 1));
+  hipStream_t cs = ctx->side[0];
+  hipGraph_t g = nullptr;
+  SCS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  int rc = SCS_OK;
+  for (int e = 0; e < E && rc >= 0; ++e) rc = epoch_launches(cs, -1, clk);
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (rc < 0) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  SCS_HIP(ec);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  SCS_HIP(ei);
+  hipEvent_t* tev = ctx->tevents.data();
+  int r = 0;
+  for (; r < R; ++r) {
+    const hipError_t el = hipGraphLaunch(exec, st);
+    if (el != hipSuccess) {
+      hipStreamSynchronize(st);
+      hipGraphExecDestroy(exec);
+      SCS_HIP(el);
+    }
+    SCS_HIP(hipEventRecord(tev[4 + r], st));
+    if (r >= 1) {
+      SCS_HIP(hipEventSynchronize(tev[4 + r - 1]));
+      for (int e = (r - 1) * E; e < r * E; ++e)
+        if (__atomic_load_n(ctx->stop_flags + e, __ATOMIC_ACQUIRE)) *stopped = true;
+      if (*stopped) {
+        ++r;
+        break;
+      }
+    }
+  }
+  SCS_HIP(hipStreamSynchronize(st));
+  hipGraphExecDestroy(exec);
+  for (int e = (r - 1) * E; e < r * E && !*stopped; ++e)
+    if (__atomic_load_n(ctx->stop_flags + e, __ATOMIC_ACQUIRE)) *stopped = true;
+  *s_next = r * E;
+  return SCS_OK;
+}
+
 // Sketch of Alg. 2 with one block. Fills ws buffers "U32" (d x k), "UT32" (k x d), "U64", "lam",
 // and, if want_z, "Z" = X U~ (n x k, leading dimension gemm_wide_kpad(k), zero up to the next multiple
 // of 16) computed as (X Q) V_k. rank_def set if CholeskyQR broke down.
@@ -1315,22 +1381,32 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   const int64_t* d_dr = prefix + 2 * (nprob + 1);
 
   // ---- epochs of all problems in shared launches (Alg. 1 per problem)
-  constexpr int kLookahead = 3;
-  int epochs_launched = 0;
-  for (int s = 0; s <= S; ++s) {
-    SCS_CHECK(launch_premap_batched(st, desc, nprob, 0, nullptr));
-    SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, 0, wg_pre[nv], max_d_v, 1));
-    SCS_CHECK(launch_grad_partial_batched(st, desc, nprob, d_wg, wg_pre[nv], wg_pre[nprob] - wg_pre[nv], max_d_s, 0));
-    SCS_CHECK(launch_grad_finish_batched(st, desc, nprob, d_cb, cb_pre[nprob], s == 0 ? 1 : 0, done_count,
-                                         ctx->stop_flags + s));
-    if (s == S) break;
+  // One epoch of every problem; clk != nullptr: the epoch number comes from the device clock (graph replay).
+  auto epoch_launches = [&](hipStream_t q, int s, const int* clk) -> int {
+    SCS_CHECK(launch_premap_batched(q, desc, nprob, 0, nullptr));
+    SCS_CHECK(launch_grad_partial_batched(q, desc, nprob, d_wg, 0, wg_pre[nv], max_d_v, 1));
+    SCS_CHECK(launch_grad_partial_batched(q, desc, nprob, d_wg, wg_pre[nv], wg_pre[nprob] - wg_pre[nv], max_d_s, 0));
+    SCS_CHECK(launch_grad_finish_batched(q, desc, nprob, d_cb, cb_pre[nprob], s == 0 ? 1 : 0, done_count,
+                                         clk ? ctx->stop_flags : ctx->stop_flags + s, clk));
+    if (!clk && s == S) return SCS_OK;
     const int slot = s % G;
-    if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, nprob, d_dr, dr_pre[nprob], o.seed, s, G));
-    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
-    SCS_CHECK(launch_inner_epoch_batched(st, desc, nprob, W, max_slice, b, mixed, slot, s));
+    if (clk || slot == 0) SCS_CHECK(launch_sample_batched(q, desc, nprob, d_dr, dr_pre[nprob], o.seed, s, G, clk));
+    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], q));
+    SCS_CHECK(launch_inner_epoch_batched(q, desc, nprob, W, max_slice, b, mixed, slot, s, clk));
+    if (clk) SCS_CHECK(launch_clock_advance(q, ctx_clock(ctx)));
+    return SCS_OK;
+  };
+  int epochs_launched = 0;
+  int s0 = 0;
+  bool stopped = false;
+  if (!o.no_graph && !o.timing) SCS_CHECK(run_epoch_graph(ctx, st, S, epoch_launches, &s0, &stopped));
+  constexpr int kLookahead = 3;
+  for (int s = s0; s <= S && !stopped; ++s) {
+    SCS_CHECK(epoch_launches(st, s, nullptr));
+    if (s == S) break;
     SCS_HIP(hipEventRecord(tev[4 + s], st));
     epochs_launched = s + 1;
-    if (s + 1 >= kLookahead) {
+    if (s + 1 - s0 >= kLookahead) {
       const int q = s + 1 - kLookahead;
       SCS_HIP(hipEventSynchronize(tev[4 + q]));
       if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
@@ -1608,30 +1684,40 @@ static int path_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
   }
 
   // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X
-  constexpr int kLookahead = 3;
-  int epochs_launched = 0;
-  for (int s = 0; s <= S; ++s) {
-    SCS_CHECK(launch_premap_batched(st, desc, P, 0, nullptr));
+  auto epoch_launches = [&](hipStream_t q, int s, const int* clk) -> int {
+    SCS_CHECK(launch_premap_batched(q, desc, P, 0, nullptr));
     for (int c0 = 0; c0 < P; c0 += kPc) {
       const int pc = std::min(kPc, P - c0);
-      SCS_CHECK(launch_gemm_nt_longk(st, 0, X, n, d, ldx, W32 + (int64_t)c0 * d, pc, d, R + c0, P));
+      SCS_CHECK(launch_gemm_nt_longk(q, 0, X, n, d, ldx, W32 + (int64_t)c0 * d, pc, d, R + c0, P));
     }
-    SCS_CHECK(launch_residual_batched(st, R, n, P, Y, ny, nblk, rsq));
+    SCS_CHECK(launch_residual_batched(q, R, n, P, Y, ny, nblk, rsq));
     for (int c0 = 0; c0 < P; c0 += kPc) {
       const int pc = std::min(kPc, P - c0);
-      SCS_CHECK(launch_gemm_tn_splitk(st, 0, X, n, d, ldx, R + c0, pc, P, part, chunk, nchunks));
-      SCS_CHECK(launch_reduce_partials_t(st, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d));
+      SCS_CHECK(launch_gemm_tn_splitk(q, 0, X, n, d, ldx, R + c0, pc, P, part, chunk, nchunks));
+      SCS_CHECK(launch_reduce_partials_t(q, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d));
     }
-    SCS_CHECK(launch_grad_finalize_batched(st, desc, P, s == 0 ? 1 : 0, done_count, ctx->stop_flags + s));
-    if (s == S) break;
+    SCS_CHECK(launch_grad_finalize_batched(q, desc, P, s == 0 ? 1 : 0, done_count,
+                                           clk ? ctx->stop_flags : ctx->stop_flags + s, clk));
+    if (!clk && s == S) return SCS_OK;
     const int slot = s % G;
-    if (slot == 0) SCS_CHECK(launch_sample_batched(st, desc, P, draw_pre, dpre[P], o.seed, s, G));
-    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
-    if (implicit) SCS_CHECK(launch_inner_implicit_batched(st, desc, P, d, k_used, b, slot, s));
-    else SCS_CHECK(launch_inner_epoch_batched(st, desc, P, W, slice, b, mixed, slot, s));
+    if (clk || slot == 0) SCS_CHECK(launch_sample_batched(q, desc, P, draw_pre, dpre[P], o.seed, s, G, clk));
+    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], q));
+    if (implicit) SCS_CHECK(launch_inner_implicit_batched(q, desc, P, d, k_used, b, slot, s, clk));
+    else SCS_CHECK(launch_inner_epoch_batched(q, desc, P, W, slice, b, mixed, slot, s, clk));
+    if (clk) SCS_CHECK(launch_clock_advance(q, ctx_clock(ctx)));
+    return SCS_OK;
+  };
+  int epochs_launched = 0;
+  int s0 = 0;
+  bool stopped = false;
+  if (!o.no_graph && !o.timing) SCS_CHECK(run_epoch_graph(ctx, st, S, epoch_launches, &s0, &stopped));
+  constexpr int kLookahead = 3;
+  for (int s = s0; s <= S && !stopped; ++s) {
+    SCS_CHECK(epoch_launches(st, s, nullptr));
+    if (s == S) break;
     SCS_HIP(hipEventRecord(tev[4 + s], st));
     epochs_launched = s + 1;
-    if (s + 1 >= kLookahead) {
+    if (s + 1 - s0 >= kLookahead) {
       const int q = s + 1 - kLookahead;
       SCS_HIP(hipEventSynchronize(tev[4 + q]));
       if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;

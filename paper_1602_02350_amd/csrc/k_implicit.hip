@@ -35,7 +35,12 @@ __device__ __forceinline__ float wave_sum_f_fast(float v) {
   return __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
 }
 
-__global__ __launch_bounds__(kImpThreads) void inner_implicit_kernel(const BatchProb* P, int slot, int64_t epoch) {
+__global__ __launch_bounds__(kImpThreads) void inner_implicit_kernel(const BatchProb* P, int slot, int64_t epoch,
+                                                                     const int* clk) {
+  if (clk) {  // epochs replayed from a graph: the epoch number is on the device
+    if (clk[0] >= clk[1]) return;
+    slot = clk[0] % kEpochGroup;
+  }
   const BatchProb& q = P[blockIdx.x];
   if (q.state->done) return;
   const InnerArgs& a = q.inner;
@@ -186,13 +191,13 @@ __global__ void implicit_beta_kernel(const float* xnorm2, const float* Z, int64_
 }  // namespace
 
 int launch_inner_implicit_batched(hipStream_t st, const BatchProb* P, int nprob, int64_t max_d, int max_k, int max_b,
-                                  int epoch_slot, int64_t epoch) {
+                                  int epoch_slot, int64_t epoch, const int* clk) {
   if (nprob < 1) return SCS_OK;
   if (max_d > kImpMaxD || max_k > kImpMaxK || max_b > 64) {
     set_error("implicit inner loop: needs d <= 2048, k <= 128, b <= 64");
     return SCS_EINVAL;
   }
-  inner_implicit_kernel<<<nprob, kImpThreads, 0, st>>>(P, epoch_slot, epoch);
+  inner_implicit_kernel<<<nprob, kImpThreads, 0, st>>>(P, epoch_slot, epoch, clk);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -387,7 +387,12 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_kernel(InnerArgs a)
 // problem's sampled group.
 template <int RPT, int CPT, int WR, bool BF16>
 __global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(const BatchProb* P, int nprob, int slot,
-                                                                            int64_t epoch) {
+                                                                            int64_t epoch, const int* clk) {
+  if (clk) {  // epochs replayed from a graph: the epoch number is on the device
+    if (clk[0] >= clk[1]) return;
+    epoch = clk[0];
+    slot = clk[0] % kEpochGroup;
+  }
   const int p = blockIdx.x % nprob, w = blockIdx.x / nprob;
   InnerArgs a = P[p].inner;
   if (w >= a.W || a.state->done) return;
@@ -398,7 +403,7 @@ __global__ __launch_bounds__(kInnerThreads) void inner_epoch_batched_kernel(cons
 }
 
 template <int RPT, int CPT, int WR, bool BF16>
-int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, int64_t epoch) {
+int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, int64_t epoch, const int* clk) {
   dim3 block(kInnerThreads);
   if (W > 1) {
     // The workgroups of a problem wait on each other, so they must all be resident: problems go in
@@ -427,12 +432,13 @@ int launch_bt(hipStream_t st, const BatchProb* P, int nprob, int W, int slot, in
     for (int p0 = 0; p0 < nprob; p0 += group) {
       const BatchProb* Pg = P + p0;
       int cnt = nprob - p0 < group ? nprob - p0 : group;
-      inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<dim3((unsigned)(cnt * W)), block, 0, st>>>(Pg, cnt, slot, epoch);
+      inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<dim3((unsigned)(cnt * W)), block, 0, st>>>(Pg, cnt, slot, epoch,
+                                                                                                   clk);
       SCS_HIP(hipGetLastError());
     }
   } else {
     dim3 grid((unsigned)nprob);
-    inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch);
+    inner_epoch_batched_kernel<RPT, CPT, WR, BF16><<<grid, block, 0, st>>>(P, nprob, slot, epoch, clk);
     SCS_HIP(hipGetLastError());
   }
   return SCS_OK;
@@ -500,9 +506,9 @@ int launch_layout(hipStream_t st, InnerArgs& a, const Layout& L) {
 
 template <bool BF16>
 int launch_layout_batched(hipStream_t st, const BatchProb* P, int nprob, int W, const Layout& L, int slot,
-                          int64_t epoch) {
+                          int64_t epoch, const int* clk) {
 #define SCS_INNER_CASE(R, C, WRV) \
-  if (L.rpt == R && L.cpt == C && L.wr == WRV) return launch_bt<R, C, WRV, BF16>(st, P, nprob, W, slot, epoch);
+  if (L.rpt == R && L.cpt == C && L.wr == WRV) return launch_bt<R, C, WRV, BF16>(st, P, nprob, W, slot, epoch, clk);
   SCS_INNER_CASE(1, 1, 1) SCS_INNER_CASE(1, 2, 1) SCS_INNER_CASE(1, 3, 1) SCS_INNER_CASE(1, 4, 1)
   SCS_INNER_CASE(2, 1, 1) SCS_INNER_CASE(2, 2, 1) SCS_INNER_CASE(2, 3, 1) SCS_INNER_CASE(2, 4, 1)
   SCS_INNER_CASE(4, 1, 1) SCS_INNER_CASE(4, 2, 1) SCS_INNER_CASE(4, 3, 1) SCS_INNER_CASE(4, 4, 1)
@@ -551,7 +557,7 @@ int inner_layout_wave_rows(int b, int64_t d, int W, int wave_rows) {
 }
 
 int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
-                               int bf16, int epoch_slot, int64_t epoch) {
+                               int bf16, int epoch_slot, int64_t epoch, const int* clk) {
   if (nprob < 1) return SCS_OK;
   if (max_b < 1 || max_b > kInnerMaxB || W < 1 || W > 16) {
     set_error("batched inner loop: need 1 <= b <= 256 and 1 <= workgroups <= 16");
@@ -567,8 +573,8 @@ int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, in
               "128 columns, b > 128 at most 64)");
     return SCS_EINVAL;
   }
-  return bf16 ? launch_layout_batched<true>(st, P, nprob, W, L, epoch_slot, epoch)
-              : launch_layout_batched<false>(st, P, nprob, W, L, epoch_slot, epoch);
+  return bf16 ? launch_layout_batched<true>(st, P, nprob, W, L, epoch_slot, epoch, clk)
+              : launch_layout_batched<false>(st, P, nprob, W, L, epoch_slot, epoch, clk);
 }
 
 }  // namespace scs

@@ -198,7 +198,11 @@ __global__ void sample_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, ui
 // each problem draws `groups` epochs of its own m b draws from its own weights (same stream as a
 // single solve with the same seed).
 __global__ void sample_batched_kernel(const BatchProb* P, int nprob, const int64_t* draw_prefix, int64_t total,
-                                      uint64_t seed, uint32_t epoch0) {
+                                      uint64_t seed, uint32_t epoch0, const int* clk) {
+  if (clk) {  // epochs replayed from a graph: draw a group of epochs when the device's epoch starts one
+    if (clk[0] >= clk[1] || clk[0] % kEpochGroup != 0) return;
+    epoch0 = (uint32_t)clk[0];
+  }
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int p = find_prob(draw_prefix, nprob, g);
@@ -280,12 +284,12 @@ int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows
 }
 
 int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
-                          int64_t total_draws, uint64_t seed, int epoch, int groups) {
+                          int64_t total_draws, uint64_t seed, int epoch, int groups, const int* clk) {
   (void)groups;
   if (total_draws <= 0) return SCS_OK;
   sample_batched_kernel<<<dim3((unsigned)cdiv(total_draws, 256)), dim3(256), 0, st>>>(P, nprob, draw_prefix,
                                                                                        total_draws, seed,
-                                                                                       (uint32_t)epoch);
+                                                                                       (uint32_t)epoch, clk);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -403,7 +403,14 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
 // One workgroup per problem. A problem that finishes in this launch adds one to done_count; the
 // workgroup that brings it to nprob sets the host-pinned flag (the host then stops enqueuing).
 __global__ __launch_bounds__(kVecThreads) void grad_finalize_batched_kernel(const BatchProb* P, int nprob, int first,
-                                                                            int* done_count, int* host_stop) {
+                                                                            int* done_count, int* host_stop,
+                                                                            const int* clk) {
+  if (clk) {  // epochs replayed from a graph: the epoch number is on the device; host_stop is the flag array
+    const int s = clk[0];
+    if (s > clk[1]) return;
+    first = s == 0;
+    host_stop = host_stop ? host_stop + s : nullptr;
+  }
   const BatchProb& q = P[blockIdx.x];
   if (q.state->done) return;
   const int action = finalize_body(q.g64, q.grows, q.grsq, q.nwg, q.n, q.d, q.w32, q.lambda, q.UT, q.lam, q.k, q.mu,
@@ -724,17 +731,40 @@ int launch_premap_batched(hipStream_t st, const BatchProb* P, int nprob, int fin
 }
 
 int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
-                               int64_t total_cb, int first, int* done_count, int* host_stop) {
+                               int64_t total_cb, int first, int* done_count, int* host_stop, const int* clk) {
   if (nprob < 1) return SCS_OK;
   grad_colreduce_batched_kernel<<<dim3((unsigned)total_cb, kColSplit), dim3(256), 0, st>>>(P, nprob, cb_prefix);
   SCS_HIP(hipGetLastError());
-  return launch_grad_finalize_batched(st, P, nprob, first, done_count, host_stop);
+  return launch_grad_finalize_batched(st, P, nprob, first, done_count, host_stop, clk);
 }
 
 int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
-                                 int* host_stop) {
+                                 int* host_stop, const int* clk) {
   if (nprob < 1) return SCS_OK;
-  grad_finalize_batched_kernel<<<nprob, kVecThreads, 0, st>>>(P, nprob, first, done_count, host_stop);
+  grad_finalize_batched_kernel<<<nprob, kVecThreads, 0, st>>>(P, nprob, first, done_count, host_stop, clk);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+__global__ void clock_set_kernel(int* clk, int epoch, int epochs) {
+  if (threadIdx.x == 0) {
+    clk[0] = epoch;
+    clk[1] = epochs;
+  }
+}
+
+__global__ void clock_advance_kernel(int* clk) {
+  if (threadIdx.x == 0 && clk[0] <= clk[1]) clk[0] += 1;
+}
+
+int launch_clock_set(hipStream_t st, int* clk, int epoch, int epochs) {
+  clock_set_kernel<<<1, 64, 0, st>>>(clk, epoch, epochs);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_clock_advance(hipStream_t st, int* clk) {
+  clock_advance_kernel<<<1, 64, 0, st>>>(clk);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

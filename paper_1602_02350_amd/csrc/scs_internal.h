@@ -305,14 +305,14 @@ int launch_premap_batched(hipStream_t st, const BatchProb* P, int nprob, int fin
 int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* wg_prefix,
                                 int64_t base, int64_t count, int64_t max_d, int vec4);
 int launch_grad_finish_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* cb_prefix,
-                               int64_t total_cb, int first, int* done_count, int* host_stop);
+                               int64_t total_cb, int first, int* done_count, int* host_stop, const int* clk = nullptr);
 // implicit preconditioned rows (k_implicit.hip): one workgroup per problem; inner.Xt holds X itself
 int launch_inner_implicit_batched(hipStream_t st, const BatchProb* P, int nprob, int64_t max_d, int max_k, int max_b,
-                                  int epoch_slot, int64_t epoch);
+                                  int epoch_slot, int64_t epoch, const int* clk = nullptr);
 int launch_implicit_beta(hipStream_t st, const float* xnorm2, const float* Z, int64_t ldz, const float* UT,
                          const double* lam, int k, int64_t n, int64_t d, double lambda, float* beta);
 int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, int first, int* done_count,
-                                 int* host_stop);
+                                 int* host_stop, const int* clk = nullptr);
 // Shared-X gradient of many problems: R = X W^T (gemm), then R[i][p] -= Y[p % ny][i] with per-block
 // residual sums rsq[p][blk]; then G (P x d, FP64) = sum over row chunks of the X^T R partials.
 int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const float* Y, int ny, int nblk,
@@ -320,8 +320,15 @@ int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const fl
 int launch_reduce_partials_t(hipStream_t st, const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
                              int64_t ldg);
 int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
-                          int64_t total_draws, uint64_t seed, int epoch, int groups);
+                          int64_t total_draws, uint64_t seed, int epoch, int groups, const int* clk = nullptr);
 int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
-                               int bf16, int epoch_slot, int64_t epoch);
+                               int bf16, int epoch_slot, int64_t epoch, const int* clk = nullptr);
+// Epochs of a batched or path solve replayed from a captured graph read their epoch number from a
+// device clock: clk[0] = epoch, clk[1] = the epoch cap S. Kernels given a clock ignore their host
+// epoch arguments (and skip epochs >= S, or > S for the gradient finish); index streams are drawn
+// kEpochGroup epochs at a time, when the epoch number is a multiple of kEpochGroup.
+constexpr int kEpochGroup = 8;
+int launch_clock_set(hipStream_t st, int* clk, int epoch, int epochs);
+int launch_clock_advance(hipStream_t st, int* clk);
 
 }  // namespace scs

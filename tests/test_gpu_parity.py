@@ -748,3 +748,58 @@ def test_budget_regularization_matches_the_oracle(ctx, n, d, k):
     if k + p == d:
         ev = np.linalg.eigvalsh(ridge.correlation(X64))
         assert (pre, plain) == pytest.approx(ridge.budget_lambdas(ev, n, k), rel=1e-4)
+
+
+# ------------------------------------------------------------------ epochs replayed from a captured graph
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_graph_replay_equals_enqueued_epochs(ctx, mixed):
+    """The batched solve's epochs replayed from a captured hipGraph (the default; 8 epochs per replay, the
+    epoch number read from a device clock) give bit for bit what the host-enqueued epochs give. 21 epochs:
+    two replays (with the host waiting on the first while the second runs), then five enqueued epochs and
+    the final evaluation; a second graph solve in a row must agree too."""
+    probs = _uneven_batch(UNEVEN, seed0=90)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    common = dict(batch=16, steps=30, max_epochs=21, stop_rule=binding.STOP_EPOCHS, step_scale=1.0, seed=3,
+                  precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+    lams, ks = [P.lam for P, _ in probs], [k for _, k in probs]
+    rc_e, we, rep_e = ctx.svrg_solve_batched(Xs, ys, lams, ks, 0.0, no_graph=1, **common)
+    for rep in range(2):
+        rc_g, wg, rep_g = ctx.svrg_solve_batched(Xs, ys, lams, ks, 0.0, **common)
+        assert rc_g == rc_e == binding.OK
+        for i in range(len(probs)):
+            assert torch.equal(wg[i], we[i]), (rep, i)
+            assert rep_g[i]["epochs"] == rep_e[i]["epochs"] == 21
+
+
+def test_batched_graph_replay_stops_with_the_stop_rule(ctx):
+    """With the certificate rule every problem stops inside a replay; the graph mode returns the same weights
+    and epoch counts as the enqueued mode."""
+    probs = _uneven_batch(WELL_POSED, seed0=70)
+    Xs = [dev(P.X) for P, _ in probs]
+    ys = [dev(P.y) for P, _ in probs]
+    common = dict(batch=16, max_epochs=150, stop_rule=binding.STOP_CERTIFICATE, step_scale=2.0)
+    lams, ks = [P.lam for P, _ in probs], [k for _, k in probs]
+    rc_e, we, rep_e = ctx.svrg_solve_batched(Xs, ys, lams, ks, 1e-10, no_graph=1, **common)
+    rc_g, wg, rep_g = ctx.svrg_solve_batched(Xs, ys, lams, ks, 1e-10, **common)
+    assert rc_g == rc_e == binding.OK
+    for i in range(len(probs)):
+        assert torch.equal(wg[i], we[i]), i
+        assert rep_g[i]["epochs"] == rep_e[i]["epochs"]
+
+
+@pytest.mark.parametrize("implicit", [False, True])
+def test_path_graph_replay_equals_enqueued_epochs(ctx, implicit):
+    n, d, k, ny = 3000, 200, 10, 3
+    P = _problem(n, d, alpha=1.5, seed=75)
+    rng = np.random.default_rng(5)
+    Y = np.stack([P.y] + [(P.X.astype(np.float64) @ rng.standard_normal(d)).astype(np.float32) for _ in range(ny - 1)])
+    lams = [1e-2, 1e-3, 1e-4]
+    common = dict(batch=32, steps=40, max_epochs=19, stop_rule=binding.STOP_EPOCHS, step_scale=4.0, seed=8,
+                  implicit_apply=int(implicit))
+    X, Yd = dev(P.X), dev(Y)
+    rc_e, We, _ = ctx.svrg_solve_path(X, Yd, lams, k, 0.0, no_graph=1, **common)
+    rc_g, Wg, rep_g = ctx.svrg_solve_path(X, Yd, lams, k, 0.0, **common)
+    assert rc_e == rc_g == binding.OK
+    assert torch.equal(Wg, We)
+    assert all(r["epochs"] == 19 for r in rep_g)
