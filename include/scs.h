@@ -102,6 +102,9 @@ typedef struct scs_opts {
   int w0_preconditioned;  /* 1: w0 is the solver's own variable w~ (for example a snapshot written to wt_out) */
   int epoch_offset;       /* epoch s of this call draws the index stream of epoch s + epoch_offset */
   float* wt_out;          /* optional device d: the final snapshot w~ (the checkpoint to resume from) */
+  int krylov_blocks;      /* q: the sketch's Krylov space [C Omega, C^2 Omega, ..., C^q Omega] (Block Lanczos, Alg. 2;
+                             C = X^T X / n); 0 or 1 = the one-block range finder Y = X^T (X Omega). Each block
+                             after the first costs two more passes over X; q (k + p) <= min(d, n, 136) */
   int no_graph;           /* batched and path solves: 1 = the host enqueues every epoch's kernels; 0 (default) = the
                              epochs replay a captured hipGraph of 8 epochs whose kernels read the epoch number from
                              the device (the same kernels in the same order: results are bit-identical). timing > 0
@@ -148,7 +151,10 @@ int scs_destroy(scs_ctx* ctx);
  * (descending, clamped >= 0), U~ = Q V_{:,1..k}.
  * The lam~ estimate the eigenvalues of C = X^T X / n (Eq. (covSpec)), i.e. the
  * squared singular values of n^{-1/2} X.
- *   X: n x d (ld ldx); k in [1, d]; k + p <= min(d, n, 136).
+ *   X: n x d (ld ldx); k in [1, d]; q (k + p) <= min(d, n, 136) with q = opts->krylov_blocks (>= 1).
+ * With q > 1 the range is the Krylov space of Block Lanczos (Alg. 2) started from C Omega: each further
+ * block is C times the previous orthonormal block, projected twice against the earlier blocks and
+ * orthonormalized by CholeskyQR2; Rayleigh-Ritz then runs on all q (k + p) columns.
  *   U_out: d x k row-major FP32 (ld k); U64_out (nullable): d x k FP64; lam_out: k FP64.
  * Returns SCS_SKETCH_RANK_DEFICIENT if the Gram matrix of Y is not positive definite.
  */
@@ -225,7 +231,7 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
  * opts), the tail sum is tr(C) minus their sum, and tr(C) = ||X||_F^2 / n (FP64 sum of FP32 row norms).
  * Sketched values are Rayleigh-Ritz values, at most the true ones, so the tail and lambda_precond err
  * on the large side. Outputs are HOST doubles; the call waits for its stream.
- *   k in [1, d], k + p <= min(d, n, 136). Returns SCS_SKETCH_RANK_DEFICIENT (values still written) if the
+ *   k in [1, d], q (k + p) <= min(d, n, 136). Returns SCS_SKETCH_RANK_DEFICIENT (values still written) if the
  *   sketch lost rank.
  */
 int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k,

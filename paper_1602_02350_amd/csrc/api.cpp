@@ -238,6 +238,14 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
   return SCS_OK;
 }
 
+// Columns of the sketch's Krylov basis, q (k + p), within what the one-workgroup FP64 eigensolver and
+// CholeskyQR2 take (136) and within the rank X can have.
+bool sketch_width_ok(const scs_opts& o, int k, int64_t n, int64_t d) {
+  if (o.krylov_blocks < 0 || o.krylov_blocks > 32) return false;
+  const int64_t L = (int64_t)(k + o.oversample) * std::max(1, o.krylov_blocks);
+  return L <= d && L <= n && L <= 136;
+}
+
 // Device epoch clock of batched and path solves (two ints, see launch_clock_set).
 int* ctx_clock(scs_ctx* c) { return ws<int>(c, "epoch_clock", 2); }
 
@@ -347,39 +355,85 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     flags = ws<int>(ctx, "cholflags" + sfx, 2);
     if (!flags) return SCS_ENOMEM;
   }
-  SCS_CHECK(launch_gemm64(st, l, l, d, Y, 1, l, Y, l, 1, G, l, nullptr, 0));
-  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, flags));
-  SCS_CHECK(launch_gemm64(st, d, l, l, Y, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
-  SCS_CHECK(launch_gemm64(st, l, l, d, Q1, 1, l, Q1, l, 1, G, l, nullptr, 0));
-  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, flags + 1));
-  SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Q, l, nullptr, 0));
-  SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QT32, d));  // Q^T = R2^{-T} Q1^T
-  // Rayleigh-Ritz: Wq = X Q (n x l), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
-  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * lp);
-  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, l, d, Wq, lp, true));
-  int64_t nch2 = gemm_tn_splitk_chunks(n, l, l, Wq, lp, Wq, lp);
+  const int q = std::max(1, o.krylov_blocks);
+  int* bflags = flags;  // with several blocks, each block's CholeskyQR2 flags, ORed into flags at the end
+  if (q > 1) {
+    bflags = ws<int>(ctx, "blockflags" + sfx, (size_t)2 * q);
+    if (!bflags) return SCS_ENOMEM;
+  }
+  // CholeskyQR2 of Yb (d x l): Qout = Yb R1^{-1} R2^{-1} (leading dimension ldq), QTout = Qout^T in FP32
+  auto cholqr2 = [&](const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f) -> int {
+    SCS_CHECK(launch_gemm64(st, l, l, d, Yb, 1, l, Yb, l, 1, G, l, nullptr, 0));
+    SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f));
+    SCS_CHECK(launch_gemm64(st, d, l, l, Yb, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
+    SCS_CHECK(launch_gemm64(st, l, l, d, Q1, 1, l, Q1, l, 1, G, l, nullptr, 0));
+    SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f + 1));
+    SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Qout, ldq, nullptr, 0));
+    if (QTout) SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QTout, d));  // R2^{-T} Q1^T
+    return SCS_OK;
+  };
+  int L = l;            // columns of the orthonormal basis handed to Rayleigh-Ritz
+  const double* Qb = Q; // that basis, d x L (leading dimension L)
+  if (q == 1) {
+    SCS_CHECK(cholqr2(Y, Q, l, QT32, flags));
+  } else {
+    // Block Lanczos (Alg. 2): the Krylov space [C Omega, C^2 Omega, ..., C^q Omega] (C = X^T X / n, up to
+    // the scale of each block), built block by block: block j is C applied to the orthonormal block j-1,
+    // projected twice against the blocks before it (block Gram-Schmidt) and orthonormalized by CholeskyQR2.
+    // Its span is the span of the stacked Krylov blocks.
+    L = q * l;
+    WS(Qall, double, std::string("Qall64") + sfx, (size_t)d * L);
+    WS(QTb, float, std::string("QTb32") + sfx, (size_t)l * d);
+    WS(Yj, double, std::string("Yj64") + sfx, (size_t)d * l);
+    WS(Zj, double, std::string("Zj64") + sfx, (size_t)L * l);
+    WS(Wj, double, std::string("Wj64") + sfx, (size_t)d * l);
+    SCS_CHECK(cholqr2(Y, Qall, L, QTb, bflags));
+    for (int j = 1; j < q; ++j) {
+      // Yj = X^T (X Q_{j-1}) / n
+      SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QTb, l, d, T, lp, true));
+      SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
+      SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0 / (double)n, Yj));
+      const int64_t Pc = (int64_t)j * l;  // columns of the blocks before j
+      for (int pass = 0; pass < 2; ++pass) {
+        SCS_CHECK(launch_gemm64(st, Pc, l, d, Qall, 1, L, Yj, l, 1, Zj, l, nullptr, 0));   // Z = Q_prev^T Yj
+        SCS_CHECK(launch_gemm64(st, d, l, Pc, Qall, L, 1, Zj, l, 1, Wj, l, nullptr, 0));   // W = Q_prev Z
+        SCS_CHECK(launch_axpy64(st, (int64_t)d * l, -1.0, Wj, Yj));
+      }
+      SCS_CHECK(cholqr2(Yj, Qall + Pc, L, j + 1 < q ? QTb : nullptr, bflags + 2 * j));
+    }
+    SCS_CHECK(launch_or_flags(st, bflags, 2 * q, flags));
+    WS(QTall, float, std::string("QTall32") + sfx, (size_t)L * d);
+    SCS_CHECK(launch_transpose64to32(st, d, L, Qall, L, QTall));
+    Qb = Qall;
+    QT32 = QTall;
+  }
+  const int64_t Lp = cdiv(L, 16) * 16;
+  // Rayleigh-Ritz: Wq = X Q (n x L), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
+  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * Lp);
+  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, L, d, Wq, Lp, true));
+  int64_t nch2 = gemm_tn_splitk_chunks(n, L, L, Wq, Lp, Wq, Lp);
   int64_t chunk2 = cdiv(n, nch2);
   nch2 = cdiv(n, chunk2);
-  WS(part2, float, std::string("partial2") + sfx, (size_t)nch2 * l * l);
-  SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, l, lp, Wq, l, lp, part2, chunk2, nch2));
-  WS(B, double, std::string("B64") + sfx, (size_t)l * l);
-  SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)l * l, 1.0 / (double)n, B));
-  WS(V, double, std::string("V64") + sfx, (size_t)l * l);
-  WS(theta, double, std::string("theta") + sfx, (size_t)l);
-  WS(order, int, std::string("order") + sfx, (size_t)l);
-  WS(eigw, double, std::string("eig_work") + sfx, eig64_work_len(l));
-  SCS_CHECK(launch_eig64(st, B, l, eigw, V, theta, order));
+  WS(part2, float, std::string("partial2") + sfx, (size_t)nch2 * L * L);
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, L, Lp, Wq, L, Lp, part2, chunk2, nch2));
+  WS(B, double, std::string("B64") + sfx, (size_t)L * L);
+  SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)L * L, 1.0 / (double)n, B));
+  WS(V, double, std::string("V64") + sfx, (size_t)L * L);
+  WS(theta, double, std::string("theta") + sfx, (size_t)L);
+  WS(order, int, std::string("order") + sfx, (size_t)L);
+  WS(eigw, double, std::string("eig_work") + sfx, eig64_work_len(L));
+  SCS_CHECK(launch_eig64(st, B, L, eigw, V, theta, order));
   // lift: U~ = Q V_k, lam = theta_{1..k}
   WS(U64, double, std::string("U64") + sfx, (size_t)d * k);
   WS(U32, float, std::string("U32") + sfx, (size_t)d * k);
   WS(UT32, float, std::string("UT32") + sfx, (size_t)k * d);
   WS(lam, double, std::string("lam") + sfx, (size_t)k);
-  WS(VkT, float, std::string("VkT") + sfx, (size_t)k * l);
-  SCS_CHECK(launch_lift(st, Q, d, l, V, order, k, theta, U64, U32, UT32, lam, VkT));
+  WS(VkT, float, std::string("VkT") + sfx, (size_t)k * L);
+  SCS_CHECK(launch_lift(st, Qb, d, L, V, order, k, theta, U64, U32, UT32, lam, VkT));
   if (want_z) {
     const int64_t kz = gemm_wide_kpad(k);
     WS(Z, float, std::string("Z") + sfx, (size_t)n * kz);
-    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, l, lp, VkT, k, l, Z, kz, true));
+    SCS_CHECK(launch_gemm_nt_longk(st, bf, Wq, n, L, Lp, VkT, k, L, Z, kz, true));
   }
   if (flags_out) return SCS_OK;
   int hflags[2] = {0, 0};
@@ -522,8 +576,8 @@ int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
   scs_opts_default(&o);
   if (opts) o = *opts;
   const int l = k + o.oversample;
-  if (k < 1 || k > d || o.oversample < 0 || l > d || l > n || l > 136) {
-    set_error("sketch: need 1 <= k, k + p <= min(d, n, 136)");
+  if (k < 1 || k > d || o.oversample < 0 || !sketch_width_ok(o, k, n, d)) {
+    set_error("sketch: need 1 <= k, q (k + p) <= min(d, n, 136) for q Krylov blocks");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -621,8 +675,8 @@ int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64
   scs_opts_default(&o);
   if (opts) o = *opts;
   const int l = k + o.oversample;
-  if (k < 1 || k > d || o.oversample < 0 || l > d || l > n || l > 136) {
-    set_error("budget regularization: need 1 <= k, k + p <= min(d, n, 136)");
+  if (k < 1 || k > d || o.oversample < 0 || !sketch_width_ok(o, k, n, d)) {
+    set_error("budget regularization: need 1 <= k, q (k + p) <= min(d, n, 136) for q Krylov blocks");
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
@@ -730,8 +784,8 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   scs_opts_default(&o);
   if (opts) o = *opts;
   const int l = k + o.oversample;
-  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || l > d || l > n || l > 136))) {
-    set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || !sketch_width_ok(o, k, n, d)))) {
+    set_error("need 0 <= k and, for k > 0, q (k + p) <= min(d, n, 136) for q Krylov blocks");
     return SCS_EINVAL;
   }
   if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
@@ -1123,9 +1177,9 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     SCS_CHECK(validate_problem(X[p], n[p], d[p], ldx[p], lambda[p]));
     const int l = k[p] + o.oversample;
     if (!y[p] || !w_out[p] || k[p] < 0 || k[p] > d[p] ||
-        (k[p] > 0 && (o.oversample < 0 || l > d[p] || l > n[p] || l > 136)) || n[p] + d[p] > INT32_MAX) {
+        (k[p] > 0 && (o.oversample < 0 || !sketch_width_ok(o, k[p], n[p], d[p]))) || n[p] + d[p] > INT32_MAX) {
       set_error("batched solve: problem " + std::to_string(p) +
-                ": need y, w_out, 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+                ": need y, w_out, 0 <= k and, for k > 0, q (k + p) <= min(d, n, 136) for q Krylov blocks");
       return SCS_EINVAL;
     }
     max_d = std::max(max_d, d[p]);
@@ -1480,8 +1534,8 @@ static int path_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
   scs_opts_default(&o);
   if (opts) o = *opts;
   const int l = k + o.oversample;
-  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || l > d || l > n || l > 136)) || n + d > INT32_MAX) {
-    set_error("need 0 <= k and, for k > 0, k + p <= min(d, n, 136)");
+  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || !sketch_width_ok(o, k, n, d))) || n + d > INT32_MAX) {
+    set_error("need 0 <= k and, for k > 0, q (k + p) <= min(d, n, 136) for q Krylov blocks");
     return SCS_EINVAL;
   }
   for (int j = 0; j < nl; ++j)

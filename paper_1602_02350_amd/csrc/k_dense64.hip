@@ -174,7 +174,66 @@ int max_lds_bytes() {
   return g_max_lds;
 }
 
+// y += alpha x (FP64, count entries)
+__global__ void axpy64_kernel(int64_t count, double alpha, const double* x, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] += alpha * x[i];
+}
+
+// dst (rows x cols, leading dimension ldd) = src (rows x cols, leading dimension lds), FP64
+__global__ void copy64_kernel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e / cols, c = e % cols;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+// dst (cols x rows, FP32, row-major) = src^T, src rows x cols FP64 with leading dimension lds
+__global__ void transpose64to32_kernel(int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t c = e / rows, r = e % rows;   // consecutive threads write consecutive dst entries
+  dst[c * rows + r] = (float)src[r * lds + c];
+}
+
+// dst[0] = 1 if any of src[0 .. count) is set, dst[1] = 0
+__global__ void or_flags_kernel(const int* src, int count, int* dst) {
+  if (threadIdx.x != 0) return;
+  int any = 0;
+  for (int i = 0; i < count; ++i) any |= src[i] != 0;
+  dst[0] = any;
+  dst[1] = 0;
+}
+
 }  // namespace
+
+int launch_axpy64(hipStream_t st, int64_t count, double alpha, const double* x, double* y) {
+  if (count <= 0) return SCS_OK;
+  axpy64_kernel<<<(unsigned)cdiv(count, 256), 256, 0, st>>>(count, alpha, x, y);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_copy64(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                  int64_t ldd) {
+  if (rows * cols <= 0) return SCS_OK;
+  copy64_kernel<<<(unsigned)cdiv(rows * cols, 256), 256, 0, st>>>(rows, cols, src, lds, dst, ldd);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_transpose64to32(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst) {
+  if (rows * cols <= 0) return SCS_OK;
+  transpose64to32_kernel<<<(unsigned)cdiv(rows * cols, 256), 256, 0, st>>>(rows, cols, src, lds, dst);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_or_flags(hipStream_t st, const int* src, int count, int* dst) {
+  or_flags_kernel<<<1, 64, 0, st>>>(src, count, dst);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
 
 int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A, int64_t a_rs, int64_t a_cs,
                   const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t ldc, float* C32,

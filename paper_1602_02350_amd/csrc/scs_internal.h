@@ -191,6 +191,11 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
                   int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
                   float* C32, int64_t ldc32);
 int launch_chol_inv64(hipStream_t st, const double* G, int l, double* Rinv, int* flag);
+int launch_axpy64(hipStream_t st, int64_t count, double alpha, const double* x, double* y);
+int launch_copy64(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                  int64_t ldd);
+int launch_transpose64to32(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, float* dst);
+int launch_or_flags(hipStream_t st, const int* src, int count, int* dst);
 // symmetric eigendecomposition B = V diag(theta) V^T (k_eig64.hip); work: eig64_work_len(l) doubles
 int eig64_work_len(int l);
 int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V, double* theta, int* order);

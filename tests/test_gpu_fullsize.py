@@ -173,3 +173,28 @@ def test_fp32_accuracy_gate(ctx, full):
     print(f"\n[{full['name']}] accuracy gate: ||w - w*|| / ||w*|| = {_rel(w, ws):.3e} after 50 epochs")
     assert res.status == binding.OK, res.report
     assert _rel(w, ws) <= 1e-5
+
+
+def test_block_lanczos_sketch_stage(ctx, full):
+    """Two Krylov blocks (Alg. 2) at the benchmark size (FP32 only: 2 (k + 5) = 110 columns at k = 50)
+    against the oracle's Block Lanczos from Pi = X Omega / sqrt(n)."""
+    if full["mixed"]:
+        pytest.skip("2 (k + 5) = 266 columns exceed the 136 the FP64 eigensolver takes")
+    cfg, X64 = full["cfg"], full["X64"]
+    k, d, n = cfg["k"], cfg["d"], cfg["n"]
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 12)
+    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), krylov_blocks=2)
+    assert rc == binding.OK
+    Uo, lo, _ = sketch.block_lanczos(X64, X64 @ Om.T.astype(np.float64) / np.sqrt(n), k, 2)
+    lg = lam.cpu().numpy()
+    u_eff = 2.0 ** -24 * np.sqrt(d)
+    err = np.max(np.abs(lg - lo)) / lo[0]
+    Pg = precond.sketched_preconditioner(U64.cpu().numpy(), lg, cfg["lam"])
+    Po = precond.sketched_preconditioner(Uo, lo, cfg["lam"])
+    V = np.random.default_rng(0).standard_normal((d, 8))
+    perr = _rel(Pg @ V, Po @ V)
+    H = full.setdefault("H", ridge.hessian(X64, cfg["lam"]))
+    print(f"\n[{full['name']}] 2-block sketch: max |d lam~| / lam~_1 = {err:.3e} (bound {8 * u_eff:.1e}); "
+          f"P^-1/2 probe rel err = {perr:.3e}; kappa~ = {ridge.average_condition(Pg @ H @ Pg):.4g}")
+    assert err <= 8 * u_eff
+    assert perr < 1e-4

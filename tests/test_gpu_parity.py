@@ -803,3 +803,52 @@ def test_path_graph_replay_equals_enqueued_epochs(ctx, implicit):
     assert rc_e == rc_g == binding.OK
     assert torch.equal(Wg, We)
     assert all(r["epochs"] == 19 for r in rep_g)
+
+
+# ------------------------------------------------------------------ Block Lanczos (Alg. 2, q blocks)
+@pytest.mark.parametrize("n,d,k,p,q", [(3000, 130, 20, 5, 2), (3000, 130, 20, 5, 3), (3000, 130, 20, 5, 4),
+                                       (5000, 200, 12, 5, 4), (2000, 61, 9, 4, 3)])
+def test_block_lanczos_matches_the_oracle(ctx, n, d, k, p, q):
+    """The GPU's q-block sketch against the oracle's Block Lanczos (Alg. 2) started from Pi = X Omega / sqrt(n),
+    whose first block is the one-block range C Omega: the Ritz values and P^{-1/2} on probes agree, and the
+    Ritz values are at least the one-block sketch's (a larger Krylov space)."""
+    P = _problem(n, d, alpha=1.5, seed=n + d + q)
+    X64 = P.X.astype(np.float64)
+    Om = inputs.gaussian((k + p, d), seed=5)                      # Omega^T
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om), krylov_blocks=q)
+    assert rc == binding.OK
+    Uo, lo, _ = sketch.block_lanczos(X64, X64 @ Om.T.astype(np.float64) / np.sqrt(n), k, q)
+    lg = host(lam)
+    err = np.max(np.abs(lg - lo)) / lo[0]
+    Pg = precond.sketched_preconditioner(host(U64), lg, P.lam)
+    Po = precond.sketched_preconditioner(Uo, lo, P.lam)
+    V = np.random.default_rng(0).standard_normal((d, 8))
+    perr = rel(Pg @ V, Po @ V)
+    _, l1, _ = sketch.sketch(X64, Om.T.astype(np.float64), k)
+    print(f"\n[block lanczos q={q}] max |d lam~|/lam~_1 = {err:.2e}; P^-1/2 probe rel err = {perr:.2e}; "
+          f"lam~_k {lg[-1]:.4e} vs one block {l1[-1]:.4e}")
+    assert err <= 2e-5
+    assert perr < 1e-4
+    assert np.all(lg >= l1 * (1 - 1e-5))
+    Ug = host(U64)
+    assert np.allclose(Ug.T @ Ug, np.eye(k), atol=1e-6)
+
+
+def test_block_lanczos_width_is_bounded(ctx):
+    P = _problem(2000, 100, seed=3)
+    with pytest.raises(binding.ScsError) as e:          # 6 x (20 + 5) = 150 > 136 columns
+        ctx.sketch_build(dev(P.X), 20, krylov_blocks=6)
+    assert e.value.code == binding.EINVAL
+
+
+def test_block_lanczos_solve_reaches_the_closed_form(ctx):
+    """A whole solve preconditioned from a 3-block sketch stops at the gap against the FP64 optimum."""
+    P = _problem(6000, 150, alpha=1.5, seed=77)
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    lam, eps = 1e-5, 1e-8
+    ws = ridge.closed_form(X64, y64, lam)
+    Ls = ridge.objective(X64, y64, lam, ws)
+    r = ctx.svrg_solve(dev(P.X), dev(P.y), lam, 10, eps, krylov_blocks=3, batch=32, epoch_factor=0.25,
+                       stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=8.0, max_epochs=100)
+    assert r.status == binding.OK, r.report
+    assert ridge.objective(X64, y64, lam, host(r.w)) - Ls <= 1.5 * eps
