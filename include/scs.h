@@ -47,7 +47,7 @@ extern "C" {
 #define SCS_SKETCH_RANK_DEFICIENT 3 /* range-finder block lost rank (e.g. X = 0); solved without preconditioning */
 
 /* Precision of the sketch GEMMs and of the preconditioned rows used by the inner loop. */
-#define SCS_PREC_FP32 0       /* FP32 MFMA GEMMs, FP32 rows */
+#define SCS_PREC_FP32 0       /* FP32 MFMA for Rayleigh-Ritz and the apply, FP32 rows (range finder: see sketch_fp32) */
 #define SCS_PREC_MIXED 1      /* BF16 MFMA GEMMs (FP32 accumulation), BF16 rows in the inner loop */
 
 /* Stop rules for scs_svrg_solve (checked at the start of every epoch's full-gradient pass). */
@@ -102,6 +102,10 @@ typedef struct scs_opts {
   int w0_preconditioned;  /* 1: w0 is the solver's own variable w~ (for example a snapshot written to wt_out) */
   int epoch_offset;       /* epoch s of this call draws the index stream of epoch s + epoch_offset */
   float* wt_out;          /* optional device d: the final snapshot w~ (the checkpoint to resume from) */
+  int sketch_fp32;        /* 1: in FP32 precision the range finder's GEMMs (X Omega, X^T (X Omega) and the further
+                             Krylov blocks) use FP32 MFMA; 0 (default): BF16 MFMA with FP32 accumulation in every
+                             precision (the range only fixes the subspace; Rayleigh-Ritz, X Q and Z = X U~, follows
+                             `precision`, and the fixed point is set by the exact FP32 gradient) */
   int krylov_blocks;      /* q: the sketch's Krylov space [C Omega, C^2 Omega, ..., C^q Omega] (Block Lanczos, Alg. 2;
                              C = X^T X / n); 0 or 1 = the one-block range finder Y = X^T (X Omega). Each block
                              after the first costs two more passes over X; q (k + p) <= min(d, n, 136) */

@@ -55,6 +55,7 @@ class ScsOpts(ctypes.Structure):
         ("w0_preconditioned", ctypes.c_int),
         ("epoch_offset", ctypes.c_int),
         ("wt_out", ctypes.c_void_p),
+        ("sketch_fp32", ctypes.c_int),
         ("krylov_blocks", ctypes.c_int),
         ("no_graph", ctypes.c_int),
         ("warm_start", ctypes.c_int),

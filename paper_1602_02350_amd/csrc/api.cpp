@@ -40,6 +40,8 @@ struct scs_ctx {
   int* stop_flags = nullptr;  // host-pinned, one per epoch: set by the device when the solve is finished
   size_t stop_cap = 0;
   int xcd_stride = 8;
+  hipEvent_t fork_ev[2] = {nullptr, nullptr};  // work forked onto side stream 0 inside a single solve, and joined
+  hipEvent_t join_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -321,10 +323,14 @@ int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int*
 // sketches of different problems can run on different streams at once).
 int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
                 bool want_z, bool* rank_def, int* flags_out = nullptr, hipStream_t st_in = nullptr,
-                const std::string& sfx = "") {
+                const std::string& sfx = "", hipEvent_t x_done = nullptr) {
   hipStream_t st = st_in ? st_in : ctx->stream;
   const int l = k + o.oversample;
+  // Rayleigh-Ritz (X Q, its Gram, Z = X U~) follows the precision; the range finder (X Omega, X^T T and
+  // the further Krylov blocks) reads X in BF16 (FP32 accumulation) unless FP32 is asked for: it only
+  // fixes the subspace that Rayleigh-Ritz then resolves
   const int bf = o.precision == SCS_PREC_MIXED;
+  const int bf_range = bf || !o.sketch_fp32;
   // Omega^T (l x d)
   const float* OmT = o.omega;
   if (!OmT) {
@@ -335,13 +341,13 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   // T = X Omega (n x l, leading dimension l rounded up to 16 and zero-filled)
   const int64_t lp = cdiv(l, 16) * 16;
   WS(T, float, std::string("T") + sfx, (size_t)n * lp);
-  SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, OmT, l, d, T, lp, true));
+  SCS_CHECK(launch_gemm_nt_longk(st, bf_range, X, n, d, ldx, OmT, l, d, T, lp, true));
   // Y = X^T T (d x l), split over row chunks, summed in FP64
   int64_t nchunks = gemm_tn_splitk_chunks(n, d, l, X, ldx, T, lp);
   int64_t chunk = cdiv(n, nchunks);
   nchunks = cdiv(n, chunk);
   WS(part, float, std::string("partial") + sfx, (size_t)nchunks * d * l);
-  SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
+  SCS_CHECK(launch_gemm_tn_splitk(st, bf_range, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
   WS(Y, double, std::string("Y64") + sfx, (size_t)d * l);
   SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
   // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
@@ -390,8 +396,8 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     SCS_CHECK(cholqr2(Y, Qall, L, QTb, bflags));
     for (int j = 1; j < q; ++j) {
       // Yj = X^T (X Q_{j-1}) / n
-      SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QTb, l, d, T, lp, true));
-      SCS_CHECK(launch_gemm_tn_splitk(st, bf, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
+      SCS_CHECK(launch_gemm_nt_longk(st, bf_range, X, n, d, ldx, QTb, l, d, T, lp, true));
+      SCS_CHECK(launch_gemm_tn_splitk(st, bf_range, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
       SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0 / (double)n, Yj));
       const int64_t Pc = (int64_t)j * l;  // columns of the blocks before j
       for (int pass = 0; pass < 2; ++pass) {
@@ -411,6 +417,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   // Rayleigh-Ritz: Wq = X Q (n x L), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
   WS(Wq, float, std::string("Wq") + sfx, (size_t)n * Lp);
   SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, L, d, Wq, Lp, true));
+  if (x_done) SCS_HIP(hipEventRecord(x_done, st));  // the sketch reads X no more after this point
   int64_t nch2 = gemm_tn_splitk_chunks(n, L, L, Wq, Lp, Wq, Lp);
   int64_t chunk2 = cdiv(n, nch2);
   nch2 = cdiv(n, chunk2);
@@ -445,19 +452,44 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
 
 // Preconditioned rows: Xt = X/s + Z (U D)^T (ld ldt), reg = sqrt(n lambda)(U (U D)^T + I/s), beta = row norms.
 // Z: n x k with leading dimension gemm_wide_kpad(k), zero up to the next multiple of 16.
+// Events for work forked onto side stream 0 inside one call (fork slot i: fork_ev[i] / join_ev[i]).
+int ensure_fork_events(scs_ctx* c) {
+  for (int i = 0; i < 2; ++i) {
+    if (!c->fork_ev[i]) SCS_HIP(hipEventCreateWithFlags(&c->fork_ev[i], hipEventDisableTiming));
+    if (!c->join_ev[i]) SCS_HIP(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
+  }
+  return ensure_side_streams(c, 1);
+}
+
+// Preconditioned rows: Xt = X/s + Z (U D)^T (ld ldt), reg = sqrt(n lambda)(U (U D)^T + I/s), beta = row norms.
+// Z: n x k with leading dimension gemm_wide_kpad(k), zero up to the next multiple of 16.
+// aux (nullable): a second stream for the regularizer rows, which then run beside the data rows (the
+// caller's stream waits for them before returning from this enqueue sequence's join).
 int apply_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* U32, const float* Z,
                const double* lam, int k, double lambda, int gemm_bf16, int out_bf16, void* Xt, void* reg,
-               int64_t ldt, float* beta, SolveState* state, hipStream_t st_in = nullptr, const std::string& sfx = "") {
+               int64_t ldt, float* beta, SolveState* state, hipStream_t st_in = nullptr, const std::string& sfx = "",
+               bool fork_reg = false) {
   hipStream_t st = st_in ? st_in : ctx->stream;
   const int64_t kz = gemm_wide_kpad(k), drows = gemm_wide_bt_rows(d);
   WS(UD, float, "UD32" + sfx, (size_t)drows * kz);
   WS(Up, float, "Upad32" + sfx, (size_t)drows * kz);
   WS(scal, double, "scal" + sfx, 2);
   SCS_CHECK(launch_precond_setup(st, lam, k, lambda, n, U32, d, UD, Up, kz, scal, state));
+  hipStream_t rs = st;
+  if (fork_reg) {  // the d x d regularizer GEMM fills few CUs: run it beside the n x d one
+    SCS_CHECK(ensure_fork_events(ctx));
+    rs = ctx->side[0];
+    SCS_HIP(hipEventRecord(ctx->fork_ev[1], st));
+    SCS_HIP(hipStreamWaitEvent(rs, ctx->fork_ev[1], 0));
+  }
+  SCS_CHECK(launch_gemm_nt_wide(rs, gemm_bf16, Up, d, k, kz, UD, d, kz, (float)std::sqrt((double)n * lambda),
+                                nullptr, 0, 0.f, nullptr, 0.f, scal + 1, out_bf16, reg, ldt, beta ? beta + n : nullptr));
   SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Z, n, k, kz, UD, d, kz, 1.0f, X, ldx, 0.f, scal, 0.f, nullptr,
                                 out_bf16, Xt, ldt, beta));
-  SCS_CHECK(launch_gemm_nt_wide(st, gemm_bf16, Up, d, k, kz, UD, d, kz, (float)std::sqrt((double)n * lambda),
-                                nullptr, 0, 0.f, nullptr, 0.f, scal + 1, out_bf16, reg, ldt, beta ? beta + n : nullptr));
+  if (fork_reg) {
+    SCS_HIP(hipEventRecord(ctx->join_ev[1], rs));
+    SCS_HIP(hipStreamWaitEvent(st, ctx->join_ev[1], 0));
+  }
   return SCS_OK;
 }
 
@@ -824,11 +856,32 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
 
   WS(state, SolveState, "state", 1);
   SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
+  WS(w32, float, "w32", (size_t)d);
+  const int nwg = grad_num_workgroups(n, d);
+  WS(gpart, float, "gpart", (size_t)nwg * d);
+  WS(grsq, double, "grsq", (size_t)nwg);
+
+  // The first snapshot is w~ = 0 (no start point given), so w = P^{-1/2} w~ = 0 and the first gradient
+  // pass does not depend on the sketch: it runs on a side stream while the sketch's one-workgroup FP64
+  // kernels occupy one CU (after the sketch's last pass over X), and is joined before the first gradient
+  // finish. (Not with timing >= 2, which brackets every pass with events on the solve's stream.)
+  const bool early_grad = !sketch_failed && k > 0 && !o.w0 && o.timing < 2;
+  if (early_grad) SCS_CHECK(ensure_fork_events(ctx));
 
   // ---- sketch (Alg. 3, Block Lanczos step)
   int k_used = sketch_failed ? 0 : k;
   const bool rank_def = sketch_failed;
-  if (k_used > 0) SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, nullptr, chol_flags));
+  if (k_used > 0)
+    SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, true, nullptr, chol_flags, nullptr, "",
+                          early_grad ? ctx->fork_ev[0] : nullptr));
+  if (early_grad) {
+    // forked once the sketch has finished streaming X, so that it overlaps the sketch's FP64 algebra
+    hipStream_t gs = ctx->side[0];
+    SCS_HIP(hipStreamWaitEvent(gs, ctx->fork_ev[0], 0));
+    SCS_CHECK(launch_zero3(gs, w32, (int64_t)sizeof(float) * d, nullptr, 0, nullptr, 0));
+    SCS_CHECK(launch_grad_partial(gs, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
+    SCS_HIP(hipEventRecord(ctx->join_ev[0], gs));
+  }
   auto sketch_broke = [&]() {
     return k_used > 0 && (__atomic_load_n(chol_flags, __ATOMIC_ACQUIRE) || __atomic_load_n(chol_flags + 1, __ATOMIC_ACQUIRE));
   };
@@ -850,7 +903,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     UT32 = ws<float>(ctx, "UT32", 0);
     lam = ws<double>(ctx, "lam", 0);
     SCS_CHECK(apply_impl(ctx, X, n, d, ldx, U32, ws<float>(ctx, "Z", 0), lam, k_used, lambda, mixed, mixed, xt, rg,
-                         ldt, beta, state));
+                         ldt, beta, state, nullptr, "", true));
     Xt = xt;
   } else {
     if (mixed) {
@@ -890,13 +943,9 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   int W = choose_workgroups(o, d);
   WS(wt, float, "wt", (size_t)d);
   WS(wt_prev, float, "wt_prev", (size_t)d);
-  WS(w32, float, "w32", (size_t)d);
   WS(mu, float, "mu", (size_t)d);
   WS(tmp, double, "vtmp", (size_t)d);
   WS(g64, double, "g64", (size_t)16 * d);  // kColSplit x d first-level gradient sums
-  const int nwg = grad_num_workgroups(n, d);
-  WS(gpart, float, "gpart", (size_t)nwg * d);
-  WS(grsq, double, "grsq", (size_t)nwg);
   // index streams are drawn kSampleGroup epochs per launch
   constexpr int kSampleGroup = 8;
   WS(idxb, int32_t, "idx", (size_t)kSampleGroup * m * b);
@@ -947,10 +996,16 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   bool redo = false;
   for (int s = 0; s <= S; ++s) {
     float* trace_row = (o.trace_w && s < S) ? o.trace_w + (int64_t)s * d : nullptr;
-    SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w32, trace_row, tmp, state));
-    if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g0(s), st));
-    SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
-    if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g1(s), st));
+    if (s == 0 && early_grad) {
+      // the pass at w = 0 already ran beside the sketch
+      if (trace_row) SCS_CHECK(launch_zero3(st, trace_row, (int64_t)sizeof(float) * d, nullptr, 0, nullptr, 0));
+      SCS_HIP(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
+    } else {
+      SCS_CHECK(launch_premap(st, UT32, U32, lam, k_used, d, lambda, wt, w32, trace_row, tmp, state));
+      if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g0(s), st));
+      SCS_CHECK(launch_grad_partial(st, X, n, d, ldx, y, w32, gpart, grsq, nwg, state));
+      if (o.timing >= 2) SCS_HIP(hipEventRecord(ev_g1(s), st));
+    }
     SCS_CHECK(launch_grad_finish(st, gpart, grsq, nwg, n, d, w32, lambda, UT32, U32, lam, k_used, mu, g64, tmp, state,
                                  o.stop_rule, eps, o.f_star, wt, wt_prev, s == 0 ? 1 : 0, ctx->stop_flags + s));
     if (s == S) break;

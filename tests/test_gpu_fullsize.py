@@ -52,15 +52,21 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_sketch_stage(ctx, full):
+@pytest.mark.parametrize("sketch_fp32", [0, 1])
+def test_sketch_stage(ctx, full, sketch_fp32):
+    """The default sketch (BF16 GEMMs, FP32 accumulation) and, in FP32 mode, the FP32-MFMA sketch."""
+    if sketch_fp32 and full["mixed"]:
+        pytest.skip("mixed precision always sketches in BF16")
     cfg, X64 = full["cfg"], full["X64"]
     k, d = cfg["k"], cfg["d"]
     Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 12)
-    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), precision=full["prec"])
+    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), precision=full["prec"],
+                                       sketch_fp32=sketch_fp32)
     assert rc == binding.OK
     Uo, lo, _ = sketch.sketch(X64, Om.T.astype(np.float64), k)
     lg = lam.cpu().numpy()
-    u_eff = 2.0 ** -8 if full["mixed"] else 2.0 ** -24 * np.sqrt(d)
+    bf16 = full["mixed"] or not sketch_fp32
+    u_eff = 2.0 ** -8 if bf16 else 2.0 ** -24 * np.sqrt(d)
     err = np.max(np.abs(lg - lo)) / lo[0]
     Pg = precond.sketched_preconditioner(U64.cpu().numpy(), lg, cfg["lam"])
     Po = precond.sketched_preconditioner(Uo, lo, cfg["lam"])
@@ -77,7 +83,7 @@ def test_sketch_stage(ctx, full):
           f"P^-1/2 probe rel err = {perr:.3e}; sin theta_max = {sin_max:.3e}; "
           f"kappa^ = {k_hat:.4g} -> kappa~ = {kt_g:.4g} (oracle sketch {kt_o:.4g})")
     assert err <= 8 * u_eff
-    assert perr < (5e-2 if full["mixed"] else 1e-4)
+    assert perr < (5e-2 if bf16 else 1e-4)
     assert abs(kt_g - kt_o) <= 1e-2 * kt_o and kt_g < k_hat
     full["U32"], full["lam"] = U, lam
 
@@ -183,7 +189,8 @@ def test_block_lanczos_sketch_stage(ctx, full):
     cfg, X64 = full["cfg"], full["X64"]
     k, d, n = cfg["k"], cfg["d"], cfg["n"]
     Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED + 12)
-    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), krylov_blocks=2)
+    U, U64, lam, rc = ctx.sketch_build(full["X"], k, omega=torch.from_numpy(Om).cuda(), krylov_blocks=2,
+                                       sketch_fp32=1)
     assert rc == binding.OK
     Uo, lo, _ = sketch.block_lanczos(X64, X64 @ Om.T.astype(np.float64) / np.sqrt(n), k, 2)
     lg = lam.cpu().numpy()

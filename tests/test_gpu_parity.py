@@ -81,7 +81,7 @@ def _problem(n, d, alpha=1.5, lam=1e-4, seed=1):
 def test_sketch_matches_oracle_with_the_same_omega(ctx, n, d, k, p, mixed):
     P = _problem(n, d, seed=n + d)
     Om = inputs.gaussian((k + p, d), seed=3)                      # Omega^T, (k+p) x d
-    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om),
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om), sketch_fp32=int(not mixed),
                                        precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
     assert rc == binding.OK
     Uo, lo, _ = sketch.sketch(P.X.astype(np.float64), Om.T.astype(np.float64), k)
@@ -100,7 +100,7 @@ def test_sketch_matches_oracle_with_the_same_omega(ctx, n, d, k, p, mixed):
 def test_full_width_sketch_is_exact_on_gpu(ctx):
     """k + p = d: Rayleigh-Ritz on all of R^d returns the eigenvalues of C."""
     P = _problem(600, 24, alpha=1.0, seed=5)
-    U, U64, lam, rc = ctx.sketch_build(dev(P.X), 19, oversample=5)
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), 19, oversample=5, sketch_fp32=1)
     ev = np.sort(np.linalg.eigvalsh(ridge.correlation(P.X.astype(np.float64))))[::-1]
     assert np.allclose(host(lam), ev[:19], rtol=2e-5, atol=1e-6 * ev[0])
 
@@ -336,7 +336,7 @@ def test_papers_synthetic_data_tracks_the_oracle(ctx, alpha):
     m, S = n // b, 3
     idx = inputs.index_stream(n + d, S * m * b, seed=79).reshape(S, -1)
     res = ctx.svrg_solve(dev(X), dev(y), lam, k, 0.0, omega=dev(Om), indices=dev(idx, torch.int32), steps=m, batch=b,
-                         max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=8.0)
+                         max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=8.0, sketch_fp32=1)
     assert res.status == binding.OK, res.report
     wo, _, info = svrg.scsvrg(X64, y64, lam, k, Om.T.astype(np.float64), m, S, b, lambda s: idx[s], c=8.0)
     ws = ridge.closed_form(X64, y64, lam)
@@ -357,7 +357,7 @@ def test_solve_with_injected_randomness_tracks_the_oracle(ctx):
     m, S = n // b, 4
     idx = inputs.index_stream(n + d, S * m * b, seed=77).reshape(S, -1)
     res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, omega=dev(Om), indices=dev(idx, torch.int32),
-                         steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=4.0)
+                         steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=4.0, sketch_fp32=1)
     assert res.status == binding.OK
     wo, _, info = svrg.scsvrg(X64, y64, cfg["lam"], k, Om.T.astype(np.float64), m, S, b, lambda s: idx[s], c=4.0)
     ws = ridge.closed_form(X64, y64, cfg["lam"])
@@ -378,7 +378,7 @@ def test_uniform_sampling_tracks_the_oracle(ctx, k):
     idx = inputs.index_stream(n + d, S * m * b, seed=78).reshape(S, -1)
     res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, omega=dev(Om) if k else None,
                          indices=dev(idx, torch.int32), steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS,
-                         step_scale=c, uniform_sampling=1)
+                         step_scale=c, uniform_sampling=1, sketch_fp32=1)
     assert res.status == binding.OK
     Pm, _, _ = svrg.preconditioner_from_sketch(X64, cfg["lam"], k, Om.T.astype(np.float64))
     comp = precond.Components(X64, y64, cfg["lam"], Pm)
@@ -737,7 +737,7 @@ def test_budget_regularization_matches_the_oracle(ctx, n, d, k):
     p = min(5, d - k)
     seed = 123
     Om = sampling.gaussian(seed, (k + p) * d).astype(np.float32).reshape(k + p, d)   # the drawn Omega^T
-    pre, plain, rc = ctx.regularization_for_budget(dev(P.X), k, oversample=p, seed=seed)
+    pre, plain, rc = ctx.regularization_for_budget(dev(P.X), k, oversample=p, seed=seed, sketch_fp32=1)
     assert rc == binding.OK
     _, lt, _ = sketch.sketch(X64, Om.T.astype(np.float64), k)
     trace = float(np.sum(X64 * X64)) / n
@@ -815,7 +815,7 @@ def test_block_lanczos_matches_the_oracle(ctx, n, d, k, p, q):
     P = _problem(n, d, alpha=1.5, seed=n + d + q)
     X64 = P.X.astype(np.float64)
     Om = inputs.gaussian((k + p, d), seed=5)                      # Omega^T
-    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om), krylov_blocks=q)
+    U, U64, lam, rc = ctx.sketch_build(dev(P.X), k, oversample=p, omega=dev(Om), krylov_blocks=q, sketch_fp32=1)
     assert rc == binding.OK
     Uo, lo, _ = sketch.block_lanczos(X64, X64 @ Om.T.astype(np.float64) / np.sqrt(n), k, q)
     lg = host(lam)
@@ -852,3 +852,26 @@ def test_block_lanczos_solve_reaches_the_closed_form(ctx):
                        stop_rule=binding.STOP_GAP, f_star=Ls, step_scale=8.0, max_epochs=100)
     assert r.status == binding.OK, r.report
     assert ridge.objective(X64, y64, lam, host(r.w)) - Ls <= 1.5 * eps
+
+
+
+def test_default_bf16_sketch_solve_tracks_the_oracle(ctx):
+    """The default FP32 solve runs its sketch GEMMs in BF16 (FP32 accumulation): with the same Omega and index
+    stream it follows the oracle's trajectory to the accuracy of a BF16 sketch (P^{-1/2} within about 1e-2),
+    and the FP32 accuracy gate still holds (the gradient is exact)."""
+    cfg = inputs.WORKLOADS["small_n2000_d100"]
+    P = inputs.make_ridge(cfg["n"], cfg["d"], cfg["alpha"], cfg["lam"], seed=inputs.BASE_SEED)
+    n, d, k, b = cfg["n"], cfg["d"], cfg["k"], cfg["b"]
+    X64, y64 = P.X.astype(np.float64), P.y.astype(np.float64)
+    Om = inputs.gaussian((k + 5, d), seed=inputs.BASE_SEED)
+    m, S = n // b, 4
+    idx = inputs.index_stream(n + d, S * m * b, seed=77).reshape(S, -1)
+    res = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, omega=dev(Om), indices=dev(idx, torch.int32),
+                         steps=m, batch=b, max_epochs=S, stop_rule=binding.STOP_EPOCHS, step_scale=4.0)
+    assert res.status == binding.OK
+    wo, _, _ = svrg.scsvrg(X64, y64, cfg["lam"], k, Om.T.astype(np.float64), m, S, b, lambda s: idx[s], c=4.0)
+    ws = ridge.closed_form(X64, y64, cfg["lam"])
+    assert_tracks(host(res.w), wo, ws, 3e-1)
+    gate = ctx.svrg_solve(dev(P.X), dev(P.y), cfg["lam"], k, 0.0, batch=b, max_epochs=60,
+                          stop_rule=binding.STOP_EPOCHS, step_scale=8.0)
+    assert rel(host(gate.w), ws) <= 1e-5
