@@ -251,6 +251,10 @@ __device__ __forceinline__ void inner_epoch_body(const InnerArgs& a, const int w
         if (xrow)
           __hip_atomic_store(&slot[(int64_t)w * 64], ((uint64_t)target << 32) | __float_as_uint(cl),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // first poll about 0.2 us (512 cycles) after the post: polls issued at once mostly return
+        // stale words and slow the posts of the other workgroups down (measured: 2.33 -> 1.94 us per
+        // step at 16 workgroups, b = 64; 2.42 -> 2.05 at 8)
+        __builtin_amdgcn_s_sleep(8);
         uint64_t xv[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
