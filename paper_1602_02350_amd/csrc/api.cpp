@@ -571,6 +571,7 @@ int scs_destroy(scs_ctx* c) {
   if (!c) return SCS_OK;
   Guard g(c->device);
   hipStreamSynchronize(c->stream);
+  for (auto q : c->side) hipStreamSynchronize(q);
   for (auto& kv : c->bufs)
     if (kv.second.p) hipFree(kv.second.p);
   for (auto e : c->events) hipEventDestroy(e);

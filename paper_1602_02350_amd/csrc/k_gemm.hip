@@ -41,21 +41,30 @@ int resident_blocks(const void* fn, int threads, size_t lds) {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// gfx950's 16x16x32 BF16 MFMA. Lane (r, g) supplies 8 K values of row (A) or column (B) r; the kernels
+// give it the 4-value fragments of two consecutive 16-wide K blocks (K 16 q + 4 g .. +3 and
+// 16 (q + 1) + 4 g .. +3) in both operands, so every product pairs equal K and the 32 K values of the
+// two blocks are each summed once.
+__device__ __forceinline__ s8v cat8(const s4v& lo, const s4v& hi) {
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+__device__ __forceinline__ f4v mfma_bf16_k32(const s8v& a, const s8v& b, const f4v& acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), acc, 0,
+                                                 0, 0);
+}
 
 __device__ __forceinline__ short bf16s(float f) { return (short)f32_to_bf16(f); }
+__device__ __forceinline__ s4v bf16x4(const float4& a) { return s4v{bf16s(a.x), bf16s(a.y), bf16s(a.z), bf16s(a.w)}; }
 
-template <bool BF16>
-__device__ __forceinline__ void mfma16(const float4& a, const float4& b, f4v& acc) {
-  if constexpr (BF16) {
-    s4v av = {bf16s(a.x), bf16s(a.y), bf16s(a.z), bf16s(a.w)};
-    s4v bv = {bf16s(b.x), bf16s(b.y), bf16s(b.z), bf16s(b.w)};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-  } else {
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
-  }
+// four FP32 16x16x4 MFMAs over the K values a.x .. a.w (lane (r, g): K 4 g .. 4 g + 3 of a 16-wide block)
+__device__ __forceinline__ void mfma16_f32(const float4& a, const float4& b, f4v& acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
 }
 
 // Guarded load of 4 consecutive floats of row `row` starting at column `col`.
@@ -125,16 +134,35 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
     stash();
     __syncthreads();
     if (k0 + kLkBK < K) fetch(k0 + kLkBK);
-#pragma unroll
-    for (int kq = 0; kq < kLkBK; kq += 16) {
-      const int ko = kq + 4 * (lane >> 4);
-      float4 a0 = *reinterpret_cast<const float4*>(&As[(wave * 32 + (lane & 15)) * LDS_W + ko]);
-      float4 a1 = *reinterpret_cast<const float4*>(&As[(wave * 32 + 16 + (lane & 15)) * LDS_W + ko]);
+    if constexpr (BF16) {
+      static_assert(kLkBK == 32, "one 16x16x32 MFMA per chunk");
+      const int ko = 4 * (lane >> 4);
+      const float* a0p = &As[(wave * 32 + (lane & 15)) * LDS_W + ko];
+      const float* a1p = &As[(wave * 32 + 16 + (lane & 15)) * LDS_W + ko];
+      const s8v a0 = cat8(bf16x4(*reinterpret_cast<const float4*>(a0p)),
+                          bf16x4(*reinterpret_cast<const float4*>(a0p + 16)));
+      const s8v a1 = cat8(bf16x4(*reinterpret_cast<const float4*>(a1p)),
+                          bf16x4(*reinterpret_cast<const float4*>(a1p + 16)));
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        float4 b = *reinterpret_cast<const float4*>(&Bs[(cb * 16 + (lane & 15)) * LDS_W + ko]);
-        mfma16<BF16>(a0, b, acc[0][cb]);
-        mfma16<BF16>(a1, b, acc[1][cb]);
+        const float* bp = &Bs[(cb * 16 + (lane & 15)) * LDS_W + ko];
+        const s8v b = cat8(bf16x4(*reinterpret_cast<const float4*>(bp)),
+                           bf16x4(*reinterpret_cast<const float4*>(bp + 16)));
+        acc[0][cb] = mfma_bf16_k32(a0, b, acc[0][cb]);
+        acc[1][cb] = mfma_bf16_k32(a1, b, acc[1][cb]);
+      }
+    } else {
+#pragma unroll
+      for (int kq = 0; kq < kLkBK; kq += 16) {
+        const int ko = kq + 4 * (lane >> 4);
+        float4 a0 = *reinterpret_cast<const float4*>(&As[(wave * 32 + (lane & 15)) * LDS_W + ko]);
+        float4 a1 = *reinterpret_cast<const float4*>(&As[(wave * 32 + 16 + (lane & 15)) * LDS_W + ko]);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          float4 b = *reinterpret_cast<const float4*>(&Bs[(cb * 16 + (lane & 15)) * LDS_W + ko]);
+          mfma16_f32(a0, b, acc[0][cb]);
+          mfma16_f32(a1, b, acc[1][cb]);
+        }
       }
     }
   }
@@ -153,7 +181,8 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
 // ------------------------------------------------------------------ NT, long K, A in registers
 // The same product as gemm_nt_longk for 16-byte aligned rows of A (X): each wave owns 16 rows of A
 // and reads its MFMA fragments straight from global memory into registers, one K chunk ahead
-// (lane (r, g) holds A[row0 + r][k0 + 16 q + 4 g .. +3]); Bt's K chunk (N <= 144 rows) is staged
+// (lane (r, g) holds A[row0 + r][k0 + 16 q + 4 g .. +3] in FP32, A[row0 + r][k0 + 32 p + 8 g .. +7] for
+// the BF16 16x16x32 MFMA); Bt's K chunk (N <= 144 rows) is staged
 // through LDS, double-buffered and rounded to BF16 once in BF16 mode. One barrier per chunk;
 // workgroups loop over row tiles (grid sized to the resident capacity). The last chunk, where K may
 // end inside it, is loaded with guards.
@@ -224,24 +253,28 @@ __global__ __launch_bounds__(lr_threads(BF16), lr_waves(BF16)) void gemm_nt_long
     }
   };
 
+  // K offset of fragment q within a chunk: FP32 lane group g takes K 16 q + 4 g .. +3; BF16 lane group g
+  // takes the 8 consecutive K 32 (q / 2) + 8 g .. +7 of the 16x16x32 MFMA, as fragments q (even) and q + 1
+  const int ga = BF16 ? 2 * g4 : g4;
+  auto koff = [](int q) { return BF16 ? 32 * (q >> 1) + 4 * (q & 1) : 16 * q; };
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row = tile * kLrBM + wave * 16 + rl;
-    const float* arow = A + (row < M ? row : M - 1) * lda + g4;
+    const float* arow = A + (row < M ? row : M - 1) * lda + ga;
     f4v af[NQ], an[NQ];   // chunks c and c + 1
     auto load_a = [&](int64_t c, f4v (&dst)[NQ]) {
       const int64_t k0 = c * KC;
       if (k0 + KC <= K) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) dst[q] = *reinterpret_cast<const f4v*>(arow + k0 + 16 * q);
+        for (int q = 0; q < NQ; ++q) dst[q] = *reinterpret_cast<const f4v*>(arow + k0 + koff(q));
       } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const int64_t k = k0 + 16 * q + g4;
+          const int64_t k = k0 + koff(q) + ga;
           f4v v = {0.f, 0.f, 0.f, 0.f};
           if (k + 3 < K) {
-            v = *reinterpret_cast<const f4v*>(arow + k0 + 16 * q);
+            v = *reinterpret_cast<const f4v*>(arow + k0 + koff(q));
           } else {
-            const float* p = arow + k0 + 16 * q;
+            const float* p = arow + k0 + koff(q);
             if (k < K) v[0] = p[0];
             if (k + 1 < K) v[1] = p[1];
             if (k + 2 < K) v[2] = p[2];
@@ -264,15 +297,18 @@ __global__ __launch_bounds__(lr_threads(BF16), lr_waves(BF16)) void gemm_nt_long
       if (c + 1 < nch) load_a(c + 1, an);
       const float* base = S + (int)(c & 1) * BUF;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < NQ; q += BF16 ? 2 : 1) {
         if constexpr (BF16) {
-          const uint32_t lo = pack_bf16x2(af[q][0], af[q][1]), hi = pack_bf16x2(af[q][2], af[q][3]);
-          const s4v ah = {(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
+          static_assert(NQ % 2 == 0, "K blocks are taken in pairs");
+          const uint32_t l0 = pack_bf16x2(af[q][0], af[q][1]), h0 = pack_bf16x2(af[q][2], af[q][3]);
+          const uint32_t l1 = pack_bf16x2(af[q + 1][0], af[q + 1][1]), h1 = pack_bf16x2(af[q + 1][2], af[q + 1][3]);
+          const s8v ah = {(short)(l0 & 0xffff), (short)(l0 >> 16), (short)(h0 & 0xffff), (short)(h0 >> 16),
+                          (short)(l1 & 0xffff), (short)(l1 >> 16), (short)(h1 & 0xffff), (short)(h1 >> 16)};
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb) {
-            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
-                                                         (cb * 16 + rl) * LH + 16 * q + g4);
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bv, acc[cb], 0, 0, 0);
+            const s8v bv = *reinterpret_cast<const s8v*>(reinterpret_cast<const uint16_t*>(base) +
+                                                         (cb * 16 + rl) * LH + 16 * q + ga);
+            acc[cb] = mfma_bf16_k32(ah, bv, acc[cb]);
           }
         } else {
 #pragma unroll
@@ -313,8 +349,8 @@ __global__ __launch_bounds__(lr_threads(BF16), lr_waves(BF16)) void gemm_nt_long
 // m_base = blockIdx.x 8 16 TC + 16 TC w. Lane (r, g) loads A[row][m_base + TC r .. + TC - 1] as one
 // vector (16 lanes cover 16 TC contiguous floats of a row, 4 rows per instruction), and component c
 // of it feeds output tile c: rows m = m_base + TC i + c. With the FP32 16x16x4 MFMA a K step is 4
-// rows (lane group g supplies row g); with the BF16 16x16x16 MFMA a K step is 16 rows (lane group g
-// supplies rows 4 g .. 4 g + 3, from four loads). B's rows are staged through LDS in tiles of 64
+// rows (lane group g supplies row g); with gfx950's BF16 16x16x32 MFMA a K step is 32 rows (lane group g
+// supplies rows 8 g .. 8 g + 7, from eight loads). B's rows are staged through LDS in tiles of 64
 // rows, double-buffered (FP32 row-major; BF16 transposed and rounded once), one barrier per tile;
 // the A loads of the next K step are issued before the MFMAs of the current one.
 constexpr int kTgThreads = 512;
@@ -327,7 +363,7 @@ __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __
                                                                  int64_t ldb, float* __restrict__ partial,
                                                                  int64_t chunk_rows) {
   constexpr int TC = tg_tc(NB);                // output tiles (columns of A per lane)
-  constexpr int KS = BF16 ? 16 : 4;            // rows per K step
+  constexpr int KS = BF16 ? 32 : 4;            // rows per K step
   constexpr int KR = 64;                       // rows per staged B tile
   constexpr int SPT = KR / KS;                 // K steps per tile
   constexpr int BN = NB * 16;
@@ -336,7 +372,7 @@ __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __
   constexpr int BUF = BF16 ? BN * LH / 2 : KR * LF;
   constexpr int NE = KR * BN / 4;              // float4 per B tile
   constexpr int RB = (NE + kTgThreads - 1) / kTgThreads;
-  constexpr int NL = BF16 ? 4 : 1;             // loads of A per lane and K step
+  constexpr int NL = BF16 ? 8 : 1;             // loads of A per lane and K step
   typedef float tcv __attribute__((ext_vector_type(TC)));
   __shared__ float S[2 * BUF];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -393,7 +429,7 @@ __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __
   auto load_a = [&](int64_t s, tcv (&x)[NL]) {
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int64_t row = r0 + s * KS + (BF16 ? 4 * g + u : g);
+      const int64_t row = r0 + s * KS + (BF16 ? 8 * g + u : g);
       tcv v;
 #pragma unroll
       for (int c = 0; c < TC; ++c) v[c] = 0.f;
@@ -436,13 +472,18 @@ __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) {
           if constexpr (BF16) {
-            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
-                                                         (16 * cb + rl) * LH + ss * KS + 4 * g);
+            const s8v bv = *reinterpret_cast<const s8v*>(reinterpret_cast<const uint16_t*>(base) +
+                                                         (16 * cb + rl) * LH + ss * KS + 8 * g);
 #pragma unroll
             for (int c = 0; c < TC; ++c) {
-              const uint32_t lo = pack_bf16x2(xa[0][c], xa[1][c]), hi = pack_bf16x2(xa[2][c], xa[3][c]);
-              const s4v av = {(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
-              acc[c][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[c][cb], 0, 0, 0);
+              s8v av;
+#pragma unroll
+              for (int u = 0; u < 8; u += 2) {
+                const uint32_t h = pack_bf16x2(xa[u][c], xa[u + 1][c]);
+                av[u] = (short)(h & 0xffff);
+                av[u + 1] = (short)(h >> 16);
+              }
+              acc[c][cb] = mfma_bf16_k32(av, bv, acc[c][cb]);
             }
           } else {
             const float bv = base[(ss * KS + g) * LF + 16 * cb + rl];
@@ -552,15 +593,19 @@ __global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_k
     const int64_t row = tile * kWdBM + wave * 16 + rl;
     const bool row_ok = row < M;
     const int64_t rowc = row_ok ? row : M - 1;
-    // A fragments: lane holds A[row][16 q + g4 .. +3]
+    // A fragments: lane holds A[row][16 q + g4 .. +3] (FP32, or BF16 with an odd block count), or for
+    // the BF16 16x16x32 MFMA the 8 consecutive A[row][32 (q / 2) + 2 g4 .. +7] as fragments q and q + 1
+    constexpr bool K32 = BF16 && NKQ % 2 == 0;
+    const int ga = K32 ? 2 * g4 : g4;
+    auto koff = [](int q) { return K32 ? 32 * (q >> 1) + 4 * (q & 1) : 16 * q; };
     float4 af[NKQ];
     s4v ah[NKQ];
     {
-      const float* arow = A + rowc * lda + g4;
+      const float* arow = A + rowc * lda + ga;
 #pragma unroll
       for (int q = 0; q < NKQ; ++q) {
-        float4 v = *reinterpret_cast<const float4*>(arow + 16 * q);
-        if (q >= nq) v = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 v = *reinterpret_cast<const float4*>(arow + koff(q));
+        if (koff(q) + ga >= 16 * nq) v = make_float4(0.f, 0.f, 0.f, 0.f);   // past the valid 16-column blocks
         if constexpr (BF16) {
           const uint32_t lo = pack_bf16x2(v.x, v.y), hi = pack_bf16x2(v.z, v.w);
           ah[q] = s4v{(short)(lo & 0xffff), (short)(lo >> 16), (short)(hi & 0xffff), (short)(hi >> 16)};
@@ -657,12 +702,16 @@ __global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_k
       for (int cb = 0; cb < 4; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
       const float* base = S + (c & 1) * BUF;
 #pragma unroll
-      for (int q = 0; q < NKQ; ++q) {
+      for (int q = 0; q < NKQ; q += K32 ? 2 : 1) {
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          if constexpr (BF16) {
-            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) +
-                                                         (cb * 16 + rl) * LH + 16 * q + g4);
+          if constexpr (K32) {
+            const s8v bv = *reinterpret_cast<const s8v*>(reinterpret_cast<const uint16_t*>(base) + (cb * 16 + rl) * LH +
+                                                         16 * q + ga);
+            acc[cb] = mfma_bf16_k32(bv, cat8(ah[q], ah[q + 1]), acc[cb]);
+          } else if constexpr (BF16) {   // one 16-wide K block (K = 16)
+            const s4v bv = *reinterpret_cast<const s4v*>(reinterpret_cast<const uint16_t*>(base) + (cb * 16 + rl) * LH +
+                                                         16 * q + g4);
             acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bv, ah[q], acc[cb], 0, 0, 0);
           } else {
             const float4 bv = *reinterpret_cast<const float4*>(base + (cb * 16 + rl) * LW + 16 * q + g4);
@@ -731,7 +780,7 @@ __global__ __launch_bounds__(wd_threads(NKQ), wd_waves(NKQ)) void gemm_nt_wide_k
 }
 
 // ------------------------------------------------------------------ TN split-K
-constexpr int kTnBM = 64, kTnBK = 16;
+constexpr int kTnBM = 64;
 
 template <int NB, bool BF16>
 __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __restrict__ A, int64_t R, int64_t M,
@@ -739,6 +788,7 @@ __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __rest
                                                              int64_t ldb, float* __restrict__ partial,
                                                              int64_t chunk_rows, bool a_al, bool b_al) {
   constexpr int BN = NB * 16;
+  constexpr int kTnBK = BF16 ? 32 : 16;   // rows per chunk: one MFMA K step
   constexpr int AW = kTnBM + 4, BW = BN + 4;
   __shared__ float As[kTnBK * AW];
   __shared__ float Bs[kTnBK * BW];
@@ -750,12 +800,13 @@ __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __rest
   f4v acc[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
-  float4 ra, rb[B_SLOTS];
+  float4 ra[kTnBK / 16], rb[B_SLOTS];
   auto fetch = [&](int64_t k0) {
-    {
-      int r = tid >> 4, c4 = tid & 15;  // 16 rows x 16 float4
+#pragma unroll
+    for (int q = 0; q < kTnBK / 16; ++q) {
+      int r = (tid >> 4) + 16 * q, c4 = tid & 15;  // 16 rows x 16 float4 per slot
       int64_t row = k0 + r;
-      ra = row < r1 ? load4(A, lda, R, M, row, m0 + 4 * c4, a_al) : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra[q] = row < r1 ? load4(A, lda, R, M, row, m0 + 4 * c4, a_al) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int q = 0; q < B_SLOTS; ++q) {
@@ -767,9 +818,10 @@ __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __rest
     }
   };
   auto stash = [&]() {
-    {
-      int r = tid >> 4, c4 = tid & 15;
-      *reinterpret_cast<float4*>(&As[r * AW + 4 * c4]) = ra;
+#pragma unroll
+    for (int q = 0; q < kTnBK / 16; ++q) {
+      int r = (tid >> 4) + 16 * q, c4 = tid & 15;
+      *reinterpret_cast<float4*>(&As[r * AW + 4 * c4]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < B_SLOTS; ++q) {
@@ -785,14 +837,22 @@ __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __rest
     __syncthreads();
     if (k0 + kTnBK < r1) fetch(k0 + kTnBK);
     const int g = lane >> 4, mi = wave * 16 + (lane & 15);
-    float4 a = make_float4(As[(4 * g + 0) * AW + mi], As[(4 * g + 1) * AW + mi], As[(4 * g + 2) * AW + mi],
-                           As[(4 * g + 3) * AW + mi]);
+    // lane group g takes rows 4 g .. 4 g + 3 of each 16-row half of the chunk
+    auto col4 = [&](const float* T, int w, int j, int h) {
+      return make_float4(T[(16 * h + 4 * g + 0) * w + j], T[(16 * h + 4 * g + 1) * w + j],
+                         T[(16 * h + 4 * g + 2) * w + j], T[(16 * h + 4 * g + 3) * w + j]);
+    };
+    if constexpr (BF16) {
+      const s8v a = cat8(bf16x4(col4(As, AW, mi, 0)), bf16x4(col4(As, AW, mi, 1)));
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
-      int nj = cb * 16 + (lane & 15);
-      float4 b = make_float4(Bs[(4 * g + 0) * BW + nj], Bs[(4 * g + 1) * BW + nj], Bs[(4 * g + 2) * BW + nj],
-                             Bs[(4 * g + 3) * BW + nj]);
-      mfma16<BF16>(a, b, acc[cb]);
+      for (int cb = 0; cb < NB; ++cb) {
+        const int nj = cb * 16 + (lane & 15);
+        acc[cb] = mfma_bf16_k32(a, cat8(bf16x4(col4(Bs, BW, nj, 0)), bf16x4(col4(Bs, BW, nj, 1))), acc[cb]);
+      }
+    } else {
+      const float4 a = col4(As, AW, mi, 0);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) mfma16_f32(a, col4(Bs, BW, cb * 16 + (lane & 15), 0), acc[cb]);
     }
   }
   float* out = partial + (int64_t)blockIdx.y * M * N;
