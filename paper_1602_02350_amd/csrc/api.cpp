@@ -1793,18 +1793,23 @@ static int path_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
     }
   }
 
-  // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X
+  // ---- epochs: the gradients of all P solves as two MFMA GEMMs over the shared X; once every solve
+  // has stopped (epochs queued ahead of the host's stop decision, or the rest of a replayed graph)
+  // they return at entry, as the per-solve kernels do
+  Gate all_done;
+  all_done.count = done_count;
+  all_done.total = P;
   auto epoch_launches = [&](hipStream_t q, int s, const int* clk) -> int {
     SCS_CHECK(launch_premap_batched(q, desc, P, 0, nullptr));
     for (int c0 = 0; c0 < P; c0 += kPc) {
       const int pc = std::min(kPc, P - c0);
-      SCS_CHECK(launch_gemm_nt_longk(q, 0, X, n, d, ldx, W32 + (int64_t)c0 * d, pc, d, R + c0, P));
+      SCS_CHECK(launch_gemm_nt_longk(q, 0, X, n, d, ldx, W32 + (int64_t)c0 * d, pc, d, R + c0, P, false, all_done));
     }
-    SCS_CHECK(launch_residual_batched(q, R, n, P, Y, ny, nblk, rsq));
+    SCS_CHECK(launch_residual_batched(q, R, n, P, Y, ny, nblk, rsq, all_done));
     for (int c0 = 0; c0 < P; c0 += kPc) {
       const int pc = std::min(kPc, P - c0);
-      SCS_CHECK(launch_gemm_tn_splitk(q, 0, X, n, d, ldx, R + c0, pc, P, part, chunk, nchunks));
-      SCS_CHECK(launch_reduce_partials_t(q, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d));
+      SCS_CHECK(launch_gemm_tn_splitk(q, 0, X, n, d, ldx, R + c0, pc, P, part, chunk, nchunks, all_done));
+      SCS_CHECK(launch_reduce_partials_t(q, part, nchunks, d, pc, gsum + (int64_t)c0 * d, d, all_done));
     }
     SCS_CHECK(launch_grad_finalize_batched(q, desc, P, s == 0 ? 1 : 0, done_count,
                                            clk ? ctx->stop_flags : ctx->stop_flags + s, clk));

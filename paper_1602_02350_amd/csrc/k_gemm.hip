@@ -59,6 +59,8 @@ __device__ __forceinline__ f4v mfma_bf16_k32(const s8v& a, const s8v& b, const f
 __device__ __forceinline__ short bf16s(float f) { return (short)f32_to_bf16(f); }
 __device__ __forceinline__ s4v bf16x4(const float4& a) { return s4v{bf16s(a.x), bf16s(a.y), bf16s(a.z), bf16s(a.w)}; }
 
+__device__ __forceinline__ bool gate_shut(const Gate& g) { return g.count && *g.count >= g.total; }
+
 // four FP32 16x16x4 MFMAs over the K values a.x .. a.w (lane (r, g): K 4 g .. 4 g + 3 of a 16-wide block)
 __device__ __forceinline__ void mfma16_f32(const float4& a, const float4& b, f4v& acc) {
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
@@ -88,7 +90,8 @@ template <int NB, bool BF16>
 __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restrict__ A, int64_t M, int64_t K,
                                                             int64_t lda, const float* __restrict__ Bt, int64_t N,
                                                             int64_t ldb, float* __restrict__ C, int64_t ldc,
-                                                            int64_t nst, bool a_al, bool b_al) {
+                                                            int64_t nst, bool a_al, bool b_al, Gate gate) {
+  if (gate_shut(gate)) return;
   constexpr int BN = NB * 16;
   constexpr int LDS_W = kLkBK + kLkPad;
   __shared__ float As[kLkBM * LDS_W];
@@ -196,7 +199,8 @@ constexpr int lr_waves(bool bf16) { return bf16 ? 4 : 3; }
 template <int NB, bool BF16>
 __global__ __launch_bounds__(lr_threads(BF16), lr_waves(BF16)) void gemm_nt_longk_reg_kernel(
     const float* __restrict__ A, int64_t M, int64_t K, int64_t lda, const float* __restrict__ Bt, int64_t N,
-    int64_t ldb, float* __restrict__ C, int64_t ldc, int64_t nst) {
+    int64_t ldb, float* __restrict__ C, int64_t ldc, int64_t nst, Gate gate) {
+  if (gate_shut(gate)) return;
   constexpr int KC = BF16 ? 64 : 32;          // K per chunk
   constexpr int kLrThreads = lr_threads(BF16), kLrBM = 16 * (kLrThreads / 64);
   constexpr int NQ = KC / 16;                  // MFMA K steps per chunk
@@ -361,7 +365,8 @@ template <int NB, bool BF16>
 __global__ __launch_bounds__(kTgThreads) void gemm_tn_reg_kernel(const float* __restrict__ A, int64_t R, int64_t M,
                                                                  int64_t lda, const float* __restrict__ B, int64_t N,
                                                                  int64_t ldb, float* __restrict__ partial,
-                                                                 int64_t chunk_rows) {
+                                                                 int64_t chunk_rows, Gate gate) {
+  if (gate_shut(gate)) return;
   constexpr int TC = tg_tc(NB);                // output tiles (columns of A per lane)
   constexpr int KS = BF16 ? 32 : 4;            // rows per K step
   constexpr int KR = 64;                       // rows per staged B tile
@@ -786,7 +791,8 @@ template <int NB, bool BF16>
 __global__ __launch_bounds__(256) void gemm_tn_splitk_kernel(const float* __restrict__ A, int64_t R, int64_t M,
                                                              int64_t lda, const float* __restrict__ B, int64_t N,
                                                              int64_t ldb, float* __restrict__ partial,
-                                                             int64_t chunk_rows, bool a_al, bool b_al) {
+                                                             int64_t chunk_rows, bool a_al, bool b_al, Gate gate) {
+  if (gate_shut(gate)) return;
   constexpr int BN = NB * 16;
   constexpr int kTnBK = BF16 ? 32 : 16;   // rows per chunk: one MFMA K step
   constexpr int AW = kTnBM + 4, BW = BN + 4;
@@ -879,7 +885,8 @@ __global__ void reduce_partials_kernel(const float* partial, int64_t nchunks, in
 // Column sums of the split-K partials, transposed: G[c ldg + j] = sum_chunk partial[chunk][j][c] (FP64, in
 // chunk order), so that column c (one problem) becomes a contiguous row of G.
 __global__ void reduce_partials_t_kernel(const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
-                                         int64_t ldg) {
+                                         int64_t ldg, Gate gate) {
+  if (gate_shut(gate)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t elems = d * Pc;
   if (e >= elems) return;
@@ -893,7 +900,8 @@ __global__ void reduce_partials_t_kernel(const float* partial, int64_t nchunks, 
 // R[i][p] -= Y[p mod ny][i] for the n x P residual matrix of a shared-X batch, and the FP64 residual
 // sums of squares per (problem, row block): rsq[p nblk + blk].
 __global__ __launch_bounds__(256) void residual_batched_kernel(float* R, int64_t n, int P, const float* Y, int ny,
-                                                               int nblk, double* rsq) {
+                                                               int nblk, double* rsq, Gate gate) {
+  if (gate_shut(gate)) return;
   const int64_t rows = (n + nblk - 1) / nblk;
   const int64_t i0 = (int64_t)blockIdx.x * rows;
   const int64_t i1 = i0 + rows < n ? i0 + rows : n;
@@ -913,7 +921,7 @@ bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (
 
 template <int NB, bool BF16>
 int longk_reg_launch(hipStream_t st, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt, int64_t N,
-                     int64_t ldb, float* C, int64_t ldc, int64_t nst) {
+                     int64_t ldb, float* C, int64_t ldc, int64_t nst, Gate gate) {
   const void* fn = (const void*)gemm_nt_longk_reg_kernel<NB, BF16>;
   constexpr int kLrThreads = lr_threads(BF16), kLrBM = 16 * (kLrThreads / 64);
   const int res = resident_blocks(fn, kLrThreads, 0);
@@ -923,25 +931,25 @@ int longk_reg_launch(hipStream_t st, const float* A, int64_t M, int64_t K, int64
   }
   const int64_t grid = std::min<int64_t>(cdiv(M, kLrBM), (int64_t)res);
   gemm_nt_longk_reg_kernel<NB, BF16><<<dim3((unsigned)grid), dim3(kLrThreads), 0, st>>>(A, M, K, lda, Bt, N, ldb, C,
-                                                                                      ldc, nst);
+                                                                                      ldc, nst, gate);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
 
 template <bool BF16>
 int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K, int64_t lda, const float* Bt,
-                   int64_t N, int64_t ldb, float* C, int64_t ldc, int64_t nst) {
+                   int64_t N, int64_t ldb, float* C, int64_t ldc, int64_t nst, Gate gate) {
   if (aligned16(A, lda)) {
     switch (nb) {
-      case 1: return longk_reg_launch<1, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 2: return longk_reg_launch<2, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 3: return longk_reg_launch<3, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 4: return longk_reg_launch<4, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 5: return longk_reg_launch<5, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 6: return longk_reg_launch<6, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 7: return longk_reg_launch<7, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 8: return longk_reg_launch<8, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
-      case 9: return longk_reg_launch<9, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+      case 1: return longk_reg_launch<1, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 2: return longk_reg_launch<2, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 3: return longk_reg_launch<3, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 4: return longk_reg_launch<4, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 5: return longk_reg_launch<5, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 6: return longk_reg_launch<6, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 7: return longk_reg_launch<7, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 8: return longk_reg_launch<8, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
+      case 9: return longk_reg_launch<9, BF16>(st, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
       default: break;
     }
   }
@@ -949,7 +957,7 @@ int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K,
   bool aa = aligned16(A, lda), ba = aligned16(Bt, ldb);
 #define SCS_LK(NBV) \
   case NBV:         \
-    gemm_nt_longk_kernel<NBV, BF16><<<grid, 256, 0, st>>>(A, M, K, lda, Bt, N, ldb, C, ldc, nst, aa, ba); break;
+    gemm_nt_longk_kernel<NBV, BF16><<<grid, 256, 0, st>>>(A, M, K, lda, Bt, N, ldb, C, ldc, nst, aa, ba, gate); break;
   switch (nb) {
     SCS_LK(1) SCS_LK(2) SCS_LK(3) SCS_LK(4) SCS_LK(5) SCS_LK(6) SCS_LK(7) SCS_LK(8) SCS_LK(9)
     default:
@@ -963,12 +971,12 @@ int longk_dispatch(hipStream_t st, int nb, const float* A, int64_t M, int64_t K,
 
 template <bool BF16>
 int tn_dispatch(hipStream_t st, int nb, const float* A, int64_t R, int64_t M, int64_t lda, const float* B, int64_t N,
-                int64_t ldb, float* partial, int64_t chunk_rows, int64_t nchunks) {
+                int64_t ldb, float* partial, int64_t chunk_rows, int64_t nchunks, Gate gate) {
   if (aligned16(A, lda) && aligned16(B, ldb)) {
     const dim3 g((unsigned)cdiv(M, nb <= 4 ? tg_cols(4) : tg_cols(9)), (unsigned)nchunks), blk(kTgThreads);
 #define SCS_TG(NBV)                                                                                        \
   case NBV:                                                                                                \
-    gemm_tn_reg_kernel<NBV, BF16><<<g, blk, 0, st>>>(A, R, M, lda, B, N, ldb, partial, chunk_rows); \
+    gemm_tn_reg_kernel<NBV, BF16><<<g, blk, 0, st>>>(A, R, M, lda, B, N, ldb, partial, chunk_rows, gate); \
     break;
     switch (nb) {
       SCS_TG(1) SCS_TG(2) SCS_TG(3) SCS_TG(4) SCS_TG(5) SCS_TG(6) SCS_TG(7) SCS_TG(8) SCS_TG(9)
@@ -985,7 +993,7 @@ int tn_dispatch(hipStream_t st, int nb, const float* A, int64_t R, int64_t M, in
 #define SCS_TN(NBV)                                                                                             \
   case NBV:                                                                                                     \
     gemm_tn_splitk_kernel<NBV, BF16><<<grid, 256, 0, st>>>(A, R, M, lda, B, N, ldb, partial, chunk_rows, aa, \
-                                                           ba);                                                 \
+                                                           ba, gate);                                                 \
     break;
   switch (nb) {
     SCS_TN(1) SCS_TN(2) SCS_TN(3) SCS_TN(4) SCS_TN(5) SCS_TN(6) SCS_TN(7) SCS_TN(8) SCS_TN(9)
@@ -1001,7 +1009,7 @@ int tn_dispatch(hipStream_t st, int nb, const float* A, int64_t R, int64_t M, in
 }  // namespace
 
 int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
-                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16) {
+                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16, Gate gate) {
   if (M <= 0 || N <= 0) return SCS_OK;
   int nb = (int)cdiv(N, 16);
   const int64_t nst = pad16 ? 16 * (int64_t)nb : N;   // columns N.. of the last 16 are zero
@@ -1009,8 +1017,8 @@ int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, in
     set_error("gemm_nt_longk: ldc smaller than the stored width");
     return SCS_EINVAL;
   }
-  return bf16 ? longk_dispatch<true>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst)
-              : longk_dispatch<false>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst);
+  return bf16 ? longk_dispatch<true>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate)
+              : longk_dispatch<false>(st, nb, A, M, K, lda, Bt, N, ldb, C, ldc, nst, gate);
 }
 
 int gemm_wide_kpad(int64_t K) {
@@ -1092,25 +1100,25 @@ int64_t gemm_tn_splitk_chunks(int64_t R, int64_t M, int64_t N, const float* A, i
 
 int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,
                           const float* B, int64_t N, int64_t ldb, float* partial, int64_t chunk_rows,
-                          int64_t nchunks) {
+                          int64_t nchunks, Gate gate) {
   if (M <= 0 || N <= 0) return SCS_OK;
   int nb = (int)cdiv(N, 16);
-  return bf16 ? tn_dispatch<true>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks)
-              : tn_dispatch<false>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks);
+  return bf16 ? tn_dispatch<true>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks, gate)
+              : tn_dispatch<false>(st, nb, A, R, M, lda, B, N, ldb, partial, chunk_rows, nchunks, gate);
 }
 
 int launch_reduce_partials_t(hipStream_t st, const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
-                             int64_t ldg) {
+                             int64_t ldg, Gate gate) {
   if (d * Pc <= 0) return SCS_OK;
-  reduce_partials_t_kernel<<<dim3((unsigned)cdiv(d * Pc, 256)), dim3(256), 0, st>>>(partial, nchunks, d, Pc, G, ldg);
+  reduce_partials_t_kernel<<<dim3((unsigned)cdiv(d * Pc, 256)), dim3(256), 0, st>>>(partial, nchunks, d, Pc, G, ldg, gate);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
 
 int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const float* Y, int ny, int nblk,
-                            double* rsq) {
+                            double* rsq, Gate gate) {
   if (n <= 0 || P <= 0) return SCS_OK;
-  residual_batched_kernel<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(R, n, P, Y, ny, nblk, rsq);
+  residual_batched_kernel<<<dim3((unsigned)nblk), dim3(256), 0, st>>>(R, n, P, Y, ny, nblk, rsq, gate);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -167,9 +167,16 @@ int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n
 int64_t sampler_scratch_len(int64_t N);
 
 // gemm (MFMA)
+// A launch gated on a device counter does nothing once *count >= total (read at kernel entry): the
+// shared-X gradient GEMMs of a regularization path skip epochs in which every solve has stopped.
+struct Gate {
+  const int* count = nullptr;
+  int total = 0;
+};
 // pad16: also store columns N .. (N rounded up to 16) - 1, which come out zero
 int launch_gemm_nt_longk(hipStream_t st, int bf16, const float* A, int64_t M, int64_t K, int64_t lda,
-                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16 = false);
+                         const float* Bt, int64_t N, int64_t ldb, float* C, int64_t ldc, bool pad16 = false,
+                         Gate gate = Gate());
 // Leading dimension (and zero-padded width) the wide GEMM wants for operands with K columns.
 int gemm_wide_kpad(int64_t K);
 // Rows the wide GEMM reads from Bt: N rounded up to 64.
@@ -183,7 +190,7 @@ int64_t gemm_tn_splitk_chunks(int64_t R, int64_t M, int64_t N, const float* A, i
                               int64_t ldb);
 int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,
                           const float* B, int64_t N, int64_t ldb, float* partial, int64_t chunk_rows,
-                          int64_t nchunks);
+                          int64_t nchunks, Gate gate = Gate());
 int launch_reduce_partials_f64(hipStream_t st, const float* partial, int64_t nchunks, int64_t elems,
                                double scale, double* out);
 // fp64 dense
@@ -321,9 +328,9 @@ int launch_grad_finalize_batched(hipStream_t st, const BatchProb* P, int nprob, 
 // Shared-X gradient of many problems: R = X W^T (gemm), then R[i][p] -= Y[p % ny][i] with per-block
 // residual sums rsq[p][blk]; then G (P x d, FP64) = sum over row chunks of the X^T R partials.
 int launch_residual_batched(hipStream_t st, float* R, int64_t n, int P, const float* Y, int ny, int nblk,
-                            double* rsq);
+                            double* rsq, Gate gate = Gate());
 int launch_reduce_partials_t(hipStream_t st, const float* partial, int64_t nchunks, int64_t d, int Pc, double* G,
-                             int64_t ldg);
+                             int64_t ldg, Gate gate = Gate());
 int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const int64_t* draw_prefix,
                           int64_t total_draws, uint64_t seed, int epoch, int groups, const int* clk = nullptr);
 int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, int W, int64_t max_slice, int max_b,
