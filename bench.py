@@ -195,7 +195,7 @@ def cpu_baseline_batch(args, Xs, ys, shapes, c, reps, seeds, sample=4):
                        f"to all {len(shapes)} problems by sum of n d (1 + epochs)")}
 
 
-KERNEL_SOURCES = {"inner_epoch": "k_inner.hip", "grad_partial": "k_grad.hip"}
+KERNEL_SOURCES = {"inner_epoch": "k_inner.hip", "inner_la": "k_inner_la.hip", "grad_partial": "k_grad.hip"}
 
 
 def pmc_traffic(kernel, workload, **shape):
@@ -453,7 +453,7 @@ def bench_curves(args, cfg):
                                                                       "plain": int(min(range(S), key=lambda s: curves["plain"][s])) + 1},
                  "step_scale": tuned, "solve_s": secs,
                  "suboptimality_per_epoch": {name: [float(f"{v:.4g}") for v in curves[name]] for name in curves},
-                 "roofline": {"kernel": "inner_epoch", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
+                 "roofline": {"kernel": inner_kernel, "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": None,
                               "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms,
                               "us_per_step": 1e3 * inner_ms / m},
@@ -602,7 +602,9 @@ def main():
     sk_flops = 3 * 2.0 * n * d * l_sk + 2.0 * n * l_sk * l_sk + 2.0 * n * l_sk * k
     sk_ms = rp["ms_sketch"]
 
-    inner_traffic = pmc_traffic("inner_epoch", args.workload, m=m, b=b)
+    # the inner loop's kernel: the look-ahead variant when the tuned layout is SCS_LOOKAHEAD
+    inner_kernel = "inner_la" if int(rp.get("wave_rows", 0)) == binding.LOOKAHEAD else "inner_epoch"
+    inner_traffic = pmc_traffic(inner_kernel, args.workload, m=m, b=b)
     grad_traffic = pmc_traffic("grad_partial", args.workload)
 
     cpu = None
@@ -640,6 +642,8 @@ def main():
         "tuned": tuned,
         "steps_per_epoch": {"precond": rp["steps"], "plain": reps["plain"][-1].report["steps"]},
         "workgroups": {"precond": rp["workgroups"], "plain": reps["plain"][-1].report["workgroups"]},
+        "inner_layout": {"precond": rp.get("wave_rows"), "plain": reps["plain"][-1].report.get("wave_rows"),
+                         "note": "wave-rows of the inner loop; 8 = the look-ahead loop"},
         "certificate_stop": cert,
         "suboptimality": so,
         "w_rel_err": relerr,
@@ -649,7 +653,7 @@ def main():
                         "frac_fp32_mfma": sk_flops / (sk_ms * 1e-3) / 157.3e12 if not mixed else None,
                         "note": "flops of the five sketch GEMMs at l = k + 5 over the whole sketch stage, which also "
                                 "holds the FP64 CholeskyQR2 and eigensolver; per-kernel times are in profiles/"},
-        "roofline": {"kernel": "inner_epoch", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": inner_kernel, "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": inner_traffic,
                      "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms,
                      "us_per_step": 1e3 * inner_ms / m,

@@ -47,6 +47,13 @@ extern "C" {
 #define SCS_SKETCH_RANK_DEFICIENT 3 /* range-finder block lost rank (e.g. X = 0); solved without preconditioning */
 
 /* Precision of the sketch GEMMs and of the preconditioned rows used by the inner loop. */
+/* wave_rows value of the look-ahead inner loop: each step's next dot products are formed while the step's
+   cross-workgroup exchange is in flight, as P - eta G g with P = R_{t+1}(delta_t - eta mu) and the Gram block
+   G = R_{t+1} R_t^T of the workgroup's columns (Alg. 1's update expanded one step; FP32 rows use a three-term
+   BF16 product for G, about 2^-16 relative error per entry; BF16 rows are exact). Same results as the
+   direct loop up to rounding. */
+#define SCS_LOOKAHEAD 8
+
 #define SCS_PREC_FP32 0       /* FP32 MFMA for Rayleigh-Ritz and the apply, FP32 rows (range finder: see sketch_fp32) */
 #define SCS_PREC_MIXED 1      /* BF16 MFMA GEMMs (FP32 accumulation), BF16 rows in the inner loop */
 
@@ -91,7 +98,8 @@ typedef struct scs_opts {
                              the default 0); eta = c / beta_hat either way, so c is tuned per sampling rule */
   int wave_rows;          /* inner-loop layout (single solves): how each workgroup's 8 waves split the minibatch's
                              rows, 1, 2 or 4 wave-rows of 8 / wave_rows waves (64 rows each at most; slices of at
-                             most 512, 128 or 64 columns); 0 = chosen from b and the slice width, or autotuned
+                             most 512, 128 or 64 columns); SCS_LOOKAHEAD = the look-ahead loop (b <= 64, slices of
+                             at most 64 columns, see below); 0 = chosen from b and the slice width, or autotuned
                              together with the workgroups when workgroups = -1 */
   /* Warm starts and checkpoints (single solves). A solve stopped after S1 epochs with wt_out set, then
      resumed with w0 = that snapshot, w0_preconditioned = 1 and epoch_offset = S1 (same X, y, lambda, k,
@@ -137,6 +145,7 @@ typedef struct scs_report {
   int n_grad, n_inner;      /* number of launches summed in ms_grad and ms_inner */
   int backoffs;             /* rejected snapshots: each restored the previous one and halved the step */
   int workgroups;           /* inner-loop workgroups used per problem */
+  int wave_rows;            /* inner-loop layout used (single solves): 1, 2, 4 wave-rows or SCS_LOOKAHEAD */
 } scs_report;
 
 void scs_opts_default(scs_opts* opts);
@@ -198,7 +207,7 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
  * Xt: n x d rows, reg: d x d rows, both with leading dimension ldt (a multiple of 4), FP32 or BF16 as
  * xt_bf16; beta: n + d, idx: m x b int32 in [0, n+d) (device); 1 <= b <= 256.
  * wt is updated in place; mu = grad L~(w~) (device FP32). workgroups = 0 chooses from d and b;
- * wave_rows as scs_opts.wave_rows (0 = chosen from b and the slice width).
+ * wave_rows as scs_opts.wave_rows (0 = chosen from b and the slice width; SCS_LOOKAHEAD for the look-ahead loop).
  */
 int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const void* reg, int64_t ldt, int xt_bf16,
                    const float* beta, const float* mu, const int32_t* idx, int64_t m, int b,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libscs.so")
 OK, EINVAL, ENONFINITE, ENOMEM, EDEVICE = 0, -1, -2, -3, -4
 NOT_CONVERGED, DIVERGED, SKETCH_RANK_DEFICIENT = 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
+LOOKAHEAD = 8   # SCS_LOOKAHEAD: wave_rows value of the look-ahead inner loop
 STOP_EPOCHS, STOP_CERTIFICATE, STOP_GAP = 0, 1, 2
 
 EXPORTED = [
@@ -83,6 +84,7 @@ class ScsReport(ctypes.Structure):
         ("n_inner", ctypes.c_int),
         ("backoffs", ctypes.c_int),
         ("workgroups", ctypes.c_int),
+        ("wave_rows", ctypes.c_int),
     ]
 
     def as_dict(self):

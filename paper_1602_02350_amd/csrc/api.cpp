@@ -164,14 +164,18 @@ int autotune_workgroups(scs_ctx* ctx, hipStream_t st, const InnerArgs& base, int
     return SCS_OK;
   }
   // a layout with wr wave-rows takes at most 64 rows per wave-row and slices of at most 512 (wr = 1),
-  // 128 (wr = 2) or 64 (wr = 4) columns
+  // 128 (wr = 2) or 64 (wr = 4) columns; the look-ahead loop b <= 64 and slices of at most 64 columns
   std::vector<std::pair<int, int>> cand;
   for (int cols : {128, 64, 32}) {
     const int W = (int)std::max<int64_t>(1, std::min<int64_t>(16, cdiv(base.d, cols)));
     const int64_t slice = cdiv(cdiv(base.d, W), 4) * 4;
-    for (int wr : {1, 2, 4}) {
-      const int64_t max_slice = wr == 1 ? 512 : wr == 2 ? 128 : 64;
-      if (cdiv(base.b, wr) > 64 || slice > max_slice) continue;
+    for (int wr : {1, 2, 4, kInnerLookahead}) {
+      if (wr == kInnerLookahead) {
+        if (!inner_lookahead_fits(base.b, base.d, W)) continue;
+      } else {
+        const int64_t max_slice = wr == 1 ? 512 : wr == 2 ? 128 : 64;
+        if (cdiv(base.b, wr) > 64 || slice > max_slice) continue;
+      }
       const std::pair<int, int> c{W, wr};
       if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
     }
@@ -984,7 +988,12 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   a.xbuf = xbuf;
   a.state = state;
   a.wave_rows = o.wave_rows;
-  if (o.workgroups < 0) {
+  if (o.wave_rows == kInnerLookahead && o.workgroups <= 0) {
+    // the look-ahead loop takes slices of at most 64 columns
+    W = (int)std::max<int64_t>(1, cdiv(d, 64));
+    a.W = W;
+    a.xcd_stride = W > 1 ? ctx->xcd_stride : 1;
+  } else if (o.workgroups < 0) {
     int wr = 0;
     SCS_CHECK(autotune_workgroups(ctx, st, a, rows_bf16, cum, N, o.seed, &W, &wr));
     a.W = W;
@@ -1080,6 +1089,8 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     report->lam_top = hs.lam_top;
     report->backoffs = hs.backoffs;
     report->workgroups = W;
+    report->wave_rows =
+        a.wave_rows == kInnerLookahead ? kInnerLookahead : inner_layout_wave_rows(b, d, W, a.wave_rows);
     float t1 = 0, t2 = 0, t3 = 0;
     hipEventElapsedTime(&t1, ev_start, ev_sketch);
     hipEventElapsedTime(&t2, ev_sketch, ev_apply);

@@ -534,6 +534,7 @@ int inner_default_workgroups(int64_t d) {
 }
 
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
+  if (a.wave_rows == kInnerLookahead) return launch_inner_epoch_lookahead(st, a, bf16);
   if (a.b < 1 || a.b > kInnerMaxB || a.m < 1 || a.W < 1 || a.W > 16) {
     set_error("inner loop: need 1 <= b <= 256, m >= 1, 1 <= workgroups <= 16");
     return SCS_EINVAL;
@@ -543,7 +544,7 @@ int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16) {
     return SCS_EINVAL;
   }
   if (a.wave_rows != 0 && a.wave_rows != 1 && a.wave_rows != 2 && a.wave_rows != 4) {
-    set_error("inner loop: wave_rows must be 0, 1, 2 or 4");
+    set_error("inner loop: wave_rows must be 0, 1, 2, 4 or SCS_LOOKAHEAD");
     return SCS_EINVAL;
   }
   a.slice = cdiv(cdiv(a.d, a.W), 4) * 4;

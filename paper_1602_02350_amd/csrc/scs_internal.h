@@ -260,16 +260,22 @@ struct InnerArgs {
   float* wt_prev;      // copy of the incoming snapshot (nullable)
   uint64_t* xbuf;      // inner_xbuf_words(W) words: (step tag << 32) | partial dot product bits; zeroed per solve
   SolveState* state;
-  int wave_rows;       // 0 = chosen from b and the slice width; 1, 2 or 4: waves split over rows
+  int wave_rows;       // 0 = chosen from b and the slice width; 1, 2 or 4: waves split over rows;
+                       // kInnerLookahead: the look-ahead kernel (k_inner_la.hip)
 };
 // Largest minibatch of the inner loop, and the exchange words its workgroups post (two step parities
 // x up to 4 wave-rows x W workgroups x 64 rows = 2 W kInnerMaxB).
 constexpr int kInnerMaxB = 256;
+constexpr int kInnerLookahead = SCS_LOOKAHEAD;   // wave_rows value selecting the look-ahead kernel
 inline int64_t inner_xbuf_words(int W) { return (int64_t)2 * W * kInnerMaxB; }
 int launch_inner_epoch(hipStream_t st, InnerArgs& a, int bf16);
 // wave-row count launch_inner_epoch uses for (b, d, W, requested wave_rows)
 int inner_layout_wave_rows(int b, int64_t d, int W, int wave_rows);
 int inner_default_workgroups(int64_t d);
+// The look-ahead variant of the inner loop (the next step's dot products formed while the current
+// exchange is in flight): same arguments and results up to rounding; needs b <= 64 and W >= d / 64.
+bool inner_lookahead_fits(int b, int64_t d, int W);
+int launch_inner_epoch_lookahead(hipStream_t st, InnerArgs& a, int bf16);
 
 // ---------------------------------------------------------------- allocation-free entry (noalloc.hip)
 // Looks up the device address of the fixed scratch array on `device` (which must be current); once per device.

@@ -52,7 +52,7 @@ def gradient_scale(X, y, lam, Pm, wt, row_chunks=2048, C=None):
     return np.sqrt((Pm ** 2) @ (e_g ** 2)) + U32 * np.abs(mu)
 
 
-def epoch_scale(rows, scale, idx, trace, wbar, mu, eta, b):
+def epoch_scale(rows, scale, idx, trace, wbar, mu, eta, b, gram_rel=0.0):
     """Scale of the per-element error of the averaged step (1/m) sum_t (w_t - wbar) of one inner loop
     run in FP32 on delta = w - wbar (Alg. 1 with minibatches of b), given the oracle's iterates w_t.
 
@@ -66,12 +66,18 @@ def epoch_scale(rows, scale, idx, trace, wbar, mu, eta, b):
       * delta -= eta (g + mu) rounds eta, the sum and the update (u each).
     The local errors of the m steps propagate through the contracting iteration and add in
     quadrature; the snapshot gradient mu is FP32-rounded (a constant error u |mu| per step).
+
+    gram_rel > 0 models the look-ahead loop, which forms a_j^T delta_t as a_j^T (delta_{t-1} - eta mu)
+    - eta sum_i (a_j^T a_i) gamma_i over the previous step's rows a_i, with each product a_j^T a_i carrying
+    a relative error of at most gram_rel (times the norms): an extra error of
+    eta gram_rel ||a_j|| sum_i |gamma_i| ||a_i|| in the dot, plus an FP32 mat-vec over b terms.
     """
     d = wbar.size
     m = len(trace)
     acc = np.zeros(d)
     sys_mu = np.zeros(d)
     delta = np.zeros(d)
+    prev = None
     for t in range(m):
         it = idx[t * b:(t + 1) * b]
         A = rows(it)                                   # b x d
@@ -79,6 +85,13 @@ def epoch_scale(rows, scale, idx, trace, wbar, mu, eta, b):
         gam = sc * (A @ delta) / b
         e_gam = U32 * np.sqrt(4.0 + np.log2(d)) * sc * np.sqrt((A ** 2) @ (delta ** 2)) / b
         e_gam = np.sqrt(e_gam ** 2 + (3.0 * U32 * gam) ** 2)
+        if gram_rel > 0.0 and prev is not None:
+            A_p, gam_p = prev
+            na, na_p = np.linalg.norm(A, axis=1), np.linalg.norm(A_p, axis=1)
+            cross = np.abs(gam_p) @ na_p
+            e_la = eta * (gram_rel * na * cross + U32 * np.sqrt(b) * np.sqrt((np.abs(A @ A_p.T) ** 2) @ (gam_p ** 2)))
+            e_gam = np.sqrt(e_gam ** 2 + (sc * e_la / b) ** 2)
+        prev = (A, gam)
         g2 = np.sqrt((gam ** 2) @ (A ** 2))
         e_t = eta * np.sqrt((U32 * np.sqrt(b / 16.0 + 4.0) * g2) ** 2 + (e_gam ** 2) @ (A ** 2)
                             + (2.0 * U32 * (gam @ A + mu)) ** 2)

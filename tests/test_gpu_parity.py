@@ -265,7 +265,10 @@ def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed, wave_rows
         it = np.asarray(it)
         return np.where((it < n)[:, None], Xt64[np.minimum(it, n - 1)], reg64[np.maximum(it - n, 0)])
 
-    scale = epoch_scale(rows, 1.0 / (n * q), idx, trace, wt0, mu64, eta, b)
+    # the look-ahead loop's Gram block: three BF16 products per FP32 entry (relative error below 2^-16),
+    # exact for BF16 rows (FP32 accumulation only)
+    gram_rel = 0.0 if wave_rows != binding.LOOKAHEAD else (8 * U32 if bf16 else 2.0 ** -15)
+    scale = epoch_scale(rows, 1.0 / (n * q), idx, trace, wt0, mu64, eta, b, gram_rel=gram_rel)
     scale = 8.0 * scale + 2 * U32 * (np.abs(wo) + np.abs(step_o))
     ratio = np.abs(step_g - step_o) / scale
     print(f"\n[epoch n={n} d={d} b={b} m={m} W={W} wave_rows={wave_rows} bf16={bf16}] "
@@ -283,7 +286,11 @@ def _epoch_parity(ctx, X, y, lam_reg, Pm, b, m, W, bf16, ldt, c, seed, wave_rows
     (3000, 100, 10, 100, 1, False, 100, 2), (3000, 100, 10, 128, 2, True, 128, 2),
     (4000, 130, 10, 200, 3, False, 132, 4), (4000, 61, 5, 256, 1, False, 64, 4),
     (2000, 100, 10, 37, 2, False, 100, 1), (2000, 100, 10, 37, 2, False, 100, 2),
-    (2000, 100, 10, 37, 2, False, 100, 4), (1500, 61, 5, 150, 15, True, 64, 4)])
+    (2000, 100, 10, 37, 2, False, 100, 4), (1500, 61, 5, 150, 15, True, 64, 4),
+    # the look-ahead loop (b <= 64, at most 64 columns per workgroup)
+    (400, 24, 4, 8, 1, False, 24, 8), (2000, 100, 10, 64, 2, False, 100, 8), (2000, 100, 10, 64, 2, True, 128, 8),
+    (1500, 257, 12, 33, 5, False, 260, 8), (900, 37, 0, 5, 1, False, 40, 8), (700, 61, 5, 40, 15, True, 64, 8),
+    (2000, 100, 10, 17, 2, False, 100, 8)])
 def test_epoch_matches_oracle_on_an_injected_stream(ctx, n, d, k, b, W, bf16, ldt, wr):
     """Small and ragged shapes, including more workgroups than column quads (W = 16 at d = 24 and
     W = 15 at d = 61: the last workgroups own no column and only take part in the exchange), minibatches
@@ -310,14 +317,15 @@ def bench_shape_rows():
 
 @pytest.mark.parametrize("W", [16, 8])
 @pytest.mark.parametrize("bf16", [False, True])
-@pytest.mark.parametrize("b,wr", [(64, 0), (64, 1), (128, 2), (256, 4)])
+@pytest.mark.parametrize("b,wr", [(64, 0), (64, 1), (128, 2), (256, 4), (64, binding.LOOKAHEAD),
+                                  (32, binding.LOOKAHEAD)])
 def test_epoch_at_the_benchmark_launch_shape(ctx, bench_shape_rows, W, bf16, b, wr):
     """The inner loop at the benchmark's shape (n = 100000, d = 1000, rows padded to 1024 columns) with
     16 or 8 cooperating workgroups of 64 or 128 columns, minibatches of 64 to 256 rows and the wave-row
     split each uses; m = 6272 / b steps (98 at b = 64, the benchmark's epoch)."""
     P, Pm, cfg = bench_shape_rows
-    if wr == 4 and W == 8:
-        pytest.skip("four wave-rows take slices of at most 64 columns")
+    if W == 8 and wr in (4, binding.LOOKAHEAD):
+        pytest.skip("four wave-rows and the look-ahead loop take slices of at most 64 columns")
     _epoch_parity(ctx, P.X, P.y, cfg["lam"], Pm, b, 6272 // b, W, bf16, 1024, 64.0, seed=101,
                   wave_rows=wr)
 
