@@ -257,10 +257,12 @@ int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64
  * shape (workgroups and wave-rows, timed per b). Each candidate is a full scs_svrg_solve to the stop
  * rule of `base` (certificate or gap; eps as given), scored by its wall time; the scan over c for a
  * (b, m) stops at the first divergence or step halving, and once the time has risen twice in a row.
- * Candidates draw Omega and the index stream from a seed derived from base->seed, never from it.
+ * The four fastest candidates are then solved three more times, each with another sampler stream,
+ * and the lowest median of the four wall times wins.
+ * Candidates draw Omega and the index stream from seeds derived from base->seed, never from it.
  *   base (nullable): the options to start from; tuned (HOST): receives them with batch, step_scale,
  *   epoch_factor (steps = 0), workgroups and wave_rows set, seed/timing/epoch_ms from base.
- *   best_ms (HOST, nullable): the winner's wall time in milliseconds.
+ *   best_ms (HOST, nullable): the winner's median wall time in milliseconds.
  * Returns SCS_NOT_CONVERGED if no candidate met the stop rule within base->max_epochs.
  */
 int scs_autotune(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, const float* y, double lambda,

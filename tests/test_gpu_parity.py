@@ -488,20 +488,22 @@ def test_batched_equals_single_solves(ctx, mixed):
     assert rc == binding.OK, [r["status"] for r in reps]
 
 
-def test_split_apply_is_bit_identical_to_the_one_workgroup_apply(ctx):
+@pytest.mark.parametrize("d,k,W", [(1100, 120, 3), (1000, 50, 2)])
+def test_split_apply_is_bit_identical_to_the_one_workgroup_apply(ctx, d, k, W):
     """With k d >= 20000 a single solve spreads the P^{-1/2} applies of the premap and the gradient
-    finish over many workgroups; a batch of one problem keeps them in one workgroup. Same per-row and
-    per-quad arithmetic: the two solves agree bit for bit (with the same 3 inner-loop workgroups, the
-    fewest that keep 1100 columns within 512 per workgroup)."""
-    probs = _uneven_batch([(3000, 1100, 1.5, 1e-4, 120)], seed0=80)
-    assert 120 * 1100 >= 20000
+    finish over many workgroups (k d = 132000, and 50000 as in the FP32 n = 100000 benchmark); a batch
+    of one problem keeps them in one workgroup. Same per-row and per-quad arithmetic: the two solves
+    agree bit for bit (with the same W inner-loop workgroups, the fewest that keep d columns within 512
+    per workgroup)."""
+    probs = _uneven_batch([(3000, d, 1.5, 1e-4, k)], seed0=80)
+    assert k * d >= 20000
     common = dict(batch=16, steps=60, max_epochs=3, stop_rule=binding.STOP_EPOCHS, step_scale=2.0, seed=7,
-                  workgroups=3)
+                  workgroups=W)
     (P, k), = probs
     X, y = dev(P.X), dev(P.y)
     rc, wb, reps = ctx.svrg_solve_batched([X], [y], [P.lam], [k], 0.0, **common)
     r = ctx.svrg_solve(X, y, P.lam, k, 0.0, **common)
-    assert rc == binding.OK and r.status == binding.OK and reps[0]["workgroups"] == 3
+    assert rc == binding.OK and r.status == binding.OK and reps[0]["workgroups"] == W
     assert torch.equal(wb[0], r.w), rel(host(wb[0]), host(r.w))
     assert reps[0]["objective"] == r.report["objective"]
 
