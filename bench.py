@@ -461,6 +461,95 @@ def bench_curves(args, cfg):
     ctx.close()
 
 
+def bench_f64(args, cfg):
+    """The FP64 workload (n = 2000, d = 100, spectrum j^-2, lambda = 1e-4, k = 10): seconds to
+    L(w) - L(w*) <= eps of the FP64 preconditioned solve, with plain FP64 SVRG beside it. Step scale and
+    epoch length are tuned per method on another data seed (median of three sampler streams each)."""
+    import numpy as np
+    import torch
+    from paper_1602_02350_amd import binding, inputs
+    n, d, k, b, lam, eps = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["lam"], cfg["eps"]
+
+    def problem(seed):
+        P = inputs.make_ridge(n, d, cfg["alpha"], lam, seed=seed, dtype=np.float64)
+        X = torch.from_numpy(P.X).cuda()
+        y = torch.from_numpy(P.y).cuda()
+        ws, Ls, H = reference_optimum(X, y, lam)
+        return X, y, ws, Ls, H
+
+    X, y, ws, Ls, H = problem(inputs.BASE_SEED + 1)
+    Xt_, yt_, _, Lt_, _ = problem(inputs.BASE_SEED + 101)
+    torch.cuda.synchronize()
+    ctx = binding.Context(0)
+
+    def solve(Xa, ya, La, kk, t, seed, timing=0):
+        return ctx.svrg_solve_f64(Xa, ya, lam, kk, eps, batch=b, epoch_factor=t["epoch_factor"], max_epochs=400,
+                                  stop_rule=binding.STOP_GAP, f_star=La, step_scale=t["step_scale"], seed=seed,
+                                  timing=timing)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    tuned = {}
+    for name, kk in (("precond", k), ("plain", 0)):
+        best = None
+        for mf in (0.25, 0.5, 1.0, 2.0):
+            for c in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0):
+                t = {"step_scale": c, "epoch_factor": mf}
+                runs = [timed(lambda: solve(Xt_, yt_, Lt_, kk, t, 1000 + r)) for r in range(3)]
+                if any(r.status != binding.OK or r.report["backoffs"] > 0 for _, r in runs):
+                    break  # larger steps only diverge further
+                med = statistics.median(dt for dt, _ in runs)
+                if best is None or med < best[0]:
+                    best = (med, t)
+        tuned[name] = dict(best[1], batch=b)
+        log(args, f"tuned {name}: {tuned[name]} ({1e3 * best[0]:.2f} ms on the tuning problem)")
+
+    times = {"precond": [], "plain": []}
+    reps = {"precond": [], "plain": []}
+    for it in range(args.warmup + args.steps):
+        for name, kk in (("precond", k), ("plain", 0)):
+            dt, r = timed(lambda: solve(X, y, Ls, kk, tuned[name], inputs.BASE_SEED + it))
+            assert r.status == binding.OK, (name, r.status, r.report)
+            if it >= args.warmup:
+                times[name].append(dt)
+                reps[name].append(r)
+    value = statistics.median(times["precond"])
+    plain = statistics.median(times["plain"])
+    rp = reps["precond"][len(reps["precond"]) // 2].report
+    rt = solve(X, y, Ls, k, tuned["precond"], inputs.BASE_SEED, timing=1).report
+    m = rt["steps"]
+    inner_bytes = m * b * (8 * d + 4 + 8)
+    inner_ms = rt["ms_inner"] / max(1, rt["n_inner"])
+    inner_gbs = inner_bytes / (inner_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "timing the FP64 oracle on the host ...")
+        ep = int(statistics.median(r.report["epochs"] for r in reps["precond"]))
+        cpu = cpu_baseline(args, X, y, cfg, k, tuned["precond"]["step_scale"], m, ep, inputs.BASE_SEED)
+    _multi_line(args, f"seconds to L(w)-L(w*)<={eps:g} in FP64 (precond vs plain SVRG, 1 GPU)", value,
+                {"workload": args.workload, "n": n, "d": d, "k": k, "b": b, "lambda": lam, "eps": eps,
+                 "spectrum": f"j^-{cfg['alpha']}", "sampling": "proportional to beta_i", "parallelism": "1 GPU"},
+                {"dtype": "f64", "value_min_max": [min(times["precond"]), max(times["precond"])],
+                 "plain_svrg_s": plain, "plain_svrg_min_max": [min(times["plain"]), max(times["plain"])],
+                 "speedup_vs_plain": plain / value, "tuned": tuned,
+                 "epochs": {name: [r.report["epochs"] for r in reps[name]] for name in reps},
+                 "suboptimality": {name: subopt(H, reps[name][0].w, ws) for name in reps},
+                 "stage_ms": {"sketch": rp["ms_sketch"], "apply": rp["ms_apply"], "solve": rp["ms_solve"]},
+                 "roofline": {"kernel": "inner64", "bound": "hbm", "achieved": inner_gbs, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": inner_gbs / HBM_PEAK_GBS, "traffic": None,
+                              "bytes_per_launch": inner_bytes, "avg_launch_ms": inner_ms,
+                              "us_per_step": 1e3 * inner_ms / m,
+                              "note": "one workgroup per epoch, a chain of m dependent steps of b FP64 rows; "
+                                      "bound by the per-step barrier latency, not by HBM"},
+                 "cpu_baseline": cpu})
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -472,6 +561,8 @@ def main():
     from paper_1602_02350_amd import binding, inputs
 
     cfg = dict(inputs.WORKLOADS[args.workload])
+    if cfg.get("fp64"):
+        return bench_f64(args, cfg)
     if "nl" in cfg:
         return bench_path(args, cfg)
     if "nprob" in cfg:

@@ -237,6 +237,36 @@ int scs_svrg_solve(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t l
                    scs_report* report);
 
 /*
+ * The FP64 instantiation (Alg. 3 with X, y, the sketch, the preconditioned rows, the iterate and every
+ * sum in FP64), for problems whose columns fit one workgroup: d <= 4096, n + d < 2^31, one Krylov
+ * block with k + p <= min(d, n, 136).
+ * Sketch (Alg. 2, q = 1): Y = X^T (X Omega), Q = CholeskyQR2(Y), B = (X Q)^T (X Q) / n = V Theta V^T,
+ * lam~ = Theta_{1..k} (descending, clamped >= 0), U~ = Q V_{:,1..k}, all products FP64. Omega^T is
+ * opts->omega (FP32, (k + p) x d) widened to FP64, or drawn from opts->seed as in scs_sketch_build.
+ *   X: n x d FP64 (ld ldx, device); U_out: d x k FP64 (ld k, device); lam_out: k FP64 (device).
+ * Returns SCS_SKETCH_RANK_DEFICIENT if the Gram matrix of Y is not positive definite.
+ */
+int scs_sketch_build_f64(scs_ctx* ctx, const double* X, int64_t n, int64_t d, int64_t ldx, int k,
+                         const scs_opts* opts, double* U_out, double* lam_out);
+
+/*
+ * Sketched Preconditioned SVRG in FP64: scs_svrg_solve's method and options (batch b <= 256, steps /
+ * epoch_factor, step_scale, max_epochs, stop rules, f_star, seed, omega, indices, epoch_offset,
+ * average, uniform_sampling, epoch_ms), with the rows x~_i = x_i/s + U~ D U~^T x_i and the
+ * regularizer rows sqrt(n lambda) P^{-1/2} e_j formed in FP64, the index draws of scs_sample_indices
+ * (weights quantized from FP64 beta_i, 1/(n q_i) kept in FP64), the full gradient, the stop rules and
+ * the inner loop in FP64 (one persistent workgroup per epoch). w0, trace_w and wt_out are FP32-only
+ * (SCS_EINVAL here); workgroups, wave_rows, precision and sketch_fp32 are ignored; timing >= 1 times
+ * the inner loops (ms_inner, n_inner) and nothing more.
+ *   X: n x d FP64 (ld ldx), y: n FP64 (device). w_out: d FP64 (device). report: HOST, nullable
+ *   (workgroups = 1; ms_grad is not measured).
+ * Status codes as scs_svrg_solve.
+ */
+int scs_svrg_solve_f64(scs_ctx* ctx, const double* X, int64_t n, int64_t d, int64_t ldx, const double* y,
+                       double lambda, int k, double eps, const scs_opts* opts, double* w_out,
+                       scs_report* report);
+
+/*
  * The bias-complexity rule (Sec. 2.2): the regularization at which each method's runtime is O~(ndk),
  *   lambda_precond = (k lam_k + sum_{i>k} lam_i) / (n k)   (Eq. (decay), preconditioned SVRG)
  *   lambda_plain   = (sum_i lam_i) / (n k)                 (Eq. (decaySVRG), plain SVRG),

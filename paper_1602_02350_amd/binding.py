@@ -26,7 +26,8 @@ EXPORTED = [
     "scs_opts_default", "scs_status_string", "scs_last_error", "scs_create", "scs_destroy",
     "scs_sketch_build", "scs_precondition_apply", "scs_full_gradient", "scs_svrg_epoch",
     "scs_sample_indices", "scs_gaussian", "scs_svrg_solve", "scs_svrg_solve_batched", "scs_svrg_solve_path",
-    "scs_full_gradient_noalloc", "scs_autotune", "scs_regularization_for_budget",
+    "scs_full_gradient_noalloc", "scs_autotune", "scs_regularization_for_budget", "scs_sketch_build_f64",
+    "scs_svrg_solve_f64",
 ]
 
 
@@ -135,6 +136,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.scs_sample_indices.argtypes = [vp, vp, i64, u64, i32, i64, vp]
     L.scs_gaussian.argtypes = [vp, u64, i64, vp]
     L.scs_svrg_solve.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), vp, P(ScsReport)]
+    L.scs_sketch_build_f64.argtypes = [vp, vp, i64, i64, i64, i32, P(ScsOpts), vp, vp]
+    L.scs_svrg_solve_f64.argtypes = [vp, vp, i64, i64, i64, vp, dbl, i32, dbl, P(ScsOpts), vp, P(ScsReport)]
     L.scs_svrg_solve_batched.argtypes = [vp, i32, P(vp), P(i64), P(i64), P(i64), P(vp), P(dbl), P(i32), dbl,
                                          P(dbl), P(ScsOpts), P(vp), P(ScsReport)]
     L.scs_svrg_solve_path.argtypes = [vp, vp, i64, i64, i64, vp, i32, P(dbl), i32, i32, dbl, P(dbl), P(ScsOpts),
@@ -360,6 +363,33 @@ class Context:
         tuned = {f: getattr(t, f) for f, _ in ScsOpts._fields_
                  if f not in ("omega", "indices", "trace_w", "epoch_ms", "w0", "wt_out")}
         return tuned, ms.value
+
+    def sketch_build_f64(self, X: torch.Tensor, k: int, **opts):
+        """FP64 sketch: (U d x k FP64, lam k FP64, status)."""
+        _dev(X, torch.float64)
+        n, d = X.shape
+        U = torch.empty(d, k, dtype=torch.float64, device=X.device)
+        lam = torch.empty(k, dtype=torch.float64, device=X.device)
+        o = self.opts(**opts)
+        rc = _check(self._L.scs_sketch_build_f64(self._h, _ptr(X), n, d, X.stride(0), k, ctypes.byref(o), _ptr(U),
+                                                 _ptr(lam)), "scs_sketch_build_f64")
+        return U, lam, rc
+
+    def svrg_solve_f64(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
+        """FP64 solve (X, y FP64 device tensors); w is FP64."""
+        _dev(X, torch.float64)
+        _dev(y, torch.float64)
+        n, d = X.shape
+        w = torch.empty(d, dtype=torch.float64, device=X.device)
+        o = self.opts(**opts)
+        S = o.max_epochs
+        ms = (ctypes.c_double * S)()
+        o.epoch_ms = ctypes.cast(ms, ctypes.c_void_p)
+        rep = ScsReport()
+        rc = _check(self._L.scs_svrg_solve_f64(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), float(lam_reg), int(k),
+                                               float(eps), ctypes.byref(o), _ptr(w), ctypes.byref(rep)),
+                    "scs_svrg_solve_f64")
+        return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms))
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
         _dev(X, torch.float32)

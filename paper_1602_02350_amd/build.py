@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wno-unused-command-line-argument"]
 
 SOURCES = ["k_rng.hip", "k_gemm.hip", "k_dense64.hip", "k_eig64.hip", "k_vec.hip", "k_grad.hip", "k_inner.hip",
-           "k_implicit.hip", "k_inner_la.hip", "noalloc.hip", "api.cpp"]
+           "k_implicit.hip", "k_inner_la.hip", "k_f64.hip", "noalloc.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -325,6 +325,20 @@ int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int*
 // does not wait for them and *rank_def is left unchanged (the caller reads the flags later).
 // st_in / sfx: the stream to use and a suffix for the names of its workspace buffers (so that
 // sketches of different problems can run on different streams at once).
+// CholeskyQR2 of Yb (d x l, FP64): Qout = Yb R1^{-1} R2^{-1} (leading dimension ldq), QTout (nullable)
+// = Qout^T in FP32; f[0], f[1] receive the two factorizations' breakdown flags. G, Rinv: l x l, Q1: d x l.
+int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f,
+               double* G, double* Rinv, double* Q1) {
+  SCS_CHECK(launch_gemm64(st, l, l, d, Yb, 1, l, Yb, l, 1, G, l, nullptr, 0));
+  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f));
+  SCS_CHECK(launch_gemm64(st, d, l, l, Yb, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
+  SCS_CHECK(launch_gemm64(st, l, l, d, Q1, 1, l, Q1, l, 1, G, l, nullptr, 0));
+  SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f + 1));
+  SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Qout, ldq, nullptr, 0));
+  if (QTout) SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QTout, d));  // R2^{-T} Q1^T
+  return SCS_OK;
+}
+
 int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
                 bool want_z, bool* rank_def, int* flags_out = nullptr, hipStream_t st_in = nullptr,
                 const std::string& sfx = "", hipEvent_t x_done = nullptr) {
@@ -371,16 +385,8 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     bflags = ws<int>(ctx, "blockflags" + sfx, (size_t)2 * q);
     if (!bflags) return SCS_ENOMEM;
   }
-  // CholeskyQR2 of Yb (d x l): Qout = Yb R1^{-1} R2^{-1} (leading dimension ldq), QTout = Qout^T in FP32
   auto cholqr2 = [&](const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f) -> int {
-    SCS_CHECK(launch_gemm64(st, l, l, d, Yb, 1, l, Yb, l, 1, G, l, nullptr, 0));
-    SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f));
-    SCS_CHECK(launch_gemm64(st, d, l, l, Yb, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
-    SCS_CHECK(launch_gemm64(st, l, l, d, Q1, 1, l, Q1, l, 1, G, l, nullptr, 0));
-    SCS_CHECK(launch_chol_inv64(st, G, l, Rinv, f + 1));
-    SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Qout, ldq, nullptr, 0));
-    if (QTout) SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QTout, d));  // R2^{-T} Q1^T
-    return SCS_OK;
+    return cholqr2_64(st, d, l, Yb, Qout, ldq, QTout, f, G, Rinv, Q1);
   };
   int L = l;            // columns of the orthonormal basis handed to Rayleigh-Ritz
   const double* Qb = Q; // that basis, d x L (leading dimension L)
@@ -497,7 +503,7 @@ int apply_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, 
   return SCS_OK;
 }
 
-int validate_problem(const float* X, int64_t n, int64_t d, int64_t ldx, double lambda) {
+int validate_problem(const void* X, int64_t n, int64_t d, int64_t ldx, double lambda) {
   if (!X) {
     set_error("null X");
     return SCS_EINVAL;
@@ -602,7 +608,7 @@ int scs_sample_indices(scs_ctx* ctx, const float* beta, int64_t N, uint64_t seed
   WS(cum, uint64_t, "cum", (size_t)N);
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
   SCS_CHECK(launch_sampler_prepare(ctx->stream, beta, N, cum, scr, sampler_scratch_len(N), nullptr));
-  return launch_sample(ctx->stream, cum, N, N, seed, epoch, count, count, out, nullptr, nullptr);
+  return launch_sample(ctx->stream, cum, N, N, seed, epoch, count, count, out, static_cast<float*>(nullptr), nullptr);
 }
 
 int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts* opts,
@@ -1248,6 +1254,288 @@ int scs_autotune(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx
   *tuned = best_o;
   if (best_ms_out) *best_ms_out = best;
   return SCS_OK;
+}
+
+// ================================================================ the FP64 path
+// The one-block sketch (Alg. 2 with q = 1) of FP64 X, every product in FP64: T = X Omega, Y = X^T T,
+// Q = CholeskyQR2(Y), W = X Q, B = W^T W / n = V Theta V^T, U~ = Q V_k, lam = Theta_{1..k}, and with
+// want_z also Z = X U~ (n x k). Leaves f64_U (d x k), f64_lam (k) and f64_Z in the workspace; flags
+// (device, 2 ints) receive CholeskyQR's breakdown flags. Omega^T is o.omega (FP32, l x d) or drawn
+// from o.seed, as in the FP32 path, and widened to FP64.
+static int sketch64_impl(scs_ctx* ctx, hipStream_t st, const double* X, int64_t n, int64_t d, int64_t ldx, int k,
+                         const scs_opts& o, bool want_z, int* flags) {
+  const int l = k + o.oversample;
+  const float* om32 = o.omega;
+  if (!om32) {
+    WS(g32, float, "f64_omega32", (size_t)l * d);
+    SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, g32));
+    om32 = g32;
+  }
+  WS(om, double, "f64_omega", (size_t)l * d);
+  SCS_CHECK(launch_f32_to_f64(st, (int64_t)l * d, om32, om));
+  WS(T, double, "f64_T", (size_t)n * l);
+  WS(Y, double, "f64_Y", (size_t)d * l);
+  SCS_CHECK(launch_gemm64(st, n, l, d, X, ldx, 1, om, 1, d, T, l, nullptr, 0));  // T = X Omega
+  SCS_CHECK(launch_gemm64(st, d, l, n, X, 1, ldx, T, l, 1, Y, l, nullptr, 0));   // Y = X^T T
+  WS(G, double, "f64_G", (size_t)l * l);
+  WS(Rinv, double, "f64_Rinv", (size_t)l * l);
+  WS(Q1, double, "f64_Q1", (size_t)d * l);
+  WS(Q, double, "f64_Q", (size_t)d * l);
+  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1));
+  // Rayleigh-Ritz: W = X Q (over T), B = W^T W / n
+  SCS_CHECK(launch_gemm64(st, n, l, d, X, ldx, 1, Q, l, 1, T, l, nullptr, 0));
+  WS(B, double, "f64_B", (size_t)l * l);
+  SCS_CHECK(launch_gemm64(st, l, l, n, T, 1, l, T, l, 1, B, l, nullptr, 0));
+  SCS_CHECK(launch_scale64(st, (int64_t)l * l, 1.0 / (double)n, B));
+  WS(V, double, "f64_V", (size_t)l * l);
+  WS(theta, double, "f64_theta", (size_t)l);
+  WS(order, int, "f64_order", (size_t)l);
+  WS(eigw, double, "f64_eig_work", eig64_work_len(l));
+  SCS_CHECK(launch_eig64(st, B, l, eigw, V, theta, order));
+  WS(U, double, "f64_U", (size_t)d * k);
+  WS(lam, double, "f64_lam", (size_t)k);
+  WS(U32, float, "f64_U32", (size_t)d * k);
+  WS(UT32, float, "f64_UT32", (size_t)k * d);
+  WS(VkT, float, "f64_VkT", (size_t)k * l);
+  SCS_CHECK(launch_lift(st, Q, d, l, V, order, k, theta, U, U32, UT32, lam, VkT));
+  if (want_z) {
+    WS(Z, double, "f64_Z", (size_t)n * k);
+    SCS_CHECK(launch_gemm64(st, n, k, d, X, ldx, 1, U, k, 1, Z, k, nullptr, 0));  // Z = X U~
+  }
+  return SCS_OK;
+}
+
+static int check_f64_problem(const double* X, int64_t n, int64_t d, int64_t ldx, double lambda, int k,
+                             const scs_opts& o) {
+  SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
+  if (d > kF64MaxD || n + d > INT32_MAX) {
+    set_error("FP64 path: need d <= 4096 and n + d < 2^31");
+    return SCS_EINVAL;
+  }
+  if (k < 0 || k > d || (k > 0 && (o.oversample < 0 || o.krylov_blocks > 1 || k + o.oversample > d ||
+                                   k + o.oversample > n || k + o.oversample > kF64MaxL))) {
+    set_error("FP64 path: need 0 <= k and, for k > 0, one Krylov block and k + p <= min(d, n, 136)");
+    return SCS_EINVAL;
+  }
+  return SCS_OK;
+}
+
+static int svrg_solve_f64_impl(scs_ctx* ctx, const double* X, int64_t n, int64_t d, int64_t ldx, const double* y,
+                               double lambda, int k, double eps, const scs_opts* opts, double* w_out,
+                               scs_report* report, bool sketch_failed) {
+  if (!ctx || !y || !w_out) {
+    set_error("null argument");
+    return SCS_EINVAL;
+  }
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  SCS_CHECK(check_f64_problem(X, n, d, ldx, lambda, k, o));
+  if (o.batch < 1 || o.batch > kInnerMaxB || o.max_epochs < 1 || o.steps < 0 || !(o.step_scale > 0.0) ||
+      !(o.epoch_factor >= 0.0) || o.stop_rule < 0 || o.stop_rule > 2 || o.epoch_offset < 0 || o.w0 || o.trace_w ||
+      o.wt_out) {
+    set_error("FP64 path: need 1 <= batch <= 256, max_epochs >= 1, steps >= 0, step_scale > 0, epoch_offset >= 0; "
+              "w0, trace_w and wt_out are FP32-only");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int b = o.batch;
+  const int64_t m = epoch_steps(o, n, b);
+  const int64_t N = n + d;
+  const int S = o.max_epochs;
+  const int64_t ldt = cdiv(d, 32) * 32;  // rows start on 256-byte boundaries
+  // events: 0 start, 1 sketch done, 2 rows and sampler done, 3 end, 4 + s end of epoch s; with timing,
+  // 4 + S + s opens the inner loop of epoch s
+  SCS_CHECK(ensure_events(ctx, 0, (size_t)(o.timing ? 4 + 2 * S : 4 + S)));
+  SCS_CHECK(ensure_stop_flags(ctx, (size_t)S + 3));
+  std::memset(ctx->stop_flags, 0, sizeof(int) * (S + 3));
+  int* chol_flags = ctx->stop_flags + S + 1;
+  hipEvent_t* tev = ctx->tevents.data();
+  SCS_HIP(hipEventRecord(tev[0], st));
+  WS(state, SolveState, "f64_state", 1);
+  SCS_HIP(hipMemsetAsync(state, 0, sizeof(SolveState), st));
+
+  // ---- sketch (Alg. 3's first step); a CholeskyQR breakdown reruns the solve with P = I
+  const int k_used = sketch_failed ? 0 : k;
+  if (k_used > 0) {
+    SCS_CHECK(sketch64_impl(ctx, st, X, n, d, ldx, k, o, true, chol_flags));
+    SCS_HIP(hipStreamSynchronize(st));
+    if (__atomic_load_n(chol_flags, __ATOMIC_ACQUIRE) || __atomic_load_n(chol_flags + 1, __ATOMIC_ACQUIRE))
+      return svrg_solve_f64_impl(ctx, X, n, d, ldx, y, lambda, k, eps, opts, w_out, report, true);
+  }
+  SCS_HIP(hipEventRecord(tev[1], st));
+
+  // ---- preconditioned rows a_i (data, then regularizer) and beta_i = ||a_i||^2
+  WS(Xt, double, "f64_Xt", (size_t)n * ldt);
+  WS(reg, double, "f64_reg", (size_t)d * ldt);
+  WS(beta, double, "f64_beta", (size_t)N);
+  const double* U = nullptr;
+  const double* lam = nullptr;
+  const double* UT = nullptr;
+  const double sq = std::sqrt((double)n * lambda);
+  if (k_used > 0) {
+    U = ws<double>(ctx, "f64_U", 0);
+    lam = ws<double>(ctx, "f64_lam", 0);
+    WS(UTb, double, "f64_UT", (size_t)k_used * d);
+    WS(UDT, double, "f64_UDT", (size_t)k_used * d);
+    SCS_CHECK(launch_precond_setup64(st, U, lam, k_used, d, lambda, UTb, UDT, state));
+    SCS_CHECK(launch_rows64(st, n, ws<double>(ctx, "f64_Z", 0), k_used, UDT, k_used, X, ldx, d, lam, lambda, 1.0, Xt,
+                            ldt, beta));
+    SCS_CHECK(launch_rows64(st, d, U, k_used, UDT, k_used, nullptr, 0, d, lam, lambda, sq, reg, ldt, beta + n));
+    UT = UTb;
+  } else {
+    SCS_CHECK(launch_rows64(st, n, nullptr, 0, nullptr, 0, X, ldx, d, nullptr, lambda, 1.0, Xt, ldt, beta));
+    SCS_CHECK(launch_rows64(st, d, nullptr, 0, nullptr, 0, nullptr, 0, d, nullptr, lambda, sq, reg, ldt, beta + n));
+  }
+  // ---- sampling weights (Alg. 1: q_i = beta_i / sum beta)
+  WS(cum, uint64_t, "f64_cum", (size_t)N);
+  WS(scr, double, "f64_sampler_scratch", (size_t)sampler_scratch_len(N));
+  SCS_CHECK(launch_sampler_prepare(st, beta, N, cum, scr, sampler_scratch_len(N), state, o.uniform_sampling));
+  SCS_HIP(hipEventRecord(tev[2], st));
+
+  // ---- SVRG epochs (Alg. 1)
+  const int nwg = grad64_workgroups(n);
+  WS(wt, double, "f64_wt", (size_t)d);
+  WS(wt_prev, double, "f64_wt_prev", (size_t)d);
+  WS(w, double, "f64_w", (size_t)d);
+  WS(mu, double, "f64_mu", (size_t)d);
+  WS(part, double, "f64_gpart", (size_t)nwg * d);
+  WS(rsq, double, "f64_grsq", (size_t)nwg);
+  constexpr int kSampleGroup = 8;  // epochs of index draws per sampler launch
+  WS(idxb, int32_t, "f64_idx", (size_t)kSampleGroup * m * b);
+  WS(scale, double, "f64_scale", (size_t)kSampleGroup * m * b);
+  SCS_CHECK(launch_zero3(st, wt, (int64_t)sizeof(double) * d, wt_prev, (int64_t)sizeof(double) * d, nullptr, 0));
+  Inner64Args a{};
+  a.n = n;
+  a.d = d;
+  a.Xt = Xt;
+  a.reg = reg;
+  a.ld = ldt;
+  a.m = m;
+  a.b = b;
+  a.mu = mu;
+  a.wt = wt;
+  a.wt_prev = wt_prev;
+  a.step_scale = o.step_scale;
+  a.average = o.average;
+  a.state = state;
+  constexpr int kLookahead = 3;
+  int last_epoch = -1;
+  for (int s = 0; s <= S; ++s) {
+    SCS_CHECK(launch_premap64(st, UT, lam, k_used, d, lambda, wt, w, state));
+    SCS_CHECK(launch_grad64(st, X, n, d, ldx, y, w, nwg, part, rsq, state));
+    SCS_CHECK(launch_finish64(st, part, rsq, nwg, n, d, w, lambda, UT, lam, k_used, mu, state, o.stop_rule, eps,
+                              o.f_star, wt, wt_prev, s == 0 ? 1 : 0, ctx->stop_flags + s));
+    if (s == S) break;
+    const int64_t mb = m * b, slot = s % kSampleGroup;
+    if (slot == 0) {
+      const int64_t cnt = (int64_t)std::min(kSampleGroup, S - s) * mb;
+      if (o.indices) SCS_CHECK(launch_index_scale(st, cum, N, n, o.indices + (int64_t)s * mb, cnt, scale, state));
+      else SCS_CHECK(launch_sample(st, cum, N, n, o.seed, s + o.epoch_offset, mb, cnt, idxb, scale, state));
+    }
+    a.idx = o.indices ? o.indices + (int64_t)s * mb : idxb + slot * mb;
+    a.scale = scale + slot * mb;
+    if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
+    SCS_CHECK(launch_inner64(st, a));
+    SCS_HIP(hipEventRecord(tev[4 + s], st));
+    last_epoch = s;
+    if (s + 1 >= kLookahead) {  // as in the FP32 solve: stop enqueuing once a finished snapshot is seen
+      const int q = s + 1 - kLookahead;
+      SCS_HIP(hipEventSynchronize(tev[4 + q]));
+      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+    }
+  }
+  SCS_CHECK(launch_premap64(st, UT, lam, k_used, d, lambda, wt, w_out, nullptr));
+  SCS_HIP(hipEventRecord(tev[3], st));
+  SolveState hs;
+  SCS_HIP(hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+
+  int status = SCS_OK;
+  if (hs.status == SCS_ENONFINITE) {
+    set_error("non-finite value in X or y");
+    status = hs.status;
+  } else if (hs.status == SCS_DIVERGED) {
+    status = SCS_DIVERGED;
+  } else if (o.stop_rule != SCS_STOP_EPOCHS && !hs.done) {
+    status = SCS_NOT_CONVERGED;
+  } else if (sketch_failed) {
+    status = SCS_SKETCH_RANK_DEFICIENT;
+  }
+  if (o.epoch_ms) {
+    for (int s = 0; s < S; ++s) {
+      float ms = -1.f;
+      if (s > last_epoch || hipEventElapsedTime(&ms, tev[0], tev[4 + s]) != hipSuccess) ms = -1.f;
+      o.epoch_ms[s] = ms;
+    }
+  }
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->status = status;
+    report->epochs = hs.epochs;
+    report->k_used = k_used;
+    report->steps = m;
+    report->eta = hs.eta;
+    report->beta_hat = hs.beta_sum / (double)n;
+    report->objective = hs.obj;
+    report->grad_norm = std::sqrt(hs.gnorm2);
+    report->certificate = hs.cert;
+    report->lam_top = hs.lam_top;
+    report->backoffs = hs.backoffs;
+    report->workgroups = 1;
+    report->wave_rows = 0;
+    float t1 = 0, t2 = 0, t3 = 0;
+    hipEventElapsedTime(&t1, tev[0], tev[1]);
+    hipEventElapsedTime(&t2, tev[1], tev[2]);
+    hipEventElapsedTime(&t3, tev[2], tev[3]);
+    report->ms_sketch = t1;
+    report->ms_apply = t2;
+    report->ms_solve = t3;
+    if (o.timing) {
+      double si = 0.0;
+      for (int s = 0; s < hs.epochs; ++s) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, tev[4 + S + s], tev[4 + s]);
+        si += ms;
+      }
+      report->ms_inner = si;
+      report->n_inner = hs.epochs;
+    }
+  }
+  return status;
+}
+
+int scs_sketch_build_f64(scs_ctx* ctx, const double* X, int64_t n, int64_t d, int64_t ldx, int k,
+                         const scs_opts* opts, double* U_out, double* lam_out) {
+  if (!ctx || !U_out || !lam_out) {
+    set_error("null argument");
+    return SCS_EINVAL;
+  }
+  scs_opts o;
+  scs_opts_default(&o);
+  if (opts) o = *opts;
+  SCS_CHECK(check_f64_problem(X, n, d, ldx, 1.0, k, o));
+  if (k < 1) {
+    set_error("sketch: need k >= 1");
+    return SCS_EINVAL;
+  }
+  Guard g(ctx->device);
+  hipStream_t st = ctx->stream;
+  int* flags = ws<int>(ctx, "f64_cholflags", 2);
+  if (!flags) return SCS_ENOMEM;
+  SCS_CHECK(sketch64_impl(ctx, st, X, n, d, ldx, k, o, false, flags));
+  SCS_HIP(hipMemcpyAsync(U_out, ws<double>(ctx, "f64_U", 0), sizeof(double) * d * k, hipMemcpyDeviceToDevice, st));
+  SCS_HIP(hipMemcpyAsync(lam_out, ws<double>(ctx, "f64_lam", 0), sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  int hflags[2] = {0, 0};
+  SCS_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  SCS_HIP(hipStreamSynchronize(st));
+  return hflags[0] || hflags[1] ? SCS_SKETCH_RANK_DEFICIENT : SCS_OK;
+}
+
+int scs_svrg_solve_f64(scs_ctx* ctx, const double* X, int64_t n, int64_t d, int64_t ldx, const double* y,
+                       double lambda, int k, double eps, const scs_opts* opts, double* w_out, scs_report* report) {
+  return svrg_solve_f64_impl(ctx, X, n, d, ldx, y, lambda, k, eps, opts, w_out, report, false);
 }
 
 int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const int64_t* n, const int64_t* d,

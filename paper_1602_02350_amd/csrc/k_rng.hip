@@ -33,7 +33,8 @@ __global__ void gaussian_kernel(uint64_t seed, int64_t count, float* out) {
 }
 
 // Partial max and sum of beta (FP64) per workgroup; non-finite values poison the max.
-__global__ void beta_stats_partial(const float* beta, int64_t N, double* part) {
+template <typename BT>
+__global__ void beta_stats_partial(const BT* beta, int64_t N, double* part) {
   double mx = 0.0, sm = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     double b = (double)beta[i];
@@ -67,7 +68,8 @@ __global__ void beta_stats_partial(const float* beta, int64_t N, double* part) {
 
 // Quantize to W_i = max(1, rint(beta_i * scale)) (0 for beta_i = 0) and scan one tile (inclusive).
 // uniform: every component gets weight 1 (q_i = 1/N) while the sum of beta still goes to the state
-__global__ void quantize_scan_tile(const float* beta, int64_t N, const double* part, int nparts, uint64_t* cum,
+template <typename BT>
+__global__ void quantize_scan_tile(const BT* beta, int64_t N, const double* part, int nparts, uint64_t* cum,
                                    uint64_t* tile_sum, SolveState* state, int uniform) {
   __shared__ double s_scale;
   __shared__ uint64_t s_warp[kScanThreads / 64];
@@ -172,21 +174,24 @@ __device__ __forceinline__ int64_t upper_bound_u64(const uint64_t* cum, int64_t 
   return lo;
 }
 
-// 1 / (n q_i) with q_i = W_i / T, in FP64 then rounded.
-__device__ __forceinline__ float inv_nq(const uint64_t* cum, int64_t i, int64_t n_rows, uint64_t T) {
+// 1 / (n q_i) with q_i = W_i / T, in FP64, then rounded to the scale's type.
+template <typename ST>
+__device__ __forceinline__ ST inv_nq(const uint64_t* cum, int64_t i, int64_t n_rows, uint64_t T) {
   uint64_t wi = cum[i] - (i > 0 ? cum[i - 1] : 0ull);
-  return (float)((double)T / ((double)n_rows * (double)wi));
+  return (ST)((double)T / ((double)n_rows * (double)wi));
 }
 
 // Draws `count` indices for consecutive epochs epoch0, epoch0 + 1, ... (per_epoch draws each); draw
 // g of epoch e uses Philox call g/2 with counter (call_lo, call_hi, e, 0), words (x0, x1) for even g
 // and (x2, x3) for odd g, so a multi-epoch launch draws exactly what per-epoch launches would.
+template <typename ST>
 __device__ __forceinline__ void sample_one(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed,
                                            uint32_t epoch0, int64_t per_epoch, int64_t g, int32_t* idx,
-                                           float* scale);
+                                           ST* scale);
 
+template <typename ST>
 __global__ void sample_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, uint32_t epoch0,
-                              int64_t per_epoch, int64_t count, int32_t* idx, float* scale,
+                              int64_t per_epoch, int64_t count, int32_t* idx, ST* scale,
                               const SolveState* state) {
   if (state && state->done) return;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,12 +213,13 @@ __global__ void sample_batched_kernel(const BatchProb* P, int nprob, const int64
   const int p = find_prob(draw_prefix, nprob, g);
   const BatchProb& q = P[p];
   if (q.state->done) return;
-  sample_one(q.cum, q.N, q.n, seed, epoch0, q.draws, g - draw_prefix[p], q.idx, q.scale);
+  sample_one<float>(q.cum, q.N, q.n, seed, epoch0, q.draws, g - draw_prefix[p], q.idx, q.scale);
 }
 
+template <typename ST>
 __device__ __forceinline__ void sample_one(const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed,
                                            uint32_t epoch0, int64_t per_epoch, int64_t g, int32_t* idx,
-                                           float* scale) {
+                                           ST* scale) {
   const uint32_t epoch = epoch0 + (uint32_t)(g / per_epoch);
   const int64_t gl = g % per_epoch;
   uint64_t c = (uint64_t)gl >> 1;
@@ -224,18 +230,19 @@ __device__ __forceinline__ void sample_one(const uint64_t* cum, int64_t N, int64
   int64_t i = upper_bound_u64(cum, N, u);
   if (i >= N) i = N - 1;  // unreachable for u < T; kept as a guard
   idx[g] = (int32_t)i;
-  if (scale) scale[g] = inv_nq(cum, i, n_rows, T);
+  if (scale) scale[g] = inv_nq<ST>(cum, i, n_rows, T);
 }
 
+template <typename ST>
 __global__ void index_scale_kernel(const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
-                                   int64_t count, float* scale, const SolveState* state) {
+                                   int64_t count, ST* scale, const SolveState* state) {
   if (state && state->done) return;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= count) return;
   int64_t i = idx[g];
   if (i < 0) i = 0;
   if (i >= N) i = N - 1;
-  scale[g] = inv_nq(cum, i, n_rows, cum[N - 1]);
+  scale[g] = inv_nq<ST>(cum, i, n_rows, cum[N - 1]);
 }
 
 constexpr int kStatBlocks = 256;
@@ -254,17 +261,18 @@ int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out) {
 // scratch layout (in doubles): [2*kStatBlocks partials][tile sums as uint64]
 int64_t sampler_scratch_len(int64_t N) { return 2 * kStatBlocks + cdiv(N, kScanTile) + 1; }
 
-int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
+template <typename BT>
+static int sampler_prepare(hipStream_t st, const BT* beta, int64_t N, uint64_t* cum, double* scratch,
                            int64_t scratch_len, SolveState* state, int uniform) {
   if (N <= 0) return SCS_EINVAL;
   if (scratch_len < sampler_scratch_len(N)) return SCS_EINVAL;
   double* part = scratch;
   uint64_t* tiles = reinterpret_cast<uint64_t*>(scratch + 2 * kStatBlocks);
   int64_t ntiles = cdiv(N, kScanTile);
-  beta_stats_partial<<<kStatBlocks, 256, 0, st>>>(beta, N, part);
+  beta_stats_partial<BT><<<kStatBlocks, 256, 0, st>>>(beta, N, part);
   SCS_HIP(hipGetLastError());
-  quantize_scan_tile<<<dim3((unsigned)ntiles), dim3(kScanThreads), 0, st>>>(beta, N, part, kStatBlocks, cum, tiles,
-                                                                            state, uniform);
+  quantize_scan_tile<BT><<<dim3((unsigned)ntiles), dim3(kScanThreads), 0, st>>>(beta, N, part, kStatBlocks, cum,
+                                                                                tiles, state, uniform);
   SCS_HIP(hipGetLastError());
   scan_tile_sums<<<1, 256, 0, st>>>(tiles, ntiles);
   SCS_HIP(hipGetLastError());
@@ -273,11 +281,22 @@ int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_
   return SCS_OK;
 }
 
-int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
-                  int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state) {
+int launch_sampler_prepare(hipStream_t st, const float* beta, int64_t N, uint64_t* cum, double* scratch,
+                           int64_t scratch_len, SolveState* state, int uniform) {
+  return sampler_prepare(st, beta, N, cum, scratch, scratch_len, state, uniform);
+}
+
+int launch_sampler_prepare(hipStream_t st, const double* beta, int64_t N, uint64_t* cum, double* scratch,
+                           int64_t scratch_len, SolveState* state, int uniform) {
+  return sampler_prepare(st, beta, N, cum, scratch, scratch_len, state, uniform);
+}
+
+template <typename ST>
+static int sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
+                  int64_t per_epoch, int64_t count, int32_t* idx, ST* scale, const SolveState* state) {
   if (count <= 0) return SCS_OK;
   if (per_epoch <= 0) per_epoch = count;
-  sample_kernel<<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, seed, (uint32_t)epoch,
+  sample_kernel<ST><<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, seed, (uint32_t)epoch,
                                                                         per_epoch, count, idx, scale, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
@@ -294,13 +313,34 @@ int launch_sample_batched(hipStream_t st, const BatchProb* P, int nprob, const i
   return SCS_OK;
 }
 
-int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
-                       int64_t count, float* scale, const SolveState* state) {
+int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
+                  int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state) {
+  return sample(st, cum, N, n_rows, seed, epoch, per_epoch, count, idx, scale, state);
+}
+
+int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
+                  int64_t per_epoch, int64_t count, int32_t* idx, double* scale, const SolveState* state) {
+  return sample(st, cum, N, n_rows, seed, epoch, per_epoch, count, idx, scale, state);
+}
+
+template <typename ST>
+static int index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
+                       int64_t count, ST* scale, const SolveState* state) {
   if (count <= 0) return SCS_OK;
-  index_scale_kernel<<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, idx, count, scale,
-                                                                             state);
+  index_scale_kernel<ST><<<dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st>>>(cum, N, n_rows, idx, count,
+                                                                                 scale, state);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
+}
+
+int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
+                       int64_t count, float* scale, const SolveState* state) {
+  return index_scale(st, cum, N, n_rows, idx, count, scale, state);
+}
+
+int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
+                       int64_t count, double* scale, const SolveState* state) {
+  return index_scale(st, cum, N, n_rows, idx, count, scale, state);
 }
 
 }  // namespace scs

@@ -332,47 +332,9 @@ __device__ __forceinline__ int finalize_tail(const double* rsq_part, int nwg, in
   double rs = 0.0;
   for (int q = threadIdx.x; q < nwg; q += blockDim.x) rs += rsq_part[q];
   rs = block_sum_d(rs, sred);
-  if (threadIdx.x == 0) {
-    double obj = rs / (2.0 * (double)n) + 0.5 * lambda * wn;
-    // H~ = P^{-1/2} H P^{-1/2} >= lambda P^{-1} >= lambda / (lam_1 + lambda) I, so
-    // L - L* <= ||mu||^2 / (2 lambda_min(H~)) <= ||mu||^2 (lam_1 + lambda) / (2 lambda); with P = I the
-    // factor lam_1 + lambda is 1
-    double lam_top = k > 0 ? fmax(lam[0], 0.0) : 0.0;
-    double cert = gn * (k > 0 ? lam_top + lambda : 1.0) / (2.0 * lambda);
-    bool finite = isfinite(obj) && isfinite(gn);
-    // 0 = continue, 1 = stop (converged), 2 = diverged (restore, stop), 3 = non-finite input,
-    // 4 = rejected snapshot: restore the previous one, halve the step size and continue
-    int action = 0;
-    if (first) {
-      if (!finite) action = 3;
-      else state->obj0 = obj;
-    } else if (!finite || obj > 10.0 * state->obj0) {
-      if (state->backoffs < kMaxBackoffs) {
-        state->backoffs += 1;
-        action = 4;
-      } else {
-        action = 2;
-      }
-    }
-    if (action == 0) {
-      state->obj = obj;
-      state->gnorm2 = gn;
-      state->cert = cert;
-      if (stop_rule == SCS_STOP_CERTIFICATE && cert <= eps) action = 1;
-      if (stop_rule == SCS_STOP_GAP && obj - f_star <= eps) action = 1;
-    }
-    if (action == 1) {
-      state->done = 1;
-      state->status = SCS_OK;
-    } else if (action == 2) {
-      state->done = 1;
-      state->status = SCS_DIVERGED;
-    } else if (action == 3) {
-      state->done = 1;
-      state->status = SCS_ENONFINITE;
-    }
-    s_action = action;
-  }
+  if (threadIdx.x == 0)
+    s_action = snapshot_decision(state, rs / (2.0 * (double)n) + 0.5 * lambda * wn, gn, lam, k, lambda, first,
+                                 stop_rule, eps, f_star);
   __syncthreads();
   if ((s_action == 2 || s_action == 4) && wt_prev) {
     for (int64_t j = threadIdx.x; j < d; j += blockDim.x) wt_cur[j] = wt_prev[j];

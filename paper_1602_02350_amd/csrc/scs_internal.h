@@ -154,6 +154,51 @@ struct SolveState {
 };
 constexpr int kMaxBackoffs = 6;  // a further rejected snapshot ends the solve with SCS_DIVERGED
 
+// The decision on an evaluated snapshot (one thread; obj = L at the snapshot, gn = ||mu||^2 with
+// mu = grad L~ = P^{-1/2} grad L). Returns 0 = continue, 1 = stop (converged), 2 = diverged (restore,
+// stop), 3 = non-finite input, 4 = rejected snapshot (restore the previous one, halve the step size
+// and continue), and records the outcome in the state.
+// Certificate: H~ = P^{-1/2} H P^{-1/2} >= lambda P^{-1} >= lambda / (lam_1 + lambda) I, so
+// L - L* <= ||mu||^2 / (2 lambda_min(H~)) <= ||mu||^2 (lam_1 + lambda) / (2 lambda); with P = I the
+// factor lam_1 + lambda is 1.
+__device__ __forceinline__ int snapshot_decision(SolveState* state, double obj, double gn, const double* lam, int k,
+                                                 double lambda, int first, int stop_rule, double eps,
+                                                 double f_star) {
+  const double lam_top = k > 0 ? fmax(lam[0], 0.0) : 0.0;
+  const double cert = gn * (k > 0 ? lam_top + lambda : 1.0) / (2.0 * lambda);
+  const bool finite = isfinite(obj) && isfinite(gn);
+  int action = 0;
+  if (first) {
+    if (!finite) action = 3;
+    else state->obj0 = obj;
+  } else if (!finite || obj > 10.0 * state->obj0) {
+    if (state->backoffs < kMaxBackoffs) {
+      state->backoffs += 1;
+      action = 4;
+    } else {
+      action = 2;
+    }
+  }
+  if (action == 0) {
+    state->obj = obj;
+    state->gnorm2 = gn;
+    state->cert = cert;
+    if (stop_rule == SCS_STOP_CERTIFICATE && cert <= eps) action = 1;
+    if (stop_rule == SCS_STOP_GAP && obj - f_star <= eps) action = 1;
+  }
+  if (action == 1) {
+    state->done = 1;
+    state->status = SCS_OK;
+  } else if (action == 2) {
+    state->done = 1;
+    state->status = SCS_DIVERGED;
+  } else if (action == 3) {
+    state->done = 1;
+    state->status = SCS_ENONFINITE;
+  }
+  return action;
+}
+
 // ---------------------------------------------------------------- launchers (defined in the .hip files)
 // rng
 int launch_gaussian(hipStream_t st, uint64_t seed, int64_t count, float* out);
@@ -164,6 +209,13 @@ int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows
                   int64_t per_epoch, int64_t count, int32_t* idx, float* scale, const SolveState* state);
 int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
                        int64_t count, float* scale, const SolveState* state);
+// the same from FP64 beta, and with the scales 1/(n q_i) kept in FP64 (the FP64 path)
+int launch_sampler_prepare(hipStream_t st, const double* beta, int64_t N, uint64_t* cum, double* scratch,
+                           int64_t scratch_len, SolveState* state, int uniform = 0);
+int launch_sample(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, uint64_t seed, int epoch,
+                  int64_t per_epoch, int64_t count, int32_t* idx, double* scale, const SolveState* state);
+int launch_index_scale(hipStream_t st, const uint64_t* cum, int64_t N, int64_t n_rows, const int32_t* idx,
+                       int64_t count, double* scale, const SolveState* state);
 int64_t sampler_scratch_len(int64_t N);
 
 // gemm (MFMA)
@@ -348,5 +400,42 @@ int launch_inner_epoch_batched(hipStream_t st, const BatchProb* P, int nprob, in
 constexpr int kEpochGroup = 8;
 int launch_clock_set(hipStream_t st, int* clk, int epoch, int epochs);
 int launch_clock_advance(hipStream_t st, int* clk);
+
+// ---------------------------------------------------------------- the FP64 path (k_f64.hip)
+constexpr int kF64MaxD = 4096;  // columns: one workgroup of 1024 threads, four columns each
+constexpr int kF64MaxL = 136;   // sketch width k + p (the eigensolver's limit)
+struct Inner64Args {
+  int64_t n, d;
+  const double* Xt;    // n data rows, stride ld
+  const double* reg;   // d regularizer rows, stride ld
+  int64_t ld;
+  const int32_t* idx;  // m b component indices of the epoch
+  const double* scale; // 1/(n q_i) per draw
+  int64_t m;
+  int b;
+  const double* mu;    // full gradient at the snapshot (preconditioned coordinates)
+  double* wt;          // the snapshot in, the next snapshot out
+  double* wt_prev;     // receives the snapshot (nullable)
+  double step_scale;   // eta = step_scale n / sum(beta), halved per rejected snapshot
+  int average;
+  SolveState* state;
+};
+int launch_f32_to_f64(hipStream_t st, int64_t count, const float* src, double* dst);
+int launch_scale64(hipStream_t st, int64_t count, double alpha, double* x);
+int launch_precond_setup64(hipStream_t st, const double* U, const double* lam, int k, int64_t d, double lambda,
+                           double* UT, double* UDT, SolveState* state);
+int launch_rows64(hipStream_t st, int64_t rows, const double* A, int64_t lda, const double* UDT, int k,
+                  const double* base, int64_t ldb, int64_t d, const double* lam, double lambda, double alpha,
+                  double* out, int64_t ldo, double* beta);
+int grad64_workgroups(int64_t n);
+int launch_grad64(hipStream_t st, const double* X, int64_t n, int64_t d, int64_t ldx, const double* y,
+                  const double* w, int nwg, double* part, double* rsq, const SolveState* state);
+int launch_finish64(hipStream_t st, const double* part, const double* rsq, int nwg, int64_t n, int64_t d,
+                    const double* w, double lambda, const double* UT, const double* lam, int k, double* mu,
+                    SolveState* state, int stop_rule, double eps, double f_star, double* wt, const double* wt_prev,
+                    int first, int* host_stop);
+int launch_premap64(hipStream_t st, const double* UT, const double* lam, int k, int64_t d, double lambda,
+                    const double* wt, double* w, const SolveState* state);
+int launch_inner64(hipStream_t st, const Inner64Args& a);
 
 }  // namespace scs

@@ -160,6 +160,8 @@ def random_vector(d: int, seed: int, scale: float = 1.0) -> np.ndarray:
 WORKLOADS = {
     # n=2000, d=100, spectrum j^-2, lambda=1e-4, k=10, p=5; solved to 1e-8.
     "small_n2000_d100": dict(n=2000, d=100, alpha=2.0, lam=1e-4, k=10, b=8, eps=1e-8, floor=0.0),
+    # the same recipe for the FP64 path (X and y drawn in FP64)
+    "fp64_n2000_d100": dict(n=2000, d=100, alpha=2.0, lam=1e-4, k=10, b=8, eps=1e-8, floor=0.0, fp64=True),
     # n=1e5, d=1000, spectrum j^-1.5, lambda=1e-5, k=50, minibatch 64; solved to 1e-6 in FP32.
     "fp32_n100000_d1000": dict(n=100000, d=1000, alpha=1.5, lam=1e-5, k=50, b=64, eps=1e-6, floor=0.0),
     # n=5e5, d=2048, spectrum j^-2 + 1e-6, lambda=1e-6, k=128; BF16 sketch and rows.
