@@ -26,6 +26,7 @@ constexpr int kF64Cols = kF64MaxD / kF64Block;  // columns per thread in the inn
 constexpr int kRowBlock = 256;                   // threads of the row and gradient kernels
 constexpr int kGradCols = kF64MaxD / kRowBlock;  // columns per thread in the gradient pass
 constexpr int kGradRows = 64;                    // rows whose residuals one pass of grad64 stages
+constexpr int kF64StageRows = 3072;              // doubles of LDS for the inner loop's staged rows
 
 // Sum over a workgroup; every thread returns the same value (xor butterflies give every lane the
 // same bits, and the wave sums are added in wave order).
@@ -118,18 +119,30 @@ __global__ __launch_bounds__(kRowBlock) void grad64_kernel(const double* X, int6
   __syncthreads();
   for (int64_t rb = r0; rb < r1; rb += kGradRows) {
     const int nr = (int)(r1 - rb < kGradRows ? r1 - rb : kGradRows);
-    for (int rr = wave; rr < nr; rr += kRowBlock / 64) {
-      const double* x = X + (rb + rr) * ldx;
-      double dot = 0.0;
-      for (int64_t j = lane; j < d; j += 64) dot += x[j] * w_s[j];
-      dot = warp_sum_d(dot);
-      if (lane == 0) {
-        const double r = dot - y[rb + rr];
-        r_s[rr] = r;
-        rs += r * r;
+    // each wave takes rows wave, wave + 4, ...: four of them at a time, their loads in flight together
+    for (int r4 = wave; r4 < nr; r4 += 4 * (kRowBlock / 64)) {
+      double dot[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int64_t j = lane; j < d; j += 64) {
+        const double wj = w_s[j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int rr = r4 + u * (kRowBlock / 64);
+          if (rr < nr) dot[u] += X[(rb + rr) * ldx + j] * wj;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r4 + u * (kRowBlock / 64);
+        const double t = warp_sum_d(dot[u]);
+        if (lane == 0 && rr < nr) {
+          const double r = t - y[rb + rr];
+          r_s[rr] = r;
+          rs += r * r;
+        }
       }
     }
     __syncthreads();
+#pragma unroll 4
     for (int rr = 0; rr < nr; ++rr) {
       const double r = r_s[rr];
       const double* x = X + (rb + rr) * ldx;
@@ -241,15 +254,27 @@ __global__ __launch_bounds__(kF64Block) void premap64_kernel(const double* UT, c
 // scale_j = 1/(n q_{i_j}) (the variance-reduced direction divided by N q_i, times N/n for the
 // N/n of each component), and adds delta to the running sum; at the end w~ <- w_bar + (sum / m)
 // (average) or w_bar + delta (last iterate). eta = c n / sum(beta), halved per rejected snapshot.
+// Step t: wave w forms the dot products of rows j = w, w + 16, ... (lanes over the columns) and, when
+// b d fits, stages the rows in LDS; after a barrier each thread updates its columns (c = thread +
+// 1024 q). PR > 0 (b <= 16 PR, d <= 64 PQ, the rows staged): each wave holds its rows of step t + 1 in
+// registers, loaded during step t together with the indices of step t + 2, through global-address
+// pointers so that the barriers do not wait for them.
+typedef __attribute__((address_space(1))) const double gdouble;
+typedef __attribute__((address_space(1))) const int32_t gint32;
+
+template <int PR, int PQ>
 __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
   if (a.state->done) return;
   __shared__ double dl_s[kF64MaxD];
+  __shared__ double rows_s[kF64StageRows];  // the step's b rows when b d fits, for the update phase
   __shared__ double coef[kInnerMaxB];
   __shared__ int row_s[kInnerMaxB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t d = a.d;
+  const int64_t d = a.d, N = a.n + a.d;
+  const int b = a.b;
+  const bool staged = PR > 0 || (int64_t)b * d <= kF64StageRows;
   const double eta = ldexp(a.step_scale * (double)a.n / a.state->beta_sum, -a.state->backoffs);
-  const double inv_b = 1.0 / (double)a.b;
+  const double inv_b = 1.0 / (double)b;
   double w0[kF64Cols], muv[kF64Cols], dl[kF64Cols], sm[kF64Cols];
 #pragma unroll
   for (int q = 0; q < kF64Cols; ++q) {
@@ -260,39 +285,112 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
     sm[q] = 0.0;
     if (c < d) dl_s[c] = 0.0;
   }
-  __syncthreads();
-  for (int64_t t = 0; t < a.m; ++t) {
-    const int32_t* idx = a.idx + t * a.b;
-    const double* sc = a.scale + t * a.b;
-    for (int j = wave; j < a.b; j += kF64Waves) {
-      int64_t i = idx[j];
-      i = i < 0 ? 0 : i >= a.n + d ? a.n + d - 1 : i;  // a caller's index stream is clamped as the scales are
-      const double* row = i < a.n ? a.Xt + i * a.ld : a.reg + (i - a.n) * a.ld;
-      double dot = 0.0;
-      for (int64_t c = lane; c < d; c += 64) dot += row[c] * dl_s[c];
-      dot = warp_sum_d(dot);
-      if (lane == 0) {
-        coef[j] = sc[j] * dot;
-        row_s[j] = (int)i;
-      }
-    }
-    __syncthreads();
+  // a caller's index stream is clamped as the scales are
+  auto clampi = [&](int64_t i) { return i < 0 ? (int64_t)0 : i >= N ? N - 1 : i; };
+  auto rowp = [&](int64_t i) { return i < a.n ? a.Xt + i * a.ld : a.reg + (i - a.n) * a.ld; };
+  // the update phase of step t, once coef and (when staged) rows_s hold the step
+  auto update = [&]() {
 #pragma unroll
     for (int q = 0; q < kF64Cols; ++q) {
       const int64_t c = threadIdx.x + (int64_t)q * kF64Block;
       if (c < d) {
         double v = 0.0;
-        for (int j = 0; j < a.b; ++j) {
-          const int64_t i = row_s[j];
-          const double* row = i < a.n ? a.Xt + i * a.ld : a.reg + (i - a.n) * a.ld;
-          v += coef[j] * row[c];
+        if (staged) {
+          for (int j = 0; j < b; ++j) v += coef[j] * rows_s[j * d + c];
+        } else {
+          for (int j = 0; j < b; ++j) v += coef[j] * rowp(row_s[j])[c];
         }
         dl[q] -= eta * (v * inv_b + muv[q]);
         sm[q] += dl[q];
         dl_s[c] = dl[q];
       }
     }
-    __syncthreads();
+  };
+  __syncthreads();
+  if constexpr (PR == 0) {
+    for (int64_t t = 0; t < a.m; ++t) {
+      const int32_t* idx = a.idx + t * b;
+      const double* sc = a.scale + t * b;
+      for (int j = wave; j < b; j += kF64Waves) {
+        const int64_t i = clampi(idx[j]);
+        const double* row = rowp(i);
+        double dot = 0.0;
+        for (int64_t c = lane; c < d; c += 64) {
+          const double x = row[c];
+          dot += x * dl_s[c];
+          if (staged) rows_s[j * d + c] = x;
+        }
+        dot = warp_sum_d(dot);
+        if (lane == 0) {
+          coef[j] = sc[j] * dot;
+          row_s[j] = (int)i;
+        }
+      }
+      __syncthreads();
+      update();
+      __syncthreads();
+    }
+  } else {
+    const gint32* gidx = (const gint32*)a.idx;
+    const gdouble* gsc = (const gdouble*)a.scale;
+    auto load = [&](int64_t t, const int64_t (&ii)[PR], double (&x)[PR][PQ], double (&scv)[PR]) {
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int j = wave + kF64Waves * r;
+        const gdouble* row = (const gdouble*)rowp(ii[r]);
+        scv[r] = j < b ? gsc[t * b + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int64_t c = lane + 64 * q;
+          x[r][q] = (j < b && c < d) ? row[c] : 0.0;
+        }
+      }
+    };
+    auto indices = [&](int64_t t, int64_t (&ii)[PR]) {
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int j = wave + kF64Waves * r;
+        ii[r] = (t < a.m && j < b) ? clampi(gidx[t * b + j]) : 0;
+      }
+    };
+    int64_t i_cur[PR], i_next[PR];
+    double x_cur[PR][PQ], s_cur[PR];
+    indices(0, i_cur);
+    indices(1, i_next);
+    if (a.m > 0) load(0, i_cur, x_cur, s_cur);
+    for (int64_t t = 0; t < a.m; ++t) {
+      double x_next[PR][PQ], s_next[PR];
+      int64_t i_after[PR];
+      if (t + 1 < a.m) load(t + 1, i_next, x_next, s_next);
+      indices(t + 2, i_after);
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int j = wave + kF64Waves * r;
+        if (j < b) {  // uniform over the wave
+          double dot = 0.0;
+#pragma unroll
+          for (int q = 0; q < PQ; ++q) {
+            const int64_t c = lane + 64 * q;
+            if (c < d) {
+              dot += x_cur[r][q] * dl_s[c];
+              rows_s[j * d + c] = x_cur[r][q];
+            }
+          }
+          dot = warp_sum_d(dot);
+          if (lane == 0) coef[j] = s_cur[r] * dot;
+        }
+      }
+      __syncthreads();
+      update();
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        s_cur[r] = s_next[r];
+        i_next[r] = i_after[r];
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) x_cur[r][q] = x_next[r][q];
+      }
+    }
   }
 #pragma unroll
   for (int q = 0; q < kF64Cols; ++q) {
@@ -346,9 +444,10 @@ int launch_rows64(hipStream_t st, int64_t rows, const double* A, int64_t lda, co
 }
 
 int grad64_workgroups(int64_t n) {
-  // at least kGradRows rows per workgroup, at most 512 workgroups
-  const int64_t w = cdiv(n, (int64_t)4 * kGradRows);
-  return (int)(w < 1 ? 1 : w > 512 ? 512 : w);
+  // one workgroup per kGradRows rows up to 256 workgroups (the finish adds the partials of every
+  // workgroup for each column), more rows per workgroup beyond
+  const int64_t w = cdiv(n, (int64_t)kGradRows);
+  return (int)(w < 1 ? 1 : w > 256 ? 256 : w);
 }
 
 int launch_grad64(hipStream_t st, const double* X, int64_t n, int64_t d, int64_t ldx, const double* y,
@@ -381,7 +480,10 @@ int launch_premap64(hipStream_t st, const double* UT, const double* lam, int k, 
 
 int launch_inner64(hipStream_t st, const Inner64Args& a) {
   if (a.d > kF64MaxD || a.b < 1 || a.b > kInnerMaxB || a.m < 0) return SCS_EINVAL;
-  inner64_kernel<<<1, kF64Block, 0, st>>>(a);
+  const bool fits = (int64_t)a.b * a.d <= kF64StageRows;
+  if (fits && a.b <= kF64Waves && a.d <= 128) inner64_kernel<1, 2><<<1, kF64Block, 0, st>>>(a);
+  else if (fits && a.b <= 2 * kF64Waves && a.d <= 256) inner64_kernel<2, 4><<<1, kF64Block, 0, st>>>(a);
+  else inner64_kernel<0, 0><<<1, kF64Block, 0, st>>>(a);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

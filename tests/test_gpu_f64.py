@@ -118,6 +118,28 @@ def test_f64_epochs_match_the_oracle_on_an_injected_stream(ctx, k, uniform):
     assert abs(res.report["eta"] - eta) <= 1e-13 * eta
 
 
+@pytest.mark.parametrize("n,d,k,b", [(1500, 120, 12, 24), (1000, 20, 4, 100), (3000, 300, 20, 64),
+                                     (700, 4096, 0, 3)])
+def test_f64_epochs_match_the_oracle_at_other_shapes(ctx, n, d, k, b):
+    """The inner loop's three forms: rows prefetched a step ahead (b <= 32, d <= 256, b d <= 3072), rows
+    staged in LDS (b d <= 3072), rows read twice from memory; d = 4096 is the widest the FP64 path
+    takes. Two epochs on an injected stream against the oracle, as above."""
+    P = inputs.make_ridge(n, d, 1.5, 1e-3, seed=61 + d, dtype=np.float64)
+    lam = P.lam
+    m, S, c = max(1, n // (4 * b)), 2, 2.0
+    Om = inputs.gaussian((k + 5, d), seed=62 + d)
+    idx = inputs.index_stream(n + d, S * m * b, seed=63 + d).reshape(S, -1)
+    res = ctx.svrg_solve_f64(dev(P.X), dev(P.y), lam, k, 0.0, omega=dev(Om, torch.float32) if k else None,
+                             indices=dev(idx, torch.int32), steps=m, batch=b, max_epochs=S,
+                             stop_rule=binding.STOP_EPOCHS, step_scale=c)
+    assert res.status == binding.OK and res.report["epochs"] == S
+    Pm, _, _ = svrg.preconditioner_from_sketch(P.X, lam, k, Om.astype(np.float64).T)
+    comp = precond.Components(P.X, P.y, lam, Pm)
+    wt, _ = svrg.svrg(comp, np.zeros(d), m, c / svrg.beta_hat(comp), S, b, lambda s: idx[s], q=quantized_q(comp))
+    ws = ridge.closed_form(P.X, P.y, lam)
+    assert_close_trajectory(host(res.w), Pm @ wt, ws, 1e-11, f"f64 epochs n={n} d={d} k={k} b={b}")
+
+
 def test_f64_solve_draws_the_oracles_stream(ctx):
     """No injection: Omega from the counter-based Gaussian and the indices from the integer sampler of
     the seed, which the oracle reproduces (both are exact integer computations up to the FP64 beta_i
