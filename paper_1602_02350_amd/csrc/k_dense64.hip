@@ -44,17 +44,22 @@ __global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_
   }
 }
 
-// Cholesky G = R^T R (upper R) and R^{-1}, one workgroup, R packed in LDS (l (l + 1) / 2 doubles,
-// then the l reciprocal diagonal entries). Right-looking with one barrier per column: phase j reads
-// the finished diagonal entry p_j and the unscaled row j, updates the trailing triangle with
-// S[a][c] -= S[j][a] S[j][c] / p_j (a wave per row a, lanes over columns c >= a), and scales
-// row j - 1 (which nothing reads in that phase) by 1/sqrt(p_{j-1}). The inverse X = R^{-1} is then
-// formed one column per wave by back substitution in axpy form: x = e_j, and for q = j, ..., 0:
-// x_q *= 1/R[q][q], x_i -= R[i][q] x_q (i < q); lane t keeps x_t, x_{t+64}, x_{t+128} in registers
-// and the entries of R for step q - 1 are read from LDS while step q runs.
+// Cholesky G = R^T R (upper R), then R^{-1}, in two launches.
+// chol64: one workgroup; G arrives as the partial Gram matrices of gram_part64 (upper triangles),
+// added in order; R packed in LDS (l (l + 1) / 2 doubles, then the l reciprocal diagonal entries),
+// copied out in that layout. Right-looking with one barrier per column: phase j reads the finished
+// diagonal entry p_j and the unscaled row j, updates the trailing triangle with
+// S[a][c] -= (S[j][a] / p_j) S[j][c] (lanes over columns c, each holding S[j][c] in a register, waves
+// over rows a, four rows' updates in flight), and scales row j - 1 (which nothing reads in that phase)
+// by 1/sqrt(p_{j-1}).
+// rinv64: X = R^{-1} one column per wave, over as many workgroups as the columns need, by back
+// substitution in axpy form: x = e_j, and for q = j, ..., 0: x_q *= 1/R[q][q], x_i -= R[i][q] x_q
+// (i < q); lane t keeps x_t, x_{t+64}, x_{t+128} in registers and the entries of R for step q - 1 are
+// read from LDS while step q runs.
 // flag: 0 on success, 1 if a pivot is not positive relative to the largest diagonal entry of G
 // (that pivot is replaced by 1 so the factor stays finite).
 constexpr int kCholThreads = 512;
+constexpr int kRinvWaves = 4;  // columns of R^{-1} per workgroup
 
 __device__ __forceinline__ int packed_up(int i, int j, int l) { return i * (2 * l - i + 1) / 2 + (j - i); }
 // offset of row i of the packed triangle, so that R[i][j] = S[packed_row(i, l) + j] for j >= i
@@ -67,15 +72,21 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* G, int l, double* Rinv, int* flag) {
+__global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part, int nparts, int l, double* Rp,
+                                                              int* flag) {
   extern __shared__ double S[];
   __shared__ double s_dmax;
   double* rdiag = S + l * (l + 1) / 2;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nwave = nt >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over it stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int e = tid; e < l * l; e += nt) {
     int i = e / l, j = e % l;
-    if (j >= i) S[packed_row(i, l) + j] = G[e];
+    if (j >= i) {
+      double g = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < nparts; ++q) g += part[(int64_t)q * l * l + e];
+      S[packed_row(i, l) + j] = g;
+    }
   }
   __syncthreads();
   if (wave == 0) {  // largest diagonal entry: one wave, lanes over the diagonal
@@ -87,7 +98,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* 
   __syncthreads();
   const double dmax = s_dmax;
   int bad = 0;
-  double p_prev = 1.0;
   auto pivot = [&](int j) {
     double p = S[packed_row(j, l) + j];
     if (!(p > 1e-30 * dmax) || !isfinite(p)) {
@@ -96,69 +106,109 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv64_kernel(const double* 
     }
     return p;
   };
-  auto finish_row = [&](int r, double p) {
-    const double sp = sqrt(p), isp = 1.0 / sp;
+  // row r scaled by 1 / sqrt(p_r), its diagonal set to sqrt(p_r) (both formed when p_r is read)
+  auto finish_row = [&](int r, double sp, double isp) {
     const int row = packed_row(r, l);
     for (int c = r + tid; c < l; c += nt) S[row + c] = c == r ? sp : S[row + c] * isp;
     if (tid == 0) rdiag[r] = isp;
   };
+  double sp_prev = 1.0, isp_prev = 1.0;
   for (int j = 0; j < l; ++j) {
     const double p = pivot(j), ip = 1.0 / p;
+    const double sp = sqrt(p), isp = 1.0 / sp;  // independent of the update: overlaps it
     const int rowj = packed_row(j, l);
-    for (int a = j + 1 + wave; a < l; a += nwave) {
-      const double ra = S[rowj + a] * ip;
-      const int rowa = packed_row(a, l);
-      for (int c = a + lane; c < l; c += 64) S[rowa + c] -= ra * S[rowj + c];
+    for (int c0 = j + 1; c0 < l; c0 += 64) {
+      const int c = c0 + lane;
+      const bool cok = c < l;
+      const double sjc = cok ? S[rowj + c] : 0.0;
+#pragma unroll 4
+      for (int a = j + 1 + wave; a < l; a += nwave) {
+        if (cok && c >= a) {
+          const double ra = S[rowj + a] * ip;
+          S[packed_row(a, l) + c] -= ra * sjc;
+        }
+      }
     }
-    if (j > 0) finish_row(j - 1, p_prev);
-    p_prev = p;
+    if (j > 0) finish_row(j - 1, sp_prev, isp_prev);
+    sp_prev = sp;
+    isp_prev = isp;
     __syncthreads();
   }
-  finish_row(l - 1, p_prev);
+  finish_row(l - 1, sp_prev, isp_prev);
   __syncthreads();
+  for (int e = tid; e < l * (l + 1) / 2 + l; e += nt) Rp[e] = S[e];
+  if (tid == 0) *flag = bad;
+}
+
+__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* Rp, int l, double* Rinv) {
+  extern __shared__ double S[];
+  double* rdiag = S + l * (l + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < l * (l + 1) / 2 + l; e += blockDim.x) S[e] = Rp[e];
+  __syncthreads();
+  const int j = (int)blockIdx.x * kRinvWaves + wave;
+  if (j >= l) return;
   int roff[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) roff[r] = packed_row(min(lane + 64 * r, l - 1), l);
-  for (int j = wave; j < l; j += nwave) {
-    // S reads use in-bounds clamped addresses (lanes past the triangle read a valid entry that the
-    // update then ignores), so the loop has no per-lane branches
-    double x[3], sv[3];
+  // S reads use in-bounds clamped addresses (lanes past the triangle read a valid entry that the
+  // update then ignores), so the loop has no per-lane branches
+  double x[3], sv[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int i = lane + 64 * r;
-      x[r] = i == j ? 1.0 : 0.0;
-      sv[r] = S[roff[r] + max(j, min(i, l - 1))];
-    }
-    double rq = rdiag[j];
-    for (int q = j; q >= 0; --q) {
-      // entries for step q - 1, read while step q runs
-      double sn[3];
-      const int qn = max(q - 1, 0);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) sn[r] = S[roff[r] + max(qn, min(lane + 64 * r, l - 1))];
-      const double rq_next = rdiag[qn];
-      const int slot = q >> 6, owner = q & 63;  // uniform across the wave
-      const double mine = slot == 0 ? x[0] : (slot == 1 ? x[1] : x[2]);
-      const double xq = readlane_d(mine, owner) * rq;
-      if (lane == owner) {
-        if (slot == 0) x[0] = xq;
-        else if (slot == 1) x[1] = xq;
-        else x[2] = xq;
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        if (lane + 64 * r < q) x[r] -= sv[r] * xq;
-#pragma unroll
-      for (int r = 0; r < 3; ++r) sv[r] = sn[r];
-      rq = rq_next;
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int i = lane + 64 * r;
-      if (i < l) Rinv[(int64_t)i * l + j] = i <= j ? x[r] : 0.0;
-    }
+  for (int r = 0; r < 3; ++r) {
+    const int i = lane + 64 * r;
+    x[r] = i == j ? 1.0 : 0.0;
+    sv[r] = S[roff[r] + max(j, min(i, l - 1))];
   }
-  if (tid == 0) *flag = bad;
+  double rq = rdiag[j];
+  for (int q = j; q >= 0; --q) {
+    // entries for step q - 1, read while step q runs
+    double sn[3];
+    const int qn = max(q - 1, 0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sn[r] = S[roff[r] + max(qn, min(lane + 64 * r, l - 1))];
+    const double rq_next = rdiag[qn];
+    const int slot = q >> 6, owner = q & 63;  // uniform across the wave
+    const double mine = slot == 0 ? x[0] : (slot == 1 ? x[1] : x[2]);
+    const double xq = readlane_d(mine, owner) * rq;
+    if (lane == owner) {
+      if (slot == 0) x[0] = xq;
+      else if (slot == 1) x[1] = xq;
+      else x[2] = xq;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (lane + 64 * r < q) x[r] -= sv[r] * xq;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sv[r] = sn[r];
+    rq = rq_next;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int i = lane + 64 * r;
+    if (i < l) Rinv[(int64_t)i * l + j] = i <= j ? x[r] : 0.0;
+  }
+}
+
+// Partial Gram matrices of Y d x l (row-major, ld l): each workgroup stages kGramRows rows of Y in LDS
+// and forms their Y_r^T Y_r (upper triangle, one thread per entry, rows in order); chol64 adds them.
+constexpr int kGramRows = 32;
+
+__global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64_t d, int l, double* part) {
+  extern __shared__ double Ys[];
+  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+  const int nr = (int)(d - r0 < kGramRows ? d - r0 : kGramRows);
+  for (int e = threadIdx.x; e < nr * l; e += blockDim.x) Ys[e] = Y[r0 * l + e];
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * l * l;
+  for (int e = threadIdx.x; e < l * l; e += blockDim.x) {
+    const int i = e / l, j = e % l;
+    if (j < i) continue;
+    double acc = 0.0;
+    for (int r = 0; r < nr; ++r) acc += Ys[r * l + i] * Ys[r * l + j];
+    out[e] = acc;
+  }
 }
 
 int g_max_lds = -1;
@@ -245,15 +295,32 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
   return SCS_OK;
 }
 
-int launch_chol_inv64(hipStream_t st, const double* G, int l, double* Rinv, int* flag) {
+int64_t gram64_parts(int64_t d) { return cdiv(d, (int64_t)kGramRows); }
+
+int launch_gram_part64(hipStream_t st, const double* Y, int64_t d, int l, double* part) {
+  if (l <= 0 || d <= 0) return SCS_OK;
+  const size_t bytes = (size_t)kGramRows * l * sizeof(double);
+  if (bytes > 65536)
+    SCS_HIP(hipFuncSetAttribute((const void*)gram_part64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+  gram_part64_kernel<<<(unsigned)gram64_parts(d), 256, bytes, st>>>(Y, d, l, part);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag) {
   const size_t bytes = ((size_t)l * (l + 1) / 2 + l) * sizeof(double);
   if (l > 192 || (int64_t)bytes + 1024 > max_lds_bytes()) {
     set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
     return SCS_EINVAL;
   }
-  if (bytes > 65536) SCS_HIP(hipFuncSetAttribute((const void*)chol_inv64_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  chol_inv64_kernel<<<1, kCholThreads, bytes, st>>>(G, l, Rinv, flag);
+  if (bytes > 65536) {
+    SCS_HIP(hipFuncSetAttribute((const void*)chol64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    SCS_HIP(hipFuncSetAttribute((const void*)rinv64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  }
+  chol64_kernel<<<1, kCholThreads, bytes, st>>>(part, nparts, l, Rp, flag);
+  SCS_HIP(hipGetLastError());
+  rinv64_kernel<<<(unsigned)cdiv(l, kRinvWaves), 64 * kRinvWaves, bytes, st>>>(Rp, l, Rinv);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
