@@ -326,16 +326,15 @@ int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int*
 // st_in / sfx: the stream to use and a suffix for the names of its workspace buffers (so that
 // sketches of different problems can run on different streams at once).
 // CholeskyQR2 of Yb (d x l, FP64): Qout = Yb R1^{-1} R2^{-1} (leading dimension ldq), QTout (nullable)
-// = Qout^T in FP32; f[0], f[1] receive the two factorizations' breakdown flags. Rinv: l x l, Q1: d x l,
+// = Qout^T in FP32; f[0], f[1] receive the two factorizations' breakdown flags. G, Rinv: l x l, Q1: d x l,
 // Rp: l (l + 1) / 2 + l, Gp: gram64_parts(d) l^2.
 int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f,
-               double* Rinv, double* Q1, double* Rp, double* Gp) {
-  const int np = (int)gram64_parts(d);
-  SCS_CHECK(launch_gram_part64(st, Yb, d, l, Gp));
-  SCS_CHECK(launch_chol_inv64(st, Gp, np, l, Rp, Rinv, f));
+               double* G, double* Rinv, double* Q1, double* Rp, double* Gp) {
+  SCS_CHECK(launch_gram64(st, Yb, d, l, Gp, G));
+  SCS_CHECK(launch_chol_inv64(st, G, 1, l, Rp, Rinv, f));
   SCS_CHECK(launch_gemm64(st, d, l, l, Yb, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
-  SCS_CHECK(launch_gram_part64(st, Q1, d, l, Gp));
-  SCS_CHECK(launch_chol_inv64(st, Gp, np, l, Rp, Rinv, f + 1));
+  SCS_CHECK(launch_gram64(st, Q1, d, l, Gp, G));
+  SCS_CHECK(launch_chol_inv64(st, G, 1, l, Rp, Rinv, f + 1));
   SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Qout, ldq, nullptr, 0));
   if (QTout) SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QTout, d));  // R2^{-T} Q1^T
   return SCS_OK;
@@ -386,10 +385,11 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     bflags = ws<int>(ctx, "blockflags" + sfx, (size_t)2 * q);
     if (!bflags) return SCS_ENOMEM;
   }
+  WS(G, double, std::string("G64") + sfx, (size_t)l * l);
   WS(Rp, double, std::string("Rp64") + sfx, (size_t)l * (l + 1) / 2 + l);
   WS(Gp, double, std::string("Gpart64") + sfx, (size_t)gram64_parts(d) * l * l);
   auto cholqr2 = [&](const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f) -> int {
-    return cholqr2_64(st, d, l, Yb, Qout, ldq, QTout, f, Rinv, Q1, Rp, Gp);
+    return cholqr2_64(st, d, l, Yb, Qout, ldq, QTout, f, G, Rinv, Q1, Rp, Gp);
   };
   int L = l;            // columns of the orthonormal basis handed to Rayleigh-Ritz
   const double* Qb = Q; // that basis, d x L (leading dimension L)
@@ -1283,9 +1283,10 @@ static int sketch64_impl(scs_ctx* ctx, hipStream_t st, const double* X, int64_t 
   WS(Rinv, double, "f64_Rinv", (size_t)l * l);
   WS(Q1, double, "f64_Q1", (size_t)d * l);
   WS(Q, double, "f64_Q", (size_t)d * l);
+  WS(G, double, "f64_G", (size_t)l * l);
   WS(Rp, double, "f64_Rp", (size_t)l * (l + 1) / 2 + l);
   WS(Gp, double, "f64_Gpart", (size_t)gram64_parts(d) * l * l);
-  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, Rinv, Q1, Rp, Gp));
+  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1, Rp, Gp));
   // Rayleigh-Ritz: W = X Q (over T), B = W^T W / n
   SCS_CHECK(launch_gemm64(st, n, l, d, X, ldx, 1, Q, l, 1, T, l, nullptr, 0));
   WS(B, double, "f64_B", (size_t)l * l);

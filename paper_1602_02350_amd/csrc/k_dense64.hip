@@ -45,20 +45,19 @@ __global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_
 }
 
 // Cholesky G = R^T R (upper R), then R^{-1}, in two launches.
-// chol64: one workgroup; G arrives as the partial Gram matrices of gram_part64 (upper triangles),
-// added in order; R packed in LDS (l (l + 1) / 2 doubles, then the l reciprocal diagonal entries),
+// chol64: one workgroup; G arrives as nparts matrices (upper triangles) that it adds in order (one:
+// G itself); R packed in LDS (l (l + 1) / 2 doubles, then the l reciprocal diagonal entries),
 // copied out in that layout. Right-looking with one barrier per column: phase j reads the finished
 // diagonal entry p_j and the unscaled row j, updates the trailing triangle with
-// S[a][c] -= (S[j][a] / p_j) S[j][c] (lanes over columns c, each holding S[j][c] in a register, waves
-// over rows a, four rows' updates in flight), and scales row j - 1 (which nothing reads in that phase)
-// by 1/sqrt(p_{j-1}).
+// S[a][c] -= (S[j][a] / p_j) S[j][c] (lanes over columns c, each holding its S[j][c] in registers,
+// waves over rows a), and scales row j - 1 (which nothing reads in that phase) by 1/sqrt(p_{j-1}).
 // rinv64: X = R^{-1} one column per wave, over as many workgroups as the columns need, by back
 // substitution in axpy form: x = e_j, and for q = j, ..., 0: x_q *= 1/R[q][q], x_i -= R[i][q] x_q
 // (i < q); lane t keeps x_t, x_{t+64}, x_{t+128} in registers and the entries of R for step q - 1 are
 // read from LDS while step q runs.
 // flag: 0 on success, 1 if a pivot is not positive relative to the largest diagonal entry of G
 // (that pivot is replaced by 1 so the factor stays finite).
-constexpr int kCholThreads = 512;
+constexpr int kCholThreads = 1024;
 constexpr int kRinvWaves = 4;  // columns of R^{-1} per workgroup
 
 __device__ __forceinline__ int packed_up(int i, int j, int l) { return i * (2 * l - i + 1) / 2 + (j - i); }
@@ -117,16 +116,21 @@ __global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part
     const double p = pivot(j), ip = 1.0 / p;
     const double sp = sqrt(p), isp = 1.0 / sp;  // independent of the update: overlaps it
     const int rowj = packed_row(j, l);
-    for (int c0 = j + 1; c0 < l; c0 += 64) {
-      const int c = c0 + lane;
-      const bool cok = c < l;
-      const double sjc = cok ? S[rowj + c] : 0.0;
+    constexpr int kCC = 3;  // column chunks of 64: l <= 192
+    double sj[kCC];
+#pragma unroll
+    for (int q = 0; q < kCC; ++q) {
+      const int c = j + 1 + lane + 64 * q;
+      sj[q] = c < l ? S[rowj + c] : 0.0;
+    }
 #pragma unroll 4
-      for (int a = j + 1 + wave; a < l; a += nwave) {
-        if (cok && c >= a) {
-          const double ra = S[rowj + a] * ip;
-          S[packed_row(a, l) + c] -= ra * sjc;
-        }
+    for (int a = j + 1 + wave; a < l; a += nwave) {
+      const double ra = S[rowj + a] * ip;
+      const int rowa = packed_row(a, l);
+#pragma unroll
+      for (int q = 0; q < kCC; ++q) {
+        const int c = j + 1 + lane + 64 * q;
+        if (c < l && c >= a) S[rowa + c] -= ra * sj[q];
       }
     }
     if (j > 0) finish_row(j - 1, sp_prev, isp_prev);
@@ -192,7 +196,8 @@ __global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* R
 }
 
 // Partial Gram matrices of Y d x l (row-major, ld l): each workgroup stages kGramRows rows of Y in LDS
-// and forms their Y_r^T Y_r (upper triangle, one thread per entry, rows in order); chol64 adds them.
+// and forms their Y_r^T Y_r (upper triangle, one thread per entry, rows in order); gram_sum64 adds
+// them in workgroup order, one thread per entry (loads of eight partials in flight), and mirrors.
 constexpr int kGramRows = 32;
 
 __global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64_t d, int l, double* part) {
@@ -209,6 +214,18 @@ __global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64
     for (int r = 0; r < nr; ++r) acc += Ys[r * l + i] * Ys[r * l + j];
     out[e] = acc;
   }
+}
+
+__global__ __launch_bounds__(256) void gram_sum64_kernel(const double* part, int nparts, int l, double* G) {
+  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= l * l) return;
+  const int i = e / l, j = e % l;
+  if (j < i) return;
+  double g = 0.0;
+#pragma unroll 8
+  for (int p = 0; p < nparts; ++p) g += part[(int64_t)p * l * l + e];
+  G[(int64_t)i * l + j] = g;
+  G[(int64_t)j * l + i] = g;
 }
 
 int g_max_lds = -1;
@@ -297,13 +314,15 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
 
 int64_t gram64_parts(int64_t d) { return cdiv(d, (int64_t)kGramRows); }
 
-int launch_gram_part64(hipStream_t st, const double* Y, int64_t d, int l, double* part) {
+int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* part, double* G) {
   if (l <= 0 || d <= 0) return SCS_OK;
   const size_t bytes = (size_t)kGramRows * l * sizeof(double);
   if (bytes > 65536)
     SCS_HIP(hipFuncSetAttribute((const void*)gram_part64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bytes));
   gram_part64_kernel<<<(unsigned)gram64_parts(d), 256, bytes, st>>>(Y, d, l, part);
+  SCS_HIP(hipGetLastError());
+  gram_sum64_kernel<<<(unsigned)cdiv((int64_t)l * l, 256), 256, 0, st>>>(part, (int)gram64_parts(d), l, G);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -86,11 +86,19 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
       sig = eig_block_sum(part, sred);
       continue;
     }
-    // w = tau A v, with lane 0 of each wave adding up w_i v_i over its rows
+    // w = tau A v, with lane 0 of each wave adding up w_i v_i over its rows; each lane keeps its
+    // entries of v (columns lane, lane + 64, lane + 128) in registers for the column
+    constexpr int kVC = (kEigMaxL + 63) / 64;
+    double vr[kVC];
+#pragma unroll
+    for (int q = 0; q < kVC; ++q) vr[q] = lane + 64 * q < m ? vv[lane + 64 * q] : 0.0;
     double pw = 0.0;
     for (int i = wave; i < m; i += nwave) {
       double acc = 0.0;
-      for (int c = lane; c < m; c += 64) acc += A[(r0 + i) * l + r0 + c] * vv[c];
+      const double* rowi = A + (r0 + i) * l + r0;
+#pragma unroll
+      for (int q = 0; q < kVC; ++q)
+        if (lane + 64 * q < m) acc += rowi[lane + 64 * q] * vr[q];
       acc = wave_sum_d_fast(acc);
       if (lane == 0) {
         const double wi = tau * acc;
@@ -106,13 +114,20 @@ __global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B,
     for (int i = tid; i < m; i += nt) ww[i] += al * vv[i];
     __syncthreads();
     double ps = 0.0;
+    double wr[kVC];
+#pragma unroll
+    for (int q = 0; q < kVC; ++q) wr[q] = lane + 64 * q < m ? ww[lane + 64 * q] : 0.0;
     for (int i = wave; i < m; i += nwave) {
       const double vi = vv[i], wi = ww[i];
       double* row = A + (r0 + i) * l + r0;
-      for (int c = lane; c < m; c += 64) {
-        const double x = row[c] - (vi * ww[c] + wi * vv[c]);
-        row[c] = x;
-        if (c == 0 && i >= 2) ps += x * x;   // column j + 1 below its first sub-diagonal entry
+#pragma unroll
+      for (int q = 0; q < kVC; ++q) {
+        const int c = lane + 64 * q;
+        if (c < m) {
+          const double x = row[c] - (vi * wr[q] + wi * vr[q]);
+          row[c] = x;
+          if (c == 0 && i >= 2) ps += x * x;   // column j + 1 below its first sub-diagonal entry
+        }
       }
     }
     if (lane == 0) ssig[wave] = ps;
@@ -393,10 +408,16 @@ __global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const doub
     __syncthreads();
     const int lane = tid & 63, nwave = nt >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int kWC = (kEigMaxL + 63) / 64;  // each lane's entries of w (columns lane + 64 q) in registers
+    double wr[kWC];
+#pragma unroll
+    for (int q = 0; q < kWC; ++q) wr[q] = lane + 64 * q < l ? wcol[lane + 64 * q] : 0.0;
     for (int i = wave; i < m; i += nwave) {
       const double vi = vv[i];
       double* row = Zs + (r0 + i) * l;
-      for (int c = lane; c < l; c += 64) row[c] -= vi * wcol[c];
+#pragma unroll
+      for (int q = 0; q < kWC; ++q)
+        if (lane + 64 * q < l) row[lane + 64 * q] -= vi * wr[q];
     }
     __syncthreads();
   }

@@ -249,11 +249,12 @@ int launch_reduce_partials_f64(hipStream_t st, const float* partial, int64_t nch
 int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double* A, int64_t a_rs,
                   int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
                   float* C32, int64_t ldc32);
-// Partial Gram matrices Y_r^T Y_r of row chunks of Y (d x l row-major, ld l; upper triangles), into part
-// (gram64_parts(d) x l x l), and the Cholesky factor G = R^T R of their sum with R^{-1} (l x l,
-// row-major); Rp: scratch of l (l + 1) / 2 + l doubles (the packed factor and its reciprocal diagonal)
+// G = Y^T Y (l x l) for Y d x l row-major with leading dimension l, through partial Gram matrices of
+// row chunks (part: gram64_parts(d) x l x l scratch); the Cholesky factor G = R^T R of the sum of
+// nparts matrices (upper triangles read) with R^{-1} (l x l, row-major); Rp: scratch of
+// l (l + 1) / 2 + l doubles (the packed factor and its reciprocal diagonal)
 int64_t gram64_parts(int64_t d);
-int launch_gram_part64(hipStream_t st, const double* Y, int64_t d, int l, double* part);
+int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* part, double* G);
 int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag);
 int launch_axpy64(hipStream_t st, int64_t count, double alpha, const double* x, double* y);
 int launch_copy64(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
