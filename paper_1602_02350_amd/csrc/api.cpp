@@ -31,6 +31,7 @@ struct scs_ctx {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
+  std::vector<void*> retired;       // buffers replaced by larger ones, freed at the next call's entry
   std::vector<hipEvent_t> events;   // synchronizing events (host waits on them)
   std::vector<hipEvent_t> tevents;  // timing-only events (no system-scope fence when recorded)
   std::map<std::string, std::pair<int, int>> tuned_w;  // autotuned inner-loop (workgroups, wave-rows) per (d, b, precision)
@@ -46,14 +47,17 @@ struct scs_ctx {
 
 namespace {
 
-// Scratch buffer `name` with at least `bytes` (contents undefined after growth).
+// Scratch buffer `name` with at least `bytes` (contents undefined after growth). A buffer that grows
+// is replaced, not freed: work already queued on any of the context's streams may still use it, and
+// freeing it here would need a device-wide wait in the middle of enqueueing (the batched setup grows
+// its per-lane buffers as it meets wider problems, and such waits serialized its streams). Replaced
+// buffers are freed by free_retired at the entry of the next call.
 void* wsb(scs_ctx* c, const std::string& name, size_t bytes) {
   if (bytes == 0) bytes = 16;
   auto& b = c->bufs[name];
   if (b.bytes >= bytes) return b.p;
   if (b.p) {
-    hipDeviceSynchronize();  // the old buffer may be in use on any of the context's streams
-    hipFree(b.p);
+    c->retired.push_back(b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -65,6 +69,15 @@ void* wsb(scs_ctx* c, const std::string& name, size_t bytes) {
   }
   b.bytes = want;
   return b.p;
+}
+
+// Frees the buffers wsb replaced, after waiting for the device (they may be in use by work of an
+// earlier, asynchronous call). Called at the entry of the calls that allocate workspace.
+void free_retired(scs_ctx* c) {
+  if (c->retired.empty()) return;
+  hipDeviceSynchronize();
+  for (void* p : c->retired) hipFree(p);
+  c->retired.clear();
 }
 
 template <class T>
@@ -585,6 +598,7 @@ int scs_destroy(scs_ctx* c) {
   Guard g(c->device);
   hipStreamSynchronize(c->stream);
   for (auto q : c->side) hipStreamSynchronize(q);
+  free_retired(c);
   for (auto& kv : c->bufs)
     if (kv.second.p) hipFree(kv.second.p);
   for (auto e : c->events) hipEventDestroy(e);
@@ -601,6 +615,7 @@ int scs_destroy(scs_ctx* c) {
 int scs_gaussian(scs_ctx* ctx, uint64_t seed, int64_t count, float* out) {
   if (!ctx || !out || count < 0) return SCS_EINVAL;
   Guard g(ctx->device);
+  free_retired(ctx);
   return launch_gaussian(ctx->stream, seed, count, out);
 }
 
@@ -608,6 +623,7 @@ int scs_sample_indices(scs_ctx* ctx, const float* beta, int64_t N, uint64_t seed
                        int32_t* out) {
   if (!ctx || !beta || !out || N < 1 || count < 0 || N > INT32_MAX) return SCS_EINVAL;
   Guard g(ctx->device);
+  free_retired(ctx);
   WS(cum, uint64_t, "cum", (size_t)N);
   WS(scr, double, "sampler_scratch", (size_t)sampler_scratch_len(N));
   SCS_CHECK(launch_sampler_prepare(ctx->stream, beta, N, cum, scr, sampler_scratch_len(N), nullptr));
@@ -627,6 +643,7 @@ int scs_sketch_build(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   bool rd = false;
   SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, false, &rd));
   hipStream_t st = ctx->stream;
@@ -648,6 +665,7 @@ int scs_precondition_apply(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   if (k == 0) {
     // P = I: x~_i = x_i, rows sqrt(n lambda) e_j
@@ -685,6 +703,7 @@ int scs_full_gradient(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_
   SCS_CHECK(validate_problem(X, n, d, ldx, lambda));
   if (k > 256) return SCS_EINVAL;
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const float* UT = nullptr;
   if (k > 0) {
@@ -726,6 +745,7 @@ int scs_regularization_for_budget(scs_ctx* ctx, const float* X, int64_t n, int64
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   bool rd = false;
   SCS_CHECK(sketch_impl(ctx, X, n, d, ldx, k, o, false, &rd));
@@ -764,6 +784,7 @@ int scs_svrg_epoch(scs_ctx* ctx, int64_t n, int64_t d, const void* Xt, const voi
       b < 1 || b > kInnerMaxB || !(eta > 0.0))
     return SCS_EINVAL;
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const int64_t N = n + d;
   WS(cum, uint64_t, "cum", (size_t)N);
@@ -841,6 +862,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const int b = o.batch;
   const int64_t m = epoch_steps(o, n, b);
@@ -1158,6 +1180,7 @@ int scs_autotune(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx
   o.wave_rows = 0;
   o.seed = o.seed ^ 0x5ca1ab1e5eedull;  // candidates never see the caller's random streams
   Guard g(ctx->device);
+  free_retired(ctx);
   WS(wt, float, "tune_w", (size_t)d);
   // warm-up: first-use workspace and the inner-loop shape for b = 64
   {
@@ -1344,6 +1367,7 @@ static int svrg_solve_f64_impl(scs_ctx* ctx, const double* X, int64_t n, int64_t
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const int b = o.batch;
   const int64_t m = epoch_steps(o, n, b);
@@ -1526,6 +1550,7 @@ int scs_sketch_build_f64(scs_ctx* ctx, const double* X, int64_t n, int64_t d, in
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   int* flags = ws<int>(ctx, "f64_cholflags", 2);
   if (!flags) return SCS_ENOMEM;
@@ -1600,6 +1625,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const int b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
   const int es = mixed ? 2 : 4;
@@ -1701,10 +1727,12 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     SCS_HIP(hipMemcpy2DAsync(rg, ldt[p] * es, rtmp, d[p] * es, d[p] * es, d[p], hipMemcpyDeviceToDevice, sq));
     return SCS_OK;
   };
-  // Problems are independent until their epochs: their sketches and preconditioned rows are built
-  // on up to kLanes streams at once (each with its own workspace buffers), largest problems first,
-  // so the latency-bound small kernels of different problems overlap on different CUs.
-  constexpr int kLanes = 8;
+  // Problems are independent until their epochs: their sketches, preconditioned rows and sampling
+  // weights are built on up to kLanes streams at once (each with its own workspace buffers), largest
+  // problems first, so the latency-bound small kernels of different problems overlap on different
+  // CUs. (256 uneven problems: 16 lanes 40.5 ms, 8 lanes 46.3 ms; the runtime's 4 hardware queues
+  // are shared by the lanes, and 16 or 32 queues gave no gain.)
+  constexpr int kLanes = 16;
   const int lanes = std::min(nprob, kLanes);
   SCS_CHECK(ensure_side_streams(ctx, lanes));
   SCS_HIP(hipEventRecord(tev[1], st));
@@ -1728,6 +1756,11 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     } else {
       SCS_CHECK(setup_identity(p, sq, sfx));
     }
+    // sampling weights on the same lane, with the lane's own scratch (a problem whose CholeskyQR
+    // breaks down is redone below)
+    WS(lscr, double, "sampler_scratch" + sfx, (size_t)sampler_scratch_len(max_N));
+    SCS_CHECK(launch_sampler_prepare(sq, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], lscr,
+                                     sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling));
   }
   for (int q = 0; q < lanes; ++q) {
     SCS_HIP(hipEventRecord(ctx->side_events[q], ctx->side[q]));
@@ -1744,11 +1777,10 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
       rank_def[p] = 1;
       k_used[p] = 0;
       SCS_CHECK(setup_identity(p, st, ""));
+      SCS_CHECK(launch_sampler_prepare(st, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], scr,
+                                       sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling));
     }
   }
-  for (int p = 0; p < nprob; ++p)
-    SCS_CHECK(launch_sampler_prepare(st, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], scr,
-                                     sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling));
   SCS_HIP(hipEventRecord(tev[1], st));
 
   // ---- descriptors and flattened-grid prefixes
@@ -1949,6 +1981,7 @@ static int path_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t
     return SCS_EINVAL;
   }
   Guard g(ctx->device);
+  free_retired(ctx);
   hipStream_t st = ctx->stream;
   const int P = nl * ny, b = o.batch, S = o.max_epochs, mixed = o.precision == SCS_PREC_MIXED;
   const int es = mixed ? 2 : 4;
