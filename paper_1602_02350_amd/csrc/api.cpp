@@ -353,10 +353,22 @@ int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout,
   return SCS_OK;
 }
 
+// Where a split sketch stops: the Rayleigh-Ritz matrix B (L x L), the basis Q (d x L) and Wq = X Q
+// (n x Lp), in buffers named with the caller's persistent suffix, for a batched eigensolver and lift.
+struct SketchSplit {
+  const double* B = nullptr;
+  const double* Q = nullptr;
+  int L = 0;
+  const float* Wq = nullptr;
+  int64_t Lp = 0;
+};
+
 int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx, int k, const scs_opts& o,
                 bool want_z, bool* rank_def, int* flags_out = nullptr, hipStream_t st_in = nullptr,
-                const std::string& sfx = "", hipEvent_t x_done = nullptr) {
+                const std::string& sfx = "", hipEvent_t x_done = nullptr, SketchSplit* split = nullptr,
+                const std::string& psfx = "") {
   hipStream_t st = st_in ? st_in : ctx->stream;
+  const std::string& ksfx = split ? psfx : sfx;  // buffers that must outlive the call in split mode
   const int l = k + o.oversample;
   // Rayleigh-Ritz (X Q, its Gram, Z = X U~) follows the precision; the range finder (X Omega, X^T T and
   // the further Krylov blocks) reads X in BF16 (FP32 accumulation) unless FP32 is asked for: it only
@@ -385,7 +397,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
   WS(Rinv, double, std::string("Rinv64") + sfx, (size_t)l * l);
   WS(Q1, double, std::string("Q1_64") + sfx, (size_t)d * l);
-  WS(Q, double, std::string("Q64") + sfx, (size_t)d * l);
+  WS(Q, double, std::string("Q64") + ksfx, (size_t)d * l);
   WS(QT32, float, std::string("QT32") + sfx, (size_t)l * d);
   int* flags = flags_out;
   if (!flags) {
@@ -414,7 +426,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
     // projected twice against the blocks before it (block Gram-Schmidt) and orthonormalized by CholeskyQR2.
     // Its span is the span of the stacked Krylov blocks.
     L = q * l;
-    WS(Qall, double, std::string("Qall64") + sfx, (size_t)d * L);
+    WS(Qall, double, std::string("Qall64") + ksfx, (size_t)d * L);
     WS(QTb, float, std::string("QTb32") + sfx, (size_t)l * d);
     WS(Yj, double, std::string("Yj64") + sfx, (size_t)d * l);
     WS(Zj, double, std::string("Zj64") + sfx, (size_t)L * l);
@@ -441,7 +453,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   }
   const int64_t Lp = cdiv(L, 16) * 16;
   // Rayleigh-Ritz: Wq = X Q (n x L), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
-  WS(Wq, float, std::string("Wq") + sfx, (size_t)n * Lp);
+  WS(Wq, float, std::string("Wq") + ksfx, (size_t)n * Lp);
   SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, L, d, Wq, Lp, true));
   if (x_done) SCS_HIP(hipEventRecord(x_done, st));  // the sketch reads X no more after this point
   int64_t nch2 = gemm_tn_splitk_chunks(n, L, L, Wq, Lp, Wq, Lp);
@@ -449,8 +461,16 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   nch2 = cdiv(n, chunk2);
   WS(part2, float, std::string("partial2") + sfx, (size_t)nch2 * L * L);
   SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, L, Lp, Wq, L, Lp, part2, chunk2, nch2));
-  WS(B, double, std::string("B64") + sfx, (size_t)L * L);
+  WS(B, double, std::string("B64") + ksfx, (size_t)L * L);
   SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)L * L, 1.0 / (double)n, B));
+  if (split) {
+    split->B = B;
+    split->Q = Qb;
+    split->L = L;
+    split->Wq = Wq;
+    split->Lp = Lp;
+    return SCS_OK;
+  }
   WS(V, double, std::string("V64") + sfx, (size_t)L * L);
   WS(theta, double, std::string("theta") + sfx, (size_t)L);
   WS(order, int, std::string("order") + sfx, (size_t)L);
@@ -1737,34 +1757,85 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   SCS_CHECK(ensure_side_streams(ctx, lanes));
   SCS_HIP(hipEventRecord(tev[1], st));
   for (int q = 0; q < lanes; ++q) SCS_HIP(hipStreamWaitEvent(ctx->side[q], tev[1], 0));
+  // Three phases. 1 (lanes): each problem's range finder, CholeskyQR2 and Rayleigh-Ritz matrix B,
+  // kept with its basis Q and X Q in buffers of its own. 2 (one stream): the eigendecompositions of
+  // every B and the lifts U~ = Q V_k, one launch each for all problems (one workgroup per problem),
+  // writing U~^T and lam~ straight into the batch arrays. 3 (lanes): Z = (X Q) V_k, the
+  // preconditioned rows and the sampling weights. Problems without a sketch are set up in phase 1.
+  auto join_lanes = [&]() -> int {
+    for (int q = 0; q < lanes; ++q) {
+      SCS_HIP(hipEventRecord(ctx->side_events[q], ctx->side[q]));
+      SCS_HIP(hipStreamWaitEvent(st, ctx->side_events[q], 0));
+    }
+    return SCS_OK;
+  };
+  auto prepare_sampler = [&](int p, hipStream_t sq, const std::string& sfx) -> int {
+    // with the lane's own scratch (a problem whose CholeskyQR breaks down is redone below)
+    WS(lscr, double, "sampler_scratch" + sfx, (size_t)sampler_scratch_len(max_N));
+    return launch_sampler_prepare(sq, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], lscr,
+                                  sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling);
+  };
+  std::vector<SketchSplit> split(nprob);
   for (int i = 0; i < nprob; ++i) {
     const int p = ord[i], lane = i % lanes;
     hipStream_t sq = ctx->side[lane];
     const std::string sfx = "#" + std::to_string(lane);
     if (k[p] > 0) {
       bool unused = false;
-      SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p, sq, sfx));
-      const float* U32 = ws<float>(ctx, "U32" + sfx, 0);
-      SCS_HIP(hipMemcpyAsync(ut_all + o_ut[p], ws<float>(ctx, "UT32" + sfx, 0), sizeof(float) * k[p] * d[p],
-                             hipMemcpyDeviceToDevice, sq));
-      SCS_HIP(hipMemcpyAsync(lam_all + o_lam[p], ws<double>(ctx, "lam" + sfx, 0), sizeof(double) * k[p],
-                             hipMemcpyDeviceToDevice, sq));
-      SCS_CHECK(apply_impl(ctx, X[p], n[p], d[p], ldx[p], U32, ws<float>(ctx, "Z" + sfx, 0), lam_all + o_lam[p],
-                           k[p], lambda[p], mixed, mixed, (char*)xt_all + o_xt[p] * es,
-                           (char*)reg_all + o_reg[p] * es, ldt[p], beta_all + o_beta[p], states + sidx[p], sq,
-                           sfx));
+      SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p, sq, sfx,
+                            nullptr, &split[p], "#p" + std::to_string(p)));
     } else {
       SCS_CHECK(setup_identity(p, sq, sfx));
+      SCS_CHECK(prepare_sampler(p, sq, sfx));
     }
-    // sampling weights on the same lane, with the lane's own scratch (a problem whose CholeskyQR
-    // breaks down is redone below)
-    WS(lscr, double, "sampler_scratch" + sfx, (size_t)sampler_scratch_len(max_N));
-    SCS_CHECK(launch_sampler_prepare(sq, beta_all + o_beta[p], n[p] + d[p], cum_all + o_beta[p], lscr,
-                                     sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling));
   }
-  for (int q = 0; q < lanes; ++q) {
-    SCS_HIP(hipEventRecord(ctx->side_events[q], ctx->side[q]));
-    SCS_HIP(hipStreamWaitEvent(st, ctx->side_events[q], 0));
+  SCS_CHECK(join_lanes());
+  std::vector<Eig64Job> ej;
+  std::vector<LiftJob> lj;
+  std::vector<int> jp;  // problem of each job
+  int max_L = 1;
+  int64_t max_elems = 1;
+  for (int p = 0; p < nprob; ++p) {
+    if (k[p] <= 0) continue;
+    const int L = split[p].L;
+    const std::string ps = "#p" + std::to_string(p);
+    WS(V, double, "V64" + ps, (size_t)L * L);
+    WS(theta, double, "theta" + ps, (size_t)L);
+    WS(order, int, "order" + ps, (size_t)L);
+    WS(eigw, double, "eig_work" + ps, eig64_work_len(L));
+    WS(U32, float, "U32" + ps, (size_t)d[p] * k[p]);
+    WS(VkT, float, "VkT" + ps, (size_t)k[p] * L);
+    ej.push_back(Eig64Job{split[p].B, L, eigw, V, theta, order});
+    lj.push_back(LiftJob{split[p].Q, d[p], L, V, order, k[p], theta, nullptr, U32, ut_all + o_ut[p],
+                         lam_all + o_lam[p], VkT});
+    jp.push_back(p);
+    max_L = std::max(max_L, L);
+    max_elems = std::max(max_elems, std::max<int64_t>(d[p] * k[p], (int64_t)k[p] * L));
+  }
+  if (!ej.empty()) {
+    WS(ejd, Eig64Job, "b_eigjobs", ej.size());
+    WS(ljd, LiftJob, "b_liftjobs", lj.size());
+    SCS_HIP(hipMemcpyAsync(ejd, ej.data(), sizeof(Eig64Job) * ej.size(), hipMemcpyHostToDevice, st));
+    SCS_HIP(hipMemcpyAsync(ljd, lj.data(), sizeof(LiftJob) * lj.size(), hipMemcpyHostToDevice, st));
+    SCS_CHECK(launch_eig64_batched(st, ejd, (int)ej.size(), max_L));
+    SCS_CHECK(launch_lift_batched(st, ljd, (int)lj.size(), max_elems));
+    SCS_HIP(hipEventRecord(tev[2], st));
+    for (int q = 0; q < lanes; ++q) SCS_HIP(hipStreamWaitEvent(ctx->side[q], tev[2], 0));
+    const int bf = mixed;
+    for (size_t i = 0; i < jp.size(); ++i) {
+      const int p = jp[i], lane = (int)(i % lanes);
+      hipStream_t sq = ctx->side[lane];
+      const std::string sfx = "#" + std::to_string(lane);
+      const int64_t kz = gemm_wide_kpad(k[p]);
+      WS(Z, float, "Z" + sfx, (size_t)n[p] * kz);
+      SCS_CHECK(launch_gemm_nt_longk(sq, bf, split[p].Wq, n[p], split[p].L, split[p].Lp, lj[i].VkT, k[p],
+                                     split[p].L, Z, kz, true));
+      SCS_CHECK(apply_impl(ctx, X[p], n[p], d[p], ldx[p], lj[i].U32, Z, lam_all + o_lam[p], k[p], lambda[p], mixed,
+                           mixed, (char*)xt_all + o_xt[p] * es, (char*)reg_all + o_reg[p] * es, ldt[p],
+                           beta_all + o_beta[p], states + sidx[p], sq, sfx));
+      SCS_CHECK(prepare_sampler(p, sq, sfx));
+    }
+    SCS_CHECK(join_lanes());
   }
   // CholeskyQR breakdown: those problems fall back to P = I (status SKETCH_RANK_DEFICIENT)
   std::vector<int> hflags(2 * nprob, 0);

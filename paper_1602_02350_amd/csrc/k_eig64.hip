@@ -34,9 +34,8 @@ __device__ __forceinline__ double eig_block_sum(double v, double* sred) {
 // H_j = I - tau_j v v^T, v = (1, v_1, ..., v_{m-1}) acting on rows j+1 .. l-1, maps column j below
 // the diagonal onto beta_j e_1; the trailing block is updated as A - v w^T - w v^T with
 // w = tau A v - (tau^2 / 2)(v^T A v) v.
-__global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B, int l, double* dd, double* ee,
-                                                                double* Vh, double* tau_out) {
-  extern __shared__ double A[];  // l x l
+__device__ __forceinline__ void tridiag64_body(double* A /* LDS, l x l */, const double* B, int l, double* dd,
+                                               double* ee, double* Vh, double* tau_out) {
   __shared__ double vv[kEigMaxL], ww[kEigMaxL];
   __shared__ double sred[kEigThreads / 64];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nwave = nt >> 6;
@@ -268,9 +267,10 @@ __device__ void normalize2(double* zz, int l, int t) {
 // Eigenpairs of the symmetric tridiagonal T (diagonal dd, off-diagonal ee). The vectors live in
 // LDS; the rows of U of the solves (3 l^2 doubles) follow them in LDS when ULDS, else they go to work.
 template <bool ULDS>
-__global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* dd, const double* ee, int l,
-                                                                  double* theta, double* Z, double* work) {
-  extern __shared__ double zz[];  // l x l: the inverse-iteration vectors, element i of vector t at [i * l + t]
+__device__ __forceinline__ void tridiag_eig_body(double* zz /* LDS: l x l vectors (element i of vector t at
+                                                 [i * l + t]), then 3 l^2 rows of U when ULDS */,
+                                                 const double* dd, const double* ee, int l, double* theta,
+                                                 double* Z, double* work) {
   __shared__ double sd[kEigMaxL], se[kEigMaxL], se2[kEigMaxL], sth[kEigMaxL], csc[kEigMaxL];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < l; i += nt) {
@@ -377,10 +377,9 @@ __global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* 
 
 // V = Qh Z = H_0 (H_1 (... (H_{l-3} Z))): reflector j acts on rows j+1 .. l-1. Z in LDS; each
 // column dot is split over `parts` threads.
-__global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const double* Zin, const double* Vh,
-                                                                      const double* tau, int l, double* V,
-                                                                      const double* theta, int* order) {
-  extern __shared__ double Zs[];  // l x l
+__device__ __forceinline__ void backtransform64_body(double* Zs /* LDS, l x l */, const double* Zin,
+                                                     const double* Vh, const double* tau, int l, double* V,
+                                                     const double* theta, int* order) {
   __shared__ double vv[kEigMaxL], wcol[kEigMaxL];
   __shared__ double red[8][kEigMaxL];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -427,6 +426,62 @@ __global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const doub
   (void)theta;
 }
 
+// One-problem kernels and their batched forms (one workgroup per problem, its arguments from jobs).
+__global__ __launch_bounds__(kEigThreads) void tridiag64_kernel(const double* B, int l, double* dd, double* ee,
+                                                                double* Vh, double* tau_out) {
+  extern __shared__ double dyn[];
+  tridiag64_body(dyn, B, l, dd, ee, Vh, tau_out);
+}
+
+template <bool ULDS>
+__global__ __launch_bounds__(kEigThreads) void tridiag_eig_kernel(const double* dd, const double* ee, int l,
+                                                                  double* theta, double* Z, double* work) {
+  extern __shared__ double dyn[];
+  tridiag_eig_body<ULDS>(dyn, dd, ee, l, theta, Z, work);
+}
+
+__global__ __launch_bounds__(kEigThreads) void backtransform64_kernel(const double* Zin, const double* Vh,
+                                                                      const double* tau, int l, double* V,
+                                                                      const double* theta, int* order) {
+  extern __shared__ double dyn[];
+  backtransform64_body(dyn, Zin, Vh, tau, l, V, theta, order);
+}
+
+// the layout of a problem's work array (eig64_work_len(l) doubles), as launch_eig64 uses it
+struct EigWork {
+  double *Vh, *dd, *ee, *tau, *Zt, *tw;
+  __host__ __device__ EigWork(double* work, int l) {
+    Vh = work;
+    dd = work + (int64_t)l * l;
+    ee = dd + l;
+    tau = ee + l;
+    Zt = tau + l;
+    tw = Zt + (int64_t)l * l;
+  }
+};
+
+__global__ __launch_bounds__(kEigThreads) void tridiag64_batched_kernel(const Eig64Job* jobs) {
+  extern __shared__ double dyn[];
+  const Eig64Job j = jobs[blockIdx.x];
+  const EigWork w(j.work, j.l);
+  tridiag64_body(dyn, j.B, j.l, w.dd, w.ee, w.Vh, w.tau);
+}
+
+template <bool ULDS>
+__global__ __launch_bounds__(kEigThreads) void tridiag_eig_batched_kernel(const Eig64Job* jobs) {
+  extern __shared__ double dyn[];
+  const Eig64Job j = jobs[blockIdx.x];
+  const EigWork w(j.work, j.l);
+  tridiag_eig_body<ULDS>(dyn, w.dd, w.ee, j.l, j.theta, w.Zt, w.tw);
+}
+
+__global__ __launch_bounds__(kEigThreads) void backtransform64_batched_kernel(const Eig64Job* jobs) {
+  extern __shared__ double dyn[];
+  const Eig64Job j = jobs[blockIdx.x];
+  const EigWork w(j.work, j.l);
+  backtransform64_body(dyn, w.Zt, w.Vh, w.tau, j.l, j.V, j.theta, j.order);
+}
+
 int g_max_lds_eig = -1;
 
 int max_lds_eig() {
@@ -450,12 +505,10 @@ int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V
     set_error("eigendecomposition: the sketch width k + p must be in [1, 136]");
     return SCS_EINVAL;
   }
-  double* Vh = work;                         // l x l reflectors
-  double* dd = work + (int64_t)l * l;        // l
-  double* ee = dd + l;                       // l
-  double* tau = ee + l;                      // l
-  double* Zt = tau + l;                      // l x l
-  double* tw = Zt + (int64_t)l * l;          // 3 l^2: rows of U of the inverse-iteration solves
+  // l x l reflectors, the diagonal, off-diagonal and reflector scales (l each), the l x l vectors of T,
+  // then 3 l^2 for the rows of U of the inverse-iteration solves
+  const EigWork w(work, l);
+  double *Vh = w.Vh, *dd = w.dd, *ee = w.ee, *tau = w.tau, *Zt = w.Zt, *tw = w.tw;
   if (bytes > 65536) {
     SCS_HIP(hipFuncSetAttribute((const void*)tridiag64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     SCS_HIP(hipFuncSetAttribute((const void*)backtransform64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -478,6 +531,39 @@ int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V
   }
   SCS_HIP(hipGetLastError());
   backtransform64_kernel<<<1, kEigThreads, bytes, st>>>(Zt, Vh, tau, l, V, theta, order);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_eig64_batched(hipStream_t st, const Eig64Job* jobs, int njobs, int max_l) {
+  if (njobs <= 0) return SCS_OK;
+  const size_t bytes = (size_t)max_l * max_l * sizeof(double);
+  if (max_l < 1 || max_l > kEigMaxL || (int64_t)bytes + 16384 > max_lds_eig()) {
+    set_error("eigendecomposition: the sketch width k + p must be in [1, 136]");
+    return SCS_EINVAL;
+  }
+  if (bytes > 65536) {
+    SCS_HIP(hipFuncSetAttribute((const void*)tridiag64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+    SCS_HIP(hipFuncSetAttribute((const void*)backtransform64_batched_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  }
+  tridiag64_batched_kernel<<<(unsigned)njobs, 512, bytes, st>>>(jobs);
+  SCS_HIP(hipGetLastError());
+  const size_t ebytes = 4 * bytes;
+  if ((int64_t)ebytes + 8192 <= max_lds_eig()) {
+    if (ebytes > 65536)
+      SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_batched_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ebytes));
+    tridiag_eig_batched_kernel<true><<<(unsigned)njobs, kEigThreads, ebytes, st>>>(jobs);
+  } else {
+    if (bytes > 65536)
+      SCS_HIP(hipFuncSetAttribute((const void*)tridiag_eig_batched_kernel<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    tridiag_eig_batched_kernel<false><<<(unsigned)njobs, kEigThreads, bytes, st>>>(jobs);
+  }
+  SCS_HIP(hipGetLastError());
+  backtransform64_batched_kernel<<<(unsigned)njobs, kEigThreads, bytes, st>>>(jobs);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

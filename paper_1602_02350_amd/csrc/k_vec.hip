@@ -535,9 +535,9 @@ __global__ void transpose_kernel(const float* A, int64_t rows, int64_t cols, flo
 }
 
 // U~ = Q V_k with the columns of V taken in descending order of theta; lam = max(theta, 0).
-__global__ void lift_kernel(const double* Q, int64_t d, int l, const double* V, const int* order, int k,
-                            const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lift_body(int64_t e, const double* Q, int64_t d, int l, const double* V,
+                                          const int* order, int k, const double* theta, double* U64, float* U32,
+                                          float* UT32, double* lam, float* VkT) {
   if (e < d * k) {
     int64_t j = e / k;
     int i = (int)(e - j * k);
@@ -553,6 +553,18 @@ __global__ void lift_kernel(const double* Q, int64_t d, int l, const double* V, 
     VkT[e] = (float)V[(int64_t)c * l + order[i]];
   }
   if (e < k) lam[e] = fmax(theta[order[e]], 0.0);
+}
+
+__global__ void lift_kernel(const double* Q, int64_t d, int l, const double* V, const int* order, int k,
+                            const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT) {
+  lift_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, Q, d, l, V, order, k, theta, U64, U32, UT32, lam, VkT);
+}
+
+// job blockIdx.y; its elements beyond max(d k, k l) are idle threads
+__global__ void lift_batched_kernel(const LiftJob* jobs) {
+  const LiftJob j = jobs[blockIdx.y];
+  lift_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, j.Q, j.d, j.l, j.V, j.order, j.k, j.theta, j.U64,
+            j.U32, j.UT32, j.lam, j.VkT);
 }
 
 // s = sqrt(lam_k + lambda); D_i = 1/sqrt(lam_i + lambda) - 1/s; UD = U diag(D) and Up = U, both with
@@ -771,6 +783,13 @@ int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double*
   int64_t tot = d * k > (int64_t)k * l ? d * k : (int64_t)k * l;
   lift_kernel<<<dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, st>>>(Q, d, l, V, order, k, theta, U64, U32, UT32,
                                                                     lam, VkT);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_lift_batched(hipStream_t st, const LiftJob* jobs, int njobs, int64_t max_elems) {
+  if (njobs <= 0 || max_elems <= 0) return SCS_OK;
+  lift_batched_kernel<<<dim3((unsigned)cdiv(max_elems, 256), (unsigned)njobs), dim3(256), 0, st>>>(jobs);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -264,6 +264,33 @@ int launch_or_flags(hipStream_t st, const int* src, int count, int* dst);
 // symmetric eigendecomposition B = V diag(theta) V^T (k_eig64.hip); work: eig64_work_len(l) doubles
 int eig64_work_len(int l);
 int launch_eig64(hipStream_t st, const double* B, int l, double* work, double* V, double* theta, int* order);
+// one problem of a batched eigendecomposition (the arguments of launch_eig64)
+struct Eig64Job {
+  const double* B;
+  int l;
+  double* work;  // eig64_work_len(l) doubles
+  double* V;
+  double* theta;
+  int* order;
+};
+// launch_eig64 for njobs problems at once, one workgroup per problem (jobs: device array)
+int launch_eig64_batched(hipStream_t st, const Eig64Job* jobs, int njobs, int max_l);
+// one problem of a batched lift (the arguments of launch_lift; U64 may be null)
+struct LiftJob {
+  const double* Q;
+  int64_t d;
+  int l;
+  const double* V;
+  const int* order;
+  int k;
+  const double* theta;
+  double* U64;
+  float* U32;
+  float* UT32;
+  double* lam;
+  float* VkT;
+};
+int launch_lift_batched(hipStream_t st, const LiftJob* jobs, int njobs, int64_t max_elems);
 // vector / small kernels
 int launch_lift(hipStream_t st, const double* Q, int64_t d, int l, const double* V, const int* order, int k,
                 const double* theta, double* U64, float* U32, float* UT32, double* lam, float* VkT);
