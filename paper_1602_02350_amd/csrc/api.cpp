@@ -353,9 +353,15 @@ int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout,
   return SCS_OK;
 }
 
-// Where a split sketch stops: the Rayleigh-Ritz matrix B (L x L), the basis Q (d x L) and Wq = X Q
-// (n x Lp), in buffers named with the caller's persistent suffix, for a batched eigensolver and lift.
+// A sketch in parts, for the batched setup (buffers that cross parts are named with the caller's
+// persistent suffix). stage 0: up to the Rayleigh-Ritz matrix B (L x L), with the basis Q (d x L) and
+// Wq = X Q (n x Lp), for a batched eigensolver and lift; 1: the range finder alone, up to Y (d x l),
+// for a batched CholeskyQR2 that writes Q64 and QT32 of the same suffix (one Krylov block); 2: from
+// that Q up to B, as stage 0.
 struct SketchSplit {
+  int stage = 0;
+  double* Y = nullptr;
+  int l = 0;
   const double* B = nullptr;
   const double* Q = nullptr;
   int L = 0;
@@ -369,36 +375,44 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
                 const std::string& psfx = "") {
   hipStream_t st = st_in ? st_in : ctx->stream;
   const std::string& ksfx = split ? psfx : sfx;  // buffers that must outlive the call in split mode
+  const int stage = split ? split->stage : 0;
   const int l = k + o.oversample;
   // Rayleigh-Ritz (X Q, its Gram, Z = X U~) follows the precision; the range finder (X Omega, X^T T and
   // the further Krylov blocks) reads X in BF16 (FP32 accumulation) unless FP32 is asked for: it only
   // fixes the subspace that Rayleigh-Ritz then resolves
   const int bf = o.precision == SCS_PREC_MIXED;
   const int bf_range = bf || !o.sketch_fp32;
-  // Omega^T (l x d)
-  const float* OmT = o.omega;
-  if (!OmT) {
-    WS(om, float, std::string("omega") + sfx, (size_t)l * d);
-    SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, om));
-    OmT = om;
-  }
-  // T = X Omega (n x l, leading dimension l rounded up to 16 and zero-filled)
+  // T = X Omega (n x l, leading dimension l rounded up to 16 and zero-filled), then Y = X^T T (d x l),
+  // split over row chunks, summed in FP64
   const int64_t lp = cdiv(l, 16) * 16;
   WS(T, float, std::string("T") + sfx, (size_t)n * lp);
-  SCS_CHECK(launch_gemm_nt_longk(st, bf_range, X, n, d, ldx, OmT, l, d, T, lp, true));
-  // Y = X^T T (d x l), split over row chunks, summed in FP64
   int64_t nchunks = gemm_tn_splitk_chunks(n, d, l, X, ldx, T, lp);
   int64_t chunk = cdiv(n, nchunks);
   nchunks = cdiv(n, chunk);
   WS(part, float, std::string("partial") + sfx, (size_t)nchunks * d * l);
-  SCS_CHECK(launch_gemm_tn_splitk(st, bf_range, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
-  WS(Y, double, std::string("Y64") + sfx, (size_t)d * l);
-  SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
+  WS(Y, double, std::string("Y64") + ksfx, (size_t)d * l);
+  if (stage != 2) {
+    // Omega^T (l x d)
+    const float* OmT = o.omega;
+    if (!OmT) {
+      WS(om, float, std::string("omega") + sfx, (size_t)l * d);
+      SCS_CHECK(launch_gaussian(st, o.seed, (int64_t)l * d, om));
+      OmT = om;
+    }
+    SCS_CHECK(launch_gemm_nt_longk(st, bf_range, X, n, d, ldx, OmT, l, d, T, lp, true));
+    SCS_CHECK(launch_gemm_tn_splitk(st, bf_range, X, n, d, ldx, T, l, lp, part, chunk, nchunks));
+    SCS_CHECK(launch_reduce_partials_f64(st, part, nchunks, d * l, 1.0, Y));
+    if (stage == 1) {
+      split->Y = Y;
+      split->l = l;
+      return SCS_OK;
+    }
+  }
   // CholeskyQR2: Q1 = Y R1^{-1}, Q = Q1 R2^{-1}
   WS(Rinv, double, std::string("Rinv64") + sfx, (size_t)l * l);
   WS(Q1, double, std::string("Q1_64") + sfx, (size_t)d * l);
   WS(Q, double, std::string("Q64") + ksfx, (size_t)d * l);
-  WS(QT32, float, std::string("QT32") + sfx, (size_t)l * d);
+  WS(QT32, float, std::string("QT32") + ksfx, (size_t)l * d);
   int* flags = flags_out;
   if (!flags) {
     flags = ws<int>(ctx, "cholflags" + sfx, 2);
@@ -419,7 +433,7 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   int L = l;            // columns of the orthonormal basis handed to Rayleigh-Ritz
   const double* Qb = Q; // that basis, d x L (leading dimension L)
   if (q == 1) {
-    SCS_CHECK(cholqr2(Y, Q, l, QT32, flags));
+    if (stage != 2) SCS_CHECK(cholqr2(Y, Q, l, QT32, flags));
   } else {
     // Block Lanczos (Alg. 2): the Krylov space [C Omega, C^2 Omega, ..., C^q Omega] (C = X^T X / n, up to
     // the scale of each block), built block by block: block j is C applied to the orthonormal block j-1,
@@ -1757,11 +1771,13 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   SCS_CHECK(ensure_side_streams(ctx, lanes));
   SCS_HIP(hipEventRecord(tev[1], st));
   for (int q = 0; q < lanes; ++q) SCS_HIP(hipStreamWaitEvent(ctx->side[q], tev[1], 0));
-  // Three phases. 1 (lanes): each problem's range finder, CholeskyQR2 and Rayleigh-Ritz matrix B,
-  // kept with its basis Q and X Q in buffers of its own. 2 (one stream): the eigendecompositions of
-  // every B and the lifts U~ = Q V_k, one launch each for all problems (one workgroup per problem),
-  // writing U~^T and lam~ straight into the batch arrays. 3 (lanes): Z = (X Q) V_k, the
-  // preconditioned rows and the sampling weights. Problems without a sketch are set up in phase 1.
+  // Five phases. 1 (lanes): each problem's range finder Y = X^T (X Omega), kept in a buffer of its own.
+  // 2 (one stream): CholeskyQR2 of every Y, eleven launches for all problems. 3 (lanes): X Q and the
+  // Rayleigh-Ritz matrix B, kept with Q and X Q. 4 (one stream): the eigendecompositions of every B
+  // and the lifts U~ = Q V_k, one launch each for all problems (one workgroup per problem), writing
+  // U~^T and lam~ straight into the batch arrays. 5 (lanes): Z = (X Q) V_k, the preconditioned rows
+  // and the sampling weights. Problems without a sketch are set up in phase 1; with several Krylov
+  // blocks (CholeskyQR2 once per block, between the block's GEMMs) a sketch runs whole in phase 1.
   auto join_lanes = [&]() -> int {
     for (int q = 0; q < lanes; ++q) {
       SCS_HIP(hipEventRecord(ctx->side_events[q], ctx->side[q]));
@@ -1776,12 +1792,14 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
                                   sampler_scratch_len(max_N), states + sidx[p], o.uniform_sampling);
   };
   std::vector<SketchSplit> split(nprob);
+  const bool staged = std::max(1, o.krylov_blocks) == 1;
   for (int i = 0; i < nprob; ++i) {
     const int p = ord[i], lane = i % lanes;
     hipStream_t sq = ctx->side[lane];
     const std::string sfx = "#" + std::to_string(lane);
     if (k[p] > 0) {
       bool unused = false;
+      split[p].stage = staged ? 1 : 0;
       SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p, sq, sfx,
                             nullptr, &split[p], "#p" + std::to_string(p)));
     } else {
@@ -1790,6 +1808,43 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
     }
   }
   SCS_CHECK(join_lanes());
+  if (staged) {
+    std::vector<CholJob> cj;
+    int64_t max_dc = 1;
+    int max_lc = 1;
+    for (int p = 0; p < nprob; ++p) {
+      if (k[p] <= 0) continue;
+      const int l = split[p].l;
+      const std::string ps = "#p" + std::to_string(p);
+      WS(Gp, double, "Gpart64" + ps, (size_t)gram64_parts(d[p]) * l * l);
+      WS(G, double, "G64" + ps, (size_t)l * l);
+      WS(Rp, double, "Rp64" + ps, (size_t)l * (l + 1) / 2 + l);
+      WS(Rinv, double, "Rinv64" + ps, (size_t)l * l);
+      WS(Q1, double, "Q1_64" + ps, (size_t)d[p] * l);
+      WS(Q, double, "Q64" + ps, (size_t)d[p] * l);
+      WS(QT, float, "QT32" + ps, (size_t)l * d[p]);
+      cj.push_back(CholJob{split[p].Y, d[p], l, Gp, G, Rp, Rinv, Q1, Q, l, QT, flags_all + 2 * p});
+      max_dc = std::max<int64_t>(max_dc, d[p]);
+      max_lc = std::max(max_lc, l);
+    }
+    if (!cj.empty()) {
+      WS(cjd, CholJob, "b_choljobs", cj.size());
+      SCS_HIP(hipMemcpyAsync(cjd, cj.data(), sizeof(CholJob) * cj.size(), hipMemcpyHostToDevice, st));
+      SCS_CHECK(launch_cholqr2_batched(st, cjd, (int)cj.size(), max_dc, max_lc));
+      SCS_HIP(hipEventRecord(tev[2], st));
+      for (int q = 0; q < lanes; ++q) SCS_HIP(hipStreamWaitEvent(ctx->side[q], tev[2], 0));
+      for (int i = 0; i < nprob; ++i) {
+        const int p = ord[i], lane = i % lanes;
+        if (k[p] <= 0) continue;
+        bool unused = false;
+        split[p].stage = 2;
+        SCS_CHECK(sketch_impl(ctx, X[p], n[p], d[p], ldx[p], k[p], o, true, &unused, flags_all + 2 * p,
+                              ctx->side[lane], "#" + std::to_string(lane), nullptr, &split[p],
+                              "#p" + std::to_string(p)));
+      }
+      SCS_CHECK(join_lanes());
+    }
+  }
   std::vector<Eig64Job> ej;
   std::vector<LiftJob> lj;
   std::vector<int> jp;  // problem of each job

@@ -14,13 +14,12 @@ constexpr int kT = 16;
 // walk interleaved 16-wide K tiles in lockstep, and their partial tiles are added in slice order.
 constexpr int kKZ = 4;
 
-__global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_t N, int64_t K, const double* A,
-                                                               int64_t a_rs, int64_t a_cs, const double* B,
-                                                               int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
-                                                               float* C32, int64_t ldc32) {
+__device__ __forceinline__ void gemm64_body(int bx, int by, int64_t M, int64_t N, int64_t K, const double* A,
+                                            int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs,
+                                            int64_t b_cs, double* C, int64_t ldc, float* C32, int64_t ldc32) {
   __shared__ double As[kKZ][kT][kT + 1], Bs[kKZ][kT][kT + 1];
   const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-  const int64_t i = (int64_t)blockIdx.y * kT + ty, j = (int64_t)blockIdx.x * kT + tx;
+  const int64_t i = (int64_t)by * kT + ty, j = (int64_t)bx * kT + tx;
   double acc = 0.0;
   const int64_t iters = (K + kT * kKZ - 1) / (kT * kKZ);
   for (int64_t it = 0; it < iters; ++it) {
@@ -42,6 +41,13 @@ __global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_
     if (C) C[i * ldc + j] = v;
     if (C32) C32[i * ldc32 + j] = (float)v;
   }
+}
+
+__global__ __launch_bounds__(kT * kT * kKZ) void gemm64_kernel(int64_t M, int64_t N, int64_t K, const double* A,
+                                                               int64_t a_rs, int64_t a_cs, const double* B,
+                                                               int64_t b_rs, int64_t b_cs, double* C, int64_t ldc,
+                                                               float* C32, int64_t ldc32) {
+  gemm64_body((int)blockIdx.x, (int)blockIdx.y, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, C32, ldc32);
 }
 
 // Cholesky G = R^T R (upper R), then R^{-1}, in two launches.
@@ -71,9 +77,8 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part, int nparts, int l, double* Rp,
-                                                              int* flag) {
-  extern __shared__ double S[];
+__device__ __forceinline__ void chol64_body(double* S /* LDS */, const double* part, int nparts, int l, double* Rp,
+                                            int* flag) {
   __shared__ double s_dmax;
   double* rdiag = S + l * (l + 1) / 2;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nwave = nt >> 6;
@@ -144,14 +149,19 @@ __global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part
   if (tid == 0) *flag = bad;
 }
 
-__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* Rp, int l, double* Rinv) {
-  extern __shared__ double S[];
+__global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part, int nparts, int l, double* Rp,
+                                                              int* flag) {
+  extern __shared__ double dyn[];
+  chol64_body(dyn, part, nparts, l, Rp, flag);
+}
+
+__device__ __forceinline__ void rinv64_body(double* S /* LDS */, int bx, const double* Rp, int l, double* Rinv) {
   double* rdiag = S + l * (l + 1) / 2;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int e = tid; e < l * (l + 1) / 2 + l; e += blockDim.x) S[e] = Rp[e];
   __syncthreads();
-  const int j = (int)blockIdx.x * kRinvWaves + wave;
+  const int j = bx * kRinvWaves + wave;
   if (j >= l) return;
   int roff[3];
 #pragma unroll
@@ -195,18 +205,24 @@ __global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* R
   }
 }
 
+__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* Rp, int l, double* Rinv) {
+  extern __shared__ double dyn[];
+  rinv64_body(dyn, (int)blockIdx.x, Rp, l, Rinv);
+}
+
 // Partial Gram matrices of Y d x l (row-major, ld l): each workgroup stages kGramRows rows of Y in LDS
 // and forms their Y_r^T Y_r (upper triangle, one thread per entry, rows in order); gram_sum64 adds
 // them in workgroup order, one thread per entry (loads of eight partials in flight), and mirrors.
 constexpr int kGramRows = 32;
+__host__ __device__ __forceinline__ int64_t gram64_parts_dev(int64_t d) { return (d + kGramRows - 1) / kGramRows; }
 
-__global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64_t d, int l, double* part) {
-  extern __shared__ double Ys[];
-  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+__device__ __forceinline__ void gram_part64_body(double* Ys /* LDS */, int bx, const double* Y, int64_t d, int l,
+                                                 double* part) {
+  const int64_t r0 = (int64_t)bx * kGramRows;
   const int nr = (int)(d - r0 < kGramRows ? d - r0 : kGramRows);
   for (int e = threadIdx.x; e < nr * l; e += blockDim.x) Ys[e] = Y[r0 * l + e];
   __syncthreads();
-  double* out = part + (int64_t)blockIdx.x * l * l;
+  double* out = part + (int64_t)bx * l * l;
   for (int e = threadIdx.x; e < l * l; e += blockDim.x) {
     const int i = e / l, j = e % l;
     if (j < i) continue;
@@ -216,8 +232,12 @@ __global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64
   }
 }
 
-__global__ __launch_bounds__(256) void gram_sum64_kernel(const double* part, int nparts, int l, double* G) {
-  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void gram_part64_kernel(const double* Y, int64_t d, int l, double* part) {
+  extern __shared__ double dyn[];
+  gram_part64_body(dyn, (int)blockIdx.x, Y, d, l, part);
+}
+
+__device__ __forceinline__ void gram_sum64_body(int e, const double* part, int nparts, int l, double* G) {
   if (e >= l * l) return;
   const int i = e / l, j = e % l;
   if (j < i) return;
@@ -226,6 +246,54 @@ __global__ __launch_bounds__(256) void gram_sum64_kernel(const double* part, int
   for (int p = 0; p < nparts; ++p) g += part[(int64_t)p * l * l + e];
   G[(int64_t)i * l + j] = g;
   G[(int64_t)j * l + i] = g;
+}
+
+__global__ __launch_bounds__(256) void gram_sum64_kernel(const double* part, int nparts, int l, double* G) {
+  gram_sum64_body((int)(blockIdx.x * blockDim.x + threadIdx.x), part, nparts, l, G);
+}
+
+// CholeskyQR2 of many problems at once (jobs[blockIdx.y or .z]); the per-problem arithmetic is the
+// one-problem kernels'. Workgroups past a problem's own grid return.
+__global__ __launch_bounds__(256) void gram_part64_batched_kernel(const CholJob* jobs, int pass) {
+  extern __shared__ double dyn[];
+  const CholJob jb = jobs[blockIdx.y];
+  if ((int64_t)blockIdx.x >= gram64_parts_dev(jb.d)) return;
+  gram_part64_body(dyn, (int)blockIdx.x, pass == 0 ? jb.Y : jb.Q1, jb.d, jb.l, jb.Gp);
+}
+
+__global__ __launch_bounds__(256) void gram_sum64_batched_kernel(const CholJob* jobs) {
+  const CholJob jb = jobs[blockIdx.y];
+  gram_sum64_body((int)(blockIdx.x * blockDim.x + threadIdx.x), jb.Gp, (int)gram64_parts_dev(jb.d), jb.l, jb.G);
+}
+
+__global__ __launch_bounds__(kCholThreads) void chol64_batched_kernel(const CholJob* jobs, int pass) {
+  extern __shared__ double dyn[];
+  const CholJob jb = jobs[blockIdx.x];
+  chol64_body(dyn, jb.G, 1, jb.l, jb.Rp, jb.flags + pass);
+}
+
+__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_batched_kernel(const CholJob* jobs) {
+  extern __shared__ double dyn[];
+  const CholJob jb = jobs[blockIdx.y];
+  if ((int)blockIdx.x * kRinvWaves >= jb.l) return;  // uniform: before any barrier
+  rinv64_body(dyn, (int)blockIdx.x, jb.Rp, jb.l, jb.Rinv);
+}
+
+// step 0: Q1 = Y R1^{-1}; 1: Q = Q1 R2^{-1}; 2: Q^T in FP32 as R2^{-T} Q1^T
+__global__ __launch_bounds__(kT * kT * kKZ) void gemm64_chol_batched_kernel(const CholJob* jobs, int step) {
+  const CholJob jb = jobs[blockIdx.z];
+  const int64_t d = jb.d;
+  const int l = jb.l;
+  if (step == 0) {
+    if ((int64_t)blockIdx.y * kT >= d || (int)blockIdx.x * kT >= l) return;
+    gemm64_body((int)blockIdx.x, (int)blockIdx.y, d, l, l, jb.Y, l, 1, jb.Rinv, l, 1, jb.Q1, l, nullptr, 0);
+  } else if (step == 1) {
+    if ((int64_t)blockIdx.y * kT >= d || (int)blockIdx.x * kT >= l) return;
+    gemm64_body((int)blockIdx.x, (int)blockIdx.y, d, l, l, jb.Q1, l, 1, jb.Rinv, l, 1, jb.Q, jb.ldq, nullptr, 0);
+  } else {
+    if (!jb.QT || (int)blockIdx.y * kT >= l || (int64_t)blockIdx.x * kT >= d) return;
+    gemm64_body((int)blockIdx.x, (int)blockIdx.y, l, d, l, jb.Rinv, 1, l, jb.Q1, 1, l, nullptr, 0, jb.QT, d);
+  }
 }
 
 int g_max_lds = -1;
@@ -312,7 +380,7 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
   return SCS_OK;
 }
 
-int64_t gram64_parts(int64_t d) { return cdiv(d, (int64_t)kGramRows); }
+int64_t gram64_parts(int64_t d) { return gram64_parts_dev(d); }
 
 int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* part, double* G) {
   if (l <= 0 || d <= 0) return SCS_OK;
@@ -340,6 +408,43 @@ int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, dou
   chol64_kernel<<<1, kCholThreads, bytes, st>>>(part, nparts, l, Rp, flag);
   SCS_HIP(hipGetLastError());
   rinv64_kernel<<<(unsigned)cdiv(l, kRinvWaves), 64 * kRinvWaves, bytes, st>>>(Rp, l, Rinv);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_cholqr2_batched(hipStream_t st, const CholJob* jobs, int nj, int64_t max_d, int max_l) {
+  if (nj <= 0) return SCS_OK;
+  const size_t cbytes = ((size_t)max_l * (max_l + 1) / 2 + max_l) * sizeof(double);
+  const size_t gbytes = (size_t)kGramRows * max_l * sizeof(double);
+  if (max_l > 192 || (int64_t)cbytes + 1024 > max_lds_bytes()) {
+    set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
+    return SCS_EINVAL;
+  }
+  if (cbytes > 65536) {
+    SCS_HIP(hipFuncSetAttribute((const void*)chol64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)cbytes));
+    SCS_HIP(hipFuncSetAttribute((const void*)rinv64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)cbytes));
+  }
+  if (gbytes > 65536)
+    SCS_HIP(hipFuncSetAttribute((const void*)gram_part64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gbytes));
+  for (int pass = 0; pass < 2; ++pass) {
+    gram_part64_batched_kernel<<<dim3((unsigned)gram64_parts_dev(max_d), (unsigned)nj), 256, gbytes, st>>>(jobs, pass);
+    SCS_HIP(hipGetLastError());
+    gram_sum64_batched_kernel<<<dim3((unsigned)cdiv((int64_t)max_l * max_l, 256), (unsigned)nj), 256, 0, st>>>(jobs);
+    SCS_HIP(hipGetLastError());
+    chol64_batched_kernel<<<(unsigned)nj, kCholThreads, cbytes, st>>>(jobs, pass);
+    SCS_HIP(hipGetLastError());
+    rinv64_batched_kernel<<<dim3((unsigned)cdiv(max_l, kRinvWaves), (unsigned)nj), 64 * kRinvWaves, cbytes, st>>>(
+        jobs);
+    SCS_HIP(hipGetLastError());
+    gemm64_chol_batched_kernel<<<dim3((unsigned)cdiv(max_l, kT), (unsigned)cdiv(max_d, kT), (unsigned)nj),
+                                 dim3(kT, kT, kKZ), 0, st>>>(jobs, pass);
+    SCS_HIP(hipGetLastError());
+  }
+  gemm64_chol_batched_kernel<<<dim3((unsigned)cdiv(max_d, kT), (unsigned)cdiv(max_l, kT), (unsigned)nj),
+                               dim3(kT, kT, kKZ), 0, st>>>(jobs, 2);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

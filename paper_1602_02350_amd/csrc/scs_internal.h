@@ -256,6 +256,25 @@ int launch_gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K, const double*
 int64_t gram64_parts(int64_t d);
 int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* part, double* G);
 int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag);
+// one problem of a batched CholeskyQR2 (the buffers of cholqr2_64: Y d x l, Gp gram64_parts(d) l^2, G and
+// Rinv l x l, Rp l (l + 1) / 2 + l, Q1 d x l, Q d x l with leading dimension ldq, QT l x d FP32 or null,
+// flags[0..1] the two factorizations' breakdown flags)
+struct CholJob {
+  const double* Y;
+  int64_t d;
+  int l;
+  double* Gp;
+  double* G;
+  double* Rp;
+  double* Rinv;
+  double* Q1;
+  double* Q;
+  int64_t ldq;
+  float* QT;
+  int* flags;
+};
+// CholeskyQR2 of nj problems at once (jobs: device array), eleven launches in all
+int launch_cholqr2_batched(hipStream_t st, const CholJob* jobs, int nj, int64_t max_d, int max_l);
 int launch_axpy64(hipStream_t st, int64_t count, double alpha, const double* x, double* y);
 int launch_copy64(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                   int64_t ldd);
