@@ -334,14 +334,47 @@ def bench_batch(args, cfg):
         wss.append(ws)
         Hs.append(H)
     torch.cuda.synchronize()
-    c, mf = (float(v) for v in (args.fixed or "16,0.25").split(";")[0].split(","))
     ctx = binding.Context(0)
-    times, res = [], None
-    def run(timing):
-        return ctx.svrg_solve_batched(Xs, ys, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
-                                      f_star=fs, batch=cfg["b"], epoch_factor=mf, max_epochs=600,
-                                      stop_rule=binding.STOP_GAP, step_scale=c, workgroups=max(args.workgroups, 0),
+
+    def solve_batch(Xa, ya, fa, c_, mf_, timing):
+        return ctx.svrg_solve_batched(Xa, ya, [s_[3] for s_ in shapes], [s_[4] for s_ in shapes], cfg["eps"],
+                                      f_star=fa, batch=cfg["b"], epoch_factor=mf_, max_epochs=600,
+                                      stop_rule=binding.STOP_GAP, step_scale=c_, workgroups=max(args.workgroups, 0),
                                       timing=timing, precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+
+    # ---- tuning (untimed): one step scale c and epoch factor for the whole batch, scored by the wall
+    # time of the batched solve on the same shapes drawn with other data seeds
+    tuned = None
+    if args.fixed:
+        c, mf = (float(v) for v in args.fixed.split(";")[0].split(","))
+    else:
+        Xt_, yt_, ft_ = [], [], []
+        for p, (n, d, a, lam, k) in enumerate(shapes):
+            X_, y_ = make_problem_gpu({"n": n, "d": d, "alpha": a, "floor": cfg["floor"]}, 20160207 + 5000 + p)
+            _, L_, _ = reference_optimum(X_, y_, lam)
+            Xt_.append(X_)
+            yt_.append(y_)
+            ft_.append(L_)
+        solve_batch(Xt_, yt_, ft_, 16.0, 0.25, 0)  # first use: workspace and graph setup
+        tuned = []
+        for c_ in (16.0, 32.0, 64.0, 128.0):
+            for mf_ in (0.25, 0.5, 1.0):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc_, _, reps_ = solve_batch(Xt_, yt_, ft_, c_, mf_, 0)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ok = all(r_["status"] == binding.OK for r_ in reps_)
+                tuned.append({"step_scale": c_, "epoch_factor": mf_, "ms": round(1e3 * dt, 2), "all_ok": ok})
+                log(args, f"tune batch c={c_} mf={mf_}: {1e3 * dt:.1f} ms, all OK {ok}")
+        best = min((t for t in tuned if t["all_ok"]), key=lambda t: t["ms"])
+        c, mf = best["step_scale"], best["epoch_factor"]
+        del Xt_, yt_
+        torch.cuda.empty_cache()
+    times, res = [], None
+
+    def run(timing):
+        return solve_batch(Xs, ys, fs, c, mf, timing)
 
     # timed solves replay their epochs from a captured graph (timing 0); one more solve enqueues them
     # with events around the shared inner-loop launches for the roofline (timing 1)
@@ -382,6 +415,8 @@ def bench_batch(args, cfg):
                 {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
                  "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
                  "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
+                 "tuning": {"data": "the same shapes drawn with data seeds 20160207 + 5000 + p",
+                            "candidates": tuned} if tuned else "fixed",
                  "stage_ms": {"setup": reps[0]["ms_sketch"], "solve": reps[0]["ms_solve"]},
                  "roofline": roof, "cpu_baseline": cpu})
     ctx.close()
