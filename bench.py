@@ -235,39 +235,72 @@ def bench_path(args, cfg):
     from paper_1602_02350_amd import binding, inputs
     n, d, k, b, eps, ny, nl = cfg["n"], cfg["d"], cfg["k"], cfg["b"], cfg["eps"], cfg["ny"], cfg["nl"]
     mixed = args.precision == "mixed"
-    seed = 20160207 + 3
-    X, y0 = make_problem_gpu(cfg, seed)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed + 1)
-    Y = torch.empty(ny, n, device="cuda", dtype=torch.float32)
-    Y[0] = y0
-    for r in range(1, ny):
-        w0 = torch.randn(d, generator=g, device="cuda", dtype=torch.float64)
-        Y[r] = (X.double() @ w0 + 0.1 * torch.randn(n, generator=g, device="cuda", dtype=torch.float64)).float()
     lams = np.logspace(np.log10(cfg["lam_lo"]), np.log10(cfg["lam_hi"]), nl)
-    # FP64 optima (measurement only): one Gram matrix, one Cholesky per lambda
-    Xd = X.double()
-    C = Xd.T @ Xd / n
-    B = Xd.T @ Y.double().T / n
-    Wst, fs, Hs = [], [], []
-    for lam in lams:
-        H = C + lam * torch.eye(d, device="cuda", dtype=torch.float64)
-        Ws = torch.cholesky_solve(B, torch.linalg.cholesky(H))           # d x ny
-        Rr = Xd @ Ws - Y.double().T
-        for r in range(ny):
-            fs.append(0.5 * float(Rr[:, r] @ Rr[:, r]) / n + 0.5 * lam * float(Ws[:, r] @ Ws[:, r]))
-            Wst.append(Ws[:, r])
-        Hs.append(H)
-    del Xd
+
+    def draw(seed):
+        """X, the ny targets Y and, per lambda, the FP64 optima (measurement only: one Gram matrix, one
+        Cholesky per lambda)."""
+        X, y0 = make_problem_gpu(cfg, seed)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed + 1)
+        Y = torch.empty(ny, n, device="cuda", dtype=torch.float32)
+        Y[0] = y0
+        for r in range(1, ny):
+            w0 = torch.randn(d, generator=g, device="cuda", dtype=torch.float64)
+            Y[r] = (X.double() @ w0 + 0.1 * torch.randn(n, generator=g, device="cuda", dtype=torch.float64)).float()
+        Xd = X.double()
+        C = Xd.T @ Xd / n
+        B = Xd.T @ Y.double().T / n
+        Wst, fs, Hs = [], [], []
+        for lam in lams:
+            H = C + lam * torch.eye(d, device="cuda", dtype=torch.float64)
+            Ws = torch.cholesky_solve(B, torch.linalg.cholesky(H))           # d x ny
+            Rr = Xd @ Ws - Y.double().T
+            for r in range(ny):
+                fs.append(0.5 * float(Rr[:, r] @ Rr[:, r]) / n + 0.5 * lam * float(Ws[:, r] @ Ws[:, r]))
+                Wst.append(Ws[:, r])
+            Hs.append(H)
+        del Xd
+        return X, Y, fs, Wst, Hs
+
+    seed = 20160207 + 3
+    X, Y, fs, Wst, Hs = draw(seed)
     torch.cuda.synchronize()
-    c, mf = (float(v) for v in (args.fixed or "16,0.25").split(";")[0].split(","))
     ctx = binding.Context(0)
-    times, res = [], None
-    def run(timing):
-        return ctx.svrg_solve_path(X, Y, list(lams), k, eps, f_star=fs, batch=b, epoch_factor=mf, max_epochs=150,
-                                   stop_rule=binding.STOP_GAP, step_scale=c, implicit_apply=int(args.implicit_apply),
+
+    def solve_path(Xa, Ya, fa, c_, mf_, timing):
+        return ctx.svrg_solve_path(Xa, Ya, list(lams), k, eps, f_star=fa, batch=b, epoch_factor=mf_, max_epochs=150,
+                                   stop_rule=binding.STOP_GAP, step_scale=c_, implicit_apply=int(args.implicit_apply),
                                    workgroups=max(args.workgroups, 0), timing=timing,
                                    precision=binding.PREC_MIXED if mixed else binding.PREC_FP32)
+
+    # ---- tuning (untimed): one step scale c and epoch factor for all solves, scored by the wall time of
+    # the path on a second draw of X and Y from the same recipe
+    tuned = None
+    if args.fixed:
+        c, mf = (float(v) for v in args.fixed.split(";")[0].split(","))
+    else:
+        Xt_, Yt_, ft_, _, _ = draw(seed + 100)
+        solve_path(Xt_, Yt_, ft_, 16.0, 0.25, 0)  # first use: workspace and graph setup
+        tuned = []
+        for c_ in (16.0, 32.0, 64.0, 128.0, 256.0):
+            for mf_ in (0.03125, 0.0625, 0.125):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, reps_ = solve_path(Xt_, Yt_, ft_, c_, mf_, 0)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ok = all(r_["status"] == binding.OK for r_ in reps_)
+                tuned.append({"step_scale": c_, "epoch_factor": mf_, "ms": round(1e3 * dt, 2), "all_ok": ok})
+                log(args, f"tune path c={c_} mf={mf_}: {1e3 * dt:.1f} ms, all OK {ok}")
+        best = min((t for t in tuned if t["all_ok"]), key=lambda t: t["ms"])
+        c, mf = best["step_scale"], best["epoch_factor"]
+        del Xt_, Yt_
+        torch.cuda.empty_cache()
+    times, res = [], None
+
+    def run(timing):
+        return solve_path(X, Y, fs, c, mf, timing)
 
     # timed solves replay their epochs from a captured graph (timing 0); one more solve enqueues them
     # with events around the shared inner-loop launches for the roofline (timing 1)
@@ -311,6 +344,8 @@ def bench_path(args, cfg):
                 {"dtype": "bf16+f32" if mixed else "f32", "status": rc, "status_counts": st,
                  "epochs": {"min": min(ep), "max": max(ep), "mean": sum(ep) / len(ep)},
                  "suboptimality_max": max(so), "step_scale": c, "epoch_factor": mf,
+                 "tuning": {"data": "a second draw of X and Y (seed 20160207 + 103)", "candidates": tuned}
+                 if tuned else "fixed",
                  "implicit_apply": bool(args.implicit_apply),
                  "stage_ms": {"sketch": reps[0]["ms_sketch"], "apply": reps[0]["ms_apply"],
                               "solve": reps[0]["ms_solve"]},
@@ -358,7 +393,7 @@ def bench_batch(args, cfg):
         solve_batch(Xt_, yt_, ft_, 16.0, 0.25, 0)  # first use: workspace and graph setup
         tuned = []
         for c_ in (16.0, 32.0, 64.0, 128.0):
-            for mf_ in (0.25, 0.5, 1.0):
+            for mf_ in (0.125, 0.25, 0.5):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 rc_, _, reps_ = solve_batch(Xt_, yt_, ft_, c_, mf_, 0)
