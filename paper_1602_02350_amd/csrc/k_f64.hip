@@ -256,14 +256,16 @@ __global__ __launch_bounds__(kF64Block) void premap64_kernel(const double* UT, c
 // (average) or w_bar + delta (last iterate). eta = c n / sum(beta), halved per rejected snapshot.
 // Step t: wave w forms the dot products of rows j = w, w + 16, ... (lanes over the columns) and, when
 // b d fits, stages the rows in LDS; after a barrier each thread updates its columns (c = thread +
-// 1024 q). PR > 0 (b <= 16 PR, d <= 64 PQ, the rows staged): each wave holds its rows of step t + 1 in
+// NT q). PR > 0 (b <= (NT / 64) PR, d <= 64 PQ, the rows staged): each wave holds its rows of step t + 1 in
 // registers, loaded during step t together with the indices of step t + 2, through global-address
 // pointers so that the barriers do not wait for them.
 typedef __attribute__((address_space(1))) const double gdouble;
 typedef __attribute__((address_space(1))) const int32_t gint32;
 
-template <int PR, int PQ>
-__global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
+// NT threads (NT / 64 waves), CPT columns per thread: d <= NT CPT.
+template <int PR, int PQ, int NT, int CPT>
+__global__ __launch_bounds__(NT) void inner64_kernel(Inner64Args a) {
+  constexpr int kWaves = NT / 64;
   if (a.state->done) return;
   __shared__ double dl_s[kF64MaxD];
   __shared__ double rows_s[kF64StageRows];  // the step's b rows when b d fits, for the update phase
@@ -275,10 +277,10 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
   const bool staged = PR > 0 || (int64_t)b * d <= kF64StageRows;
   const double eta = ldexp(a.step_scale * (double)a.n / a.state->beta_sum, -a.state->backoffs);
   const double inv_b = 1.0 / (double)b;
-  double w0[kF64Cols], muv[kF64Cols], dl[kF64Cols], sm[kF64Cols];
+  double w0[CPT], muv[CPT], dl[CPT], sm[CPT];
 #pragma unroll
-  for (int q = 0; q < kF64Cols; ++q) {
-    const int64_t c = threadIdx.x + (int64_t)q * kF64Block;
+  for (int q = 0; q < CPT; ++q) {
+    const int64_t c = threadIdx.x + (int64_t)q * NT;
     w0[q] = c < d ? a.wt[c] : 0.0;
     muv[q] = c < d ? a.mu[c] : 0.0;
     dl[q] = 0.0;
@@ -291,8 +293,8 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
   // the update phase of step t, once coef and (when staged) rows_s hold the step
   auto update = [&]() {
 #pragma unroll
-    for (int q = 0; q < kF64Cols; ++q) {
-      const int64_t c = threadIdx.x + (int64_t)q * kF64Block;
+    for (int q = 0; q < CPT; ++q) {
+      const int64_t c = threadIdx.x + (int64_t)q * NT;
       if (c < d) {
         double v = 0.0;
         if (staged) {
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
     for (int64_t t = 0; t < a.m; ++t) {
       const int32_t* idx = a.idx + t * b;
       const double* sc = a.scale + t * b;
-      for (int j = wave; j < b; j += kF64Waves) {
+      for (int j = wave; j < b; j += kWaves) {
         const int64_t i = clampi(idx[j]);
         const double* row = rowp(i);
         double dot = 0.0;
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
     auto load = [&](int64_t t, const int64_t (&ii)[PR], double (&x)[PR][PQ], double (&scv)[PR]) {
 #pragma unroll
       for (int r = 0; r < PR; ++r) {
-        const int j = wave + kF64Waves * r;
+        const int j = wave + kWaves * r;
         const gdouble* row = (const gdouble*)rowp(ii[r]);
         scv[r] = j < b ? gsc[t * b + j] : 0.0;
 #pragma unroll
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
     auto indices = [&](int64_t t, int64_t (&ii)[PR]) {
 #pragma unroll
       for (int r = 0; r < PR; ++r) {
-        const int j = wave + kF64Waves * r;
+        const int j = wave + kWaves * r;
         ii[r] = (t < a.m && j < b) ? clampi(gidx[t * b + j]) : 0;
       }
     };
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
       indices(t + 2, i_after);
 #pragma unroll
       for (int r = 0; r < PR; ++r) {
-        const int j = wave + kF64Waves * r;
+        const int j = wave + kWaves * r;
         if (j < b) {  // uniform over the wave
           double dot = 0.0;
 #pragma unroll
@@ -393,8 +395,8 @@ __global__ __launch_bounds__(kF64Block) void inner64_kernel(Inner64Args a) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < kF64Cols; ++q) {
-    const int64_t c = threadIdx.x + (int64_t)q * kF64Block;
+  for (int q = 0; q < CPT; ++q) {
+    const int64_t c = threadIdx.x + (int64_t)q * NT;
     if (c < d) {
       if (a.wt_prev) a.wt_prev[c] = w0[q];
       a.wt[c] = w0[q] + (a.average ? sm[q] / (double)a.m : dl[q]);
@@ -481,9 +483,11 @@ int launch_premap64(hipStream_t st, const double* UT, const double* lam, int k, 
 int launch_inner64(hipStream_t st, const Inner64Args& a) {
   if (a.d > kF64MaxD || a.b < 1 || a.b > kInnerMaxB || a.m < 0) return SCS_EINVAL;
   const bool fits = (int64_t)a.b * a.d <= kF64StageRows;
-  if (fits && a.b <= kF64Waves && a.d <= 128) inner64_kernel<1, 2><<<1, kF64Block, 0, st>>>(a);
-  else if (fits && a.b <= 2 * kF64Waves && a.d <= 256) inner64_kernel<2, 4><<<1, kF64Block, 0, st>>>(a);
-  else inner64_kernel<0, 0><<<1, kF64Block, 0, st>>>(a);
+  // (four waves with two rows each were slower at b = 8, d = 100: 1.49 against 1.37 us per step)
+  if (fits && a.b <= kF64Waves && a.d <= 128) inner64_kernel<1, 2, kF64Block, kF64Cols><<<1, kF64Block, 0, st>>>(a);
+  else if (fits && a.b <= 2 * kF64Waves && a.d <= 256)
+    inner64_kernel<2, 4, kF64Block, kF64Cols><<<1, kF64Block, 0, st>>>(a);
+  else inner64_kernel<0, 0, kF64Block, kF64Cols><<<1, kF64Block, 0, st>>>(a);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
