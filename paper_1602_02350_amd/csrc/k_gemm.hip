@@ -181,6 +181,67 @@ __global__ __launch_bounds__(256) void gemm_nt_longk_kernel(const float* __restr
       }
 }
 
+// ------------------------------------------------------------------ narrow Gram W^T W (FP32)
+// Partial Gram matrices of W (R x L row-major, leading dimension ldw, L <= 64): workgroup g sums rows
+// [g chunk, (g + 1) chunk) in 64-row slabs staged transposed in LDS (Ws[c][r]); wave w owns output rows
+// 16 w .. 16 w + 15 and all four 16-column blocks, with the FP32 16x16x4 MFMA over the slab's rows
+// (lane (r, q) feeds rows 4 q .. 4 q + 3 of each group of 16, as mfma16_f32 takes them).
+// partial[g][i L + j] = sum over the chunk of W[r][i] W[r][j] (i, j < L).
+constexpr int kGramSlab = 64;
+constexpr int kGramLW = kGramSlab + 4;  // LDS row pitch of the transposed slab (floats)
+
+__global__ __launch_bounds__(256) void gram_rr_f32_kernel(const float* __restrict__ W, int64_t R, int L, int64_t ldw,
+                                                          int64_t chunk, float* __restrict__ partial) {
+  __shared__ __align__(16) float Ws[64 * kGramLW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t r_end = r_begin + chunk < R ? r_begin + chunk : R;
+  f4v acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
+  // Thread tid stages rows (tid >> 6) + 4 q, column c = tid & 63 of each slab. Loads are unconditional
+  // from a clamped address (row and column inside W) and masked to zero when stored to LDS, so the 16
+  // loads of a slab are in flight together; the next slab is loaded while the MFMAs consume this one.
+  const int c = tid & 63, rr = tid >> 6;
+  const bool col_ok = c < L;
+  const int cc = col_ok ? c : L - 1;
+  float v[16];
+  auto load_slab = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t row = r0 + rr + 4 * q;
+      const int64_t rc = row < r_end ? row : r_end - 1;
+      v[q] = W[rc * ldw + cc];
+    }
+  };
+  load_slab(r_begin);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramSlab) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Ws[c * kGramLW + rr + 4 * q] = (col_ok && r0 + rr + 4 * q < r_end) ? v[q] : 0.f;
+    __syncthreads();
+    if (r0 + kGramSlab < r_end) load_slab(r0 + kGramSlab);
+#pragma unroll
+    for (int kq = 0; kq < kGramSlab; kq += 16) {
+      const int ko = kq + 4 * (lane >> 4);
+      const float4 a = *reinterpret_cast<const float4*>(&Ws[(wave * 16 + (lane & 15)) * kGramLW + ko]);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const float4 b = *reinterpret_cast<const float4*>(&Ws[(cb * 16 + (lane & 15)) * kGramLW + ko]);
+        mfma16_f32(a, b, acc[cb]);
+      }
+    }
+  }
+  float* out = partial + (int64_t)blockIdx.x * L * L;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = wave * 16 + 4 * (lane >> 4) + r, j = cb * 16 + (lane & 15);
+      if (i < L && j < L) out[(int64_t)i * L + j] = acc[cb][r];
+    }
+}
+
 // ------------------------------------------------------------------ NT, long K, A in registers
 // The same product as gemm_nt_longk for 16-byte aligned rows of A (X): each wave owns 16 rows of A
 // and reads its MFMA fragments straight from global memory into registers, one K chunk ahead
@@ -1128,6 +1189,23 @@ int launch_reduce_partials_f64(hipStream_t st, const float* partial, int64_t nch
   if (elems <= 0) return SCS_OK;
   reduce_partials_kernel<<<dim3((unsigned)cdiv(elems, 256)), dim3(256), 0, st>>>(partial, nchunks, elems, scale,
                                                                                  out);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+// rows per workgroup: a multiple of the slab, for about min(256, R / 512) workgroups
+static int64_t gram_rr_f32_chunk(int64_t R) {
+  const int64_t target = std::max<int64_t>(1, std::min<int64_t>(256, cdiv(R, 512)));
+  return cdiv(cdiv(R, target), (int64_t)kGramSlab) * kGramSlab;
+}
+
+int64_t gram_rr_f32_parts(int64_t R) { return R <= 0 ? 1 : cdiv(R, gram_rr_f32_chunk(R)); }
+
+int launch_gram_rr_f32(hipStream_t st, const float* W, int64_t R, int L, int64_t ldw, float* partial) {
+  if (R <= 0 || L <= 0) return SCS_OK;
+  if (L > 64 || ldw < L) return SCS_EINVAL;
+  const int64_t chunk = gram_rr_f32_chunk(R);
+  gram_rr_f32_kernel<<<(unsigned)cdiv(R, chunk), 256, 0, st>>>(W, R, L, ldw, chunk, partial);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }

@@ -240,6 +240,10 @@ int launch_gemm_nt_wide(hipStream_t st, int bf16, const float* A, int64_t M, int
 // Row chunks for gemm_tn_splitk over R rows (the same operands as the launch that follows).
 int64_t gemm_tn_splitk_chunks(int64_t R, int64_t M, int64_t N, const float* A, int64_t lda, const float* B,
                               int64_t ldb);
+// Partial Gram matrices W^T W of row chunks of W (R x L, leading dimension ldw, L <= 64) in FP32 MFMA:
+// partial[c][i L + j] for the gram_rr_f32_parts(R) chunks c
+int64_t gram_rr_f32_parts(int64_t R);
+int launch_gram_rr_f32(hipStream_t st, const float* W, int64_t R, int L, int64_t ldw, float* partial);
 int launch_gemm_tn_splitk(hipStream_t st, int bf16, const float* A, int64_t R, int64_t M, int64_t lda,
                           const float* B, int64_t N, int64_t ldb, float* partial, int64_t chunk_rows,
                           int64_t nchunks, Gate gate = Gate());
