@@ -469,7 +469,6 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   // Rayleigh-Ritz: Wq = X Q (n x L), B = Wq^T Wq / n (FP64), B = V diag(theta) V^T
   WS(Wq, float, std::string("Wq") + ksfx, (size_t)n * Lp);
   SCS_CHECK(launch_gemm_nt_longk(st, bf, X, n, d, ldx, QT32, L, d, Wq, Lp, true));
-  if (x_done) SCS_HIP(hipEventRecord(x_done, st));  // the sketch reads X no more after this point
   // in FP32 with L <= 64 the narrow Gram kernel (slabs of X Q staged in LDS); else the split-K TN GEMM
   const bool narrow = !bf && L <= 64;
   int64_t nch2 = narrow ? gram_rr_f32_parts(n) : gemm_tn_splitk_chunks(n, L, L, Wq, Lp, Wq, Lp);
@@ -480,6 +479,9 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   else SCS_CHECK(launch_gemm_tn_splitk(st, bf, Wq, n, L, Lp, Wq, L, Lp, part2, chunk2, nch2));
   WS(B, double, std::string("B64") + ksfx, (size_t)L * L);
   SCS_CHECK(launch_reduce_partials_f64(st, part2, nch2, (int64_t)L * L, 1.0 / (double)n, B));
+  // the sketch reads X no more, and what follows is mostly one-workgroup FP64 algebra: work forked
+  // here overlaps it (forked before this reduce, a gradient pass slowed the reduce down fourfold)
+  if (x_done) SCS_HIP(hipEventRecord(x_done, st));
   if (split) {
     split->B = B;
     split->Q = Qb;
