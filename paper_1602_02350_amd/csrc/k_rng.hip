@@ -74,21 +74,33 @@ __global__ void quantize_scan_tile(const BT* beta, int64_t N, const double* part
   __shared__ double s_scale;
   __shared__ uint64_t s_warp[kScanThreads / 64];
   __shared__ double s_part[2 * kMaxStatParts];
-  // the partials reach LDS in one coalesced pass; thread 0 then combines them in order from LDS (a
-  // serial walk over global memory had cost about 40 us per launch)
+  // the partials reach LDS in one coalesced pass; the first wave combines them: lane t takes partials
+  // t, t + 64, ... in order, then a butterfly over the wave (lane 0's sum is the one kept). The max, and
+  // so the scale and every quantized weight, does not depend on the order. (A serial walk by one thread
+  // cost about 20 us per launch from LDS, and about 40 us from global memory.)
   for (int e = threadIdx.x; e < 2 * nparts; e += blockDim.x) s_part[e] = part[e];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    auto nanmax = [](double a, double b) {
+      return (isnan(a) || isnan(b)) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(a, b);
+    };
     double mx = 0.0, sm = 0.0;
-    for (int p = 0; p < nparts; ++p) {
-      mx = (isnan(mx) || isnan(s_part[2 * p])) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(mx, s_part[2 * p]);
+    for (int p = threadIdx.x; p < nparts; p += 64) {
+      mx = nanmax(mx, s_part[2 * p]);
       sm += s_part[2 * p + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      mx = nanmax(mx, __shfl_xor(mx, o));
+      sm += __shfl_xor(sm, o);
     }
     int lg = 0;
     while (((int64_t)1 << lg) < (N < 2 ? 2 : N)) ++lg;
     double two_b = ldexp(1.0, 62 - lg);
-    s_scale = (mx > 0.0 && !isnan(mx)) ? two_b / mx : 0.0;
-    if (blockIdx.x == 0 && state) state->beta_sum = sm;
+    if (threadIdx.x == 0) {
+      s_scale = (mx > 0.0 && !isnan(mx)) ? two_b / mx : 0.0;
+      if (blockIdx.x == 0 && state) state->beta_sum = sm;
+    }
   }
   __syncthreads();
   const double scale = s_scale;
