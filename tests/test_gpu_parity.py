@@ -76,8 +76,13 @@ def _problem(n, d, alpha=1.5, lam=1e-4, seed=1):
     return inputs.make_ridge(n, d, alpha, lam, seed=seed)
 
 
+# The FP32 Rayleigh-Ritz Gram (X Q)^T (X Q) takes the narrow 64-row-slab kernel for k + p <= 64 and the
+# split-K GEMM above: n = 40 is one partial slab, 1500 rows end inside a slab of the last chunk,
+# and k + p = 64 and 65 sit on either side of the switch.
 @pytest.mark.parametrize("n,d,k,p,mixed", [(700, 40, 6, 5, False), (3000, 130, 20, 5, False),
-                                           (3000, 130, 20, 5, True), (517, 61, 9, 4, False)])
+                                           (3000, 130, 20, 5, True), (517, 61, 9, 4, False),
+                                           (40, 30, 6, 5, False), (1500, 100, 59, 5, False),
+                                           (1500, 100, 60, 5, False)])
 def test_sketch_matches_oracle_with_the_same_omega(ctx, n, d, k, p, mixed):
     P = _problem(n, d, seed=n + d)
     Om = inputs.gaussian((k + p, d), seed=3)                      # Omega^T, (k+p) x d
