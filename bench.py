@@ -475,7 +475,8 @@ def bench_curves(args, cfg):
 
     def run(kk, c, epochs, s_, trace=None, timing=0):
         return ctx.svrg_solve(X, y, lam, kk, 0.0, batch=b, steps=m, max_epochs=epochs, stop_rule=binding.STOP_EPOCHS,
-                              step_scale=c, seed=s_, trace_w=trace, timing=timing, workgroups=args.workgroups)
+                              step_scale=c, seed=s_, trace_w=trace, timing=timing, workgroups=args.workgroups,
+                              epoch_times=timing > 0)
 
     tuned = {}
     for name, kk in (("precond", k), ("plain", 0)):

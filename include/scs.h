@@ -87,7 +87,8 @@ typedef struct scs_opts {
   float* trace_w;         /* optional device max_epochs x d: w = P^{-1/2} w~ of the snapshot entering each epoch
                              (rows of epochs after the stop rule held are left untouched) */
   double* epoch_ms;       /* optional HOST array of max_epochs: milliseconds from the call's start to each epoch's
-                             end; -1 for epochs never enqueued because the stop rule had held */
+                             end; -1 for epochs never enqueued because the stop rule had held. Asking for it
+                             records an event after every epoch, a few microseconds each */
   int timing;             /* 1: time every inner-loop launch with HIP events (report.ms_inner); 2: also every
                              full-gradient pass (report.ms_grad). Each event adds a few microseconds between kernels */
   double epoch_factor;    /* with steps = 0 and epoch_factor > 0: m = ceil(epoch_factor n / b) per problem (default 0) */

@@ -391,16 +391,18 @@ class Context:
                     "scs_svrg_solve_f64")
         return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms))
 
-    def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
+    def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, epoch_times: bool = False,
+                   **opts) -> SolveResult:
+        """FP32 solve; epoch_times asks for the per-epoch times (epoch_ms, which costs an event per epoch)."""
         _dev(X, torch.float32)
         n, d = X.shape
         w = torch.empty(d, dtype=torch.float32, device=X.device)
         o = self.opts(**opts)
         S = o.max_epochs
-        ms = (ctypes.c_double * S)()
-        o.epoch_ms = ctypes.cast(ms, ctypes.c_void_p)
+        ms = (ctypes.c_double * S)() if epoch_times else None
+        o.epoch_ms = ctypes.cast(ms, ctypes.c_void_p) if epoch_times else None
         rep = ScsReport()
         rc = _check(self._L.scs_svrg_solve(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), float(lam_reg), int(k),
                                            float(eps), ctypes.byref(o), _ptr(w), ctypes.byref(rep)),
                     "scs_svrg_solve")
-        return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms))
+        return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms) if epoch_times else [])

@@ -134,6 +134,26 @@ int ensure_stop_flags(scs_ctx* c, size_t count) {
   return SCS_OK;
 }
 
+// Waits until the gradient finish of snapshot q has written its host flag (1: the solve is finished,
+// 2: continue), which it writes in every case once it has run. Between reads of the flag the stream is
+// queried now and then: an error ends the wait, and so does a drained stream whose flag is still unset.
+int wait_stop_flag(scs_ctx* c, hipStream_t st, int q, int* flag) {
+  for (uint32_t spin = 1;; ++spin) {
+    *flag = __atomic_load_n(c->stop_flags + q, __ATOMIC_ACQUIRE);
+    if (*flag) return SCS_OK;
+    if ((spin & 255u) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        *flag = __atomic_load_n(c->stop_flags + q, __ATOMIC_ACQUIRE);
+        if (*flag) return SCS_OK;
+        set_error("solve: the stream drained without writing the snapshot's stop flag");
+        return SCS_EDEVICE;
+      }
+      if (e != hipErrorNotReady) SCS_HIP(e);
+    }
+  }
+}
+
 struct Guard {  // makes the context's device current for the duration of a call
   int prev = -1;
   explicit Guard(int dev) {
@@ -1074,6 +1094,9 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   constexpr int kLookahead = 3;
   int last_epoch = -1;
   bool redo = false;
+  // an event per epoch only where its time is asked for: recording one costs a few microseconds of
+  // dispatch between two epochs, and the host's stop check waits on the flag itself
+  const bool epoch_events = o.epoch_ms != nullptr || o.timing != 0;
   for (int s = 0; s <= S; ++s) {
     float* trace_row = (o.trace_w && s < S) ? o.trace_w + (int64_t)s * d : nullptr;
     if (s == 0 && early_grad) {
@@ -1100,7 +1123,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     a.step_base = (uint32_t)((uint64_t)s * (uint64_t)m);
     if (o.timing) SCS_HIP(hipEventRecord(ev_i0(s), st));
     SCS_CHECK(launch_inner_epoch(st, a, rows_bf16));
-    SCS_HIP(hipEventRecord(ev_epoch(s), st));
+    if (epoch_events) SCS_HIP(hipEventRecord(ev_epoch(s), st));
     last_epoch = s;
     // Keep kLookahead epochs queued ahead of the host's view: once the stop flag of snapshot
     // s - kLookahead + 1 (written before that epoch's inner loop) says the solve is finished, the
@@ -1108,12 +1131,13 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
     // nothing more is enqueued.
     if (s + 1 >= kLookahead) {
       const int q = s + 1 - kLookahead;
-      SCS_HIP(hipEventSynchronize(ev_epoch(q)));
+      int flag = 0;
+      SCS_CHECK(wait_stop_flag(ctx, st, q, &flag));
       if (sketch_broke()) {
         redo = true;
         break;
       }
-      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+      if (flag == 1) break;
     }
   }
   // w = P^{-1/2} w~ with the same routine that produced the gradient's evaluation point
@@ -1141,7 +1165,7 @@ static int svrg_solve_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, i
   if (o.epoch_ms) {
     for (int s = 0; s < S; ++s) {
       float ms = -1.f;
-      if (s > last_epoch || hipEventElapsedTime(&ms, ev_start, ev_epoch(s)) != hipSuccess) ms = -1.f;
+      if (s > last_epoch || !epoch_events || hipEventElapsedTime(&ms, ev_start, ev_epoch(s)) != hipSuccess) ms = -1.f;
       o.epoch_ms[s] = ms;
     }
   }

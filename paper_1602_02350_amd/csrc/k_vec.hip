@@ -350,7 +350,8 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
     const float* UT, const double* lam, int k, float* mu, double* tmp, SolveState* state, int stop_rule, double eps,
     double f_star, float* wt_cur, const float* wt_prev, int first, int* host_stop) {
   // host_stop (host-pinned, may be null) receives 1 once no further epoch will change anything, so the
-  // host can stop enqueuing epochs; it is a plain system-scope store from one lane
+  // host can stop enqueuing epochs, else 2 (so that 0 still means "not written yet"); it is a plain
+  // system-scope store from one lane
   if (state->done) {
     if (host_stop && threadIdx.x == 0) __hip_atomic_store(host_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return;
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(kVecThreads) void grad_finalize_kernel(
   const int action = finalize_body(g_in, kColSplit, rsq_part, nwg, n, d, w, lambda, UT, lam, k, mu, tmp, state,
                                    stop_rule, eps, f_star, wt_cur, wt_prev, first);
   if (host_stop && threadIdx.x == 0)
-    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 0, __ATOMIC_RELAXED,
+    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 2, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(kVecThreads) void grad_tail_kernel(
   const int action = finalize_tail(rsq_part, nwg, n, d, w, lambda, lam, k, mu, tmp, state, stop_rule, eps, f_star,
                                    wt_cur, wt_prev, first);
   if (host_stop && threadIdx.x == 0)
-    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 0, __ATOMIC_RELAXED,
+    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 2, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
