@@ -375,21 +375,22 @@ class Context:
                                                  _ptr(lam)), "scs_sketch_build_f64")
         return U, lam, rc
 
-    def svrg_solve_f64(self, X, y, lam_reg: float, k: int, eps: float, **opts) -> SolveResult:
-        """FP64 solve (X, y FP64 device tensors); w is FP64."""
+    def svrg_solve_f64(self, X, y, lam_reg: float, k: int, eps: float, epoch_times: bool = False,
+                       **opts) -> SolveResult:
+        """FP64 solve (X, y FP64 device tensors); w is FP64. epoch_times as in svrg_solve."""
         _dev(X, torch.float64)
         _dev(y, torch.float64)
         n, d = X.shape
         w = torch.empty(d, dtype=torch.float64, device=X.device)
         o = self.opts(**opts)
         S = o.max_epochs
-        ms = (ctypes.c_double * S)()
-        o.epoch_ms = ctypes.cast(ms, ctypes.c_void_p)
+        ms = (ctypes.c_double * S)() if epoch_times else None
+        o.epoch_ms = ctypes.cast(ms, ctypes.c_void_p) if epoch_times else None
         rep = ScsReport()
         rc = _check(self._L.scs_svrg_solve_f64(self._h, _ptr(X), n, d, X.stride(0), _ptr(y), float(lam_reg), int(k),
                                                float(eps), ctypes.byref(o), _ptr(w), ctypes.byref(rep)),
                     "scs_svrg_solve_f64")
-        return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms))
+        return SolveResult(w=w, status=rc, report=rep.as_dict(), epoch_ms=list(ms) if epoch_times else [])
 
     def svrg_solve(self, X, y, lam_reg: float, k: int, eps: float, epoch_times: bool = False,
                    **opts) -> SolveResult:

@@ -1514,6 +1514,7 @@ static int svrg_solve_f64_impl(scs_ctx* ctx, const double* X, int64_t n, int64_t
   a.state = state;
   constexpr int kLookahead = 3;
   int last_epoch = -1;
+  const bool epoch_events = o.epoch_ms != nullptr || o.timing != 0;  // as in the FP32 solve
   for (int s = 0; s <= S; ++s) {
     SCS_CHECK(launch_premap64(st, UT, lam, k_used, d, lambda, wt, w, state));
     SCS_CHECK(launch_grad64(st, X, n, d, ldx, y, w, nwg, part, rsq, state));
@@ -1530,12 +1531,13 @@ static int svrg_solve_f64_impl(scs_ctx* ctx, const double* X, int64_t n, int64_t
     a.scale = scale + slot * mb;
     if (o.timing) SCS_HIP(hipEventRecord(tev[4 + S + s], st));
     SCS_CHECK(launch_inner64(st, a));
-    SCS_HIP(hipEventRecord(tev[4 + s], st));
+    if (epoch_events) SCS_HIP(hipEventRecord(tev[4 + s], st));
     last_epoch = s;
     if (s + 1 >= kLookahead) {  // as in the FP32 solve: stop enqueuing once a finished snapshot is seen
       const int q = s + 1 - kLookahead;
-      SCS_HIP(hipEventSynchronize(tev[4 + q]));
-      if (__atomic_load_n(ctx->stop_flags + q, __ATOMIC_ACQUIRE)) break;
+      int flag = 0;
+      SCS_CHECK(wait_stop_flag(ctx, st, q, &flag));
+      if (flag == 1) break;
     }
   }
   SCS_CHECK(launch_premap64(st, UT, lam, k_used, d, lambda, wt, w_out, nullptr));
@@ -1558,7 +1560,7 @@ static int svrg_solve_f64_impl(scs_ctx* ctx, const double* X, int64_t n, int64_t
   if (o.epoch_ms) {
     for (int s = 0; s < S; ++s) {
       float ms = -1.f;
-      if (s > last_epoch || hipEventElapsedTime(&ms, tev[0], tev[4 + s]) != hipSuccess) ms = -1.f;
+      if (s > last_epoch || !epoch_events || hipEventElapsedTime(&ms, tev[0], tev[4 + s]) != hipSuccess) ms = -1.f;
       o.epoch_ms[s] = ms;
     }
   }

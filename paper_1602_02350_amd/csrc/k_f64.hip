@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kF64Block) void finish64_kernel(const double* part,
   if (action == 0 || action == 1)
     for (int64_t j = threadIdx.x; j < d; j += blockDim.x) mu[j] = g_s[j];
   if (host_stop && threadIdx.x == 0)
-    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 0, __ATOMIC_RELAXED,
+    __hip_atomic_store(host_stop, (action == 1 || action == 2 || action == 3) ? 1 : 2, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
