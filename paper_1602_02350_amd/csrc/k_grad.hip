@@ -391,9 +391,7 @@ int launch_grad_partial_batched(hipStream_t st, const BatchProb* P, int nprob, c
 
 int grad_num_workgroups(int64_t n, int64_t d) {
   (void)d;
-  // 2 per CU on 256 CUs. Measured at n = 100000, d = 1000: 256 and 384 workgroups take 71.2 and 66.4 us
-  // against 64.8 (fewer waves in flight), 1024 and 2048 are slower too (more rows per wave pipeline better)
-  int64_t want = 512;
+  int64_t want = 512;  // 2 per CU on 256 CUs (measured: 1024 and 2048 are slower, more rows per wave pipeline better)
   int64_t by_rows = cdiv(n, 8);
   return (int)(want < by_rows ? want : (by_rows < 1 ? 1 : by_rows));
 }
