@@ -361,13 +361,17 @@ int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int*
 // CholeskyQR2 of Yb (d x l, FP64): Qout = Yb R1^{-1} R2^{-1} (leading dimension ldq), QTout (nullable)
 // = Qout^T in FP32; f[0], f[1] receive the two factorizations' breakdown flags. G, Rinv: l x l, Q1: d x l,
 // Rp: l (l + 1) / 2 + l, Gp: gram64_parts(d) l^2.
+// gate (device int, nullable): with it, the second pass takes the symmetric orthogonalization
+// Q = Q1 (I + E)^{-1/2} by its binomial series when Q1^T Q1 = I + E is within 1e-5 of I (the usual
+// case: the first pass leaves E of order kappa(Y)^2 u), and the Cholesky pass otherwise.
 int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f,
-               double* G, double* Rinv, double* Q1, double* Rp, double* Gp) {
+               double* G, double* Rinv, double* Q1, double* Rp, double* Gp, int* gate) {
   SCS_CHECK(launch_gram64(st, Yb, d, l, Gp, G));
   SCS_CHECK(launch_chol_inv64(st, G, 1, l, Rp, Rinv, f));
   SCS_CHECK(launch_gemm64(st, d, l, l, Yb, l, 1, Rinv, l, 1, Q1, l, nullptr, 0));
   SCS_CHECK(launch_gram64(st, Q1, d, l, Gp, G));
-  SCS_CHECK(launch_chol_inv64(st, G, 1, l, Rp, Rinv, f + 1));
+  if (gate) SCS_CHECK(launch_lowdin64(st, G, l, Rinv, f + 1, gate));
+  SCS_CHECK(launch_chol_inv64(st, G, 1, l, Rp, Rinv, f + 1, gate));
   SCS_CHECK(launch_gemm64(st, d, l, l, Q1, l, 1, Rinv, l, 1, Qout, ldq, nullptr, 0));
   if (QTout) SCS_CHECK(launch_gemm64(st, l, d, l, Rinv, 1, l, Q1, 1, l, nullptr, 0, QTout, d));  // R2^{-T} Q1^T
   return SCS_OK;
@@ -447,8 +451,9 @@ int sketch_impl(scs_ctx* ctx, const float* X, int64_t n, int64_t d, int64_t ldx,
   WS(G, double, std::string("G64") + sfx, (size_t)l * l);
   WS(Rp, double, std::string("Rp64") + sfx, (size_t)l * (l + 1) / 2 + l);
   WS(Gp, double, std::string("Gpart64") + sfx, (size_t)gram64_parts(d) * l * l);
+  WS(cgate, int, std::string("chol_gate") + sfx, 1);
   auto cholqr2 = [&](const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f) -> int {
-    return cholqr2_64(st, d, l, Yb, Qout, ldq, QTout, f, G, Rinv, Q1, Rp, Gp);
+    return cholqr2_64(st, d, l, Yb, Qout, ldq, QTout, f, G, Rinv, Q1, Rp, Gp, cgate);
   };
   int L = l;            // columns of the orthonormal basis handed to Rayleigh-Ritz
   const double* Qb = Q; // that basis, d x L (leading dimension L)
@@ -1372,7 +1377,7 @@ static int sketch64_impl(scs_ctx* ctx, hipStream_t st, const double* X, int64_t 
   WS(G, double, "f64_G", (size_t)l * l);
   WS(Rp, double, "f64_Rp", (size_t)l * (l + 1) / 2 + l);
   WS(Gp, double, "f64_Gpart", (size_t)gram64_parts(d) * l * l);
-  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1, Rp, Gp));
+  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1, Rp, Gp, nullptr));
   // Rayleigh-Ritz: W = X Q (over T), B = W^T W / n
   SCS_CHECK(launch_gemm64(st, n, l, d, X, ldx, 1, Q, l, 1, T, l, nullptr, 0));
   WS(B, double, "f64_B", (size_t)l * l);
@@ -1751,6 +1756,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
   WS(xbuf_all, uint64_t, "b_xbuf", (int64_t)nprob * inner_xbuf_words(W));
   WS(states, SolveState, "b_state", nprob);
   WS(flags_all, int, "b_cholflags", 2 * nprob);
+  WS(gates_all, int, "b_cholgates", nprob);  // written by the batched CholeskyQR2 before it reads them
   WS(done_count, int, "b_done", 1);
   WS(desc, BatchProb, "b_desc", nprob);
   WS(prefix, int64_t, "b_prefix", 3 * ((int64_t)nprob + 1));
@@ -1854,7 +1860,7 @@ int scs_svrg_solve_batched(scs_ctx* ctx, int nprob, const float* const* X, const
       WS(Q1, double, "Q1_64" + ps, (size_t)d[p] * l);
       WS(Q, double, "Q64" + ps, (size_t)d[p] * l);
       WS(QT, float, "QT32" + ps, (size_t)l * d[p]);
-      cj.push_back(CholJob{split[p].Y, d[p], l, Gp, G, Rp, Rinv, Q1, Q, l, QT, flags_all + 2 * p});
+      cj.push_back(CholJob{split[p].Y, d[p], l, Gp, G, Rp, Rinv, Q1, Q, l, QT, flags_all + 2 * p, gates_all + p});
       max_dc = std::max<int64_t>(max_dc, d[p]);
       max_lc = std::max(max_lc, l);
     }

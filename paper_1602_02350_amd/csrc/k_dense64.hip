@@ -149,10 +149,63 @@ __device__ __forceinline__ void chol64_body(double* S /* LDS */, const double* p
   if (tid == 0) *flag = bad;
 }
 
+// gate (nullable): the factor is formed only while *gate != 0
 __global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part, int nparts, int l, double* Rp,
-                                                              int* flag) {
+                                                              int* flag, const int* gate) {
+  if (gate && *gate == 0) return;
   extern __shared__ double dyn[];
   chol64_body(dyn, part, nparts, l, Rp, flag);
+}
+
+// Second pass of CholeskyQR2 when the first has already left Q1 orthonormal to working accuracy:
+// G = Q1^T Q1 = I + E (upper triangle of G read, E symmetric). If l max |E_ij| <= kLowdinTol, which
+// bounds ||E||_2, then M = I - E/2 + 3 E^2/8 equals (I + E)^{-1/2} to within 5/16 ||E||^3 (the
+// binomial series), and Q = Q1 M is orthonormal to FP64 rounding with the span of Q1 (symmetric
+// orthogonalization); M goes to Minv, the pass's breakdown flag to 0 and *use_chol to 0. Otherwise
+// (and for non-finite E) *use_chol = 1, and the Cholesky factor and its inverse, gated on that flag,
+// write R^{-1} to Minv instead. One workgroup; E in LDS (l^2 doubles).
+constexpr double kLowdinTol = 1e-5;
+
+__device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const double* G, int l, double* Minv,
+                                              int* flag, int* use_chol) {
+  __shared__ double sred[kCholThreads / 64];
+  __shared__ int s_small;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
+  double m = 0.0;
+  bool bad = false;
+  for (int e = tid; e < l * l; e += nt) {
+    const int i = e / l, j = e - i * l;
+    const double v = (i <= j ? G[(int64_t)i * l + j] : G[(int64_t)j * l + i]) - (i == j ? 1.0 : 0.0);
+    E[e] = v;
+    if (!isfinite(v)) bad = true;
+    m = fmax(m, fabs(v));
+  }
+  if (bad) m = INFINITY;
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (lane == 0) sred[wave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int w = 0; w < nt / 64; ++w) mx = fmax(mx, sred[w]);
+    const int small = (double)l * mx <= kLowdinTol ? 1 : 0;
+    s_small = small;
+    *use_chol = small ? 0 : 1;
+    if (small) *flag = 0;
+  }
+  __syncthreads();
+  if (!s_small) return;
+  for (int e = tid; e < l * l; e += nt) {
+    const int i = e / l, j = e - i * l;
+    double e2 = 0.0;
+    for (int t = 0; t < l; ++t) e2 += E[i * l + t] * E[t * l + j];
+    Minv[e] = (i == j ? 1.0 : 0.0) - 0.5 * E[e] + 0.375 * e2;
+  }
+}
+
+__global__ __launch_bounds__(kCholThreads) void lowdin64_kernel(const double* G, int l, double* Minv, int* flag,
+                                                                int* use_chol) {
+  extern __shared__ double dyn[];
+  lowdin64_body(dyn, G, l, Minv, flag, use_chol);
 }
 
 __device__ __forceinline__ void rinv64_body(double* S /* LDS */, int bx, const double* Rp, int l, double* Rinv) {
@@ -205,7 +258,9 @@ __device__ __forceinline__ void rinv64_body(double* S /* LDS */, int bx, const d
   }
 }
 
-__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* Rp, int l, double* Rinv) {
+__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_kernel(const double* Rp, int l, double* Rinv,
+                                                                const int* gate) {
+  if (gate && *gate == 0) return;
   extern __shared__ double dyn[];
   rinv64_body(dyn, (int)blockIdx.x, Rp, l, Rinv);
 }
@@ -266,16 +321,25 @@ __global__ __launch_bounds__(256) void gram_sum64_batched_kernel(const CholJob* 
   gram_sum64_body((int)(blockIdx.x * blockDim.x + threadIdx.x), jb.Gp, (int)gram64_parts_dev(jb.d), jb.l, jb.G);
 }
 
+// pass 1 runs only where the job's gate asks for the Cholesky (lowdin64_batched_kernel decides)
 __global__ __launch_bounds__(kCholThreads) void chol64_batched_kernel(const CholJob* jobs, int pass) {
   extern __shared__ double dyn[];
   const CholJob jb = jobs[blockIdx.x];
+  if (pass == 1 && *jb.gate == 0) return;
   chol64_body(dyn, jb.G, 1, jb.l, jb.Rp, jb.flags + pass);
 }
 
-__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_batched_kernel(const CholJob* jobs) {
+__global__ __launch_bounds__(kCholThreads) void lowdin64_batched_kernel(const CholJob* jobs) {
+  extern __shared__ double dyn[];
+  const CholJob jb = jobs[blockIdx.x];
+  lowdin64_body(dyn, jb.G, jb.l, jb.Rinv, jb.flags + 1, jb.gate);
+}
+
+__global__ __launch_bounds__(64 * kRinvWaves) void rinv64_batched_kernel(const CholJob* jobs, int pass) {
   extern __shared__ double dyn[];
   const CholJob jb = jobs[blockIdx.y];
   if ((int)blockIdx.x * kRinvWaves >= jb.l) return;  // uniform: before any barrier
+  if (pass == 1 && *jb.gate == 0) return;
   rinv64_body(dyn, (int)blockIdx.x, jb.Rp, jb.l, jb.Rinv);
 }
 
@@ -395,7 +459,21 @@ int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* par
   return SCS_OK;
 }
 
-int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag) {
+int launch_lowdin64(hipStream_t st, const double* G, int l, double* Minv, int* flag, int* use_chol) {
+  const size_t bytes = (size_t)l * l * sizeof(double);
+  if (l < 1 || (int64_t)bytes + 1024 > max_lds_bytes()) {
+    set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
+    return SCS_EINVAL;
+  }
+  if (bytes > 65536)
+    SCS_HIP(hipFuncSetAttribute((const void*)lowdin64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  lowdin64_kernel<<<1, kCholThreads, bytes, st>>>(G, l, Minv, flag, use_chol);
+  SCS_HIP(hipGetLastError());
+  return SCS_OK;
+}
+
+int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag,
+                      const int* gate) {
   const size_t bytes = ((size_t)l * (l + 1) / 2 + l) * sizeof(double);
   if (l > 192 || (int64_t)bytes + 1024 > max_lds_bytes()) {
     set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
@@ -405,9 +483,9 @@ int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, dou
     SCS_HIP(hipFuncSetAttribute((const void*)chol64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     SCS_HIP(hipFuncSetAttribute((const void*)rinv64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
-  chol64_kernel<<<1, kCholThreads, bytes, st>>>(part, nparts, l, Rp, flag);
+  chol64_kernel<<<1, kCholThreads, bytes, st>>>(part, nparts, l, Rp, flag, gate);
   SCS_HIP(hipGetLastError());
-  rinv64_kernel<<<(unsigned)cdiv(l, kRinvWaves), 64 * kRinvWaves, bytes, st>>>(Rp, l, Rinv);
+  rinv64_kernel<<<(unsigned)cdiv(l, kRinvWaves), 64 * kRinvWaves, bytes, st>>>(Rp, l, Rinv, gate);
   SCS_HIP(hipGetLastError());
   return SCS_OK;
 }
@@ -429,15 +507,27 @@ int launch_cholqr2_batched(hipStream_t st, const CholJob* jobs, int nj, int64_t 
   if (gbytes > 65536)
     SCS_HIP(hipFuncSetAttribute((const void*)gram_part64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)gbytes));
+  const size_t lbytes = (size_t)max_l * max_l * sizeof(double);
+  if ((int64_t)lbytes + 1024 > max_lds_bytes()) {
+    set_error("CholeskyQR: the sketch width k + p is too large for one workgroup");
+    return SCS_EINVAL;
+  }
+  if (lbytes > 65536)
+    SCS_HIP(hipFuncSetAttribute((const void*)lowdin64_batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lbytes));
   for (int pass = 0; pass < 2; ++pass) {
     gram_part64_batched_kernel<<<dim3((unsigned)gram64_parts_dev(max_d), (unsigned)nj), 256, gbytes, st>>>(jobs, pass);
     SCS_HIP(hipGetLastError());
     gram_sum64_batched_kernel<<<dim3((unsigned)cdiv((int64_t)max_l * max_l, 256), (unsigned)nj), 256, 0, st>>>(jobs);
     SCS_HIP(hipGetLastError());
+    if (pass == 1) {
+      lowdin64_batched_kernel<<<(unsigned)nj, kCholThreads, lbytes, st>>>(jobs);
+      SCS_HIP(hipGetLastError());
+    }
     chol64_batched_kernel<<<(unsigned)nj, kCholThreads, cbytes, st>>>(jobs, pass);
     SCS_HIP(hipGetLastError());
     rinv64_batched_kernel<<<dim3((unsigned)cdiv(max_l, kRinvWaves), (unsigned)nj), 64 * kRinvWaves, cbytes, st>>>(
-        jobs);
+        jobs, pass);
     SCS_HIP(hipGetLastError());
     gemm64_chol_batched_kernel<<<dim3((unsigned)cdiv(max_l, kT), (unsigned)cdiv(max_d, kT), (unsigned)nj),
                                  dim3(kT, kT, kKZ), 0, st>>>(jobs, pass);
