@@ -102,6 +102,28 @@ def test_sketch_matches_oracle_with_the_same_omega(ctx, n, d, k, p, mixed):
     assert rel(Pg @ V, Po @ V) < (5e-2 if mixed else 1e-4)
 
 
+def test_sketch_second_pass_takes_the_cholesky_when_q1_is_not_orthonormal(ctx):
+    """Top k + p eigenvalues spanning 1e6: kappa(Y) ~ 3e6 leaves Q1^T Q1 = I + E with (k + p) max|E| ~ 6e-4
+    after the first CholeskyQR pass (measured in FP64 on the host), above the 1e-5 up to which the second
+    pass uses the series for (I + E)^{-1/2}; the gated Cholesky pass must run, or Q would be built from
+    the first pass's inverse and not be orthonormal."""
+    rng = np.random.default_rng(11)
+    n, d, k, p = 2000, 40, 8, 4
+    l = k + p
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, d)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    sig = np.concatenate([np.geomspace(1.0, 1e-3, l), 1e-3 * np.geomspace(0.5, 0.1, d - l)]) * np.sqrt(n)
+    X = ((Uq * sig) @ Vq.T).astype(np.float32)
+    Om = inputs.gaussian((l, d), seed=3)
+    U, U64, lam, rc = ctx.sketch_build(dev(X), k, oversample=p, omega=dev(Om), sketch_fp32=1,
+                                       precision=binding.PREC_FP32)
+    assert rc == binding.OK
+    Ug = host(U64)
+    assert np.allclose(Ug.T @ Ug, np.eye(k), atol=1e-6)
+    _, lo, _ = sketch.sketch(X.astype(np.float64), Om.T.astype(np.float64), k)
+    assert np.all(np.abs(host(lam) - lo) <= 2e-5 * lo[0])
+
+
 def test_full_width_sketch_is_exact_on_gpu(ctx):
     """k + p = d: Rayleigh-Ritz on all of R^d returns the eigenvalues of C."""
     P = _problem(600, 24, alpha=1.0, seed=5)
