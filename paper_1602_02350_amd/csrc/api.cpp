@@ -1377,7 +1377,8 @@ static int sketch64_impl(scs_ctx* ctx, hipStream_t st, const double* X, int64_t 
   WS(G, double, "f64_G", (size_t)l * l);
   WS(Rp, double, "f64_Rp", (size_t)l * (l + 1) / 2 + l);
   WS(Gp, double, "f64_Gpart", (size_t)gram64_parts(d) * l * l);
-  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1, Rp, Gp, nullptr));
+  WS(cgate, int, "f64_chol_gate", 1);
+  SCS_CHECK(cholqr2_64(st, d, l, Y, Q, l, nullptr, flags, G, Rinv, Q1, Rp, Gp, cgate));
   // Rayleigh-Ritz: W = X Q (over T), B = W^T W / n
   SCS_CHECK(launch_gemm64(st, n, l, d, X, ldx, 1, Q, l, 1, T, l, nullptr, 0));
   WS(B, double, "f64_B", (size_t)l * l);
