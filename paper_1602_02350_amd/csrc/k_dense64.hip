@@ -194,11 +194,32 @@ __device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const 
   }
   __syncthreads();
   if (!s_small) return;
-  for (int e = tid; e < l * l; e += nt) {
-    const int i = e / l, j = e - i * l;
-    double e2 = 0.0;
-    for (int t = 0; t < l; ++t) e2 += E[i * l + t] * E[t * l + j];
-    Minv[e] = (i == j ? 1.0 : 0.0) - 0.5 * E[e] + 0.375 * e2;
+  // E^2 by waves over tasks of 8 rows x 64 columns: lane j reads E[t][j] (contiguous across the wave)
+  // and the 8 row entries E[i][t] are broadcasts, so each step costs one wide LDS read per 8 products
+  // instead of two reads per product; each entry still sums over t in order
+  constexpr int kRB = 8;
+  const int nrb = (l + kRB - 1) / kRB, ncb = (l + 63) / 64, nwave = nt >> 6;
+  for (int task = wave; task < nrb * ncb; task += nwave) {
+    const int rb = task / ncb, cb = task - rb * ncb;
+    const int j = cb * 64 + lane, jc = j < l ? j : l - 1;
+    double acc[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) acc[r] = 0.0;
+    for (int t = 0; t < l; ++t) {
+      const double b = E[t * l + jc];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int i = rb * kRB + r, ic = i < l ? i : l - 1;
+        acc[r] += E[ic * l + t] * b;
+      }
+    }
+    if (j < l) {
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int i = rb * kRB + r;
+        if (i < l) Minv[i * l + j] = (i == j ? 1.0 : 0.0) - 0.5 * E[i * l + j] + 0.375 * acc[r];
+      }
+    }
   }
 }
 
