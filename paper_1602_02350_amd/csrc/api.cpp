@@ -362,8 +362,9 @@ int run_epoch_graph(scs_ctx* ctx, hipStream_t st, int S, F& epoch_launches, int*
 // = Qout^T in FP32; f[0], f[1] receive the two factorizations' breakdown flags. G, Rinv: l x l, Q1: d x l,
 // Rp: l (l + 1) / 2 + l, Gp: gram64_parts(d) l^2.
 // gate (device int, nullable): with it, the second pass takes the symmetric orthogonalization
-// Q = Q1 (I + E)^{-1/2} by its binomial series when Q1^T Q1 = I + E is within 1e-5 of I (the usual
-// case: the first pass leaves E of order kappa(Y)^2 u), and the Cholesky pass otherwise.
+// Q = Q1 (I + E)^{-1/2} by its binomial series (first order up to l max|E_ij| = 1e-7, second order
+// up to 1e-5) when Q1^T Q1 = I + E is that close to I (the usual case: the first pass leaves E of order
+// kappa(Y)^2 u), and the Cholesky pass otherwise.
 int cholqr2_64(hipStream_t st, int64_t d, int l, const double* Yb, double* Qout, int64_t ldq, float* QTout, int* f,
                double* G, double* Rinv, double* Q1, double* Rp, double* Gp, int* gate) {
   SCS_CHECK(launch_gram64(st, Yb, d, l, Gp, G));

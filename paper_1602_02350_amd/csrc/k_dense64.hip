@@ -158,13 +158,16 @@ __global__ __launch_bounds__(kCholThreads) void chol64_kernel(const double* part
 }
 
 // Second pass of CholeskyQR2 when the first has already left Q1 orthonormal to working accuracy:
-// G = Q1^T Q1 = I + E (upper triangle of G read, E symmetric). If l max |E_ij| <= kLowdinTol, which
-// bounds ||E||_2, then M = I - E/2 + 3 E^2/8 equals (I + E)^{-1/2} to within 5/16 ||E||^3 (the
-// binomial series), and Q = Q1 M is orthonormal to FP64 rounding with the span of Q1 (symmetric
-// orthogonalization); M goes to Minv, the pass's breakdown flag to 0 and *use_chol to 0. Otherwise
-// (and for non-finite E) *use_chol = 1, and the Cholesky factor and its inverse, gated on that flag,
-// write R^{-1} to Minv instead. One workgroup; E in LDS (l^2 doubles).
-constexpr double kLowdinTol = 1e-5;
+// G = Q1^T Q1 = I + E (upper triangle of G read, E symmetric), and l max |E_ij| bounds ||E||_2.
+// (I + E)^{-1/2} = I - E/2 + 3 E^2/8 - ... (binomial series): up to kLowdinTol1 the first-order M = I - E/2
+// is within 3/8 ||E||^2 <= 4e-15 of it, up to kLowdinTol2 the second-order M within 5/16 ||E||^3 <= 4e-16.
+// Q = Q1 M is then orthonormal to FP64 rounding with the span of Q1 (symmetric orthogonalization); M goes
+// to Minv, the pass's breakdown flag to 0 and *use_chol to 0. Otherwise (and for non-finite E)
+// *use_chol = 1, and the Cholesky factor and its inverse, gated on that flag, write R^{-1} to Minv
+// instead. One workgroup; E in LDS (l^2 doubles). The E^2 term costs 6 us at l = 55 and about 100 us
+// at l = 133 (its broadcast LDS reads each move a full wave of data), still under the Cholesky's 280.
+constexpr double kLowdinTol1 = 1e-7;
+constexpr double kLowdinTol2 = 1e-5;
 
 __device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const double* G, int l, double* Minv,
                                               int* flag, int* use_chol) {
@@ -173,12 +176,16 @@ __device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
   double m = 0.0;
   bool bad = false;
+  // upper triangle of G read row-major (coalesced), mirrored into the lower triangle of E in LDS
   for (int e = tid; e < l * l; e += nt) {
     const int i = e / l, j = e - i * l;
-    const double v = (i <= j ? G[(int64_t)i * l + j] : G[(int64_t)j * l + i]) - (i == j ? 1.0 : 0.0);
-    E[e] = v;
-    if (!isfinite(v)) bad = true;
-    m = fmax(m, fabs(v));
+    if (i <= j) {
+      const double v = G[e] - (i == j ? 1.0 : 0.0);
+      E[e] = v;
+      E[j * l + i] = v;
+      if (!isfinite(v)) bad = true;
+      m = fmax(m, fabs(v));
+    }
   }
   if (bad) m = INFINITY;
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
@@ -187,16 +194,24 @@ __device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const 
   if (tid == 0) {
     double mx = 0.0;
     for (int w = 0; w < nt / 64; ++w) mx = fmax(mx, sred[w]);
-    const int small = (double)l * mx <= kLowdinTol ? 1 : 0;
-    s_small = small;
-    *use_chol = small ? 0 : 1;
-    if (small) *flag = 0;
+    const double r = (double)l * mx;
+    const int order = r <= kLowdinTol1 ? 1 : (r <= kLowdinTol2 ? 2 : 0);  // series terms kept (0: Cholesky)
+    s_small = order;
+    *use_chol = order ? 0 : 1;
+    if (order) *flag = 0;
   }
   __syncthreads();
-  if (!s_small) return;
+  const int order = s_small;
+  if (order == 0) return;
+  if (order == 1) {
+    for (int e = tid; e < l * l; e += nt) {
+      const int i = e / l, j = e - i * l;
+      Minv[e] = (i == j ? 1.0 : 0.0) - 0.5 * E[e];
+    }
+    return;
+  }
   // E^2 by waves over tasks of 8 rows x 64 columns: lane j reads E[t][j] (contiguous across the wave)
-  // and the 8 row entries E[i][t] are broadcasts, so each step costs one wide LDS read per 8 products
-  // instead of two reads per product; each entry still sums over t in order
+  // and the 8 row entries E[i][t] are wave-uniform; each entry sums over t in order
   constexpr int kRB = 8;
   const int nrb = (l + kRB - 1) / kRB, ncb = (l + 63) / 64, nwave = nt >> 6;
   for (int task = wave; task < nrb * ncb; task += nwave) {
@@ -204,20 +219,20 @@ __device__ __forceinline__ void lowdin64_body(double* E /* LDS, l x l */, const 
     const int j = cb * 64 + lane, jc = j < l ? j : l - 1;
     double acc[kRB];
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) acc[r] = 0.0;
+    for (int q = 0; q < kRB; ++q) acc[q] = 0.0;
     for (int t = 0; t < l; ++t) {
       const double b = E[t * l + jc];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int i = rb * kRB + r, ic = i < l ? i : l - 1;
-        acc[r] += E[ic * l + t] * b;
+      for (int q = 0; q < kRB; ++q) {
+        const int i = rb * kRB + q, ic = i < l ? i : l - 1;
+        acc[q] += E[ic * l + t] * b;
       }
     }
     if (j < l) {
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int i = rb * kRB + r;
-        if (i < l) Minv[i * l + j] = (i == j ? 1.0 : 0.0) - 0.5 * E[i * l + j] + 0.375 * acc[r];
+      for (int q = 0; q < kRB; ++q) {
+        const int i = rb * kRB + q;
+        if (i < l) Minv[i * l + j] = (i == j ? 1.0 : 0.0) - 0.5 * E[i * l + j] + 0.375 * acc[q];
       }
     }
   }

@@ -261,8 +261,9 @@ int64_t gram64_parts(int64_t d);
 int launch_gram64(hipStream_t st, const double* Y, int64_t d, int l, double* part, double* G);
 int launch_chol_inv64(hipStream_t st, const double* part, int nparts, int l, double* Rp, double* Rinv, int* flag,
                       const int* gate = nullptr);  // gate (device, nullable): both kernels run only while *gate != 0
-// The second CholeskyQR pass by symmetric orthogonalization when G = Q1^T Q1 is within 1e-5 of I
-// (Minv = I - E/2 + 3 E^2/8, *flag = 0, *use_chol = 0), else *use_chol = 1 for the gated Cholesky
+// The second CholeskyQR pass by symmetric orthogonalization when G = Q1^T Q1 = I + E has
+// l max|E_ij| <= 1e-5 (Minv = I - E/2, plus 3 E^2/8 above 1e-7; *flag = 0, *use_chol = 0), else
+// *use_chol = 1 for the gated Cholesky
 int launch_lowdin64(hipStream_t st, const double* G, int l, double* Minv, int* flag, int* use_chol);
 // one problem of a batched CholeskyQR2 (the buffers of cholqr2_64: Y d x l, Gp gram64_parts(d) l^2, G and
 // Rinv l x l, Rp l (l + 1) / 2 + l, Q1 d x l, Q d x l with leading dimension ldq, QT l x d FP32 or null,
